@@ -1,0 +1,216 @@
+"""Independent dense references used to pin the oracle (test-side only).
+
+None of these call the oracle or share its code.  They restate the *problem*
+(not the closed-form iteration) in dense matrices:
+
+  * velocity_dense   F, G, h of the splitting in the proof of Theorem 2
+                     (eqn. (9): F p + G q = h) and the dense cost of f(p);
+  * p_subproblem     argmin_p f(p) + rho/2 ||F p + G q - h + s||^2 by a dense
+                     linear solve (the first ADMM block before decoupling);
+  * q_subproblem     argmin_q g(q) + rho/2 ||F p + G q - h + s||^2 by bounded
+                     least squares (scipy BVLS);
+  * lqr              finite-horizon discrete Riccati recursion (textbook);
+  * eq_qp_original   equality-constrained QP of eqn. (1) in the original
+                     (x, u) coordinates solved through its KKT system;
+  * qp_admm          the general-QP ADMM of eqn. (3) on the sparse QP (2),
+                     an independent algorithm with the same optimum.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.optimize
+
+
+def velocity_dense(p):
+    """Dense F, G, h, cost P, linear term qv and box of the velocity-form
+    problem (proof of Theorem 2) for a Problem `p`.
+
+    p-vector = (du_0..du_{N-1}, xbar_1..xbar_N); q-vector = (v_0..v_{N-1},
+    z_1..z_N); constraint rows grouped (theta_k rows, beta_k rows, lambda_k rows).
+    """
+    n, m, N = p.nx, p.nu, p.N
+    nb = n + m
+    A, B, e = p.stage_A(), p.stage_B(), p.stage_e()
+    Abar = np.zeros((N, nb, nb))
+    Bbar = np.zeros((N, nb, m))
+    ebar = np.zeros((N, nb))
+    for k in range(N):
+        Abar[k][:n, :n] = A[k]
+        Abar[k][:n, n:] = B[k]
+        Abar[k][n:, n:] = np.eye(m)
+        Bbar[k][:n] = B[k]
+        Bbar[k][n:] = np.eye(m)
+        ebar[k][:n] = e[k]
+    npv = N * m + N * nb
+    nq = 2 * N * nb
+    ns = 3 * N * nb
+    F = np.zeros((ns, npv))
+    G = np.zeros((ns, nq))
+    h = np.zeros(ns)
+    du = lambda k: slice(k * m, (k + 1) * m)
+    xb = lambda k: slice(N * m + (k - 1) * nb, N * m + k * nb)  # xbar_k, k = 1..N
+    vv = lambda k: slice(k * nb, (k + 1) * nb)
+    zz = lambda k: slice(N * nb + (k - 1) * nb, N * nb + k * nb)  # z_k, k = 1..N
+    th = lambda k: slice(k * nb, (k + 1) * nb)
+    be = lambda k: slice(N * nb + k * nb, N * nb + (k + 1) * nb)
+    la = lambda k: slice(2 * N * nb + k * nb, 2 * N * nb + (k + 1) * nb)
+    I = np.eye(nb)
+    xbar0 = p.xbar0()
+    for k in range(N):
+        # xbar_{k+1} - z_{k+1} = 0
+        F[th(k), xb(k + 1)] = I
+        G[th(k), zz(k + 1)] = -I
+        # Bbar_k du_k - v_k = 0
+        F[be(k), du(k)] = Bbar[k]
+        G[be(k), vv(k)] = -I
+        # z_{k+1} - Abar_k xbar_k - v_k - ebar_k = 0
+        G[la(k), zz(k + 1)] = I
+        G[la(k), vv(k)] = -I
+        if k >= 1:
+            F[la(k), xb(k)] = -Abar[k]
+            h[la(k)] = ebar[k]
+        else:
+            h[la(k)] = ebar[k] + Abar[0] @ xbar0
+    Qbar = np.zeros((nb, nb))
+    Qbar[:n, :n] = p.Q
+    Qbar[n:, n:] = p.R
+    P = np.zeros((npv, npv))
+    qv = np.zeros(npv)
+    qbar = np.zeros(nb) if p.qbar is None else np.asarray(p.qbar)
+    for k in range(1, N + 1):
+        P[xb(k), xb(k)] = Qbar
+        qv[xb(k)] = qbar
+    lo = np.concatenate([np.full(N * nb, -np.inf), np.tile(p.lb(), N)])
+    hi = np.concatenate([np.full(N * nb, np.inf), np.tile(p.ub(), N)])
+    return dict(F=F, G=G, h=h, P=P, qv=qv, lo=lo, hi=hi, Abar=Abar, Bbar=Bbar, ebar=ebar)
+
+
+def state_to_qs(state):
+    """Oracle state (5, N, nb) = (v, z, theta, beta, lambda) -> dense (q, s)."""
+    v, z, th, be, la = state
+    q = np.concatenate([v.ravel(), z.ravel()])
+    s = np.concatenate([th.ravel(), be.ravel(), la.ravel()])
+    return q, s
+
+
+def qs_to_state(q, s, N, nb):
+    v = q[: N * nb].reshape(N, nb)
+    z = q[N * nb:].reshape(N, nb)
+    th = s[: N * nb].reshape(N, nb)
+    be = s[N * nb: 2 * N * nb].reshape(N, nb)
+    la = s[2 * N * nb:].reshape(N, nb)
+    return np.stack([v, z, th, be, la])
+
+
+def p_subproblem(D, rho, q, s):
+    """argmin_p 1/2 p'Pp - qv'p + rho/2 ||F p + G q - h + s||^2 (dense solve)."""
+    F, G, h, P, qv = D["F"], D["G"], D["h"], D["P"], D["qv"]
+    M = P + rho * F.T @ F
+    rhs = qv - rho * F.T @ (G @ q - h + s)
+    return np.linalg.solve(M, rhs)
+
+
+def q_subproblem(D, rho, pvec, s):
+    """argmin_q I_box(z) + rho/2 ||F p + G q - h + s||^2 (bounded least squares)."""
+    F, G, h = D["F"], D["G"], D["h"]
+    target = h - F @ pvec - s
+    lo, hi = D["lo"], D["hi"]
+    res = scipy.optimize.lsq_linear(G, target, bounds=(lo, hi), method="bvls", tol=1e-15,
+                                    lsmr_tol=None, max_iter=10000)
+    return res.x
+
+
+def lqr(A, B, Q, R, x0, N):
+    """Finite-horizon LQR for sum_{k<N} 1/2 x_{k+1}'Q x_{k+1} + 1/2 u_k'R u_k,
+    x_{k+1} = A x_k + B u_k.  Returns (x_1..x_N, u_0..u_{N-1})."""
+    P = Q.copy()
+    Ks = [None] * N
+    for k in range(N - 1, -1, -1):
+        Kk = np.linalg.solve(R + B.T @ P @ B, B.T @ P @ A)
+        Ks[k] = Kk
+        P = Q + A.T @ P @ (A - B @ Kk)
+    xs, us = [], []
+    x = x0.copy()
+    for k in range(N):
+        u = -Ks[k] @ x
+        x = A @ x + B @ u
+        us.append(u)
+        xs.append(x)
+    return np.array(xs), np.array(us)
+
+
+def original_qp(p):
+    """Sparse QP (2) of problem (1) in original coordinates y = col(u_0, x_1,
+    ..., u_{N-1}, x_N): cost 1/2 y'Hy, equality rows Aeq y = beq (dynamics),
+    box rows on every u and x.  Returns dict."""
+    n, m, N = p.nx, p.nu, p.N
+    A, B, e = p.stage_A(), p.stage_B(), p.stage_e()
+    ny = N * (n + m)
+    uu = lambda k: slice(k * (n + m), k * (n + m) + m)
+    xx = lambda k: slice(k * (n + m) + m, (k + 1) * (n + m))  # x_{k+1}
+    H = np.zeros((ny, ny))
+    for k in range(N):
+        H[uu(k), uu(k)] = p.R
+        H[xx(k), xx(k)] = p.Q
+    Aeq = np.zeros((N * n, ny))
+    beq = np.zeros(N * n)
+    for k in range(N):
+        r = slice(k * n, (k + 1) * n)
+        Aeq[r, xx(k)] = np.eye(n)
+        Aeq[r, uu(k)] = -B[k]
+        if k >= 1:
+            Aeq[r, xx(k - 1)] = -A[k]
+            beq[r] = e[k]
+        else:
+            beq[r] = e[k] + A[0] @ p.x0
+    lo = np.zeros(ny)
+    hi = np.zeros(ny)
+    for k in range(N):
+        lo[uu(k)], hi[uu(k)] = p.umin, p.umax
+        lo[xx(k)], hi[xx(k)] = p.xmin, p.xmax
+    return dict(H=H, Aeq=Aeq, beq=beq, lo=lo, hi=hi, uu=uu, xx=xx)
+
+
+def eq_qp_original(p):
+    """Equality-constrained QP (bounds ignored) via its KKT system."""
+    D = original_qp(p)
+    H, Aeq, beq = D["H"], D["Aeq"], D["beq"]
+    ny, ne = H.shape[0], Aeq.shape[0]
+    K = np.block([[H, Aeq.T], [Aeq, np.zeros((ne, ne))]])
+    rhs = np.concatenate([np.zeros(ny), beq])
+    sol = np.linalg.solve(K, rhs)
+    y = sol[:ny]
+    N = p.N
+    us = np.array([y[D["uu"](k)] for k in range(N)])
+    xs = np.array([y[D["xx"](k)] for k in range(N)])
+    return xs, us
+
+
+def qp_admm(p, rho=1.0, iters=60000, tol=1e-12):
+    """General-QP ADMM of eqn. (3) on the sparse QP (2): E = [Aeq; I], Y =
+    {beq} x box.  Returns (xs, us, y, w, lam, iters_run)."""
+    D = original_qp(p)
+    H, Aeq, beq, lo, hi = D["H"], D["Aeq"], D["beq"], D["lo"], D["hi"]
+    ny = H.shape[0]
+    E = np.vstack([Aeq, np.eye(ny)])
+    Ylo = np.concatenate([beq, lo])
+    Yhi = np.concatenate([beq, hi])
+    Minv = np.linalg.inv(H + rho * E.T @ E)
+    w = np.zeros(E.shape[0])
+    lam = np.zeros(E.shape[0])
+    y = np.zeros(ny)
+    it = 0
+    for it in range(1, iters + 1):
+        y = Minv @ (rho * E.T @ (w - lam))
+        Ey = E @ y
+        w_new = np.clip(Ey + lam, Ylo, Yhi)
+        lam = lam + Ey - w_new
+        r_p = np.max(np.abs(Ey - w_new))
+        r_d = rho * np.max(np.abs(E.T @ (w_new - w)))
+        w = w_new
+        if r_p < tol and r_d < tol:
+            break
+    N = p.N
+    us = np.array([y[D["uu"](k)] for k in range(N)])
+    xs = np.array([y[D["xx"](k)] for k in range(N)])
+    return dict(xs=xs, us=us, y=y, w=w, lam=lam, iters=it, E=E, H=H, Ylo=Ylo, Yhi=Yhi, rho=rho)
