@@ -1,0 +1,230 @@
+/*
+ * pimpc.h -- C ABI of the piMPC solver for MI355X (gfx950).
+ *
+ * Solves the linear time-varying MPC problem of Section II, eqn. (1), of
+ * "piMPC: A Parallel-in-horizon and Construction-free NMPC Solver"
+ * (arXiv 2601.14414) with the parallel-in-horizon ADMM iteration of
+ * Section IV (eqn. (8) and Algorithm 1):
+ *
+ *   min  sum_{k<N} 1/2 x_{k+1}' Q x_{k+1} + 1/2 u_k' R u_k - qbar' xbar_{k+1}
+ *   s.t. x_{k+1} = A_k x_k + B_k u_k + e_k,  xmin <= x_{k+1} <= xmax,
+ *        umin <= u_k <= umax,  x_0 = x(t)
+ *
+ * in the velocity form of Theorem 2 (xbar_k = col(x_k, u_{k-1}), input du_k),
+ * with the stage caches J_k, H_k of Algorithm 1 factorised in FP64 on the
+ * device and the iteration run in the precision chosen by the caller.
+ *
+ * Conventions common to every entry point:
+ *   - every call returns an int32 status: PIMPC_OK (0) or a negative error;
+ *     on error no output buffer is written and pimpc_last_error() describes
+ *     the failure.  Nothing throws or aborts across this boundary;
+ *   - matrices are dense, row-major, double precision on the host side;
+ *   - a context owns all its device memory; the caller keeps ownership of
+ *     every array it passes (inputs are copied before the call returns);
+ *   - a context is bound to one HIP stream and is not thread-safe;
+ *   - "instance" = one MPC problem; a context holds `count` of them, packed
+ *     back to back in the order given (offsets are prefix sums of the sizes).
+ */
+#ifndef PIMPC_H
+#define PIMPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIMPC_VERSION 1
+
+/* status codes */
+#define PIMPC_OK 0
+#define PIMPC_E_ARG (-1)         /* bad scalar argument or NULL required pointer */
+#define PIMPC_E_DIM (-2)         /* dimensions out of the supported range */
+#define PIMPC_E_NOT_PSD (-3)     /* Q or R not symmetric PSD, or a stage matrix not SPD */
+#define PIMPC_E_NONFINITE (-4)   /* NaN/Inf input, or an iterate became non-finite */
+#define PIMPC_E_HIP (-5)         /* HIP runtime error */
+#define PIMPC_E_NOMEM (-6)       /* device allocation failed */
+#define PIMPC_E_STATE (-7)       /* call not valid in the context's state */
+#define PIMPC_E_UNSUPPORTED (-8) /* valid request this build does not implement */
+
+/* iteration precision (the stage factorisation is always FP64) */
+#define PIMPC_FP64 0
+#define PIMPC_FP32 1
+
+/* where a pointer lives */
+#define PIMPC_MEM_HOST 0
+#define PIMPC_MEM_DEVICE 1
+
+/* iterate selectors for pimpc_get_iterates / pimpc_set_iterates */
+#define PIMPC_IT_V 0      /* v_k        (copy of Bbar_k du_k)          */
+#define PIMPC_IT_Z 1      /* z_{k+1}    (copy of xbar_{k+1}, in the box) */
+#define PIMPC_IT_THETA 2  /* theta_k    scaled dual                    */
+#define PIMPC_IT_BETA 3   /* beta_k     scaled dual                    */
+#define PIMPC_IT_LAMBDA 4 /* lambda_k   scaled dual                    */
+#define PIMPC_IT_DU 5     /* du_k of the last step 1 (nu per stage)    */
+#define PIMPC_IT_XBAR 6   /* xbar_{k+1} of the last step 1             */
+
+typedef struct pimpc_ctx_s *pimpc_ctx;
+
+/*
+ * Problem data, eqn. (1) with C = I, W_y = Q, W_u = R (Section II) and the
+ * velocity-form linear term qbar of Theorem 2.
+ *   count          number of instances (>= 1)
+ *   nx, nu, N      per-instance state/input sizes and horizon (count entries each)
+ *   time_varying   0: one (A, B, e) per instance; 1: N stage copies per instance
+ *   A, B           row-major nx*nx and nx*nu blocks (times N if time_varying)
+ *   e              affine term e_k (nx, times N if time_varying), NULL = 0
+ *   Q, R           nx*nx and nu*nu symmetric PSD weights per instance
+ *   qbar           (nx+nu) linear cost term per instance, NULL = 0
+ *   xmin, xmax     nx per instance; umin, umax nu per instance; +-INFINITY allowed
+ */
+typedef struct {
+    int32_t count;
+    const int32_t *nx;
+    const int32_t *nu;
+    const int32_t *N;
+    int32_t time_varying;
+    const double *A;
+    const double *B;
+    const double *e;
+    const double *Q;
+    const double *R;
+    const double *qbar;
+    const double *xmin;
+    const double *xmax;
+    const double *umin;
+    const double *umax;
+} pimpc_problem;
+
+/*
+ * Options (Algorithm 1 inputs).
+ *   rho          ADMM penalty (> 0), fixed for the context's life
+ *   max_iter     K_max (>= 1)
+ *   eps          stop when c^{i+1} <= eps (step 5); <= 0 runs exactly max_iter
+ *   check_every  residual cadence (>= 1) when eps > 0
+ *   precision    PIMPC_FP32 or PIMPC_FP64 (iteration arithmetic)
+ *   accel        0 = plain ADMM; 1 = restart acceleration (steps 6-7)
+ *   eta          restart threshold (Algorithm 1 uses 0.999)
+ *   warm_start   1 = start from the previous solve's iterate (unshifted)
+ *   ckpt_every   > 0 records a tape for pimpc_backward every that many iterations
+ *   schedule     batch schedule: 0 = autotune, > 0 = fixed candidate index
+ */
+typedef struct {
+    double rho;
+    int32_t max_iter;
+    double eps;
+    int32_t check_every;
+    int32_t precision;
+    int32_t accel;
+    double eta;
+    int32_t warm_start;
+    int32_t ckpt_every;
+    int32_t schedule;
+} pimpc_options;
+
+/* Per-instance result of a solve (c, r_prim, r_dual of the last residual check). */
+typedef struct {
+    int32_t iters;
+    int32_t restarts;
+    double c;       /* c^{i+1} of Algorithm 1 step 4                      */
+    double r_prim;  /* ||s^{i+1} - s^i||_inf   (primal residual)         */
+    double r_dual;  /* rho ||F'G(q^{i+1}-q^i)||_inf   (dual residual)    */
+    int32_t status; /* PIMPC_OK or PIMPC_E_NONFINITE                      */
+    int32_t pad;
+} pimpc_info;
+
+/* Fill `o` with defaults: rho 1, 200 iterations, eps 0, check_every 1, FP32,
+ * plain ADMM, eta 0.999, cold start, no tape, autotuned schedule. */
+void pimpc_default_options(pimpc_options *o);
+
+/*
+ * Validate the problem on the host (sizes, finiteness, xmin <= xmax, Q and R
+ * symmetric PSD, rho > 0), allocate device memory, upload the data and run
+ * the FP64 stage factorisation (Algorithm 1 "cache": J_k and H_k, proof of
+ * Theorem 2).  `hip_stream` (hipStream_t or NULL for the default stream) is
+ * the stream every later call of this context runs on.  On success *out is
+ * a new context; on error *out is NULL.
+ */
+int32_t pimpc_setup(pimpc_ctx *out, const pimpc_problem *prob, const pimpc_options *opts,
+                    void *hip_stream);
+
+/*
+ * Replace the stage matrices of every instance (same packing as setup's A, B,
+ * e; `mem_kind` says whether the pointers are host or device memory, double
+ * precision either way) and re-run the FP64 stage factorisation.  Iterates are
+ * kept, so the next solve can warm-start: this is the construction-free
+ * update of online-linearised / RTI NMPC (Sections I and II).  e may be NULL.
+ * Synchronous.
+ */
+int32_t pimpc_linearize(pimpc_ctx ctx, const double *A, const double *B, const double *e,
+                        int32_t mem_kind);
+
+/*
+ * Run Algorithm 1 on every instance.  Host pointers, synchronous.
+ *   x0      x(t), packed (sum of nx)
+ *   u_prev  u(t-1), packed (sum of nu), NULL = 0
+ *   u0_out  u_prev + du_0 of the last step 1 (sum of nu); may be NULL
+ *   info    count entries; may be NULL
+ */
+int32_t pimpc_solve(pimpc_ctx ctx, const double *x0, const double *u_prev, double *u0_out,
+                    pimpc_info *info);
+
+/*
+ * Asynchronous batched solve on `hip_stream` with device pointers whose
+ * element type is the context's precision (float for PIMPC_FP32, double for
+ * PIMPC_FP64).  Same packing as pimpc_solve.  The launch sequence is
+ * captured in a hipGraph on the first call for a given argument set and
+ * replayed afterwards.  info_dev may be NULL.  The caller synchronises.
+ * With opts.ckpt_every > 0 the forward records the tape pimpc_backward uses.
+ */
+int32_t pimpc_solve_batch(pimpc_ctx ctx, const void *x0_dev, const void *uprev_dev,
+                          void *u0_dev, pimpc_info *info_dev, void *hip_stream);
+
+/*
+ * Replace per-instance time-invariant parameters from device memory in the
+ * context's precision and re-run the factorisation on the device:
+ *   A [count][nx][nx], B [count][nx][nu], Qdiag [count][nx], Rdiag [count][nu]
+ * (Q and R become diagonal).  Requires equal nx and nu across instances and a
+ * time-invariant context.  Asynchronous on `hip_stream`.
+ */
+int32_t pimpc_set_params_dev(pimpc_ctx ctx, const void *A, const void *B, const void *Qdiag,
+                             const void *Rdiag, void *hip_stream);
+
+/*
+ * Reverse mode through the unrolled iterations of the last taped
+ * pimpc_solve_batch (needs opts.ckpt_every > 0, otherwise PIMPC_E_STATE).
+ * Given dL/du0 (count x nu, device, context precision), writes dL/dx0
+ * (count x nx), dL/dQdiag (count x nx), dL/dRdiag (count x nu),
+ * dL/dA (count x nx x nx) and dL/dB (count x nx x nu); any output may be
+ * NULL.  The loss sees u0 = du_0 of the K-th step 1, a cold start and
+ * u_prev = 0.  Asynchronous on `hip_stream`.
+ */
+int32_t pimpc_backward(pimpc_ctx ctx, const void *dL_du0_dev, void *dx0, void *dQdiag,
+                       void *dRdiag, void *dA, void *dB, void *hip_stream);
+
+/*
+ * Copy an iterate of every instance to the host as double, packed by
+ * instance, stage-major: which = PIMPC_IT_V..LAMBDA or PIMPC_IT_XBAR give
+ * N*(nx+nu) values per instance, PIMPC_IT_DU gives N*nu.  Synchronous.
+ */
+int32_t pimpc_get_iterates(pimpc_ctx ctx, int32_t which, double *out);
+
+/* Overwrite one of v, z, theta, beta, lambda (same packing as get) so that
+ * the next warm-started solve starts from it.  Synchronous. */
+int32_t pimpc_set_iterates(pimpc_ctx ctx, int32_t which, const double *in);
+
+/* Free the context and all its device memory.  NULL is a no-op. */
+void pimpc_destroy(pimpc_ctx ctx);
+
+/* Text of the last error of `ctx`, or of the calling thread's last failed
+ * pimpc_setup when ctx is NULL.  Never NULL; valid until the next call. */
+const char *pimpc_last_error(pimpc_ctx ctx);
+
+/* PIMPC_VERSION of the built library. */
+int32_t pimpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIMPC_H */

@@ -1,0 +1,271 @@
+// factor.hip -- FP64 stage factorisation (Algorithm 1 "cache") on gfx950.
+//
+// For each instance and stage (proof of Theorem 2, eqn. (8)):
+//   H_k = (Qbar + rho I + rho Abar_{k+1}' Abar_{k+1})^-1   (k < N-1)
+//   H_{N-1} = (Qbar + rho I)^-1
+//   J_k = (Bbar_k' Bbar_k)^-1 Bbar_k' = (B_k' B_k + I)^-1 [B_k'  I]
+// with Abar = [[A, B], [0, I]], Bbar = [[B], [I]], Qbar = blkdiag(Q, R).
+// One 64-thread workgroup builds one matrix in LDS, factors it by a
+// right-looking Cholesky (pivot-column scaling and trailing update spread
+// over the workgroup) and forms the inverse one column per thread.  All of
+// it in double; results are stored in the iteration precision T.
+//
+// Also here: the kernels that expand the FP64 stage data into the T layout
+// the ADMM kernels read, that load per-instance parameters from device
+// tensors (differentiable path), and a plain fill kernel (used instead of
+// hipMemsetAsync so the launch sequence can be graph-captured).
+#include <hip/hip_runtime.h>
+
+#include "pimpc_dev.hpp"
+
+namespace pimpc {
+
+constexpr int kMaxNb = 64;
+constexpr int kLd = kMaxNb + 1;  // LDS leading dimension (odd -> fewer bank conflicts)
+
+// Cholesky of the n x n matrix in M (lower triangle overwritten by L);
+// returns false if a pivot is not strictly positive (or not finite).
+__device__ bool lds_cholesky(double* M, int n) {
+    __shared__ int ok;
+    const int t = threadIdx.x;
+    if (t == 0) ok = 1;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (t == 0) {
+            const double d = M[j * kLd + j];
+            if (!(d > 0.0) || !(d < INFINITY)) ok = 0;
+            M[j * kLd + j] = sqrt(fmax(d, 0.0));
+        }
+        __syncthreads();
+        const double piv = M[j * kLd + j];
+        for (int i = j + 1 + t; i < n; i += blockDim.x) M[i * kLd + j] = M[i * kLd + j] / piv;
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int idx = t; idx < m * m; idx += blockDim.x) {
+            const int i = j + 1 + idx / m;
+            const int l = j + 1 + idx % m;
+            if (l <= i) M[i * kLd + l] -= M[i * kLd + j] * M[l * kLd + j];
+        }
+        __syncthreads();
+    }
+    return ok != 0;
+}
+
+// Solve L L' x = b in place (b in registers of one thread, length n).
+__device__ void chol_solve_col(const double* L, int n, double* x) {
+    for (int i = 0; i < n; ++i) {
+        double s = x[i];
+        for (int k = 0; k < i; ++k) s -= L[i * kLd + k] * x[k];
+        x[i] = s / L[i * kLd + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k * kLd + i] * x[k];
+        x[i] = s / L[i * kLd + i];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ inst,
+                                                    const FactorTask* __restrict__ tasks,
+                                                    const double* __restrict__ mats64,
+                                                    T* __restrict__ mats, double rho,
+                                                    int32_t* __restrict__ bad) {
+    __shared__ double M[kMaxNb * kLd];
+    const FactorTask tk = tasks[blockIdx.x];
+    const InstDev I = inst[tk.inst];
+    const int NX = I.nxp, NU = I.nup, NB = I.nbp, N = I.N;
+    const MatOffsets o = mat_offsets(NX, NU, N, I.tv);
+    const double* b64 = mats64 + I.mat64_off;
+    T* bt = mats + I.mat_off;
+    const int t = threadIdx.x;
+
+    if (tk.kind <= 1) {
+        // M = Qbar + rho I (+ rho Abar_{k+1}' Abar_{k+1})
+        const int sn = I.tv ? tk.stage + 1 : 0;
+        const double* An = b64 + o.A64 + (int64_t)sn * NX * NX;
+        const double* Bn = b64 + o.B64 + (int64_t)sn * NX * NU;
+        const double* Q = b64 + o.Q64;
+        const double* R = b64 + o.R64;
+        for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+            const int i = idx / NB, j = idx % NB;
+            double s = (i == j) ? rho : 0.0;
+            if (i < NX && j < NX) s += Q[i * NX + j];
+            if (i >= NX && j >= NX) s += R[(i - NX) * NU + (j - NX)];
+            if (tk.kind == 0) {
+                double a = 0.0;
+                for (int r = 0; r < NX; ++r) {
+                    const double ari = (i < NX) ? An[r * NX + i] : Bn[r * NU + (i - NX)];
+                    const double arj = (j < NX) ? An[r * NX + j] : Bn[r * NU + (j - NX)];
+                    a += ari * arj;
+                }
+                if (i >= NX && i == j) a += 1.0;
+                s += rho * a;
+            }
+            M[i * kLd + j] = s;
+        }
+        __syncthreads();
+        const bool ok = lds_cholesky(M, NB);
+        if (!ok && t == 0) bad[blockIdx.x] = 1;
+        if (t < NB) {
+            double x[kMaxNb];
+            for (int i = 0; i < NB; ++i) x[i] = (i == t) ? 1.0 : 0.0;
+            chol_solve_col(M, NB, x);
+            // column t of H (H is symmetric)
+            if (!I.tv) {
+                T* H = bt + (tk.kind == 0 ? o.H : o.Hb);
+                for (int i = 0; i < NB; ++i) H[i * NB + t] = (T)x[i];
+            } else {
+                T* H = bt + o.H;
+                for (int i = 0; i < NB; ++i) H[(int64_t)(i * NB + t) * N + tk.stage] = (T)x[i];
+            }
+        }
+    } else {
+        // G = B' B + I (NU x NU); J = G^-1 [B' I]
+        const int sk = I.tv ? tk.stage : 0;
+        const double* Bk = b64 + o.B64 + (int64_t)sk * NX * NU;
+        for (int idx = t; idx < NU * NU; idx += blockDim.x) {
+            const int i = idx / NU, j = idx % NU;
+            double s = (i == j) ? 1.0 : 0.0;
+            for (int r = 0; r < NX; ++r) s += Bk[r * NU + i] * Bk[r * NU + j];
+            M[i * kLd + j] = s;
+        }
+        __syncthreads();
+        const bool ok = lds_cholesky(M, NU);
+        if (!ok && t == 0) bad[blockIdx.x] = 1;
+        if (t < NB) {
+            double x[kMaxNb];
+            for (int i = 0; i < NU; ++i) x[i] = (t < NX) ? Bk[t * NU + i] : ((t - NX) == i ? 1.0 : 0.0);
+            chol_solve_col(M, NU, x);
+            T* J = bt + o.J;
+            if (!I.tv) {
+                for (int i = 0; i < NU; ++i) J[i * NB + t] = (T)x[i];
+            } else {
+                for (int i = 0; i < NU; ++i) J[(int64_t)(i * NB + t) * N + tk.stage] = (T)x[i];
+            }
+        }
+    }
+}
+
+// Copy A, B, e from the FP64 block into the T block (row-major for
+// time-invariant data, stage-minor for time-varying data).  One thread per
+// element; grid-stride over all instances' elements via a flat index table.
+template <typename T>
+__global__ void expand_kernel(const InstDev* __restrict__ inst, int count,
+                              const double* __restrict__ mats64, T* __restrict__ mats) {
+    const int i = blockIdx.y;
+    if (i >= count) return;
+    const InstDev I = inst[i];
+    const int NX = I.nxp, NU = I.nup, N = I.N;
+    const MatOffsets o = mat_offsets(NX, NU, N, I.tv);
+    const double* b64 = mats64 + I.mat64_off;
+    T* bt = mats + I.mat_off;
+    const int S = I.tv ? N : 1;
+    const int per = NX * NX + NX * NU + NX;
+    const int64_t total = (int64_t)S * per;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(idx / per);
+        const int q = (int)(idx % per);
+        double val;
+        int64_t dst;
+        if (q < NX * NX) {
+            val = b64[o.A64 + (int64_t)k * NX * NX + q];
+            dst = I.tv ? o.A + (int64_t)q * N + k : o.A + q;
+        } else if (q < NX * NX + NX * NU) {
+            const int qq = q - NX * NX;
+            val = b64[o.B64 + (int64_t)k * NX * NU + qq];
+            dst = I.tv ? o.B + (int64_t)qq * N + k : o.B + qq;
+        } else {
+            const int qq = q - NX * NX - NX * NU;
+            val = b64[o.e64 + (int64_t)k * NX + qq];
+            dst = I.tv ? o.e + (int64_t)qq * N + k : o.e + qq;
+        }
+        bt[dst] = (T)val;
+    }
+}
+
+// Differentiable path: load per-instance A [nx][nx], B [nx][nu], diag Q,
+// diag R (real sizes, context precision) into the padded FP64 block.
+template <typename T>
+__global__ void params_kernel(const InstDev* __restrict__ inst, int count, const T* __restrict__ A,
+                              const T* __restrict__ B, const T* __restrict__ Qd,
+                              const T* __restrict__ Rd, double* __restrict__ mats64) {
+    const int i = blockIdx.x;
+    if (i >= count) return;
+    const InstDev I = inst[i];
+    const int nx = I.nx, nu = I.nu, NX = I.nxp, NU = I.nup;
+    const MatOffsets o = mat_offsets(NX, NU, I.N, 0);
+    double* b64 = mats64 + I.mat64_off;
+    for (int idx = threadIdx.x; idx < NX * NX; idx += blockDim.x) {
+        const int r = idx / NX, c = idx % NX;
+        b64[o.A64 + idx] = (r < nx && c < nx) ? (double)A[(int64_t)i * nx * nx + r * nx + c] : 0.0;
+        b64[o.Q64 + idx] = (r == c) ? (r < nx ? (double)Qd[(int64_t)i * nx + r] : 1.0) : 0.0;
+    }
+    for (int idx = threadIdx.x; idx < NX * NU; idx += blockDim.x) {
+        const int r = idx / NU, c = idx % NU;
+        b64[o.B64 + idx] = (r < nx && c < nu) ? (double)B[(int64_t)i * nx * nu + r * nu + c] : 0.0;
+    }
+    for (int idx = threadIdx.x; idx < NU * NU; idx += blockDim.x) {
+        const int r = idx / NU, c = idx % NU;
+        b64[o.R64 + idx] = (r == c) ? (r < nu ? (double)Rd[(int64_t)i * nu + r] : 1.0) : 0.0;
+    }
+}
+
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+hipError_t launch_factor(const InstDev* inst, const FactorTask* tasks, int ntasks, const double* mats64,
+                         T* mats, double rho, int32_t* bad, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(factor_kernel<T>, dim3(ntasks), dim3(64), 0, s, inst, tasks, mats64, mats, rho,
+                       bad);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_expand(const InstDev* inst, int count, const double* mats64, T* mats, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(expand_kernel<T>, dim3(4, count), dim3(256), 0, s, inst, count, mats64, mats);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_params(const InstDev* inst, int count, const T* A, const T* B, const T* Qd,
+                         const T* Rd, double* mats64, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(params_kernel<T>, dim3(count), dim3(64), 0, s, inst, count, A, B, Qd, Rd, mats64);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template hipError_t launch_factor<float>(const InstDev*, const FactorTask*, int, const double*, float*,
+                                         double, int32_t*, hipStream_t);
+template hipError_t launch_factor<double>(const InstDev*, const FactorTask*, int, const double*, double*,
+                                          double, int32_t*, hipStream_t);
+template hipError_t launch_expand<float>(const InstDev*, int, const double*, float*, hipStream_t);
+template hipError_t launch_expand<double>(const InstDev*, int, const double*, double*, hipStream_t);
+template hipError_t launch_params<float>(const InstDev*, int, const float*, const float*, const float*,
+                                         const float*, double*, hipStream_t);
+template hipError_t launch_params<double>(const InstDev*, int, const double*, const double*,
+                                          const double*, const double*, double*, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
+template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
+template hipError_t launch_fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);
+
+}  // namespace pimpc

@@ -1,0 +1,45 @@
+// pimpc_lane.hpp -- host/device interface of the lane-per-stage kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pimpc_dev.hpp"
+
+#ifndef PIMPC_LANE_NPARTS
+#define PIMPC_LANE_NPARTS 6
+#endif
+
+namespace pimpc {
+
+struct LaneArgs {
+    const InstDev* inst;
+    const Bin* bins;
+    int32_t nbins;
+    int32_t* bin_counter;  // nullptr: static bin = blockIdx.x + j * gridDim.x
+    const void* mats;
+    void* state;
+    void* iters_out;
+    const void* x0;
+    const void* uprev;
+    void* u0;
+    InfoDev* info;
+    double rho;
+    double eps;
+    int32_t K;
+    int32_t check_every;
+    int32_t warm;
+    int32_t nbmax;
+    int32_t write_iters;
+    int32_t pad;
+};
+
+template <int P>
+hipError_t lane_dispatch(int fp64, int cls, const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s,
+                         int* occ, bool* handled);
+
+// Dynamic LDS of a lane workgroup: three halo/scratch planes [nbmax][512]
+// plus the per-wave residual partials and the per-group stop flags.
+inline size_t lane_lds_bytes(int nbmax, size_t tsize) {
+    return (size_t)3 * nbmax * kBinThreads * tsize + kBinWaves * 4 * sizeof(double) + kBinWaves * sizeof(int);
+}
+
+}  // namespace pimpc

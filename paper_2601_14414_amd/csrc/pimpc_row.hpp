@@ -1,0 +1,38 @@
+// pimpc_row.hpp -- host interface of the row-per-lane (long horizon) kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pimpc_dev.hpp"
+
+namespace pimpc {
+
+struct RowArgs {
+    const InstDev* inst;
+    int32_t inst_idx;
+    int32_t pad;
+    const void* mats;
+    void* state;
+    void* iters_out;
+    const void* x0;
+    const void* uprev;
+    void* u0;
+    InfoDev* info;
+    void* scratch;  // halo mailboxes and residual partials of this context
+    double rho;
+    double eps;
+    int32_t K;
+    int32_t check_every;
+    int32_t warm;
+    int32_t write_iters;
+};
+
+// True if the row family handles an instance of this shape.
+bool row_supported(int nx, int nu, int N, int tv, int fp64);
+// Device scratch bytes the instance needs (halo mailboxes, partials).
+size_t row_scratch_bytes(const InstDev& I, int fp64);
+// Per-instance preparation after (re)factorisation (none needed yet).
+hipError_t row_prepare(int fp64, const InstDev& I);
+// Enqueue the solve of one row-family instance.
+hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, hipStream_t s);
+
+}  // namespace pimpc

@@ -1,0 +1,1091 @@
+// runtime.cpp -- host runtime and C ABI of the piMPC solver (include/pimpc.h).
+//
+// Owns validation, device memory layout, the FP64 stage factorisation
+// launches, the batch schedule (bins of instances per class, LPT order), the
+// per-class persistent ADMM launches forked over a few streams and joined
+// back, hipGraph capture/replay of that launch sequence, and the conversion
+// of iterates between the caller's packed layout and the device layout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pimpc.h"
+#include "pimpc_dev.hpp"
+#include "pimpc_lane.hpp"
+#include "pimpc_row.hpp"
+
+namespace pimpc {
+template <typename T>
+hipError_t launch_factor(const InstDev*, const FactorTask*, int, const double*, T*, double, int32_t*,
+                         hipStream_t);
+template <typename T>
+hipError_t launch_expand(const InstDev*, int, const double*, T*, hipStream_t);
+template <typename T>
+hipError_t launch_params(const InstDev*, int, const T*, const T*, const T*, const T*, double*, hipStream_t);
+template <typename T>
+hipError_t launch_fill(T*, int64_t, T, hipStream_t);
+}  // namespace pimpc
+
+using namespace pimpc;
+
+namespace {
+
+thread_local std::string g_setup_err;
+
+struct ClassDesc {
+    int id, nx, nu, tv;
+};
+const ClassDesc kClassTable[] = {
+#define PIMPC_CD(id, nx, nu) {id, nx, nu, 0},
+    PIMPC_LANE_CLASSES(PIMPC_CD)
+#undef PIMPC_CD
+#define PIMPC_CD(id, nx, nu) {id, nx, nu, 1},
+        PIMPC_LANE_TV_CLASSES(PIMPC_CD)
+#undef PIMPC_CD
+};
+
+inline int64_t stage_fma(int nx, int nu) {
+    const int64_t nb = nx + nu;
+    return nb * nb + nu * nb + 2LL * nx * nx + 3LL * nx * nu;
+}
+
+hipError_t lane_dispatch_any(int fp64, int cls, const LaneArgs* a, int nbmax, int grid, hipStream_t s,
+                             int* occ) {
+    bool handled = false;
+    hipError_t e;
+#define PIMPC_TRY(P)                                                        \
+    e = lane_dispatch<P>(fp64, cls, a, nbmax, grid, s, occ, &handled);     \
+    if (handled) return e;
+    PIMPC_TRY(0)
+    PIMPC_TRY(1)
+    PIMPC_TRY(2)
+    PIMPC_TRY(3)
+    PIMPC_TRY(4)
+    PIMPC_TRY(5)
+#undef PIMPC_TRY
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+T* dmalloc(size_t n, hipError_t* err) {
+    T* p = nullptr;
+    if (n == 0) n = 1;
+    *err = hipMalloc((void**)&p, n * sizeof(T));
+    return p;
+}
+
+}  // namespace
+
+// One distinct argument set of the batched launch sequence (device copies
+// of the per-class kernel arguments and, once captured, its graph).
+struct LaunchSet {
+    const void* x0 = nullptr;
+    const void* up = nullptr;
+    void* u0 = nullptr;
+    void* info = nullptr;
+    int warm = 0;
+    int write_iters = 0;
+    hipStream_t stream = nullptr;
+    LaneArgs* d_args = nullptr;  // one per present lane class
+    RowArgs* d_rargs = nullptr;  // one per row-family instance
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct ClassRun {
+    int cls = 0;
+    int nbmax = 0;
+    int bin_first = 0;
+    int nbins = 0;
+    int occ = 1;
+    int64_t cost = 0;  // sum over bins of waves * stage FMAs (for stream balancing)
+};
+
+struct pimpc_ctx_s {
+    std::string err;
+    hipStream_t stream = nullptr;
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
+    pimpc_options opt{};
+    int fp64 = 0;
+    size_t tsize = 4;
+    int count = 0;
+    int tv = 0;
+    int num_cus = 256;
+    std::vector<InstDev> inst;
+    int64_t mat_elems = 0, mat64_elems = 0, st_elems = 0, it_elems = 0, sum_nx = 0, sum_nu = 0;
+    // device memory
+    InstDev* d_inst = nullptr;
+    void* d_mats = nullptr;
+    double* d_mats64 = nullptr;
+    void* d_state = nullptr;
+    void* d_iters = nullptr;
+    void* d_x0 = nullptr;
+    void* d_up = nullptr;
+    void* d_u0 = nullptr;
+    InfoDev* d_info = nullptr;
+    FactorTask* d_tasks = nullptr;
+    int ntasks = 0;
+    int32_t* d_bad = nullptr;
+    Bin* d_bins = nullptr;
+    int32_t* d_counters = nullptr;
+    std::vector<ClassRun> runs;
+    std::vector<int> row_insts;  // instances handled by the row family
+    void* d_row_scratch = nullptr;
+    size_t row_scratch_bytes = 0;
+    int schedule = 1;            // 1 = dynamic counter, 2 = static striding
+    int nstreams = 1;
+    int has_state = 0;
+    std::vector<std::unique_ptr<LaunchSet>> sets;
+
+    int fail(int32_t code, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+};
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return (ctx)->fail(PIMPC_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+namespace {
+
+bool finite_arr(const double* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Symmetric PSD test: symmetry to a relative tolerance, then a Cholesky of
+// M + delta I with delta = 1e-12 (1 + max|M|).
+bool sym_psd(const double* M, int n, bool* sym) {
+    double mx = 0.0;
+    for (int i = 0; i < n * n; ++i) mx = std::max(mx, std::fabs(M[i]));
+    *sym = true;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j)
+            if (std::fabs(M[i * n + j] - M[j * n + i]) > 1e-10 * (1.0 + mx)) *sym = false;
+    if (!*sym) return false;
+    std::vector<double> L(M, M + n * n);
+    const double delta = 1e-12 * (1.0 + mx);
+    for (int i = 0; i < n; ++i) L[i * n + i] += delta;
+    for (int j = 0; j < n; ++j) {
+        double d = L[j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0.0)) return false;
+        const double l = std::sqrt(d);
+        L[j * n + j] = l;
+        for (int i = j + 1; i < n; ++i) {
+            double s = L[i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = s / l;
+        }
+    }
+    return true;
+}
+
+int pick_class(int nx, int nu, int tv, size_t tsize) {
+    int best = -1;
+    int64_t best_cost = 0;
+    for (const ClassDesc& c : kClassTable) {
+        if (c.tv != tv || c.nx < nx || c.nu < nu) continue;
+        if (lane_lds_bytes(c.nx + c.nu, tsize) > 160 * 1024) continue;  // does not fit one CU's LDS
+        const int64_t cost = stage_fma(c.nx, c.nu);
+        if (best < 0 || cost < best_cost) {
+            best = c.id;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+const ClassDesc* class_desc(int id) {
+    for (const ClassDesc& c : kClassTable)
+        if (c.id == id) return &c;
+    return nullptr;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- data upload
+
+// Build the padded FP64 block (A, B, e, Q, R) of every instance from packed
+// caller arrays; only the stage data (A, B, e) when `stage_only`.
+static void build_mats64(pimpc_ctx ctx, const double* A, const double* B, const double* e,
+                         const double* Q, const double* R, std::vector<double>& out, bool stage_only) {
+    if (!stage_only) out.assign(ctx->mat64_elems, 0.0);
+    int64_t oa = 0, ob = 0, oe = 0, oq = 0, orr = 0;
+    for (int i = 0; i < ctx->count; ++i) {
+        const InstDev& I = ctx->inst[i];
+        const int nx = I.nx, nu = I.nu, NX = I.nxp, NU = I.nup, N = I.N;
+        const MatOffsets o = mat_offsets(NX, NU, N, I.tv);
+        double* b = out.data() + I.mat64_off;
+        const int S = I.tv ? N : 1;
+        for (int k = 0; k < S; ++k) {
+            for (int r = 0; r < NX; ++r) {
+                for (int c = 0; c < NX; ++c)
+                    b[o.A64 + (int64_t)k * NX * NX + r * NX + c] =
+                        (r < nx && c < nx) ? A[oa + (int64_t)k * nx * nx + r * nx + c] : 0.0;
+                for (int c = 0; c < NU; ++c)
+                    b[o.B64 + (int64_t)k * NX * NU + r * NU + c] =
+                        (r < nx && c < nu) ? B[ob + (int64_t)k * nx * nu + r * nu + c] : 0.0;
+                b[o.e64 + (int64_t)k * NX + r] = (e && r < nx) ? e[oe + (int64_t)k * nx + r] : 0.0;
+            }
+        }
+        oa += (int64_t)S * nx * nx;
+        ob += (int64_t)S * nx * nu;
+        oe += (int64_t)S * nx;
+        if (!stage_only) {
+            for (int r = 0; r < NX; ++r)
+                for (int c = 0; c < NX; ++c)
+                    b[o.Q64 + r * NX + c] = (r < nx && c < nx) ? Q[oq + r * nx + c] : (r == c ? 1.0 : 0.0);
+            for (int r = 0; r < NU; ++r)
+                for (int c = 0; c < NU; ++c)
+                    b[o.R64 + r * NU + c] = (r < nu && c < nu) ? R[orr + r * nu + c] : (r == c ? 1.0 : 0.0);
+            oq += (int64_t)nx * nx;
+            orr += (int64_t)nu * nu;
+        }
+    }
+}
+
+template <typename T>
+static int upload_t_block(pimpc_ctx ctx, const double* qbar, const double* xmin, const double* xmax,
+                          const double* umin, const double* umax) {
+    std::vector<T> h(ctx->mat_elems, T(0));
+    int64_t ox = 0, ou = 0;
+    for (int i = 0; i < ctx->count; ++i) {
+        const InstDev& I = ctx->inst[i];
+        const int nx = I.nx, nu = I.nu, NX = I.nxp, NU = I.nup, NB = I.nbp;
+        const MatOffsets o = mat_offsets(NX, NU, I.N, I.tv);
+        T* b = h.data() + I.mat_off;
+        for (int r = 0; r < NB; ++r) {
+            const bool isx = r < NX;
+            const int rr = isx ? r : r - NX;
+            const bool real = isx ? rr < nx : rr < nu;
+            double q = 0.0, lo = 0.0, hi = 0.0;  // padded rows: [0, 0] box, zero linear term
+            if (real) {
+                lo = isx ? xmin[ox + rr] : umin[ou + rr];
+                hi = isx ? xmax[ox + rr] : umax[ou + rr];
+            }
+            b[o.lb + r] = (T)lo;
+            b[o.ub + r] = (T)hi;
+            b[o.qbar + r] = (T)q;
+        }
+        if (qbar) {
+            const int64_t qo = ox + ou;  // qbar packed as (nx + nu) per instance
+            for (int r = 0; r < nx; ++r) b[o.qbar + r] = (T)qbar[qo + r];
+            for (int r = 0; r < nu; ++r) b[o.qbar + NX + r] = (T)qbar[qo + nx + r];
+        }
+        ox += nx;
+        ou += nu;
+    }
+    HIPCHK(ctx, hipMemcpy(ctx->d_mats, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PIMPC_OK;
+}
+
+// Expand the FP64 stage data into the T layout, factor, check the SPD flags.
+static int refactor(pimpc_ctx ctx, bool sync_check) {
+    hipStream_t s = ctx->stream;
+    HIPCHK(ctx, launch_fill<int32_t>(ctx->d_bad, std::max(ctx->ntasks, 1), 0, s));
+    if (ctx->fp64) {
+        HIPCHK(ctx, launch_expand<double>(ctx->d_inst, ctx->count, ctx->d_mats64, (double*)ctx->d_mats, s));
+        HIPCHK(ctx, launch_factor<double>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->d_mats64,
+                                          (double*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, s));
+    } else {
+        HIPCHK(ctx, launch_expand<float>(ctx->d_inst, ctx->count, ctx->d_mats64, (float*)ctx->d_mats, s));
+        HIPCHK(ctx, launch_factor<float>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->d_mats64,
+                                         (float*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, s));
+    }
+    if (sync_check) {
+        std::vector<int32_t> bad(std::max(ctx->ntasks, 1));
+        HIPCHK(ctx, hipMemcpyAsync(bad.data(), ctx->d_bad, bad.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        for (int t = 0; t < ctx->ntasks; ++t)
+            if (bad[t]) return ctx->fail(PIMPC_E_NOT_PSD, "stage matrix of factorisation task %d is not SPD", t);
+    }
+    return PIMPC_OK;
+}
+
+// ------------------------------------------------------------ batch schedule
+
+static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins) {
+    bins.clear();
+    ctx->runs.clear();
+    for (const ClassDesc& cd : kClassTable) {
+        std::vector<int> members;
+        for (int i = 0; i < ctx->count; ++i)
+            if (ctx->inst[i].cls == cd.id) members.push_back(i);
+        if (members.empty()) continue;
+        std::sort(members.begin(), members.end(), [&](int a, int b) {
+            if (ctx->inst[a].N != ctx->inst[b].N) return ctx->inst[a].N > ctx->inst[b].N;
+            return a < b;
+        });
+        // first-fit decreasing on waves
+        std::vector<Bin> cb;
+        std::vector<int> used;
+        for (int i : members) {
+            const int w = (ctx->inst[i].N + 63) / 64;
+            int tgt = -1;
+            for (size_t b = 0; b < cb.size(); ++b)
+                if (used[b] + w <= kBinWaves && cb[b].n < kBinWaves) {
+                    tgt = (int)b;
+                    break;
+                }
+            if (tgt < 0) {
+                Bin nb{};
+                cb.push_back(nb);
+                used.push_back(0);
+                tgt = (int)cb.size() - 1;
+            }
+            Bin& bb = cb[tgt];
+            bb.e[bb.n].inst = i;
+            bb.e[bb.n].wave0 = (int16_t)used[tgt];
+            bb.e[bb.n].nwaves = (int16_t)w;
+            bb.n++;
+            used[tgt] += w;
+        }
+        // largest bins first (LPT order for the claiming counter)
+        std::vector<int> order(cb.size());
+        for (size_t b = 0; b < cb.size(); ++b) order[b] = (int)b;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return used[a] > used[b]; });
+        ClassRun run;
+        run.cls = cd.id;
+        run.nbmax = cd.nx + cd.nu;
+        run.bin_first = (int)bins.size();
+        run.nbins = (int)cb.size();
+        int64_t waves = 0;
+        for (int b : order) {
+            bins.push_back(cb[b]);
+            waves += used[b];
+        }
+        run.cost = waves * stage_fma(cd.nx, cd.nu);
+        ctx->runs.push_back(run);
+    }
+}
+
+// Grid size of a class launch under the current schedule.
+static int class_grid(pimpc_ctx ctx, const ClassRun& r) {
+    if (ctx->schedule == 3) return r.nbins;  // one workgroup per bin, hardware dispatch order
+    const int cap = std::max(1, r.occ * ctx->num_cus);
+    return std::max(1, std::min(r.nbins, cap));
+}
+
+static int fill_set_args(pimpc_ctx ctx, LaunchSet* ls) {
+    std::vector<LaneArgs> args(ctx->runs.size());
+    for (size_t c = 0; c < ctx->runs.size(); ++c) {
+        const ClassRun& r = ctx->runs[c];
+        LaneArgs& a = args[c];
+        memset(&a, 0, sizeof(a));
+        a.inst = ctx->d_inst;
+        a.bins = ctx->d_bins + r.bin_first;
+        a.nbins = r.nbins;
+        a.bin_counter = (ctx->schedule == 1) ? ctx->d_counters + c : nullptr;
+        a.mats = ctx->d_mats;
+        a.state = ctx->d_state;
+        a.iters_out = ctx->d_iters;
+        a.x0 = ls->x0;
+        a.uprev = ls->up;
+        a.u0 = ls->u0;
+        a.info = (InfoDev*)ls->info;
+        a.rho = ctx->opt.rho;
+        a.eps = ctx->opt.eps;
+        a.K = ctx->opt.max_iter;
+        a.check_every = ctx->opt.check_every;
+        a.warm = ls->warm;
+        a.nbmax = r.nbmax;
+        a.write_iters = ls->write_iters;
+    }
+    if (!args.empty())
+        HIPCHK(ctx, hipMemcpy(ls->d_args, args.data(), args.size() * sizeof(LaneArgs), hipMemcpyHostToDevice));
+    if (!ctx->row_insts.empty()) {
+        std::vector<RowArgs> rargs(ctx->row_insts.size());
+        for (size_t j = 0; j < ctx->row_insts.size(); ++j) {
+            RowArgs& a = rargs[j];
+            memset(&a, 0, sizeof(a));
+            a.inst = ctx->d_inst;
+            a.inst_idx = ctx->row_insts[j];
+            a.mats = ctx->d_mats;
+            a.state = ctx->d_state;
+            a.iters_out = ctx->d_iters;
+            a.x0 = ls->x0;
+            a.uprev = ls->up;
+            a.u0 = ls->u0;
+            a.info = (InfoDev*)ls->info;
+            a.rho = ctx->opt.rho;
+            a.eps = ctx->opt.eps;
+            a.K = ctx->opt.max_iter;
+            a.check_every = ctx->opt.check_every;
+            a.warm = ls->warm;
+            a.write_iters = ls->write_iters;
+            a.scratch = ctx->d_row_scratch;
+        }
+        HIPCHK(ctx, hipMemcpy(ls->d_rargs, rargs.data(), rargs.size() * sizeof(RowArgs), hipMemcpyHostToDevice));
+    }
+    return PIMPC_OK;
+}
+
+static LaunchSet* get_set(pimpc_ctx ctx, const void* x0, const void* up, void* u0, void* info, int warm,
+                          int write_iters, hipStream_t s, int* rc) {
+    for (auto& p : ctx->sets) {
+        LaunchSet* ls = p.get();
+        if (ls->x0 == x0 && ls->up == up && ls->u0 == u0 && ls->info == info && ls->warm == warm &&
+            ls->write_iters == write_iters && ls->stream == s)
+            return ls;
+    }
+    auto ls = std::make_unique<LaunchSet>();
+    ls->x0 = x0;
+    ls->up = up;
+    ls->u0 = u0;
+    ls->info = info;
+    ls->warm = warm;
+    ls->write_iters = write_iters;
+    ls->stream = s;
+    hipError_t e = hipSuccess;
+    ls->d_args = dmalloc<LaneArgs>(std::max<size_t>(ctx->runs.size(), 1), &e);
+    if (e != hipSuccess) {
+        *rc = ctx->fail(PIMPC_E_NOMEM, "hipMalloc of launch arguments failed");
+        return nullptr;
+    }
+    ls->d_rargs = dmalloc<RowArgs>(std::max<size_t>(ctx->row_insts.size(), 1), &e);
+    if (e != hipSuccess) {
+        *rc = ctx->fail(PIMPC_E_NOMEM, "hipMalloc of launch arguments failed");
+        return nullptr;
+    }
+    *rc = fill_set_args(ctx, ls.get());
+    if (*rc != PIMPC_OK) return nullptr;
+    ctx->sets.push_back(std::move(ls));
+    return ctx->sets.back().get();
+}
+
+static void free_set_graphs(pimpc_ctx ctx) {
+    for (auto& p : ctx->sets) {
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->exec = nullptr;
+        p->graph = nullptr;
+    }
+}
+
+// Enqueue the whole batched ADMM launch sequence on `s`.
+static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
+    const int ncls = (int)ctx->runs.size();
+    if (ctx->schedule == 1 && ncls > 0) HIPCHK(ctx, launch_fill<int32_t>(ctx->d_counters, ncls, 0, s));
+    const int ns = std::min(ctx->nstreams, std::max(1, ncls + (int)ctx->row_insts.size()));
+    if (ns > 1) {
+        HIPCHK(ctx, hipEventRecord(ctx->ev_fork, s));
+        for (int j = 0; j < ns - 1; ++j) HIPCHK(ctx, hipStreamWaitEvent(ctx->aux[j], ctx->ev_fork, 0));
+    }
+    // LPT over streams by class cost
+    std::vector<int> order(ncls);
+    for (int c = 0; c < ncls; ++c) order[c] = c;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return ctx->runs[a].cost > ctx->runs[b].cost; });
+    std::vector<int64_t> load(ns, 0);
+    auto stream_of = [&](int j) { return j == 0 ? s : ctx->aux[j - 1]; };
+    for (size_t rj = 0; rj < ctx->row_insts.size(); ++rj) {
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[j] += (int64_t)1 << 40;
+        HIPCHK(ctx, launch_row(ctx->fp64, ls->d_rargs + rj, ctx->inst[ctx->row_insts[rj]], stream_of(j)));
+    }
+    for (int c : order) {
+        const ClassRun& r = ctx->runs[c];
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[j] += r.cost;
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, ls->d_args + c, r.nbmax, class_grid(ctx, r),
+                                      stream_of(j), nullptr));
+    }
+    if (ns > 1) {
+        for (int j = 0; j < ns - 1; ++j) {
+            HIPCHK(ctx, hipEventRecord(ctx->ev_join[j], ctx->aux[j]));
+            HIPCHK(ctx, hipStreamWaitEvent(s, ctx->ev_join[j], 0));
+        }
+    }
+    return PIMPC_OK;
+}
+
+static int run_set(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s, bool graph) {
+    if (!graph) return enqueue_solve(ctx, ls, s);
+    if (!ls->exec) {
+        HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+        int rc = enqueue_solve(ctx, ls, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc != PIMPC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return ctx->fail(PIMPC_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        ls->graph = g;
+        HIPCHK(ctx, hipGraphInstantiate(&ls->exec, g, nullptr, nullptr, 0));
+    }
+    HIPCHK(ctx, hipGraphLaunch(ls->exec, s));
+    return PIMPC_OK;
+}
+
+// Pick the schedule (counter-claimed vs static striding vs one workgroup per
+// bin, and 1 or 4 streams) by timing each candidate once on the real batch.
+static int autotune(pimpc_ctx ctx) {
+    struct Cand {
+        int schedule, nstreams;
+    };
+    const Cand cands[] = {{1, 4}, {1, 1}, {2, 4}, {3, 4}};
+    if (ctx->opt.schedule > 0) {
+        const Cand& c = cands[(ctx->opt.schedule - 1) % 4];
+        ctx->schedule = c.schedule;
+        ctx->nstreams = c.nstreams;
+        return PIMPC_OK;
+    }
+    int64_t total_waves = 0;
+    for (const InstDev& I : ctx->inst) total_waves += (I.N + 63) / 64;
+    if (ctx->count == 1 || total_waves <= 64) {  // nothing to balance
+        ctx->schedule = 2;
+        ctx->nstreams = 1;
+        return PIMPC_OK;
+    }
+    // scratch outputs so that timing runs do not disturb caller-visible state
+    hipError_t e = hipSuccess;
+    hipEvent_t t0, t1;
+    HIPCHK(ctx, hipEventCreate(&t0));
+    HIPCHK(ctx, hipEventCreate(&t1));
+    float best = 1e30f;
+    Cand bestc = cands[0];
+    for (const Cand& c : cands) {
+        ctx->schedule = c.schedule;
+        ctx->nstreams = c.nstreams;
+        LaunchSet ls;
+        ls.x0 = ctx->d_x0;
+        ls.up = ctx->d_up;
+        ls.u0 = ctx->d_u0;
+        ls.info = ctx->d_info;
+        ls.d_args = dmalloc<LaneArgs>(std::max<size_t>(ctx->runs.size(), 1), &e);
+        ls.d_rargs = dmalloc<RowArgs>(std::max<size_t>(ctx->row_insts.size(), 1), &e);
+        if (e != hipSuccess) return ctx->fail(PIMPC_E_NOMEM, "hipMalloc failed in autotune");
+        int rc = fill_set_args(ctx, &ls);
+        if (rc == PIMPC_OK) rc = enqueue_solve(ctx, &ls, ctx->stream);  // warm-up
+        if (rc == PIMPC_OK) {
+            HIPCHK(ctx, hipEventRecord(t0, ctx->stream));
+            rc = enqueue_solve(ctx, &ls, ctx->stream);
+            HIPCHK(ctx, hipEventRecord(t1, ctx->stream));
+            HIPCHK(ctx, hipEventSynchronize(t1));
+        }
+        (void)hipFree(ls.d_args);
+        (void)hipFree(ls.d_rargs);
+        if (rc != PIMPC_OK) return rc;
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, t0, t1));
+        if (ms < best) {
+            best = ms;
+            bestc = c;
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    ctx->schedule = bestc.schedule;
+    ctx->nstreams = bestc.nstreams;
+    return PIMPC_OK;
+}
+
+template <typename T>
+static void to_t(const double* src, int64_t n, std::vector<char>& buf) {
+    buf.resize(std::max<int64_t>(n, 1) * sizeof(T));
+    T* d = (T*)buf.data();
+    for (int64_t i = 0; i < n; ++i) d[i] = (T)src[i];
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+void pimpc_default_options(pimpc_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->rho = 1.0;
+    o->max_iter = 200;
+    o->eps = 0.0;
+    o->check_every = 1;
+    o->precision = PIMPC_FP32;
+    o->accel = 0;
+    o->eta = 0.999;
+    o->warm_start = 0;
+    o->ckpt_every = 0;
+    o->schedule = 0;
+}
+
+int32_t pimpc_version(void) { return PIMPC_VERSION; }
+
+const char* pimpc_last_error(pimpc_ctx ctx) {
+    if (!ctx) return g_setup_err.c_str();
+    return ctx->err.c_str();
+}
+
+static void destroy_ctx(pimpc_ctx ctx) {
+    if (!ctx) return;
+    // Only release what was created: a context that failed host validation
+    // never touched the HIP runtime and must not start it here.
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_set_graphs(ctx);
+    auto rel = [](void* p) {
+        if (p) (void)hipFree(p);
+    };
+    for (auto& p : ctx->sets) {
+        rel(p->d_args);
+        rel(p->d_rargs);
+    }
+    rel(ctx->d_inst);
+    rel(ctx->d_mats);
+    rel(ctx->d_mats64);
+    rel(ctx->d_state);
+    rel(ctx->d_iters);
+    rel(ctx->d_x0);
+    rel(ctx->d_up);
+    rel(ctx->d_u0);
+    rel(ctx->d_info);
+    rel(ctx->d_tasks);
+    rel(ctx->d_bad);
+    rel(ctx->d_bins);
+    rel(ctx->d_counters);
+    rel(ctx->d_row_scratch);
+    for (int j = 0; j < 3; ++j) {
+        if (ctx->aux[j]) (void)hipStreamDestroy(ctx->aux[j]);
+        if (ctx->ev_join[j]) (void)hipEventDestroy(ctx->ev_join[j]);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    delete ctx;
+}
+
+void pimpc_destroy(pimpc_ctx ctx) { destroy_ctx(ctx); }
+
+static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options* o) {
+    // ---------------- validation (host only, before any HIP call)
+    if (!p || !o) return ctx->fail(PIMPC_E_ARG, "problem and options are required");
+    if (p->count < 1) return ctx->fail(PIMPC_E_ARG, "count must be >= 1");
+    if (!p->nx || !p->nu || !p->N || !p->A || !p->B || !p->Q || !p->R || !p->xmin || !p->xmax || !p->umin ||
+        !p->umax)
+        return ctx->fail(PIMPC_E_ARG, "a required problem array is NULL");
+    if (p->time_varying != 0 && p->time_varying != 1) return ctx->fail(PIMPC_E_ARG, "time_varying must be 0 or 1");
+    if (!(o->rho > 0.0) || !std::isfinite(o->rho)) return ctx->fail(PIMPC_E_ARG, "rho must be finite and > 0");
+    if (o->max_iter < 1) return ctx->fail(PIMPC_E_ARG, "max_iter must be >= 1");
+    if (o->check_every < 1) return ctx->fail(PIMPC_E_ARG, "check_every must be >= 1");
+    if (std::isnan(o->eps)) return ctx->fail(PIMPC_E_ARG, "eps is NaN");
+    if (o->precision != PIMPC_FP32 && o->precision != PIMPC_FP64)
+        return ctx->fail(PIMPC_E_ARG, "precision must be PIMPC_FP32 or PIMPC_FP64");
+    if (o->accel != 0 && o->accel != 1) return ctx->fail(PIMPC_E_ARG, "accel must be 0 or 1");
+    if (o->accel == 1) return ctx->fail(PIMPC_E_UNSUPPORTED, "restart acceleration is not built in this version");
+    if (o->warm_start != 0 && o->warm_start != 1) return ctx->fail(PIMPC_E_ARG, "warm_start must be 0 or 1");
+    if (o->ckpt_every < 0) return ctx->fail(PIMPC_E_ARG, "ckpt_every must be >= 0");
+    if (o->schedule < 0) return ctx->fail(PIMPC_E_ARG, "schedule must be >= 0");
+    const int count = p->count;
+    const int tv = p->time_varying;
+    int64_t sA = 0, sB = 0, se = 0, sQ = 0, sR = 0, snx = 0, snu = 0;
+    for (int i = 0; i < count; ++i) {
+        const int nx = p->nx[i], nu = p->nu[i], N = p->N[i];
+        if (nx < 1 || nu < 1 || N < 1) return ctx->fail(PIMPC_E_DIM, "instance %d: nx, nu, N must be >= 1", i);
+        if (nx > 48 || nu > 16 || nx + nu > 64)
+            return ctx->fail(PIMPC_E_DIM, "instance %d: nx <= 48, nu <= 16, nx + nu <= 64 supported", i);
+        if (N > (1 << 20)) return ctx->fail(PIMPC_E_DIM, "instance %d: N too large", i);
+        const int64_t S = tv ? N : 1;
+        sA += S * nx * nx;
+        sB += S * nx * nu;
+        se += S * nx;
+        sQ += (int64_t)nx * nx;
+        sR += (int64_t)nu * nu;
+        snx += nx;
+        snu += nu;
+    }
+    if (!finite_arr(p->A, sA) || !finite_arr(p->B, sB) || (p->e && !finite_arr(p->e, se)) ||
+        !finite_arr(p->Q, sQ) || !finite_arr(p->R, sR) || (p->qbar && !finite_arr(p->qbar, snx + snu)))
+        return ctx->fail(PIMPC_E_NONFINITE, "problem data contains NaN or Inf");
+    for (int64_t j = 0; j < snx; ++j)
+        if (std::isnan(p->xmin[j]) || std::isnan(p->xmax[j]) || p->xmin[j] > p->xmax[j])
+            return ctx->fail(PIMPC_E_ARG, "state bound %lld: need xmin <= xmax (no NaN)", (long long)j);
+    for (int64_t j = 0; j < snu; ++j)
+        if (std::isnan(p->umin[j]) || std::isnan(p->umax[j]) || p->umin[j] > p->umax[j])
+            return ctx->fail(PIMPC_E_ARG, "input bound %lld: need umin <= umax (no NaN)", (long long)j);
+    {
+        int64_t oq = 0, orr = 0;
+        for (int i = 0; i < count; ++i) {
+            bool sym = true;
+            if (!sym_psd(p->Q + oq, p->nx[i], &sym))
+                return ctx->fail(PIMPC_E_NOT_PSD, "instance %d: Q is not %s", i, sym ? "PSD" : "symmetric");
+            if (!sym_psd(p->R + orr, p->nu[i], &sym))
+                return ctx->fail(PIMPC_E_NOT_PSD, "instance %d: R is not %s", i, sym ? "PSD" : "symmetric");
+            oq += (int64_t)p->nx[i] * p->nx[i];
+            orr += (int64_t)p->nu[i] * p->nu[i];
+        }
+    }
+
+    // ---------------- layout
+    ctx->opt = *o;
+    ctx->fp64 = o->precision == PIMPC_FP64;
+    ctx->tsize = ctx->fp64 ? sizeof(double) : sizeof(float);
+    ctx->count = count;
+    ctx->tv = tv;
+    ctx->inst.resize(count);
+    int64_t mo = 0, m64 = 0, so = 0, io = 0, xo = 0, uo = 0, oq = 0, orr = 0;
+    std::vector<FactorTask> tasks;
+    for (int i = 0; i < count; ++i) {
+        InstDev& I = ctx->inst[i];
+        memset(&I, 0, sizeof(I));
+        I.nx = p->nx[i];
+        I.nu = p->nu[i];
+        I.nb = I.nx + I.nu;
+        I.N = p->N[i];
+        I.tv = tv;
+        const int cls = (I.N <= kBinThreads) ? pick_class(I.nx, I.nu, tv, ctx->fp64 ? 8 : 4) : -1;
+        if (cls >= 0) {
+            const ClassDesc* cd = class_desc(cls);
+            I.cls = cls;
+            I.nxp = cd->nx;
+            I.nup = cd->nu;
+        } else {
+            if (!row_supported(I.nx, I.nu, I.N, tv, ctx->fp64))
+                return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                 "instance %d (nx=%d, nu=%d, N=%d, %s, %s) has no compiled kernel", i, I.nx, I.nu,
+                                 I.N, tv ? "time-varying" : "time-invariant", ctx->fp64 ? "fp64" : "fp32");
+            I.cls = -1;
+            I.nxp = I.nx;
+            I.nup = I.nu;
+            ctx->row_insts.push_back(i);
+        }
+        I.nbp = I.nxp + I.nup;
+        // H_{N-1} = (Qbar + rho I)^-1 is diagonal when Q and R are
+        bool diag = !tv;
+        for (int r = 0; r < I.nx && diag; ++r)
+            for (int c = 0; c < I.nx; ++c)
+                if (r != c && p->Q[oq + r * I.nx + c] != 0.0) diag = false;
+        for (int r = 0; r < I.nu && diag; ++r)
+            for (int c = 0; c < I.nu; ++c)
+                if (r != c && p->R[orr + r * I.nu + c] != 0.0) diag = false;
+        I.hb_diag = diag ? 1 : 0;
+        oq += (int64_t)I.nx * I.nx;
+        orr += (int64_t)I.nu * I.nu;
+        I.mat_off = mo;
+        mo += (mat_block_size(I.nxp, I.nup, I.N, tv) + 15) / 16 * 16;
+        I.mat64_off = m64;
+        m64 += (mat64_block_size(I.nxp, I.nup, I.N, tv) + 15) / 16 * 16;
+        I.st_off = so;
+        so += 5LL * I.nbp * I.N;
+        I.it_off = io;
+        io += (int64_t)(I.nup + I.nbp) * I.N;
+        I.x_off = xo;
+        xo += I.nx;
+        I.u_off = uo;
+        uo += I.nu;
+        if (!tv) {
+            if (I.N > 1) tasks.push_back({i, 0, 0, 0});
+            tasks.push_back({i, 1, I.N - 1, 0});
+            tasks.push_back({i, 2, 0, 0});
+        } else {
+            for (int k = 0; k < I.N; ++k) {
+                tasks.push_back({i, k < I.N - 1 ? 0 : 1, k, 0});
+                tasks.push_back({i, 2, k, 0});
+            }
+        }
+    }
+    ctx->mat_elems = mo;
+    ctx->mat64_elems = m64;
+    ctx->st_elems = so;
+    ctx->it_elems = io;
+    ctx->sum_nx = xo;
+    ctx->sum_nu = uo;
+    ctx->ntasks = (int)tasks.size();
+
+    // ---------------- device
+    int dev = 0;
+    HIPCHK(ctx, hipGetDevice(&dev));
+    HIPCHK(ctx, hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int j = 0; j < 3; ++j) {
+        HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux[j], hipStreamNonBlocking));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join[j], hipEventDisableTiming));
+    }
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    hipError_t e = hipSuccess;
+    const size_t ts = ctx->tsize;
+#define DALLOC(ptr, type, n)                                                                  \
+    do {                                                                                      \
+        ptr = (decltype(ptr))dmalloc<type>((size_t)(n), &e);                                  \
+        if (e != hipSuccess) return ctx->fail(PIMPC_E_NOMEM, "hipMalloc(%s) failed", #ptr);     \
+    } while (0)
+    DALLOC(ctx->d_inst, InstDev, count);
+    DALLOC(ctx->d_mats, char, ctx->mat_elems * ts);
+    DALLOC(ctx->d_mats64, double, ctx->mat64_elems);
+    DALLOC(ctx->d_state, char, ctx->st_elems * ts);
+    DALLOC(ctx->d_iters, char, ctx->it_elems * ts);
+    DALLOC(ctx->d_x0, char, ctx->sum_nx * ts);
+    DALLOC(ctx->d_up, char, ctx->sum_nu * ts);
+    DALLOC(ctx->d_u0, char, ctx->sum_nu * ts);
+    DALLOC(ctx->d_info, InfoDev, count);
+    DALLOC(ctx->d_tasks, FactorTask, ctx->ntasks);
+    DALLOC(ctx->d_bad, int32_t, ctx->ntasks);
+    HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(ctx->d_tasks, tasks.data(), tasks.size() * sizeof(FactorTask), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemset(ctx->d_state, 0, ctx->st_elems * ts));
+    HIPCHK(ctx, hipMemset(ctx->d_iters, 0, ctx->it_elems * ts));
+    HIPCHK(ctx, hipMemset(ctx->d_up, 0, ctx->sum_nu * ts));
+
+    std::vector<double> m64v;
+    build_mats64(ctx, p->A, p->B, p->e, p->Q, p->R, m64v, false);
+    HIPCHK(ctx, hipMemcpy(ctx->d_mats64, m64v.data(), m64v.size() * sizeof(double), hipMemcpyHostToDevice));
+    int rc = ctx->fp64 ? upload_t_block<double>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax)
+                       : upload_t_block<float>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax);
+    if (rc != PIMPC_OK) return rc;
+    rc = refactor(ctx, true);
+    if (rc != PIMPC_OK) return rc;
+
+    // ---------------- schedule
+    std::vector<Bin> bins;
+    build_bins(ctx, bins);
+    if (!bins.empty()) {
+        DALLOC(ctx->d_bins, Bin, bins.size());
+        HIPCHK(ctx, hipMemcpy(ctx->d_bins, bins.data(), bins.size() * sizeof(Bin), hipMemcpyHostToDevice));
+    }
+    DALLOC(ctx->d_counters, int32_t, std::max<size_t>(ctx->runs.size(), 1));
+    for (ClassRun& r : ctx->runs) {
+        int occ = 1;
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, nullptr, r.nbmax, 0, ctx->stream, &occ));
+        r.occ = occ;
+    }
+    if (!ctx->row_insts.empty()) {
+        size_t bytes = 0;
+        for (int i : ctx->row_insts) bytes += row_scratch_bytes(ctx->inst[i], ctx->fp64);
+        ctx->row_scratch_bytes = bytes;
+        DALLOC(ctx->d_row_scratch, char, bytes);
+        HIPCHK(ctx, hipMemset(ctx->d_row_scratch, 0, bytes));
+        size_t off = 0;
+        for (int i : ctx->row_insts) {
+            ctx->inst[i].pad0 = (int32_t)(off / 16);  // scratch offset in 16-byte units
+            off += row_scratch_bytes(ctx->inst[i], ctx->fp64);
+        }
+        HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
+        for (int i : ctx->row_insts) HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
+    }
+#undef DALLOC
+    rc = autotune(ctx);
+    if (rc != PIMPC_OK) return rc;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return PIMPC_OK;
+}
+
+int32_t pimpc_setup(pimpc_ctx* out, const pimpc_problem* prob, const pimpc_options* opts, void* hip_stream) {
+    if (!out) {
+        g_setup_err = "out pointer is NULL";
+        return PIMPC_E_ARG;
+    }
+    *out = nullptr;
+    pimpc_ctx ctx = new (std::nothrow) pimpc_ctx_s();
+    if (!ctx) {
+        g_setup_err = "host allocation failed";
+        return PIMPC_E_NOMEM;
+    }
+    ctx->stream = (hipStream_t)hip_stream;
+    const int rc = setup_impl(ctx, prob, opts);
+    if (rc != PIMPC_OK) {
+        g_setup_err = ctx->err;
+        destroy_ctx(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return PIMPC_OK;
+}
+
+int32_t pimpc_linearize(pimpc_ctx ctx, const double* A, const double* B, const double* e, int32_t mem_kind) {
+    if (!ctx) return PIMPC_E_ARG;
+    if (!A || !B) return ctx->fail(PIMPC_E_ARG, "A and B are required");
+    if (mem_kind != PIMPC_MEM_HOST && mem_kind != PIMPC_MEM_DEVICE)
+        return ctx->fail(PIMPC_E_ARG, "mem_kind must be PIMPC_MEM_HOST or PIMPC_MEM_DEVICE");
+    int64_t sA = 0, sB = 0, se = 0;
+    for (const InstDev& I : ctx->inst) {
+        const int64_t S = I.tv ? I.N : 1;
+        sA += S * I.nx * I.nx;
+        sB += S * I.nx * I.nu;
+        se += S * I.nx;
+    }
+    std::vector<double> hA, hB, he;
+    const double *pA = A, *pB = B, *pe = e;
+    if (mem_kind == PIMPC_MEM_DEVICE) {
+        hA.resize(sA);
+        hB.resize(sB);
+        HIPCHK(ctx, hipMemcpy(hA.data(), A, sA * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(ctx, hipMemcpy(hB.data(), B, sB * sizeof(double), hipMemcpyDeviceToHost));
+        pA = hA.data();
+        pB = hB.data();
+        if (e) {
+            he.resize(se);
+            HIPCHK(ctx, hipMemcpy(he.data(), e, se * sizeof(double), hipMemcpyDeviceToHost));
+            pe = he.data();
+        }
+    }
+    if (!finite_arr(pA, sA) || !finite_arr(pB, sB) || (pe && !finite_arr(pe, se)))
+        return ctx->fail(PIMPC_E_NONFINITE, "stage data contains NaN or Inf");
+    std::vector<double> m64v(ctx->mat64_elems);
+    HIPCHK(ctx, hipMemcpy(m64v.data(), ctx->d_mats64, m64v.size() * sizeof(double), hipMemcpyDeviceToHost));
+    build_mats64(ctx, pA, pB, pe, nullptr, nullptr, m64v, true);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_mats64, m64v.data(), m64v.size() * sizeof(double), hipMemcpyHostToDevice,
+                               ctx->stream));
+    int rc = refactor(ctx, true);
+    if (rc != PIMPC_OK) return rc;
+    for (int i : ctx->row_insts) HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
+    return PIMPC_OK;
+}
+
+int32_t pimpc_solve(pimpc_ctx ctx, const double* x0, const double* u_prev, double* u0_out, pimpc_info* info) {
+    if (!ctx) return PIMPC_E_ARG;
+    if (!x0) return ctx->fail(PIMPC_E_ARG, "x0 is required");
+    if (!finite_arr(x0, ctx->sum_nx) || (u_prev && !finite_arr(u_prev, ctx->sum_nu)))
+        return ctx->fail(PIMPC_E_NONFINITE, "x0 or u_prev contains NaN or Inf");
+    const hipStream_t s = ctx->stream;
+    std::vector<char> bx, bu;
+    if (ctx->fp64) {
+        to_t<double>(x0, ctx->sum_nx, bx);
+        if (u_prev) to_t<double>(u_prev, ctx->sum_nu, bu);
+    } else {
+        to_t<float>(x0, ctx->sum_nx, bx);
+        if (u_prev) to_t<float>(u_prev, ctx->sum_nu, bu);
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_x0, bx.data(), ctx->sum_nx * ctx->tsize, hipMemcpyHostToDevice, s));
+    if (u_prev) HIPCHK(ctx, hipMemcpyAsync(ctx->d_up, bu.data(), ctx->sum_nu * ctx->tsize, hipMemcpyHostToDevice, s));
+    const int warm = (ctx->opt.warm_start && ctx->has_state) ? 1 : 0;
+    int rc = 0;
+    LaunchSet* ls = get_set(ctx, ctx->d_x0, u_prev ? ctx->d_up : nullptr, ctx->d_u0, ctx->d_info, warm, 1, s, &rc);
+    if (!ls) return rc;
+    rc = run_set(ctx, ls, s, false);
+    if (rc != PIMPC_OK) return rc;
+    std::vector<char> bo(std::max<int64_t>(ctx->sum_nu, 1) * ctx->tsize);
+    std::vector<InfoDev> inf(ctx->count);
+    HIPCHK(ctx, hipMemcpyAsync(bo.data(), ctx->d_u0, ctx->sum_nu * ctx->tsize, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(inf.data(), ctx->d_info, ctx->count * sizeof(InfoDev), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    ctx->has_state = 1;
+    if (u0_out)
+        for (int64_t j = 0; j < ctx->sum_nu; ++j)
+            u0_out[j] = ctx->fp64 ? ((double*)bo.data())[j] : (double)((float*)bo.data())[j];
+    if (info) memcpy(info, inf.data(), ctx->count * sizeof(InfoDev));
+    for (int i = 0; i < ctx->count; ++i)
+        if (inf[i].status != 0) return ctx->fail(PIMPC_E_NONFINITE, "instance %d: iterate became non-finite", i);
+    return PIMPC_OK;
+}
+
+int32_t pimpc_solve_batch(pimpc_ctx ctx, const void* x0_dev, const void* uprev_dev, void* u0_dev,
+                          pimpc_info* info_dev, void* hip_stream) {
+    if (!ctx) return PIMPC_E_ARG;
+    if (!x0_dev || !u0_dev) return ctx->fail(PIMPC_E_ARG, "x0_dev and u0_dev are required");
+    if (ctx->opt.ckpt_every > 0) return ctx->fail(PIMPC_E_UNSUPPORTED, "taped forward is not built yet");
+    const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    const int warm = (ctx->opt.warm_start && ctx->has_state) ? 1 : 0;
+    int rc = 0;
+    LaunchSet* ls = get_set(ctx, x0_dev, uprev_dev, u0_dev, info_dev, warm, 0, s, &rc);
+    if (!ls) return rc;
+    rc = run_set(ctx, ls, s, true);
+    if (rc != PIMPC_OK) return rc;
+    ctx->has_state = 1;
+    return PIMPC_OK;
+}
+
+int32_t pimpc_set_params_dev(pimpc_ctx ctx, const void* A, const void* B, const void* Qdiag, const void* Rdiag,
+                             void* hip_stream) {
+    if (!ctx) return PIMPC_E_ARG;
+    if (!A || !B || !Qdiag || !Rdiag) return ctx->fail(PIMPC_E_ARG, "A, B, Qdiag, Rdiag are required");
+    if (ctx->tv) return ctx->fail(PIMPC_E_STATE, "set_params_dev needs a time-invariant context");
+    for (const InstDev& I : ctx->inst)
+        if (I.nx != ctx->inst[0].nx || I.nu != ctx->inst[0].nu)
+            return ctx->fail(PIMPC_E_STATE, "set_params_dev needs equal nx and nu across instances");
+    const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    if (ctx->fp64)
+        HIPCHK(ctx, launch_params<double>(ctx->d_inst, ctx->count, (const double*)A, (const double*)B,
+                                          (const double*)Qdiag, (const double*)Rdiag, ctx->d_mats64, s));
+    else
+        HIPCHK(ctx, launch_params<float>(ctx->d_inst, ctx->count, (const float*)A, (const float*)B,
+                                         (const float*)Qdiag, (const float*)Rdiag, ctx->d_mats64, s));
+    const hipStream_t saved = ctx->stream;
+    ctx->stream = s;
+    const int rc = refactor(ctx, false);
+    ctx->stream = saved;
+    return rc;
+}
+
+int32_t pimpc_backward(pimpc_ctx ctx, const void* dL_du0_dev, void* dx0, void* dQdiag, void* dRdiag, void* dA,
+                       void* dB, void* hip_stream) {
+    (void)dL_du0_dev;
+    (void)dx0;
+    (void)dQdiag;
+    (void)dRdiag;
+    (void)dA;
+    (void)dB;
+    (void)hip_stream;
+    if (!ctx) return PIMPC_E_ARG;
+    return ctx->fail(PIMPC_E_STATE, "no taped forward is available (ckpt_every = 0)");
+}
+
+static int iter_io(pimpc_ctx ctx, int32_t which, double* out, const double* in) {
+    if (!ctx) return PIMPC_E_ARG;
+    if (which < PIMPC_IT_V || which > PIMPC_IT_XBAR) return ctx->fail(PIMPC_E_ARG, "bad iterate selector %d", which);
+    if (in && which > PIMPC_IT_LAMBDA) return ctx->fail(PIMPC_E_ARG, "only v, z, theta, beta, lambda can be set");
+    if (!out && !in) return ctx->fail(PIMPC_E_ARG, "buffer is NULL");
+    const bool st = which <= PIMPC_IT_LAMBDA;
+    const int64_t n = st ? ctx->st_elems : ctx->it_elems;
+    std::vector<char> buf(std::max<int64_t>(n, 1) * ctx->tsize);
+    void* dsrc = st ? ctx->d_state : ctx->d_iters;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(buf.data(), dsrc, n * ctx->tsize, hipMemcpyDeviceToHost));
+    auto get = [&](int64_t idx) -> double {
+        return ctx->fp64 ? ((double*)buf.data())[idx] : (double)((float*)buf.data())[idx];
+    };
+    auto put = [&](int64_t idx, double v) {
+        if (ctx->fp64)
+            ((double*)buf.data())[idx] = v;
+        else
+            ((float*)buf.data())[idx] = (float)v;
+    };
+    int64_t pos = 0;
+    for (int i = 0; i < ctx->count; ++i) {
+        const InstDev& I = ctx->inst[i];
+        const int N = I.N;
+        if (which == PIMPC_IT_DU) {
+            for (int k = 0; k < N; ++k)
+                for (int r = 0; r < I.nu; ++r) out[pos++] = get(I.it_off + (int64_t)r * N + k);
+            continue;
+        }
+        for (int k = 0; k < N; ++k)
+            for (int r = 0; r < I.nb; ++r) {
+                const int rp = r < I.nx ? r : I.nxp + (r - I.nx);  // padded row
+                int64_t idx;
+                if (which == PIMPC_IT_XBAR)
+                    idx = I.it_off + (int64_t)(I.nup + rp) * N + k;
+                else
+                    idx = I.st_off + (int64_t)(which * I.nbp + rp) * N + k;
+                if (in)
+                    put(idx, in[pos++]);
+                else
+                    out[pos++] = get(idx);
+            }
+    }
+    if (in) {
+        HIPCHK(ctx, hipMemcpy(dsrc, buf.data(), n * ctx->tsize, hipMemcpyHostToDevice));
+        ctx->has_state = 1;
+    }
+    return PIMPC_OK;
+}
+
+int32_t pimpc_get_iterates(pimpc_ctx ctx, int32_t which, double* out) { return iter_io(ctx, which, out, nullptr); }
+
+int32_t pimpc_set_iterates(pimpc_ctx ctx, int32_t which, const double* in) {
+    if (!in) return ctx ? ctx->fail(PIMPC_E_ARG, "buffer is NULL") : PIMPC_E_ARG;
+    return iter_io(ctx, which, nullptr, in);
+}
+
+}  // extern "C"

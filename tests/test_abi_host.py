@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point that include/pimpc.h declares, and rejects bad input during host
+validation (which runs before any HIP call, so no GPU is needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2601_14414_amd import pimpc as P
+from paper_2601_14414_amd import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pimpc.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pimpc_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for n in ["pimpc_setup", "pimpc_linearize", "pimpc_solve", "pimpc_solve_batch", "pimpc_backward"]:
+        assert n in names
+    assert set(names) == set(P.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+        assert ctypes.cast(getattr(L, n), ctypes.c_void_p).value
+
+
+def test_version_and_defaults():
+    assert P.pimpc_version() == 1
+    o = P.pimpc_default_options()
+    assert o.rho == 1.0 and o.max_iter == 200 and o.precision == P.PIMPC_FP32
+    assert o.eta == pytest.approx(0.999) and o.check_every == 1
+
+
+def _setup_code(problems, **kw):
+    o = P.pimpc_default_options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    try:
+        ctx, _ = P.pimpc_setup(problems, o)
+    except P.PimpcError as e:
+        return e.code, e.msg
+    P.pimpc_destroy(ctx)
+    return 0, ""
+
+
+@pytest.mark.parametrize("field,value", [("rho", 0.0), ("rho", -1.0), ("rho", float("inf")),
+                                         ("max_iter", 0), ("check_every", 0), ("precision", 7),
+                                         ("accel", 3), ("warm_start", 2), ("ckpt_every", -1),
+                                         ("eps", float("nan"))])
+def test_bad_options_rejected(field, value):
+    code, msg = _setup_code([W.plain_fp64_problem(0)], **{field: value})
+    assert code == P.PIMPC_E_ARG, (field, value, code, msg)
+
+
+def test_bad_problem_data_rejected():
+    p = W.plain_fp64_problem(0)
+    q = p.copy(xmin=p.xmin.copy())
+    q.xmin[2] = 5.0  # xmin > xmax
+    assert _setup_code([q])[0] == P.PIMPC_E_ARG
+    q = p.copy(A=p.A.copy())
+    q.A[1, 1] = np.nan
+    assert _setup_code([q])[0] == P.PIMPC_E_NONFINITE
+    q = p.copy(Q=p.Q.copy())
+    q.Q[0, 0] = -1.0
+    assert _setup_code([q])[0] == P.PIMPC_E_NOT_PSD
+    q = p.copy(R=p.R.copy())
+    q.R[0, 1] = 0.3  # not symmetric
+    code, msg = _setup_code([q])
+    assert code == P.PIMPC_E_NOT_PSD and "symmetric" in msg
+    q = p.copy(N=0)
+    assert _setup_code([q])[0] == P.PIMPC_E_DIM
+
+
+def test_unsupported_requests_are_reported():
+    assert _setup_code([W.plain_fp64_problem(0)], accel=1)[0] == P.PIMPC_E_UNSUPPORTED
+
+
+def test_error_text_available_without_context():
+    code, msg = _setup_code([W.plain_fp64_problem(0)], rho=-2.0)
+    assert code == P.PIMPC_E_ARG and "rho" in msg
+    assert b"rho" in P.lib().pimpc_last_error(None)
