@@ -172,9 +172,10 @@ int32_t pimpc_solve(pimpc_ctx ctx, const double *x0, const double *u_prev, doubl
 /*
  * Asynchronous batched solve on `hip_stream` with device pointers whose
  * element type is the context's precision (float for PIMPC_FP32, double for
- * PIMPC_FP64).  Same packing as pimpc_solve.  The launch sequence is
- * captured in a hipGraph on the first call for a given argument set and
- * replayed afterwards.  info_dev may be NULL.  The caller synchronises.
+ * PIMPC_FP64).  Same packing as pimpc_solve.  On a created (non-NULL)
+ * stream the launch sequence is captured in a hipGraph on the first call for
+ * a given argument set and replayed afterwards; on the NULL stream it is
+ * launched directly.  info_dev may be NULL.  The caller synchronises.
  * With opts.ckpt_every > 0 the forward records the tape pimpc_backward uses.
  */
 int32_t pimpc_solve_batch(pimpc_ctx ctx, const void *x0_dev, const void *uprev_dev,

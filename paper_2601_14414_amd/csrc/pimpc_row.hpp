@@ -26,13 +26,14 @@ struct RowArgs {
     int32_t write_iters;
 };
 
-// True if the row family handles an instance of this shape.
-bool row_supported(int nx, int nu, int N, int tv, int fp64);
+// True if the row family handles an instance of this shape; sets the padded sizes.
+bool row_supported(int nx, int nu, int N, int tv, int fp64, int* nxp, int* nup);
 // Device scratch bytes the instance needs (halo mailboxes, partials).
 size_t row_scratch_bytes(const InstDev& I, int fp64);
-// Per-instance preparation after (re)factorisation (none needed yet).
-hipError_t row_prepare(int fp64, const InstDev& I);
-// Enqueue the solve of one row-family instance.
-hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, hipStream_t s);
+// Pick the stage blocking (stored in I.pad1) so the grid stays co-resident;
+// I.pad1 > 0 on entry is the preferred blocking.
+hipError_t row_prepare(int fp64, InstDev& I);
+// Enqueue the solve of one row-family instance (clears its scratch first).
+hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, void* scratch_base, hipStream_t s);
 
 }  // namespace pimpc

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -500,7 +501,8 @@ static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
     for (size_t rj = 0; rj < ctx->row_insts.size(); ++rj) {
         const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[j] += (int64_t)1 << 40;
-        HIPCHK(ctx, launch_row(ctx->fp64, ls->d_rargs + rj, ctx->inst[ctx->row_insts[rj]], stream_of(j)));
+        HIPCHK(ctx, launch_row(ctx->fp64, ls->d_rargs + rj, ctx->inst[ctx->row_insts[rj]], ctx->d_row_scratch,
+                               stream_of(j)));
     }
     for (int c : order) {
         const ClassRun& r = ctx->runs[c];
@@ -519,7 +521,8 @@ static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
 }
 
 static int run_set(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s, bool graph) {
-    if (!graph) return enqueue_solve(ctx, ls, s);
+    // The legacy default stream cannot be captured: launch directly there.
+    if (!graph || s == nullptr) return enqueue_solve(ctx, ls, s);
     if (!ls->exec) {
         HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
         int rc = enqueue_solve(ctx, ls, s);
@@ -753,13 +756,14 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             I.nxp = cd->nx;
             I.nup = cd->nu;
         } else {
-            if (!row_supported(I.nx, I.nu, I.N, tv, ctx->fp64))
+            int rnx = 0, rnu = 0;
+            if (!row_supported(I.nx, I.nu, I.N, tv, ctx->fp64, &rnx, &rnu))
                 return ctx->fail(PIMPC_E_UNSUPPORTED,
                                  "instance %d (nx=%d, nu=%d, N=%d, %s, %s) has no compiled kernel", i, I.nx, I.nu,
                                  I.N, tv ? "time-varying" : "time-invariant", ctx->fp64 ? "fp64" : "fp32");
             I.cls = -1;
-            I.nxp = I.nx;
-            I.nup = I.nu;
+            I.nxp = rnx;
+            I.nup = rnu;
             ctx->row_insts.push_back(i);
         }
         I.nbp = I.nxp + I.nup;
@@ -871,8 +875,12 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             ctx->inst[i].pad0 = (int32_t)(off / 16);  // scratch offset in 16-byte units
             off += row_scratch_bytes(ctx->inst[i], ctx->fp64);
         }
+        const char* env_s = getenv("PIMPC_ROW_STAGES");
+        for (int i : ctx->row_insts) {
+            ctx->inst[i].pad1 = env_s ? atoi(env_s) : 1;
+            HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
+        }
         HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
-        for (int i : ctx->row_insts) HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
     }
 #undef DALLOC
     rc = autotune(ctx);
@@ -939,7 +947,6 @@ int32_t pimpc_linearize(pimpc_ctx ctx, const double* A, const double* B, const d
                                ctx->stream));
     int rc = refactor(ctx, true);
     if (rc != PIMPC_OK) return rc;
-    for (int i : ctx->row_insts) HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
     return PIMPC_OK;
 }
 
