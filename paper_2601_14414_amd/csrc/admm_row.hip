@@ -113,6 +113,8 @@ __device__ inline float wait_word(uint64_t* p, uint32_t tag, int32_t* abort_flag
 __device__ inline float wait_lds(uint64_t* p, uint32_t tag, int32_t* ab, bool* f) { return wait_word<true>(p, tag, ab, f); }
 __device__ inline float wait_glb(uint64_t* p, uint32_t tag, int32_t* ab, bool* f) { return wait_word<false>(p, tag, ab, f); }
 
+__device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
+
 template <typename T>
 __device__ inline T wsum(T v) {
 #pragma unroll
@@ -135,7 +137,9 @@ template <int NX, int NU, int S>
 __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __restrict__ ap, int nwaves,
                                                              int nwg) {
     constexpr int NB = NX + NU;
+    constexpr int LD = NB + 4;  // LDS row pitch of a broadcast vector (16-byte multiple)
     static_assert(NB <= 64, "row kernel needs nx + nu <= 64");
+    static_assert(LD % 4 == 0, "broadcast rows must stay 16-byte aligned");
     const RowArgs& a = *ap;
     const InstDev I = a.inst[a.inst_idx];
     const int N = I.N;
@@ -147,18 +151,19 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
     const int gw = lwg * kRowWaves + wv;  // logical wave (block) index
     const int k0 = gw * S;
     const int ns = max(0, min(S, N - k0));  // stages in this block
-    const bool rowl = lane < NB;            // lane carries a real (padded) row
+    const bool rowl = lane < NB;            // lane carries a (padded) row
     const int r = lane;
     const float rho = (float)a.rho;
     const float third = 1.0f / 3.0f;
 
     RowScratch sc = row_scratch((char*)a.scratch + (size_t)I.pad0 * 16, nwaves, NB);
 
-    __shared__ float bcast[kRowWaves][NB + 4];               // per-wave broadcast buffer
-    __shared__ uint64_t lmbox[kRowWaves][2][6][NB];         // intra-workgroup mailboxes
+    // per-wave broadcast rows: [S + 2][LD] (one row per vector of a round)
+    __shared__ __align__(16) float bcast[kRowWaves][S + 2][LD];
+    __shared__ uint64_t lmbox[kRowWaves][2][6][NB];  // intra-workgroup mailboxes
     for (int i = threadIdx.x; i < kRowWaves * 2 * 6 * NB; i += blockDim.x) (&lmbox[0][0][0][0])[i] = 0;
     __syncthreads();
-    if (gw >= nwaves) return;  // no more workgroup barriers below this point
+    if (gw >= nwaves) return;  // no workgroup barrier below this point
 
     // ---- per-lane matrix rows (time-invariant data), padded entries are 0
     const MatOffsets o = mat_offsets(NX, NU, N, 0);
@@ -168,7 +173,6 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
     for (int j = 0; j < NB; ++j) {
         Hrow[j] = rowl ? M[o.H + r * NB + j] : 0.f;
         Jrow[j] = (r < NU) ? M[o.J + r * NB + j] : 0.f;
-        // Abar row r (rows >= NX are identity rows, handled separately)
         Arow[j] = (r < NX) ? (j < NX ? M[o.A + r * NX + j] : M[o.B + r * NU + (j - NX)]) : 0.f;
     }
 #pragma unroll
@@ -182,9 +186,9 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
     const float ub_r = rowl ? M[o.ub + r] : 0.f;
     const float hbd_r = rowl ? M[o.Hb + r * NB + r] : 0.f;
     const bool hb_diag = I.hb_diag != 0;
+    const bool owns_last = ns > 0 && k0 + ns == N;  // block holds stage N-1 (uses H_{N-1})
 
-    // xbar_0 row r
-    float xb0_r = 0.f;
+    float xb0_r = 0.f;  // row r of xbar_0 = col(x(t), u(t-1))
     if (r < NX && r < I.nx) xb0_r = ((const float*)a.x0)[I.x_off + r];
     if (r >= NX && r - NX < I.nu && a.uprev) xb0_r = ((const float*)a.uprev)[I.u_off + r - NX];
 
@@ -205,211 +209,295 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
         g[s] = 0.f;
     }
 
-    // neighbours
     const bool has_left = ns > 0 && k0 > 0;
     const bool has_right = ns > 0 && k0 + ns < N;
-    const bool left_in_wg = wv > 0;                 // wave gw-1 is in this workgroup
-    const bool right_in_wg = wv < kRowWaves - 1;    // wave gw+1 is in this workgroup
-    // Mailbox addressing.  left_out of wave w: (z, v, lambda, dd) of its first
-    // stage, read by w-1.  right_out of wave w: (z, theta) of its last stage,
-    // read by w+1.  Slot [buf][vec][row].
+    const bool left_in_wg = wv > 0;
+    const bool right_in_wg = wv < kRowWaves - 1;
     auto put = [&](bool in_wg, int buf, int vec, uint64_t word) {
         if (in_wg)
             lstore(&lmbox[wv][buf][vec][r], word);
         else
             gstore(sc.mbox + ((size_t)gw * 12 + buf * 6 + vec) * NB + r, word);
     };
-    auto publish = [&](uint32_t tag, bool with_dd, float dd0) {
-        if (ns == 0 || !rowl) return;
-        const int buf = tag & 1;
-        if (k0 > 0) {  // left_out (z, v, lambda, dd) of the first stage, read by wave gw-1
-            put(left_in_wg, buf, 0, pack(z[0], tag));
-            put(left_in_wg, buf, 1, pack(v[0], tag));
-            put(left_in_wg, buf, 2, pack(la[0], tag));
-            if (with_dd) put(left_in_wg, buf, 3, pack(dd0, tag));
-        }
-        if (k0 + ns < N) {  // right_out (z, theta) of the last stage, read by wave gw+1
-            float zl = z[0], tl = th[0];
-#pragma unroll
-            for (int s = 1; s < S; ++s)
-                if (s == ns - 1) {
-                    zl = z[s];
-                    tl = th[s];
-                }
-            put(right_in_wg, buf, 4, pack(zl, tag));
-            put(right_in_wg, buf, 5, pack(tl, tag));
-        }
-    };
     bool failed = false;
-    // word `vec` of neighbour wave (local index nl, logical index ng), waiting for `tag`
     auto recv = [&](int nl, int ng, bool in_wg, int vec, uint32_t tag) -> float {
         if (!rowl) return 0.f;
         const int buf = tag & 1;
         if (in_wg) return wait_lds(&lmbox[nl][buf][vec][r], tag, sc.abort, &failed);
         return wait_glb(sc.mbox + ((size_t)ng * 12 + buf * 6 + vec) * NB + r, tag, sc.abort, &failed);
     };
+    // left_out (z, v, lambda[, dd]) of the first stage, read by wave gw-1
+    auto publish_left = [&](uint32_t tag, bool with_dd, float dd0) {
+        if (!has_left || !rowl) return;
+        const int buf = tag & 1;
+        put(left_in_wg, buf, 0, pack(z[0], tag));
+        put(left_in_wg, buf, 1, pack(v[0], tag));
+        put(left_in_wg, buf, 2, pack(la[0], tag));
+        if (with_dd) put(left_in_wg, buf, 3, pack(dd0, tag));
+    };
+    // right_out (z, theta) of the last stage, read by wave gw+1
+    auto publish_right = [&](uint32_t tag) {
+        if (!has_right || !rowl) return;
+        const int buf = tag & 1;
+        float zl = z[0], tl = th[0];
+#pragma unroll
+        for (int s = 1; s < S; ++s)
+            if (s == ns - 1) {
+                zl = z[s];
+                tl = th[s];
+            }
+        put(right_in_wg, buf, 4, pack(zl, tag));
+        put(right_in_wg, buf, 5, pack(tl, tag));
+    };
 
-    float* bc = &bcast[wv][0];
-    // mat-vec helper: lane r returns sum_j row[j] * x[j] with x broadcast via LDS
-#define BCAST_SET(val)                       \
-    do {                                     \
-        __builtin_amdgcn_wave_barrier();     \
-        if (rowl) bc[r] = (val);             \
-        __builtin_amdgcn_wave_barrier();     \
+    float(*bc)[LD] = bcast[wv];
+    // Write this lane's row of up to S + 2 vectors, then make them visible to
+    // the wave (LDS operations of one wave complete in order).
+#define BC_PUT(row, val)                  \
+    do {                                  \
+        if (rowl) bc[(row)][r] = (val);   \
     } while (0)
+#define BC_SYNC() __builtin_amdgcn_wave_barrier()
+#define DOT(acc, coef, row, n)                                  \
+    _Pragma("unroll") for (int j_ = 0; j_ < (n); ++j_) (acc) += (coef)[j_] * bc[(row)][j_];
 
-    publish(1u, false, 0.f);  // initial iterate (tag 1)
+    publish_left(1u, false, 0.f);  // initial iterate carries tag 1
+    publish_right(1u);
 
     int iters = 0;
     double c_last = 0.0, rp_last = 0.0, rd_last = 0.0;
     int status = 0;
     bool stop = false;
 
+    // One update of stage s (steps 2-3) given its xbar_k row `xp`.
+    float cpart = 0.f, rpart = 0.f, rdpart = 0.f;
+    float ddv[S], dzv[S];
+    auto update = [&](int s, bool check) {
+        // round 3 inputs (xp, du) are already in bc rows 0 (xp) and 1 (du)
+        float ci = 0.f, bi = 0.f;
+        DOT(ci, Arow, 0, NB);
+        if (r >= NX) ci = bc[0][r];
+        ci += e_r - la[s];
+        DOT(bi, Brow, 1, NU);
+        if (r >= NX) bi = bc[1][r - NX];
+        bi += be[s];
+        const float gam = bi - ci;
+        const float y = (2.f * (xs[s] + th[s]) + bi + ci) * third;
+        const float zn = y < lb_r ? lb_r : (y > ub_r ? ub_r : y);
+        const float vn = (zn + gam) * 0.5f;
+        const float thn = th[s] + xs[s] - zn;
+        const float ben = bi - vn;
+        const float lan = zn - vn - ci;
+        if (check) {
+            const float dv = rowl ? vn - v[s] : 0.f, dz = rowl ? zn - z[s] : 0.f;
+            const float dth = rowl ? thn - th[s] : 0.f, dbe = rowl ? ben - be[s] : 0.f;
+            const float dla = rowl ? lan - la[s] : 0.f;
+            const float dd = dz - dv;
+            cpart += dth * dth + dbe * dbe + dla * dla + dz * dz + dv * dv + dd * dd;
+            rpart = fmax(rpart, fmax(fabsf(dth), fmax(fabsf(dbe), fabsf(dla))));
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                if (t == s) {
+                    ddv[t] = dd;
+                    dzv[t] = dz;
+                }
+            // du block of F'G dq: Bbar' dv = u-rows of Abar' dv
+            BC_PUT(2, dv);
+            BC_SYNC();
+            float bt = (r >= NX) ? dv : 0.f;
+            DOT(bt, Acol, 2, NX);
+            if (r >= NX && rowl) rdpart = fmax(rdpart, fabsf(bt));
+        }
+        if (rowl) {
+            v[s] = vn;
+            z[s] = zn;
+            th[s] = thn;
+            be[s] = ben;
+            la[s] = lan;
+        }
+    };
+
 #pragma unroll 1
     for (int it = 0; it < a.K && !stop; ++it) {
         const uint32_t tin = (uint32_t)it + 1;   // tag of the iterate this step reads
         const uint32_t tout = (uint32_t)it + 2;  // tag of the iterate it produces
         const bool check = (a.eps > 0.0 && ((it + 1) % a.check_every) == 0) || (it == a.K - 1);
+        cpart = rpart = rdpart = 0.f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) ddv[s] = dzv[s] = 0.f;
 
-        // ---- halos of the previous iterate
+        // ---- round 1 (own data only): du_s = J (v - beta), g_s = Abar' (z - v - ebar + lambda)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s < ns) {
+                BC_PUT(0, v[s] - be[s]);
+                BC_PUT(1, z[s] - v[s] - e_r + la[s]);
+                BC_SYNC();
+                float acc = 0.f;
+                DOT(acc, Jrow, 0, NB);
+                du[s] = acc;
+                float gg = (r >= NX) ? bc[1][r] : 0.f;
+                DOT(gg, Acol, 1, NX);
+                g[s] = gg;
+                BC_SYNC();
+            }
+        }
+        // ---- round 2 for stages whose g_{k+1} is inside the block
+#pragma unroll
+        for (int s = 0; s + 1 < S; ++s) {
+            if (s + 1 < ns) {
+                float gn = g[0];
+#pragma unroll
+                for (int t = 1; t < S; ++t)
+                    if (t == s + 1) gn = g[t];
+                BC_PUT(0, q_r + rho * (z[s] - th[s] + gn));
+                BC_SYNC();
+                float acc = 0.f;
+                DOT(acc, Hrow, 0, NB);
+                xs[s] = acc;
+                BC_SYNC();
+            }
+        }
+        // ---- round 3 for interior stages 1 .. ns-2 (xbar_k of the previous stage is inside)
+#pragma unroll
+        for (int s = 1; s + 1 < S; ++s) {
+            if (s + 1 < ns) {
+                float xp = xs[0], dus = du[0];
+#pragma unroll
+                for (int t = 1; t < S; ++t) {
+                    if (t == s - 1) xp = xs[t];
+                    if (t == s) dus = du[t];
+                }
+                BC_PUT(0, xp);
+                BC_PUT(1, dus);
+                BC_SYNC();
+                update(s, check);
+                BC_SYNC();
+            }
+        }
+
+        // ---- halos of the previous iterate (needed only by the block's end stages).
+        // All five words are loaded together each poll, so a poll costs one
+        // memory round trip whatever the number of words.
         float zR = 0.f, vR = 0.f, lR = 0.f, zL = 0.f, tL = 0.f;
-        if (has_right) {
-            zR = recv(wv + 1, gw + 1, right_in_wg, 0, tin);
-            vR = recv(wv + 1, gw + 1, right_in_wg, 1, tin);
-            lR = recv(wv + 1, gw + 1, right_in_wg, 2, tin);
+        if ((has_right || has_left) && rowl) {
+            const int buf = tin & 1;
+            uint64_t* pr[3];
+            uint64_t* pl[2];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                pr[q] = right_in_wg ? &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][buf][q][r]
+                                    : sc.mbox + ((size_t)(gw + 1) * 12 + buf * 6 + q) * NB + r;
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                pl[q] = left_in_wg ? &lmbox[wv > 0 ? wv - 1 : 0][buf][4 + q][r]
+                                   : sc.mbox + ((size_t)(gw > 0 ? gw - 1 : 0) * 12 + buf * 6 + 4 + q) * NB + r;
+            int spins = 0;
+            for (;;) {
+                uint64_t wr[3] = {0, 0, 0}, wl[2] = {0, 0};
+                if (has_right) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) wr[q] = right_in_wg ? lload(pr[q]) : gload(pr[q]);
+                }
+                if (has_left) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) wl[q] = left_in_wg ? lload(pl[q]) : gload(pl[q]);
+                }
+                const bool okr = !has_right || (unpack_tag(wr[0]) == tin && unpack_tag(wr[1]) == tin &&
+                                                 unpack_tag(wr[2]) == tin);
+                const bool okl = !has_left || (unpack_tag(wl[0]) == tin && unpack_tag(wl[1]) == tin);
+                if (okr && okl) {
+                    zR = unpack_val(wr[0]);
+                    vR = unpack_val(wr[1]);
+                    lR = unpack_val(wr[2]);
+                    zL = unpack_val(wl[0]);
+                    tL = unpack_val(wl[1]);
+                    break;
+                }
+                if ((++spins & 31) == 0) {
+                    if (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        failed = true;
+                        break;
+                    }
+                    if (spins > kSpinLimit) {
+                        __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        failed = true;
+                        break;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
         }
-        if (has_left) {
-            zL = recv(wv - 1, gw - 1, left_in_wg, 4, tin);
-            tL = recv(wv - 1, gw - 1, left_in_wg, 5, tin);
-        }
-        if (__builtin_amdgcn_readfirstlane((int)failed)) {
+        if (__builtin_amdgcn_readfirstlane((int)failed) || wave_any(failed)) {
             status = -5;
             break;
         }
-
-        // ---- step 1a per stage: du = J (v - beta), g = Abar' (z - v - ebar + lambda)
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s < ns) {
-                BCAST_SET(v[s] - be[s]);
-                float acc = 0.f;
-#pragma unroll
-                for (int j = 0; j < NB; ++j) acc += Jrow[j] * bc[j];
-                du[s] = acc;
-                const float w = z[s] - v[s] - e_r + la[s];
-                BCAST_SET(w);
-                float gg = (r >= NX) ? w : 0.f;
-#pragma unroll
-                for (int i = 0; i < NX; ++i) gg += Acol[i] * bc[i];
-                g[s] = gg;
-            }
-        }
-        // g of the stage after the block, from the right halo
+        // g of the stage after the block (right halo)
         float gR = 0.f;
         if (has_right) {
-            const float w = zR - vR - e_r + lR;
-            BCAST_SET(w);
-            gR = (r >= NX) ? w : 0.f;
-#pragma unroll
-            for (int i = 0; i < NX; ++i) gR += Acol[i] * bc[i];
+            BC_PUT(0, zR - vR - e_r + lR);
+            BC_SYNC();
+            gR = (r >= NX) ? bc[0][r] : 0.f;
+            DOT(gR, Acol, 0, NX);
+            BC_SYNC();
         }
-
-        // ---- step 1b: h_k = qbar + rho (z - theta + g_{k+1}); xbar_{k+1} = H_k h_k
+        // ---- round 2 for the last stage (needs gR) and xbar_{k0} from the left halo
+        const int sl = ns - 1;  // last stage of the block
+        float hlast = 0.f, xlast = 0.f;
+        {
+            float zl = z[0], tl = th[0];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s < ns) {
-                float gn = (s + 1 < ns) ? 0.f : gR;
-#pragma unroll
-                for (int t = 1; t < S; ++t)
-                    if (t == s + 1 && t < ns) gn = g[t];
-                const float h = q_r + rho * (z[s] - th[s] + gn);
-                const int k = k0 + s;
-                if (k == N - 1 && hb_diag) {
-                    xs[s] = hbd_r * h;
-                } else {
-                    BCAST_SET(h);
-                    float acc = 0.f;
-                    if (k == N - 1) {
-                        const float* Hb = M + o.Hb + (rowl ? r : 0) * NB;
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) acc += (rowl ? Hb[j] : 0.f) * bc[j];
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) acc += Hrow[j] * bc[j];
-                    }
-                    xs[s] = acc;
+            for (int t = 1; t < S; ++t)
+                if (t == sl) {
+                    zl = z[t];
+                    tl = th[t];
                 }
+            hlast = q_r + rho * (zl - tl + gR);
+            BC_PUT(0, hlast);
+            if (has_left) BC_PUT(1, q_r + rho * (zL - tL + g[0]));
+            BC_SYNC();
+            if (owns_last && hb_diag) {
+                xlast = hbd_r * hlast;
+            } else if (owns_last) {
+                const float* Hb = M + o.Hb + (rowl ? r : 0) * NB;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) xlast += (rowl ? Hb[j] : 0.f) * bc[0][j];
+            } else {
+                DOT(xlast, Hrow, 0, NB);
             }
-        }
-        // xbar_{k0} recomputed from the left halo (stage k0-1 < N-1 uses H_a)
-        float xsL = xb0_r;
-        if (has_left) {
-            const float h = q_r + rho * (zL - tL + g[0]);
-            BCAST_SET(h);
-            float acc = 0.f;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) acc += Hrow[j] * bc[j];
-            xsL = acc;
-        }
-
-        // ---- steps 2-3 per stage
-        float cpart = 0.f, rpart = 0.f, rdpart = 0.f, dd0 = 0.f;
-        float ddv[S], dzv[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            ddv[s] = 0.f;
-            dzv[s] = 0.f;
-            if (s < ns) {
-                float xp = xsL;
-#pragma unroll
-                for (int t = 0; t < S - 1; ++t)
-                    if (t == s - 1) xp = xs[t];
-                BCAST_SET(xp);
-                float ci = 0.f;
-#pragma unroll
-                for (int j = 0; j < NB; ++j) ci += Arow[j] * bc[j];
-                if (r >= NX) ci = bc[r];
-                ci += e_r - la[s];
-                BCAST_SET(du[s]);
-                float bi = 0.f;
-#pragma unroll
-                for (int j = 0; j < NU; ++j) bi += Brow[j] * bc[j];
-                if (r >= NX) bi = bc[r - NX];
-                bi += be[s];
-                const float gam = bi - ci;
-                const float y = (2.f * (xs[s] + th[s]) + bi + ci) * third;
-                const float zn = y < lb_r ? lb_r : (y > ub_r ? ub_r : y);
-                const float vn = (zn + gam) * 0.5f;
-                const float thn = th[s] + xs[s] - zn;
-                const float ben = bi - vn;
-                const float lan = zn - vn - ci;
-                if (check) {
-                    const float dv = rowl ? vn - v[s] : 0.f, dz = rowl ? zn - z[s] : 0.f;
-                    const float dth = rowl ? thn - th[s] : 0.f, dbe = rowl ? ben - be[s] : 0.f;
-                    const float dla = rowl ? lan - la[s] : 0.f;
-                    const float dd = dz - dv;
-                    cpart += dth * dth + dbe * dbe + dla * dla + dz * dz + dv * dv + dd * dd;
-                    rpart = fmax(rpart, fmax(fabsf(dth), fmax(fabsf(dbe), fabsf(dla))));
-                    ddv[s] = dd;
-                    dzv[s] = dz;
-                    // du block of F'G dq: Bbar' dv = u-rows of Abar' dv
-                    BCAST_SET(dv);
-                    float bt = (r >= NX) ? dv : 0.f;
-#pragma unroll
-                    for (int i = 0; i < NX; ++i) bt += Acol[i] * bc[i];
-                    if (r >= NX && rowl) rdpart = fmax(rdpart, fabsf(bt));
-                }
-                if (rowl) {
-                    v[s] = vn;
-                    z[s] = zn;
-                    th[s] = thn;
-                    be[s] = ben;
-                    la[s] = lan;
-                }
+            float xsL = xb0_r;
+            if (has_left) {
+                xsL = 0.f;
+                DOT(xsL, Hrow, 1, NB);
             }
+            BC_SYNC();
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                if (t == sl) xs[t] = xlast;
+            // ---- round 3 for the first stage (xp = xbar_{k0}) ...
+            BC_PUT(0, xsL);
+            BC_PUT(1, du[0]);
+            BC_SYNC();
+            update(0, check);
+            BC_SYNC();
         }
-        if (check) dd0 = ddv[0];
-        publish(tout, check, dd0);
+        publish_left(tout, false, 0.f);
+        // ... and for the last stage (xp = xbar of the stage before it)
+        if (sl > 0) {
+            float xp = xs[0], dus = du[0];
+#pragma unroll
+            for (int t = 1; t < S; ++t) {
+                if (t == sl - 1) xp = xs[t];
+                if (t == sl) dus = du[t];
+            }
+            BC_PUT(0, xp);
+            BC_PUT(1, dus);
+            BC_SYNC();
+            update(sl, check);
+            BC_SYNC();
+        }
+        publish_right(tout);
+        if (check) publish_left(tout, true, ddv[0]);  // dd of the first stage for the dual residual
         ++iters;
 
         if (check) {
@@ -424,10 +512,11 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
                     for (int t = 1; t < S; ++t)
                         if (t == s + 1 && t < ns) ddn = ddv[t];
                     const bool hasnext = k0 + s + 1 < N;
-                    BCAST_SET(ddn);
-                    float tg = (r >= NX) ? ddn : 0.f;
-#pragma unroll
-                    for (int i = 0; i < NX; ++i) tg += Acol[i] * bc[i];
+                    BC_PUT(0, ddn);
+                    BC_SYNC();
+                    float tg = (r >= NX) ? bc[0][r] : 0.f;
+                    DOT(tg, Acol, 0, NX);
+                    BC_SYNC();
                     if (rowl) rdpart = fmax(rdpart, fabsf(dzv[s] + (hasnext ? tg : 0.f)));
                 }
             }
@@ -441,26 +530,37 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
                 __hip_atomic_store(&sc.red_tag[gw], (uint64_t)tout, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (gw == 0) {
-                // deterministic reduction in wave order, one lane
+                // deterministic reduction: lane l accumulates waves l, l+64, ...
+                // in order, then a fixed shuffle tree combines the lanes
                 double cs = 0.0, rp = 0.0, rd = 0.0;
-                if (lane == 0) {
-                    for (int w = 0; w < nwaves; ++w) {
+                bool lfail = false;
+                for (int w0 = 0; w0 < nwaves; w0 += 64) {
+                    const int w = w0 + lane;
+                    if (w < nwaves && !lfail) {
                         int spins = 0;
-                        while (__hip_atomic_load(&sc.red_tag[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                        while (__hip_atomic_load(&sc.red_tag[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
                                (uint64_t)tout) {
                             if (++spins > kSpinLimit ||
                                 __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                                 __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                failed = true;
+                                lfail = true;
                                 break;
                             }
                             __builtin_amdgcn_s_sleep(1);
                         }
-                        if (failed) break;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    if (w < nwaves && !lfail) {
                         cs += sc.red_val[w * 3 + 0];
                         rp = fmax(rp, sc.red_val[w * 3 + 1]);
                         rd = fmax(rd, sc.red_val[w * 3 + 2]);
                     }
+                }
+                cs = wsum(cs);
+                rp = wmax(rp);
+                rd = wmax(rd);
+                const bool anyfail = wave_any(lfail);
+                if (lane == 0) {
                     c_last = a.rho * cs;
                     rp_last = rp;
                     rd_last = a.rho * rd;
@@ -470,7 +570,7 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
                         dec = 1;
                     }
                     if (a.eps > 0.0 && c_last <= a.eps) dec = 1;
-                    if (failed) {
+                    if (anyfail) {
                         status = -5;
                         dec = 1;
                     }
@@ -478,8 +578,7 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
                                        __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-            if (a.eps > 0.0) {
-                // everyone learns the decision (stop or continue)
+            if (a.eps > 0.0) {  // everyone learns the decision (stop or continue)
                 uint64_t d = 0;
                 if (lane == 0) {
                     int spins = 0;
@@ -535,7 +634,9 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
         rec.pad = 0;
         a.info[a.inst_idx] = rec;
     }
-#undef BCAST_SET
+#undef BC_PUT
+#undef BC_SYNC
+#undef DOT
 }
 
 template <typename T>

@@ -1,0 +1,131 @@
+"""Batched persistent form: the 4096-instance uneven batch through
+pimpc_solve_batch (device tensors, hipGraph capture/replay), its schedules,
+and parameter updates from device tensors -- each against the oracle and
+against the plain single-context path."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_14414_amd import pimpc as P
+from paper_2601_14414_amd import workloads as W
+
+from test_gpu_lane import TOL32, compare, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def side_stream():
+    s = torch.cuda.Stream()
+    yield s
+    torch.cuda.synchronize()
+
+
+def _solve_batch(solver, problems, stream, x0=None):
+    dev = torch.device("cuda")
+    with torch.cuda.stream(stream):
+        if x0 is None:
+            x0 = torch.tensor(np.concatenate([p.x0 for p in problems]), dtype=torch.float32, device=dev)
+        u0 = torch.full((solver.sum_nu,), float("nan"), dtype=torch.float32, device=dev)
+        info = torch.zeros((solver.count * 40,), dtype=torch.uint8, device=dev)
+        P.pimpc_solve_batch(solver.ctx, x0, None, u0, info, stream.cuda_stream)
+    stream.synchronize()
+    inf = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
+    return u0.cpu().numpy().astype(np.float64), inf, x0
+
+
+def test_full_uneven_batch_sampled(side_stream):
+    """All 4096 instances in one batched solve; 8 sampled instances (largest
+    and smallest classes included) match their oracle runs to the FP32
+    tolerance; the device path equals the host-pointer path bit for bit."""
+    problems = W.random_batch(4096, base_seed=1000, K=300)
+    s = P.Solver(problems, max_iter=300, precision=P.PIMPC_FP32, stream=side_stream.cuda_stream)
+    u0_dev, info, _ = _solve_batch(s, problems, side_stream)
+    assert np.all(np.isfinite(u0_dev)) and np.all(info["status"] == 0) and np.all(info["iters"] == 300)
+    u0_host, _ = s.solve()
+    np.testing.assert_array_equal(u0_dev, u0_host)
+    sizes = np.array([p.nx * 100 + p.N for p in problems])
+    pick = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))] +
+                      list(np.random.default_rng(0).choice(4096, 6, replace=False))))
+    offs = np.concatenate([[0], np.cumsum([p.nu for p in problems])])
+    its = {w: s.iterate(w) for w in (P.IT_Z, P.IT_LAMBDA, P.IT_XBAR)}
+    for i in pick:
+        r = oracle.solve(problems[i])
+        assert scaled_err(u0_dev[offs[i]:offs[i + 1]], r["u0"]) <= TOL32, i
+        assert scaled_err(its[P.IT_Z][i], r["state"][1]) <= TOL32, i
+        assert scaled_err(its[P.IT_LAMBDA][i], r["state"][4]) <= TOL32, i
+        assert scaled_err(its[P.IT_XBAR][i], r["xs"]) <= TOL32, i
+        c, rp, rd, _ = r["hist"][-1]
+        assert abs(info["r_prim"][i] - rp) <= 1e-4 and abs(info["r_dual"][i] - rd) <= 1e-4
+    s.close()
+
+
+def test_graph_replay_is_stable(side_stream):
+    """Replays of the captured graph, with unrelated eager work and host
+    synchronisation between them, give identical results; changing x0 in
+    place (same pointer) changes the result like a fresh host-path solve."""
+    problems = W.random_batch(96, base_seed=77, K=120)
+    s = P.Solver(problems, max_iter=120, precision=P.PIMPC_FP32, stream=side_stream.cuda_stream)
+    first, _, x0 = _solve_batch(s, problems, side_stream)
+    for rep in range(3):
+        a = torch.randn(512, 512, device="cuda")
+        (a @ a).sum().item()
+        again, _, _ = _solve_batch(s, problems, side_stream, x0=x0)
+        np.testing.assert_array_equal(again, first)
+    with torch.cuda.stream(side_stream):
+        x0.mul_(0.5)
+    side_stream.synchronize()
+    half, _, _ = _solve_batch(s, problems, side_stream, x0=x0)
+    u_host, _ = s.solve(x0=0.5 * np.concatenate([p.x0 for p in problems]).astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(half, u_host, atol=1e-6)
+    assert np.max(np.abs(half - first)) > 1e-3
+    s.close()
+
+
+@pytest.mark.parametrize("schedule", [1, 2, 3, 4])
+def test_every_schedule_gives_the_same_iterates(schedule):
+    """The autotuner's candidates only change which workgroup runs which bin,
+    so every fixed schedule yields bit-identical results."""
+    problems = W.random_batch(64, base_seed=5, K=80)
+    ref = P.Solver(problems, max_iter=80, precision=P.PIMPC_FP32, schedule=1)
+    u_ref, _ = ref.solve()
+    s = P.Solver(problems, max_iter=80, precision=P.PIMPC_FP32, schedule=schedule)
+    u, _ = s.solve()
+    np.testing.assert_array_equal(u, u_ref)
+    for w in (P.IT_Z, P.IT_THETA):
+        for a, b in zip(s.iterate(w), ref.iterate(w)):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_set_params_from_device_tensors(side_stream):
+    """pimpc_set_params_dev (differentiable path) re-factors from device
+    tensors: the solve equals a context set up with the same parameters."""
+    db = W.diff_batch(count=32, N=128, K=60)
+    rng = np.random.default_rng(1)
+    Qd = db.Qdiag * rng.uniform(0.5, 2.0, db.Qdiag.shape)
+    Rd = db.Rdiag * rng.uniform(0.5, 2.0, db.Rdiag.shape)
+    A = db.A + 0.01 * rng.standard_normal(db.A.shape)
+    B = db.Bm + 0.01 * rng.standard_normal(db.Bm.shape)
+    base = [db.instance(i) for i in range(32)]
+    s = P.Solver(base, max_iter=60, precision=P.PIMPC_FP32, stream=side_stream.cuda_stream)
+    f32 = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    tA, tB, tQ, tR = f32(A), f32(B), f32(Qd), f32(Rd)
+    side_stream.synchronize()
+    torch.cuda.synchronize()
+    P.pimpc_set_params_dev(s.ctx, tA, tB, tQ, tR, side_stream.cuda_stream)
+    side_stream.synchronize()
+    u_dev, _ = s.solve()
+    new = [db.instance(i).copy(A=A[i].astype(np.float32).astype(np.float64),
+                               B=B[i].astype(np.float32).astype(np.float64),
+                               Q=np.diag(Qd[i].astype(np.float32).astype(np.float64)),
+                               R=np.diag(Rd[i].astype(np.float32).astype(np.float64))) for i in range(32)]
+    fresh = P.Solver(new, max_iter=60, precision=P.PIMPC_FP32)
+    u_fresh, _ = fresh.solve()
+    np.testing.assert_allclose(u_dev, u_fresh, atol=1e-6)
+    for i in (0, 17):
+        r = oracle.solve(new[i], K=60)
+        assert scaled_err(u_dev[3 * i:3 * i + 3], r["u0"]) <= TOL32
+    s.close()
+    fresh.close()
