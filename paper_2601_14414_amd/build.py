@@ -33,6 +33,7 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
 
 def _units():
     units = [("factor.hip", "factor.o", []), ("admm_row.hip", "admm_row.o", []),
+             ("adjoint.hip", "adjoint.o", []),
              ("runtime.cpp", "runtime.o", ["-x", "hip"])]
     for p in range(NPARTS):
         units.append(("admm_lane.hip", f"admm_lane_{p}.o", [f"-DPIMPC_LANE_PART={p}"]))

@@ -1,0 +1,752 @@
+// adjoint.hip -- reverse mode through the unrolled ADMM iterations.
+//
+// Differentiable form of the solver (the paper names a differentiable piMPC
+// as future work in its conclusion; the transpose below is derived from the
+// closed-form iteration of eqn. (8) / Algorithm 1 steps 1-3).  The loss sees
+// u0 = u_prev + du_0 of the K-th step 1, and depends on (x0, diag Q, diag R,
+// A, B) of every instance.
+//
+// Backward kernel (one lane per stage, same bins as the forward):
+//   * the taped forward stored the iterate entering every ckpt_every-th
+//     iteration; the backward re-runs each segment from its checkpoint into a
+//     per-instance tape, then walks it in reverse;
+//   * per reverse step it recomputes the step's intermediates (du, g, h,
+//     xbar, b, c, the box mask), applies the exact transpose of steps 2-3,
+//     then of step 1; the halo directions are reversed (the adjoint of
+//     xbar_k goes to stage k-1, the adjoint of g_{k+1} to stage k+1);
+//   * parameter adjoints are sums over stages and iterations of outer
+//     products (e.g. Hbar += xbar_bar h^T).  Each wave stages the two vectors
+//     of its 64 stages in LDS and contracts over the stages with FP32 MFMA
+//     (16x16x4), accumulating in AGPR-resident 16x16 tiles: the one dense
+//     contraction on this path.
+// Chain kernel (FP64, one workgroup per instance): maps the adjoints of
+// H_a, H_{N-1}, J and the Abar/Bbar blocks to dA, dB, diag Q, diag R through
+// M_bar = -H Hbar H and the derivative of J = (Bbar'Bbar)^-1 Bbar'.
+#include <hip/hip_runtime.h>
+
+#include "lane_common.hpp"
+#include "pimpc_dev.hpp"
+#include "pimpc_lane.hpp"
+#include "pimpc_adjoint.hpp"
+
+namespace pimpc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+
+// The backward runs in 256-thread workgroups (bins of at most 4 waves) so that
+// each wave may use the whole 512-entry register file of its SIMD.
+constexpr int kBwdThreads = 256;
+constexpr int kBwdWaves = kBwdThreads / 64;
+constexpr int kBBD = kBwdThreads;  // LDS row stride of the halo buffers
+extern __shared__ __align__(16) unsigned char bwd_smem[];
+
+// C += V1 V2^T over the 64 stages of this wave.  Each lane passes its stage's
+// two 16-vectors; they are staged as [stage][16] and fed to the MFMA so that
+// lane l supplies V1[l % 16][4t + l / 16] and V2[l % 16][4t + l / 16].
+__device__ inline void stage_accum(floatx4& C, const float (&v1)[16], const float (&v2)[16], float* stg,
+                                   int lane) {
+    float4* s1 = (float4*)(stg + lane * 16);
+    float4* s2 = (float4*)(stg + 1024 + lane * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        s1[q] = make_float4(v1[4 * q], v1[4 * q + 1], v1[4 * q + 2], v1[4 * q + 3]);
+        s2[q] = make_float4(v2[4 * q], v2[4 * q + 1], v2[4 * q + 2], v2[4 * q + 3]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int i = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const float av = stg[(4 * t + kk) * 16 + i];
+        const float bv = stg[1024 + (4 * t + kk) * 16 + i];
+        C = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, C, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int NX, int NU>
+__device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool have, int gw0,
+                                        unsigned leader_mask) {
+    constexpr int NB = NX + NU;
+    static_assert(NB <= 16, "the backward kernel supports nx + nu <= 16");
+    inst_idx = __builtin_amdgcn_readfirstlane(inst_idx);
+    gw0 = __builtin_amdgcn_readfirstlane(gw0);
+    have = __builtin_amdgcn_readfirstlane((int)have) != 0;
+    const InstDev I = ((cptr<InstDev>)uniform_ptr(a.inst))[have ? inst_idx : 0];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int k = tid - gw0 * 64;
+    const int N = have ? I.N : 0;
+    const bool act = have && k >= 0 && k < N;
+    const float rho = (float)a.rho;
+    const float third = 1.0f / 3.0f;
+    const MatOffsets o = mat_offsets(NX, NU, have ? N : 1, 0);
+    const cptr<float> M0 = (cptr<float>)uniform_ptr(have ? a.mats + I.mat_off : a.mats);
+    float* xg = (float*)bwd_smem;
+    float* xx = xg + 16 * kBBD;
+    float* stg = xx + 16 * kBBD + wave * 2048;  // this wave's staging tile
+
+    const cptr<float> x0p = (cptr<float>)uniform_ptr(a.x0 + (have ? I.x_off : 0));
+    const cptr<float> upp = (cptr<float>)uniform_ptr(a.uprev ? a.uprev + (have ? I.u_off : 0) : nullptr);
+    const int nx_real = have ? I.nx : 0, nu_real = have ? I.nu : 0;
+    float xb0[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+        xb0[i] = i < NX ? (i < nx_real ? x0p[i] : 0.f) : ((upp && i - NX < nu_real) ? upp[i - NX] : 0.f);
+    const bool is_last = act && k == N - 1;
+    const bool hb_diag = have && I.hb_diag;
+
+#define ROWP(base, r, ld) ([&]() { cptr<float> p_ = (base) + (r) * (ld); asm volatile("" : "+s"(p_)); return p_; }())
+#define MATS()                           \
+    cptr<float> Mi = M0;                 \
+    asm volatile("" : "+s"(Mi));         \
+    const cptr<float> Jm = Mi + o.J;     \
+    const cptr<float> Hm = Mi + o.H;     \
+    const cptr<float> Hbm = Mi + o.Hb;   \
+    const cptr<float> Am = Mi + o.A;     \
+    const cptr<float> Bm = Mi + o.B;     \
+    const cptr<float> em = Mi + o.e;     \
+    const cptr<float> qb = Mi + o.qbar;  \
+    const cptr<float> lbm = Mi + o.lb;   \
+    const cptr<float> ubm = Mi + o.ub;   \
+    (void)Jm; (void)Hm; (void)Hbm; (void)Am; (void)Bm; (void)em; (void)qb; (void)lbm; (void)ubm;
+
+    float v[NB], z[NB], th[NB], be[NB], la[NB];
+    float sv[NB], sz[NB], sth[NB], sbe[NB], sla[NB];  // adjoint of the iterate entering the step
+    float x0b[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) sv[i] = sz[i] = sth[i] = sbe[i] = sla[i] = x0b[i] = 0.f;
+    floatx4 CHa = {0, 0, 0, 0}, CHb = {0, 0, 0, 0}, CJ = {0, 0, 0, 0}, CA = {0, 0, 0, 0}, CB = {0, 0, 0, 0};
+
+    auto load_state = [&](const float* base) {
+        const gptr<float> p = (gptr<float>)base;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            v[i] = act ? p[(int64_t)(0 * NB + i) * N + k] : 0.f;
+            z[i] = act ? p[(int64_t)(1 * NB + i) * N + k] : 0.f;
+            th[i] = act ? p[(int64_t)(2 * NB + i) * N + k] : 0.f;
+            be[i] = act ? p[(int64_t)(3 * NB + i) * N + k] : 0.f;
+            la[i] = act ? p[(int64_t)(4 * NB + i) * N + k] : 0.f;
+        }
+    };
+    auto store_state = [&](float* base) {
+        if (!act) return;
+        const gptr<float> p = (gptr<float>)base;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            p[(int64_t)(0 * NB + i) * N + k] = v[i];
+            p[(int64_t)(1 * NB + i) * N + k] = z[i];
+            p[(int64_t)(2 * NB + i) * N + k] = th[i];
+            p[(int64_t)(3 * NB + i) * N + k] = be[i];
+            p[(int64_t)(4 * NB + i) * N + k] = la[i];
+        }
+    };
+
+    // Step 1 of the iteration from the current iterate: du, h, xbar (two barriers).
+    float du[NU], h[NB], xs[NB], d[NB];
+    auto step1 = [&]() {
+        MATS()
+#pragma unroll
+        for (int i = 0; i < NB; ++i) d[i] = v[i] - be[i];
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            const cptr<float> Jr = ROWP(Jm, r, NB);
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) s += Jr[j] * d[j];
+            du[r] = s;
+        }
+        float g[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) g[c] = (c < NX) ? 0.f : (z[c] - v[c] + la[c]);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+            const float w = z[r] - v[r] - em[r] + la[r];
+            const cptr<float> Ar = ROWP(Am, r, NX);
+            const cptr<float> Br = ROWP(Bm, r, NU);
+#pragma unroll
+            for (int c = 0; c < NX; ++c) g[c] += Ar[c] * w;
+#pragma unroll
+            for (int c = 0; c < NU; ++c) g[NX + c] += Br[c] * w;
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) xg[c * kBBD + tid] = g[c];
+        __syncthreads();
+        const bool hasnext = act && (k + 1 < N);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const float gv = xg[i * kBBD + tid + 1];
+            h[i] = qb[i] + rho * (z[i] - th[i] + (hasnext ? gv : 0.f));
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const cptr<float> Hr = ROWP(Hm, r, NB);
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) s += Hr[j] * h[j];
+            xs[r] = s;
+        }
+        if (is_last) {
+            if (hb_diag) {
+#pragma unroll
+                for (int r = 0; r < NB; ++r) xs[r] = Hbm[r * NB + r] * h[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < NB; ++r) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s += Hbm[r * NB + j] * h[j];
+                    xs[r] = s;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) xx[i * kBBD + tid] = xs[i];
+        __syncthreads();
+    };
+    // b, c of steps 2-3 given xbar_k (xp); optionally the new iterate.
+    auto step23 = [&](const float (&xp)[NB], float (&b)[NB], float (&c)[NB], bool advance) {
+        MATS()
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (i < NX) {
+                const cptr<float> Ar = ROWP(Am, i, NX);
+                const cptr<float> Br = ROWP(Bm, i, NU);
+                float sb = be[i];
+#pragma unroll
+                for (int j = 0; j < NU; ++j) sb += Br[j] * du[j];
+                float sc = em[i] - la[i];
+#pragma unroll
+                for (int j = 0; j < NX; ++j) sc += Ar[j] * xp[j];
+#pragma unroll
+                for (int j = 0; j < NU; ++j) sc += Br[j] * xp[NX + j];
+                b[i] = sb;
+                c[i] = sc;
+            } else {
+                b[i] = du[i - NX] + be[i];
+                c[i] = xp[i] - la[i];
+            }
+        }
+        if (advance) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const float gam = b[i] - c[i];
+                const float y = (2.f * (xs[i] + th[i]) + b[i] + c[i]) * third;
+                const float zn = y < lbm[i] ? lbm[i] : (y > ubm[i] ? ubm[i] : y);
+                const float vn = (zn + gam) * 0.5f;
+                const float thn = th[i] + xs[i] - zn;
+                if (act) {
+                    v[i] = vn;
+                    th[i] = thn;
+                    be[i] = b[i] - vn;
+                    la[i] = zn - vn - c[i];
+                    z[i] = zn;
+                }
+            }
+        }
+    };
+    auto get_xp = [&](float (&xp)[NB]) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const float xv = xx[i * kBBD + tid - 1];
+            xp[i] = (k == 0) ? xb0[i] : (act ? xv : 0.f);
+        }
+    };
+
+    const int K = a.K;
+    const int CK = a.ckpt_every;
+    const int nck = (K + CK - 1) / CK;
+    float* tape = have ? a.tape + I.tape_off : a.tape;
+#pragma unroll 1
+    for (int seg = nck - 1; seg >= 0; --seg) {
+        const int i0 = seg * CK;
+        const int i1 = min(i0 + CK, K);
+        load_state(have ? a.ckpt + I.ck_off + (int64_t)seg * 5 * NB * N : a.ckpt);
+        // forward over the segment, keeping the iterate entering each step
+#pragma unroll 1
+        for (int i = i0; i < i1; ++i) {
+            store_state(tape + (int64_t)(i - i0) * 5 * NB * N);
+            if (i + 1 < i1) {
+                step1();
+                float xp[NB], b[NB], c[NB];
+                get_xp(xp);
+                step23(xp, b, c, true);
+            }
+        }
+        // reverse sweep
+#pragma unroll 1
+        for (int i = i1 - 1; i >= i0; --i) {
+            load_state(tape + (int64_t)(i - i0) * 5 * NB * N);
+            if (i == K - 1) {
+                // seed: u0 = u_prev + J (v_0 - beta_0) of the last step 1
+                MATS()
+                float ub[16], dd[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) ub[q] = dd[q] = 0.f;
+                if (act && k == 0) {
+#pragma unroll
+                    for (int r = 0; r < NU; ++r) ub[r] = r < nu_real ? a.dLdu0[I.u_off + r] : 0.f;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        dd[j] = v[j] - be[j];
+                        float t = 0.f;
+#pragma unroll
+                        for (int r = 0; r < NU; ++r) t += Jm[r * NB + j] * ub[r];
+                        sv[j] += t;
+                        sbe[j] -= t;
+                    }
+                }
+                stage_accum(CJ, ub, dd, stg, lane);
+                continue;
+            }
+            // ---- recompute the step's intermediates
+            step1();
+            float xp[NB], b[NB], c[NB];
+            get_xp(xp);
+            step23(xp, b, c, false);
+            MATS()
+            // ---- transpose of steps 2-3 (sv.. hold the adjoint of the new iterate)
+            float nth[NB], xsb[NB], bb[NB], cb[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const float y = (2.f * (xs[i] + th[i]) + b[i] + c[i]) * third;
+                const bool inside = y > lbm[i] && y < ubm[i];
+                float znb = sz[i] - sth[i];
+                nth[i] = sth[i];
+                xsb[i] = sth[i];
+                float bbi = sbe[i];
+                float vnb = sv[i] - sbe[i];
+                znb += sla[i];
+                vnb -= sla[i];
+                float cbi = -sla[i];
+                znb += 0.5f * vnb;
+                const float gamb = 0.5f * vnb;
+                const float yb = inside ? znb : 0.f;
+                xsb[i] += (2.f / 3.f) * yb;
+                nth[i] += (2.f / 3.f) * yb;
+                bbi += yb * third;
+                cbi += yb * third;
+                bbi += gamb;
+                cbi -= gamb;
+                bb[i] = act ? bbi : 0.f;
+                cb[i] = act ? cbi : 0.f;
+            }
+            // adjoint of the step's input iterate, first contributions
+            float nv[NB], nz[NB], nbe[NB], nla[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                nv[i] = 0.f;
+                nz[i] = 0.f;
+                nbe[i] = bb[i];
+                nla[i] = -cb[i];
+            }
+            // xbar_k adjoint = Abar' cb (to stage k-1, or to xbar_0 at k = 0)
+            float xpb[NB];
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) xpb[cc] = (cc < NX) ? 0.f : cb[cc];
+#pragma unroll
+            for (int r = 0; r < NX; ++r) {
+                const cptr<float> Ar = ROWP(Am, r, NX);
+                const cptr<float> Br = ROWP(Bm, r, NU);
+#pragma unroll
+                for (int cc = 0; cc < NX; ++cc) xpb[cc] += Ar[cc] * cb[r];
+#pragma unroll
+                for (int cc = 0; cc < NU; ++cc) xpb[NX + cc] += Br[cc] * cb[r];
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) xg[i * kBBD + tid] = xpb[i];
+            // du adjoint = Bbar' bb
+            float dub[NU];
+#pragma unroll
+            for (int cc = 0; cc < NU; ++cc) dub[cc] = bb[NX + cc];
+#pragma unroll
+            for (int r = 0; r < NX; ++r) {
+                const cptr<float> Br = ROWP(Bm, r, NU);
+#pragma unroll
+                for (int cc = 0; cc < NU; ++cc) dub[cc] += Br[cc] * bb[r];
+            }
+            {  // Abar += cb xbar_k' (top rows), Bbar += bb du' (top rows)
+                float v1[16], v2[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    v1[q] = (q < NX) ? cb[q] : 0.f;
+                    v2[q] = (q < NB && act) ? xp[q] : 0.f;
+                }
+                stage_accum(CA, v1, v2, stg, lane);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    v1[q] = (q < NX) ? bb[q] : 0.f;
+                    v2[q] = (q < NU && act) ? du[q] : 0.f;
+                }
+                stage_accum(CB, v1, v2, stg, lane);
+            }
+            __syncthreads();
+            // ---- transpose of step 1
+            const bool hasnext = act && (k + 1 < N);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const float t = xg[i * kBBD + tid + 1];
+                xsb[i] += hasnext ? t : 0.f;
+                if (act && k == 0) x0b[i] += xpb[i];
+            }
+            // h adjoint = H' xsb (H symmetric)
+            float hb[NB];
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                const cptr<float> Hr = ROWP(Hm, r, NB);
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) s += Hr[j] * xsb[j];
+                hb[r] = s;
+            }
+            if (is_last) {
+#pragma unroll
+                for (int r = 0; r < NB; ++r) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s += Hbm[j * NB + r] * xsb[j];
+                    hb[r] = s;
+                }
+            }
+            {  // H_a += xsb h' (k < N-1), H_{N-1} += xsb h' (k = N-1)
+                float v1[16], v2[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    v1[q] = (q < NB && act && !is_last) ? xsb[q] : 0.f;
+                    v2[q] = (q < NB && act) ? h[q] : 0.f;
+                }
+                stage_accum(CHa, v1, v2, stg, lane);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) v1[q] = (q < NB && is_last) ? xsb[q] : 0.f;
+                stage_accum(CHb, v1, v2, stg, lane);
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const float rh = act ? rho * hb[i] : 0.f;
+                nz[i] += rh;
+                nth[i] -= rh;
+                xx[i * kBBD + tid] = rh;  // adjoint of g_{k+1}, read by stage k+1
+            }
+            __syncthreads();
+            // g_k = Abar' w_k with w_k = z - v - ebar + lambda: adjoint from stage k-1
+            float gr[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const float t = xx[i * kBBD + tid - 1];
+                gr[i] = (act && k >= 1) ? t : 0.f;
+            }
+            float wb[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) wb[i] = (i < NX) ? 0.f : gr[i];
+#pragma unroll
+            for (int r = 0; r < NX; ++r) {
+                const cptr<float> Ar = ROWP(Am, r, NX);
+                const cptr<float> Br = ROWP(Bm, r, NU);
+                float s = 0.f;
+#pragma unroll
+                for (int cc = 0; cc < NX; ++cc) s += Ar[cc] * gr[cc];
+#pragma unroll
+                for (int cc = 0; cc < NU; ++cc) s += Br[cc] * gr[NX + cc];
+                wb[r] = s;
+            }
+            {  // Abar += w_k g_bar' (top rows)
+                float v1[16], v2[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    v1[q] = (q < NX && act) ? (z[q] - v[q] - em[q] + la[q]) : 0.f;
+                    v2[q] = (q < NB) ? gr[q] : 0.f;
+                }
+                stage_accum(CA, v1, v2, stg, lane);
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                nz[i] += wb[i];
+                nv[i] -= wb[i];
+                nla[i] += wb[i];
+            }
+            // du = J (v - beta)
+            {
+                float v1[16], v2[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    v1[q] = (q < NU && act) ? dub[q] : 0.f;
+                    v2[q] = (q < NB && act) ? d[q] : 0.f;
+                }
+                stage_accum(CJ, v1, v2, stg, lane);
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                float t = 0.f;
+#pragma unroll
+                for (int r = 0; r < NU; ++r) t += Jm[r * NB + j] * dub[r];
+                nv[j] += t;
+                nbe[j] -= t;
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                sv[i] = act ? nv[i] : 0.f;
+                sz[i] = act ? nz[i] : 0.f;
+                sth[i] = act ? nth[i] : 0.f;
+                sbe[i] = act ? nbe[i] : 0.f;
+                sla[i] = act ? nla[i] : 0.f;
+            }
+        }
+    }
+
+    // ---- reduce the per-wave tiles over the instance's waves, write raw adjoints
+    __syncthreads();
+    float* red = xx + 16 * kBBD + wave * 2048;  // reuse this wave's staging tile
+    const floatx4 tiles[5] = {CHa, CHb, CJ, CA, CB};
+#pragma unroll
+    for (int b5 = 0; b5 < 5; ++b5)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[b5 * 256 + (4 * (lane >> 4) + q) * 16 + (lane & 15)] = tiles[b5][q];
+    __syncthreads();
+    if (have && wave == gw0) {
+        const int nw = (N + 63) >> 6;
+        float* out = a.grads + I.gr_off;
+        for (int e = lane; e < 5 * 256; e += 64) {
+            float s = 0.f;
+            for (int w = gw0; w < gw0 + nw; ++w) s += (xx + 16 * kBBD)[w * 2048 + e];
+            out[e] = s;
+        }
+        if (k == 0)
+            for (int i = 0; i < 16; ++i) out[5 * 256 + i] = i < NB ? x0b[i] : 0.f;
+    }
+    __syncthreads();
+    (void)leader_mask;
+#undef ROWP
+#undef MATS
+}
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(kBwdThreads) lane_bwd_kernel(BwdArgs a) {
+    __shared__ int s_bin;
+    const int wave = threadIdx.x >> 6;
+    for (int j = 0;; ++j) {
+        int b;
+        if (a.bin_counter) {
+            if (threadIdx.x == 0) s_bin = atomicAdd(a.bin_counter, 1);
+            __syncthreads();
+            b = s_bin;
+            __syncthreads();
+        } else {
+            b = blockIdx.x + j * gridDim.x;
+        }
+        if (b >= a.nbins) break;
+        const Bin& bin = a.bins[b];
+        int my = -1;
+        unsigned leader_mask = 0;
+        for (int e = 0; e < bin.n; ++e) {
+            leader_mask |= 1u << bin.e[e].wave0;
+            if (wave >= bin.e[e].wave0 && wave < bin.e[e].wave0 + bin.e[e].nwaves) my = e;
+        }
+        my = __builtin_amdgcn_readfirstlane(my);
+        if (my >= 0)
+            bwd_run<NX, NU>(a, bin.e[my].inst, true, bin.e[my].wave0, leader_mask);
+        else
+            bwd_run<NX, NU>(a, 0, false, wave, leader_mask);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ FP64 chain
+
+constexpr int kCh = 17;  // LDS pitch of the 16 x 16 work matrices
+
+__device__ void ch_inverse(double* M, double* Out, int n) {
+    // Gauss-Jordan on an SPD matrix (thread 0; n <= 16): Out = M^-1
+    double W[16][32];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j) W[i][j] = j < n ? M[i * kCh + j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        const double p = W[c][c];
+        for (int j = 0; j < 2 * n; ++j) W[c][j] /= p;
+        for (int r = 0; r < n; ++r)
+            if (r != c) {
+                const double f = W[r][c];
+                for (int j = 0; j < 2 * n; ++j) W[r][j] -= f * W[c][j];
+            }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Out[i * kCh + j] = W[i][j + n];
+}
+
+__global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ inst, int count,
+                                                   const double* __restrict__ mats64,
+                                                   const float* __restrict__ grads, double rho, float* dx0,
+                                                   float* dQd, float* dRd, float* dA, float* dB) {
+    const int ii = blockIdx.x;
+    if (ii >= count) return;
+    const InstDev I = inst[ii];
+    const int NX = I.nxp, NU = I.nup, NB = I.nbp, N = I.N;
+    const int nx = I.nx, nu = I.nu;
+    const MatOffsets o = mat_offsets(NX, NU, N, 0);
+    const double* A = mats64 + I.mat64_off + o.A64;
+    const double* B = mats64 + I.mat64_off + o.B64;
+    const double* Q = mats64 + I.mat64_off + o.Q64;
+    const double* R = mats64 + I.mat64_off + o.R64;
+    const float* gr = grads + I.gr_off;
+    __shared__ double Ab[16 * kCh], Ma[16 * kCh], Mb[16 * kCh], Ha[16 * kCh], Hb[16 * kCh], G[16 * kCh],
+        Gi[16 * kCh], Jm[16 * kCh], T1[16 * kCh], Mba[16 * kCh], Mbb[16 * kCh], Gb[16 * kCh];
+    const int t = threadIdx.x;
+    // Abar rows (all NB rows) and the two M matrices
+    for (int e = t; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        Ab[i * kCh + j] = (i < NX) ? (j < NX ? A[i * NX + j] : B[i * NU + (j - NX)]) : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int e = t; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        double q = (i == j) ? rho : 0.0;
+        if (i < NX && j < NX) q += Q[i * NX + j];
+        if (i >= NX && j >= NX) q += R[(i - NX) * NU + (j - NX)];
+        double s = 0.0;
+        for (int r = 0; r < NB; ++r) s += Ab[r * kCh + i] * Ab[r * kCh + j];
+        Ma[i * kCh + j] = q + rho * s;
+        Mb[i * kCh + j] = q;
+    }
+    for (int e = t; e < NU * NU; e += blockDim.x) {
+        const int i = e / NU, j = e % NU;
+        double s = (i == j) ? 1.0 : 0.0;
+        for (int r = 0; r < NX; ++r) s += B[r * NU + i] * B[r * NU + j];
+        G[i * kCh + j] = s;
+    }
+    __syncthreads();
+    if (t == 0) {
+        ch_inverse(Ma, Ha, NB);
+        ch_inverse(Mb, Hb, NB);
+        ch_inverse(G, Gi, NU);
+    }
+    __syncthreads();
+    // J = G^-1 [B' I]
+    for (int e = t; e < NU * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        double s = 0.0;
+        for (int r = 0; r < NU; ++r) s += Gi[i * kCh + r] * (j < NX ? B[j * NU + r] : (j - NX == r ? 1.0 : 0.0));
+        Jm[i * kCh + j] = s;
+    }
+    // Mbar = -H Hbar H for both H
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* H = pass == 0 ? Ha : Hb;
+        const float* Hbar = gr + (pass == 0 ? 0 : 256);
+        double* Mbar = pass == 0 ? Mba : Mbb;
+        __syncthreads();
+        for (int e = t; e < NB * NB; e += blockDim.x) {
+            const int i = e / NB, j = e % NB;
+            double s = 0.0;
+            for (int r = 0; r < NB; ++r) s += H[i * kCh + r] * (double)Hbar[r * 16 + j];
+            T1[i * kCh + j] = s;
+        }
+        __syncthreads();
+        for (int e = t; e < NB * NB; e += blockDim.x) {
+            const int i = e / NB, j = e % NB;
+            double s = 0.0;
+            for (int r = 0; r < NB; ++r) s += T1[i * kCh + r] * H[r * kCh + j];
+            Mbar[i * kCh + j] = (pass == 0 && N == 1) ? 0.0 : -s;
+        }
+    }
+    __syncthreads();
+    // Gbar = -G^-1 Jbar J'
+    const float* Jbar = gr + 2 * 256;
+    for (int e = t; e < NU * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        double s = 0.0;
+        for (int r = 0; r < NU; ++r) s += Gi[i * kCh + r] * (double)Jbar[r * 16 + j];
+        T1[i * kCh + j] = s;  // G^-1 Jbar  (NU x NB)
+    }
+    __syncthreads();
+    for (int e = t; e < NU * NU; e += blockDim.x) {
+        const int i = e / NU, j = e % NU;
+        double s = 0.0;
+        for (int r = 0; r < NB; ++r) s += T1[i * kCh + r] * Jm[j * kCh + r];
+        Gb[i * kCh + j] = -s;
+    }
+    __syncthreads();
+    const float* Atop = gr + 3 * 256;
+    const float* Btop = gr + 4 * 256;
+    for (int e = t; e < nx * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        // Abar_bar top rows: raw + rho Abar (Mbar_a + Mbar_a')
+        double s = (double)Atop[i * 16 + j];
+        for (int r = 0; r < NB; ++r) s += rho * Ab[i * kCh + r] * (Mba[r * kCh + j] + Mba[j * kCh + r]);
+        if (j < NX) {
+            if (dA && j < nx) dA[(int64_t)ii * nx * nx + i * nx + j] = (float)s;
+        } else if (j - NX < nu) {
+            const int c = j - NX;
+            // Bbar_bar top rows: raw + (Jbar' G^-1)[i][c] + (Bbar (Gbar + Gbar'))[i][c]
+            double bb = (double)Btop[i * 16 + c] + T1[c * kCh + i];
+            for (int r = 0; r < NU; ++r) bb += B[i * NU + r] * (Gb[r * kCh + c] + Gb[c * kCh + r]);
+            if (dB) dB[(int64_t)ii * nx * nu + i * nu + c] = (float)(s + bb);
+        }
+    }
+    for (int i = t; i < nx; i += blockDim.x) {
+        if (dQd) dQd[(int64_t)ii * nx + i] = (float)(Mba[i * kCh + i] + Mbb[i * kCh + i]);
+        if (dx0) dx0[(int64_t)ii * nx + i] = gr[5 * 256 + i];
+    }
+    for (int i = t; i < nu; i += blockDim.x)
+        if (dRd) dRd[(int64_t)ii * nu + i] = (float)(Mba[(NX + i) * kCh + NX + i] + Mbb[(NX + i) * kCh + NX + i]);
+}
+
+// ---------------------------------------------------------------- host side
+
+inline size_t bwd_lds_bytes() { return (size_t)2 * 16 * kBBD * sizeof(float) + (size_t)kBwdWaves * 2048 * sizeof(float); }
+
+template <int NX, int NU>
+hipError_t launch_bwd_cls(const BwdArgs& a, int grid, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)lane_bwd_kernel<NX, NU>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_lds_bytes());
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((lane_bwd_kernel<NX, NU>), dim3(grid), dim3(kBwdThreads), bwd_lds_bytes(), s, a);
+    return hipGetLastError();
+}
+
+template <int NX, int NU>
+hipError_t maybe_launch_bwd(const BwdArgs& a, int grid, hipStream_t s) {
+    if constexpr (NX + NU <= 16)
+        return launch_bwd_cls<NX, NU>(a, grid, s);
+    else
+        return hipErrorInvalidValue;
+}
+
+// Backward launch for one lane class (time-invariant, FP32, nx + nu <= 16).
+hipError_t launch_backward_class(int cls, const BwdArgs& a, int grid, hipStream_t s, bool* handled) {
+    *handled = true;
+    switch (cls) {
+#define PIMPC_BWD(id, nx, nu) \
+    case id:                  \
+        return maybe_launch_bwd<nx, nu>(a, grid, s);
+        PIMPC_LANE_CLASSES(PIMPC_BWD)
+#undef PIMPC_BWD
+        default:
+            break;
+    }
+    *handled = false;
+    return hipErrorInvalidValue;
+}
+
+bool backward_class_supported(int cls) {
+    switch (cls) {
+#define PIMPC_BWD(id, nx, nu) \
+    case id:                  \
+        return (nx) + (nu) <= 16;
+        PIMPC_LANE_CLASSES(PIMPC_BWD)
+#undef PIMPC_BWD
+        default:
+            return false;
+    }
+}
+
+hipError_t launch_chain(const InstDev* inst, int count, const double* mats64, const float* grads, double rho,
+                        float* dx0, float* dQd, float* dRd, float* dA, float* dB, hipStream_t s) {
+    hipLaunchKernelGGL(chain_kernel, dim3(count), dim3(64), 0, s, inst, count, mats64, grads, rho, dx0, dQd, dRd,
+                       dA, dB);
+    return hipGetLastError();
+}
+
+}  // namespace pimpc

@@ -22,26 +22,11 @@
 
 #include "pimpc_dev.hpp"
 #include "pimpc_lane.hpp"
+#include "lane_common.hpp"
 
 namespace pimpc {
 
 constexpr int kBD = kBinThreads;  // LDS row stride of the halo buffers
-
-// Explicit address spaces: constant (4) for read-only data with uniform
-// addresses (scalar loads), global (1) for per-lane data.  Needed because the
-// per-class bodies are separate functions whose pointer arguments would
-// otherwise be generic (flat) pointers.
-#if defined(__HIP_DEVICE_COMPILE__)
-template <typename T>
-using cptr = const T __attribute__((address_space(4)))*;
-template <typename T>
-using gptr = T __attribute__((address_space(1)))*;
-#else  // the host pass only parses device code; plain pointers suffice there
-template <typename T>
-using cptr = const T*;
-template <typename T>
-using gptr = T*;
-#endif
 
 extern __shared__ __align__(16) unsigned char lane_smem[];
 
@@ -57,16 +42,6 @@ __device__ inline T wave_max(T v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     return v;
-}
-
-// Mark a pointer as wave-uniform (kept in SGPRs; loads through it become
-// scalar loads).  Only valid for pointers that are equal across the wave.
-template <typename P>
-__device__ inline P* uniform_ptr(P* p) {
-    const uint64_t v = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (P*)(((uint64_t)hi << 32) | lo);
 }
 
 template <typename T>
@@ -180,6 +155,18 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     for (int it = 0; it < a.K; ++it) {
         const bool check = (a.eps > 0.0 && ((it + 1) % a.check_every) == 0) || (it == a.K - 1);
         const bool run = !done;
+        // taped forward: keep the iterate entering this iteration every ckpt_every steps
+        if (a.ckpt_every > 0 && (it % a.ckpt_every) == 0 && act) {
+            const gptr<T> ck = (gptr<T>)((T*)a.ckpt + I.ck_off + (int64_t)(it / a.ckpt_every) * 5 * NB * N);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                ck[(int64_t)(0 * NB + i) * N + k] = v[i];
+                ck[(int64_t)(1 * NB + i) * N + k] = z[i];
+                ck[(int64_t)(2 * NB + i) * N + k] = th[i];
+                ck[(int64_t)(3 * NB + i) * N + k] = be[i];
+                ck[(int64_t)(4 * NB + i) * N + k] = la[i];
+            }
+        }
         // Row pointers are re-made opaque before use so that the scalar loads
         // of one matrix row cannot be hoisted ahead of earlier rows.
 #define ROW(base, r, ld) ([&]() { cptr<T> p_ = (base) + (r) * (ld); asm volatile("" : "+s"(p_)); return p_; }())

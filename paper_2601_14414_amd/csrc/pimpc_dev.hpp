@@ -28,7 +28,16 @@ struct InstDev {
     int64_t st_off;            // iterate block [5][nbp][N]
     int64_t it_off;            // last step-1 outputs: du [nup][N], then xbar [nbp][N]
     int64_t x_off, u_off;      // offsets into packed x0 (sum nx) and u (sum nu)
+    int64_t ck_off;            // checkpoints [nck][5][nbp][N] (taped forward)
+    int64_t tape_off;          // segment tape [ckpt_every][5][nbp][N] (backward)
+    int64_t gr_off;            // raw parameter adjoints [kGradBlocks][16][16] + xbar0 adjoint [16]
 };
+
+// Raw adjoint blocks written by the backward kernel (16 x 16 each, padded):
+// H_a (k < N-1), H_{N-1}, J, top rows of Abar, top rows of Bbar; then 16 more
+// values for the adjoint of xbar_0.
+constexpr int kGradBlocks = 5;
+constexpr int kGradStride = kGradBlocks * 256 + 16;
 
 // T matrix block of one instance (padded sizes NX, NU, NB = NX + NU).
 // Time-invariant (tv = 0), row-major:

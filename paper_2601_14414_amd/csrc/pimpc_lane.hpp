@@ -29,7 +29,8 @@ struct LaneArgs {
     int32_t warm;
     int32_t nbmax;
     int32_t write_iters;
-    int32_t pad;
+    int32_t ckpt_every;  // > 0: store the iterate entering every ckpt_every-th iteration
+    void* ckpt;          // checkpoint buffer (T), per instance at InstDev::ck_off
 };
 
 template <int P>

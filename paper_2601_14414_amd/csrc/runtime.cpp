@@ -21,6 +21,7 @@
 #include "pimpc_dev.hpp"
 #include "pimpc_lane.hpp"
 #include "pimpc_row.hpp"
+#include "pimpc_adjoint.hpp"
 
 namespace pimpc {
 template <typename T>
@@ -32,6 +33,7 @@ template <typename T>
 hipError_t launch_params(const InstDev*, int, const T*, const T*, const T*, const T*, double*, hipStream_t);
 template <typename T>
 hipError_t launch_fill(T*, int64_t, T, hipStream_t);
+
 }  // namespace pimpc
 
 using namespace pimpc;
@@ -146,6 +148,16 @@ struct pimpc_ctx_s {
     int nstreams = 1;
     int has_state = 0;
     std::vector<std::unique_ptr<LaunchSet>> sets;
+    // differentiable path (ckpt_every > 0)
+    void* d_ckpt = nullptr;
+    float* d_tape = nullptr;
+    float* d_grads = nullptr;
+    Bin* d_bwd_bins = nullptr;
+    int32_t* d_bwd_counters = nullptr;
+    std::vector<ClassRun> bwd_runs;
+    int taped = 0;
+    const void* tape_x0 = nullptr;
+    const void* tape_up = nullptr;
 
     int fail(int32_t code, const char* fmt, ...) {
         char buf[512];
@@ -325,9 +337,9 @@ static int refactor(pimpc_ctx ctx, bool sync_check) {
 
 // ------------------------------------------------------------ batch schedule
 
-static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins) {
+static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassRun>& runs, int cap_waves) {
     bins.clear();
-    ctx->runs.clear();
+    runs.clear();
     for (const ClassDesc& cd : kClassTable) {
         std::vector<int> members;
         for (int i = 0; i < ctx->count; ++i)
@@ -344,7 +356,7 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins) {
             const int w = (ctx->inst[i].N + 63) / 64;
             int tgt = -1;
             for (size_t b = 0; b < cb.size(); ++b)
-                if (used[b] + w <= kBinWaves && cb[b].n < kBinWaves) {
+                if (used[b] + w <= cap_waves && cb[b].n < cap_waves) {
                     tgt = (int)b;
                     break;
                 }
@@ -376,7 +388,7 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins) {
             waves += used[b];
         }
         run.cost = waves * stage_fma(cd.nx, cd.nu);
-        ctx->runs.push_back(run);
+        runs.push_back(run);
     }
 }
 
@@ -411,6 +423,8 @@ static int fill_set_args(pimpc_ctx ctx, LaunchSet* ls) {
         a.warm = ls->warm;
         a.nbmax = r.nbmax;
         a.write_iters = ls->write_iters;
+        a.ckpt_every = ctx->opt.ckpt_every;
+        a.ckpt = ctx->d_ckpt;
     }
     if (!args.empty())
         HIPCHK(ctx, hipMemcpy(ls->d_args, args.data(), args.size() * sizeof(LaneArgs), hipMemcpyHostToDevice));
@@ -663,6 +677,11 @@ static void destroy_ctx(pimpc_ctx ctx) {
     rel(ctx->d_bins);
     rel(ctx->d_counters);
     rel(ctx->d_row_scratch);
+    rel(ctx->d_ckpt);
+    rel(ctx->d_tape);
+    rel(ctx->d_grads);
+    rel(ctx->d_bwd_bins);
+    rel(ctx->d_bwd_counters);
     for (int j = 0; j < 3; ++j) {
         if (ctx->aux[j]) (void)hipStreamDestroy(ctx->aux[j]);
         if (ctx->ev_join[j]) (void)hipEventDestroy(ctx->ev_join[j]);
@@ -853,7 +872,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
 
     // ---------------- schedule
     std::vector<Bin> bins;
-    build_bins(ctx, bins);
+    build_bins(ctx, bins, ctx->runs, kBinWaves);
     if (!bins.empty()) {
         DALLOC(ctx->d_bins, Bin, bins.size());
         HIPCHK(ctx, hipMemcpy(ctx->d_bins, bins.data(), bins.size() * sizeof(Bin), hipMemcpyHostToDevice));
@@ -881,6 +900,33 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
         }
         HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
+    }
+    if (o->ckpt_every > 0) {
+        if (ctx->fp64 || tv || !ctx->row_insts.empty())
+            return ctx->fail(PIMPC_E_UNSUPPORTED, "the taped forward / backward needs FP32, time-invariant "
+                                                  "instances of the lane family");
+        int64_t ck = 0, tp = 0;
+        const int nck = (o->max_iter + o->ckpt_every - 1) / o->ckpt_every;
+        for (int i = 0; i < count; ++i) {
+            InstDev& I = ctx->inst[i];
+            if (!backward_class_supported(I.cls) || I.N > 256)
+                return ctx->fail(PIMPC_E_UNSUPPORTED, "instance %d: backward supports nx + nu <= 16 (padded) "
+                                                      "and N <= 256", i);
+            I.ck_off = ck;
+            ck += (int64_t)nck * 5 * I.nbp * I.N;
+            I.tape_off = tp;
+            tp += (int64_t)o->ckpt_every * 5 * I.nbp * I.N;
+            I.gr_off = (int64_t)i * kGradStride;
+        }
+        DALLOC(ctx->d_ckpt, float, ck);
+        DALLOC(ctx->d_tape, float, tp);
+        DALLOC(ctx->d_grads, float, (int64_t)count * kGradStride);
+        HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
+        std::vector<Bin> bb;
+        build_bins(ctx, bb, ctx->bwd_runs, 4);
+        DALLOC(ctx->d_bwd_bins, Bin, bb.size());
+        HIPCHK(ctx, hipMemcpy(ctx->d_bwd_bins, bb.data(), bb.size() * sizeof(Bin), hipMemcpyHostToDevice));
+        DALLOC(ctx->d_bwd_counters, int32_t, std::max<size_t>(ctx->bwd_runs.size(), 1));
     }
 #undef DALLOC
     rc = autotune(ctx);
@@ -972,6 +1018,11 @@ int32_t pimpc_solve(pimpc_ctx ctx, const double* x0, const double* u_prev, doubl
     if (!ls) return rc;
     rc = run_set(ctx, ls, s, false);
     if (rc != PIMPC_OK) return rc;
+    if (ctx->opt.ckpt_every > 0) {
+        ctx->taped = 1;
+        ctx->tape_x0 = ctx->d_x0;
+        ctx->tape_up = u_prev ? ctx->d_up : nullptr;
+    }
     std::vector<char> bo(std::max<int64_t>(ctx->sum_nu, 1) * ctx->tsize);
     std::vector<InfoDev> inf(ctx->count);
     HIPCHK(ctx, hipMemcpyAsync(bo.data(), ctx->d_u0, ctx->sum_nu * ctx->tsize, hipMemcpyDeviceToHost, s));
@@ -991,7 +1042,6 @@ int32_t pimpc_solve_batch(pimpc_ctx ctx, const void* x0_dev, const void* uprev_d
                           pimpc_info* info_dev, void* hip_stream) {
     if (!ctx) return PIMPC_E_ARG;
     if (!x0_dev || !u0_dev) return ctx->fail(PIMPC_E_ARG, "x0_dev and u0_dev are required");
-    if (ctx->opt.ckpt_every > 0) return ctx->fail(PIMPC_E_UNSUPPORTED, "taped forward is not built yet");
     const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     const int warm = (ctx->opt.warm_start && ctx->has_state) ? 1 : 0;
     int rc = 0;
@@ -1000,6 +1050,11 @@ int32_t pimpc_solve_batch(pimpc_ctx ctx, const void* x0_dev, const void* uprev_d
     rc = run_set(ctx, ls, s, true);
     if (rc != PIMPC_OK) return rc;
     ctx->has_state = 1;
+    if (ctx->opt.ckpt_every > 0) {
+        ctx->taped = 1;
+        ctx->tape_x0 = x0_dev;
+        ctx->tape_up = uprev_dev;
+    }
     return PIMPC_OK;
 }
 
@@ -1027,15 +1082,39 @@ int32_t pimpc_set_params_dev(pimpc_ctx ctx, const void* A, const void* B, const 
 
 int32_t pimpc_backward(pimpc_ctx ctx, const void* dL_du0_dev, void* dx0, void* dQdiag, void* dRdiag, void* dA,
                        void* dB, void* hip_stream) {
-    (void)dL_du0_dev;
-    (void)dx0;
-    (void)dQdiag;
-    (void)dRdiag;
-    (void)dA;
-    (void)dB;
-    (void)hip_stream;
     if (!ctx) return PIMPC_E_ARG;
-    return ctx->fail(PIMPC_E_STATE, "no taped forward is available (ckpt_every = 0)");
+    if (ctx->opt.ckpt_every <= 0 || !ctx->taped)
+        return ctx->fail(PIMPC_E_STATE, "no taped forward is available (needs ckpt_every > 0 and a solve first)");
+    if (!dL_du0_dev) return ctx->fail(PIMPC_E_ARG, "dL_du0_dev is required");
+    const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    const int ncls = (int)ctx->bwd_runs.size();
+    if (ncls > 0) HIPCHK(ctx, launch_fill<int32_t>(ctx->d_bwd_counters, ncls, 0, s));
+    for (int c = 0; c < ncls; ++c) {
+        const ClassRun& r = ctx->bwd_runs[c];
+        BwdArgs a;
+        memset(&a, 0, sizeof(a));
+        a.inst = ctx->d_inst;
+        a.bins = ctx->d_bwd_bins + r.bin_first;
+        a.nbins = r.nbins;
+        a.bin_counter = ctx->d_bwd_counters + c;
+        a.mats = (const float*)ctx->d_mats;
+        a.ckpt = (const float*)ctx->d_ckpt;
+        a.tape = ctx->d_tape;
+        a.grads = ctx->d_grads;
+        a.x0 = (const float*)ctx->tape_x0;
+        a.uprev = (const float*)ctx->tape_up;
+        a.dLdu0 = (const float*)dL_du0_dev;
+        a.rho = ctx->opt.rho;
+        a.K = ctx->opt.max_iter;
+        a.ckpt_every = ctx->opt.ckpt_every;
+        const int grid = std::max(1, std::min(r.nbins, ctx->num_cus));
+        bool handled = false;
+        HIPCHK(ctx, launch_backward_class(r.cls, a, grid, s, &handled));
+        if (!handled) return ctx->fail(PIMPC_E_UNSUPPORTED, "class %d has no backward kernel", r.cls);
+    }
+    HIPCHK(ctx, launch_chain(ctx->d_inst, ctx->count, ctx->d_mats64, ctx->d_grads, ctx->opt.rho, (float*)dx0,
+                             (float*)dQdiag, (float*)dRdiag, (float*)dA, (float*)dB, s));
+    return PIMPC_OK;
 }
 
 static int iter_io(pimpc_ctx ctx, int32_t which, double* out, const double* in) {

@@ -261,6 +261,8 @@ class Solver:
         self.count = len(self.problems)
         self.sum_nx = sum(p.nx for p in self.problems)
         self.sum_nu = sum(p.nu for p in self.problems)
+        self.nx = self.problems[0].nx
+        self.nu = self.problems[0].nu
 
     def solve(self, x0=None, u_prev=None):
         """x0/u_prev: packed arrays (default: each problem's own); returns
