@@ -27,6 +27,21 @@ PEAK_HBM = 8.0e12           # bytes/s
 METRIC = "ADMM stage-iterations/s (N=1024; 4096-batch) + fwd+bwd time vs plain"
 
 
+def measured_traffic():
+    """HBM bytes per launch of the row kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs (scaled by the copy calibration), or None if
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "row_kernel_long_horizon_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2601_14414_amd", "csrc", "admm_row.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def stage_flops(nx: int, nu: int) -> int:
     """Algorithmic flops of one stage-iteration of eqn. (8): 2 F(nx, nu) for
     the mat-vecs (F = nb^2 + nu nb + 2 nx^2 + 3 nx nu FMAs) plus 25 nb for the
@@ -137,7 +152,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
@@ -177,7 +203,7 @@ def main():
                                "factorisation at setup, x0 ~ U[-2,2] seed 0",
                    "N": p.N, "nx": p.nx, "nu": p.nu, "iterations": p.K, "instances": 1},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
                      "kernel": "row_kernel (one solve = one launch)",
                      "flops_per_launch": flops_per_launch, "avg_launch_ms": step_ms},
         "residuals": {"c": float(rec["c"]), "r_prim": float(rec["r_prim"]), "r_dual": float(rec["r_dual"])},
