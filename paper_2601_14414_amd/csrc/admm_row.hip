@@ -6,16 +6,29 @@
 // nu = 11, N = 1024), where one lane per stage would leave most of the chip
 // idle:
 //   * a wave owns a block of S consecutive stages; lane r owns row r of
-//     every stage vector (v, z, theta, beta, lambda, du, xbar, g);
-//   * lane r keeps row r of H, J, [A B] and column r of [A B] in VGPRs for
-//     the whole solve (time-invariant data), so every mat-vec is NB FMAs per
-//     lane with the input vector broadcast from a per-wave LDS buffer;
-//   * a block needs, per iteration, only its neighbours' previous iterate:
-//     the right block's first stage (z, v, lambda) gives g of the stage after
-//     the block, and the left block's last stage (z, theta) lets the block
-//     recompute xbar_k of the stage before it.  So each iteration has ONE
-//     halo exchange, sent at the end of the iteration and awaited at the start
-//     of the next one;
+//     every stage vector;
+//   * the iteration is evaluated in an algebraically equivalent "fused" form
+//     whose only dependence on a neighbouring stage is ONE vector each way:
+//       with w_k = z_k - v_k - ebar + lambda_k and d_k = z_k - theta_k of the
+//       iterate entering the step (so g_k = Abar' w_k, h_k = qbar + rho (d_k + g_{k+1})),
+//       b_k      = beta_k + (Bbar J) (v_k - beta_k)                       [= Bbar du_k + beta_k]
+//       xbar_k+1 = H q + rho H d_k + rho (H Abar') w_{k+1}                 [= H_k h_k]
+//       c_k      = (Abar H q + ebar) + rho (Abar H) d_{k-1}
+//                  + rho (Abar H Abar') w_k - lambda_k                     [= Abar xbar_k + ebar - lambda_k]
+//     with c_0 = Abar xbar_0 + ebar - lambda_0 and xbar_N = H_{N-1} (q + rho d_{N-1});
+//     the products B J, H Abar', Abar H, Abar H Abar', H q, H_{N-1} q and
+//     Abar H q + ebar are formed once per factorisation, in FP64
+//     (row_fuse_kernel), and rounded once;
+//   * so a block needs, per iteration, only w of the stage after it and d of
+//     the stage before it: each wave sends w of its first stage to the left
+//     and d of its last stage to the right at the end of an iteration, and
+//     after the wait only two dot products (one per halo) and the
+//     elementwise update remain on the critical path; everything else of
+//     the step runs while the halos are in flight;
+//   * lane r keeps row r of H, H Abar' and Abar H in VGPRs and row r of
+//     B J, Abar H Abar' and column r of [A B] in LDS (lane-private, float4
+//     interleaved, conflict free); dot-product inputs are broadcast through
+//     a per-wave LDS buffer;
 //   * halos travel as 64-bit words (32-bit value, 32-bit tag = iteration), in
 //     LDS between waves of a workgroup and in global memory (agent-scope
 //     relaxed atomics, no fences needed: every word carries its own tag)
@@ -28,44 +41,69 @@
 #include <hip/hip_runtime.h>
 
 #include "pimpc_row.hpp"
+#include "lane_common.hpp"
 
 namespace pimpc {
 
 namespace {
 
 constexpr int kSpinLimit = 1 << 22;  // polls before a wait gives up (seconds at worst)
+constexpr int kMboxVecs = 3;         // per buffer: w (to the left), d (to the right), dd (to the left)
 
-// Scratch layout of one row-family instance (16-byte aligned pieces):
-//   abort flag (int), reduction tags, decision word, per-wave partials,
-//   global mailboxes: per wave, right_out [2 buf][2 vec][NBP] and
-//   left_out [2 buf][4 vec][NBP] 64-bit words.
+// Scratch of one row-family instance (16-byte aligned pieces).  The first
+// part is cleared before every solve: abort flag, reduction tags, per-wave
+// partials, decision word, global mailboxes [nwaves][2 buf][3 vec][NBP]
+// (64-bit words).  The second part holds the fused stage data, written at
+// factorisation time.
+// Device pointers carry the global address space, so that every access is a
+// global (not flat) instruction and never waits on the LDS counter.
 struct RowScratch {
-    int32_t* abort;
-    uint64_t* red_tag;   // [nwaves]
-    double* red_val;     // [nwaves][3]
-    uint64_t* decision;  // [1]
-    uint64_t* mbox;      // [nwaves][12][NBP]
+    gptr<int32_t> abort;
+    gptr<uint64_t> red_tag;   // [nwaves]
+    gptr<double> red_val;     // [nwaves][3]
+    gptr<uint64_t> decision;  // [1]
+    gptr<uint64_t> mbox;      // [nwaves][2][kMboxVecs][NBP]
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) / 16 * 16; }
 
-__host__ __device__ inline size_t row_scratch_size(int nwaves, int nbp) {
+__host__ __device__ inline size_t row_clear_size(int nwaves, int nbp) {
     return align16(16) + align16(8ull * nwaves) + align16(24ull * nwaves) + align16(16) +
-           align16(8ull * nwaves * 12 * nbp);
+           align16(8ull * nwaves * 2 * kMboxVecs * nbp);
 }
 
-__device__ inline RowScratch row_scratch(void* base, int nwaves, int nbp) {
-    char* p = (char*)base;
+// Fused block (floats): BJ | HAt | AH | AHAt  [NB][NB] row-major, then
+// Hq | Hbq | cq [NB].
+__host__ __device__ inline size_t row_fused_floats(int nbp) { return 4ull * nbp * nbp + 3ull * nbp; }
+
+struct FusedOffsets {
+    int BJ, HAt, AH, AHAt, Hq, Hbq, cq;
+};
+__host__ __device__ inline FusedOffsets fused_offsets(int NB) {
+    FusedOffsets f;
+    f.BJ = 0;
+    f.HAt = NB * NB;
+    f.AH = 2 * NB * NB;
+    f.AHAt = 3 * NB * NB;
+    f.Hq = 4 * NB * NB;
+    f.Hbq = f.Hq + NB;
+    f.cq = f.Hbq + NB;
+    return f;
+}
+
+__device__ inline RowScratch row_scratch(gptr<char> base, int nwaves, int nbp) {
+    gptr<char> p = base;
     RowScratch s;
-    s.abort = (int32_t*)p;
+    s.abort = (gptr<int32_t>)p;
     p += align16(16);
-    s.red_tag = (uint64_t*)p;
+    s.red_tag = (gptr<uint64_t>)p;
     p += align16(8ull * nwaves);
-    s.red_val = (double*)p;
+    s.red_val = (gptr<double>)p;
     p += align16(24ull * nwaves);
-    s.decision = (uint64_t*)p;
+    s.decision = (gptr<uint64_t>)p;
     p += align16(16);
-    s.mbox = (uint64_t*)p;
+    s.mbox = (gptr<uint64_t>)p;
+    (void)nbp;
     return s;
 }
 
@@ -75,10 +113,10 @@ __device__ inline uint64_t pack(float v, uint32_t tag) {
 __device__ inline float unpack_val(uint64_t w) { return __uint_as_float((uint32_t)w); }
 __device__ inline uint32_t unpack_tag(uint64_t w) { return (uint32_t)(w >> 32); }
 
-__device__ inline void gstore(uint64_t* p, uint64_t v) {
+__device__ inline void gstore(gptr<uint64_t> p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline uint64_t gload(uint64_t* p) {
+__device__ inline uint64_t gload(gptr<uint64_t> p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void lstore(uint64_t* p, uint64_t v) {
@@ -87,31 +125,6 @@ __device__ inline void lstore(uint64_t* p, uint64_t v) {
 __device__ inline uint64_t lload(uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-
-// Wait until *p carries `tag`; returns the value, or 0 after abort/timeout.
-// Every wait is bounded and also ends when another wave raised the abort flag.
-template <bool LDS>
-__device__ inline float wait_word(uint64_t* p, uint32_t tag, int32_t* abort_flag, bool* failed) {
-    int spins = 0;
-    for (;;) {
-        const uint64_t w = LDS ? lload(p) : gload(p);
-        if (unpack_tag(w) == tag) return unpack_val(w);
-        if ((++spins & 63) == 0) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                *failed = true;
-                return 0.f;
-            }
-            if (spins > kSpinLimit) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                *failed = true;
-                return 0.f;
-            }
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-}
-__device__ inline float wait_lds(uint64_t* p, uint32_t tag, int32_t* ab, bool* f) { return wait_word<true>(p, tag, ab, f); }
-__device__ inline float wait_glb(uint64_t* p, uint32_t tag, int32_t* ab, bool* f) { return wait_word<false>(p, tag, ab, f); }
 
 __device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
 
@@ -128,23 +141,113 @@ __device__ inline T wmax(T v) {
     return v;
 }
 
+constexpr int kFuseMax = 48;  // largest padded stage size of the row family
+
 }  // namespace
 
-// Kernel geometry: kRowWaves waves per workgroup.
+// Fused stage data of one time-invariant row-family instance, from the T
+// block (FP32 J, H, H_{N-1}, A, B, e, qbar) with FP64 accumulation:
+//   BJ = Bbar J, HAt = H Abar', AH = Abar H, AHAt = Abar H Abar',
+//   Hq = H qbar, Hbq = H_{N-1} qbar, cq = Abar H qbar + ebar.
+__global__ void __launch_bounds__(256) row_fuse_kernel(const InstDev* __restrict__ inst, int inst_idx,
+                                                       const float* __restrict__ mats, float* __restrict__ fused) {
+    __shared__ double Ab[kFuseMax * kFuseMax];
+    __shared__ double Hs[kFuseMax * kFuseMax];
+    __shared__ double AHs[kFuseMax * kFuseMax];
+    const InstDev I = inst[inst_idx];
+    const int NX = I.nxp, NU = I.nup, NB = I.nbp;
+    if (NB > kFuseMax) return;  // host side never launches such a shape
+    const MatOffsets o = mat_offsets(NX, NU, I.N, 0);
+    const float* bt = mats + I.mat_off;
+    const FusedOffsets f = fused_offsets(NB);
+    const int t = threadIdx.x;
+    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+        const int r = idx / NB, c = idx % NB;
+        double a;
+        if (r < NX)
+            a = (c < NX) ? (double)bt[o.A + r * NX + c] : (double)bt[o.B + r * NU + (c - NX)];
+        else
+            a = (r == c) ? 1.0 : 0.0;
+        Ab[idx] = a;
+        Hs[idx] = (double)bt[o.H + idx];
+    }
+    __syncthreads();
+    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+        const int r = idx / NB, c = idx % NB;
+        double bj = 0.0, hat = 0.0, ah = 0.0;
+        for (int u = 0; u < NU; ++u) {
+            const double bb = (r < NX) ? (double)bt[o.B + r * NU + u] : ((r - NX) == u ? 1.0 : 0.0);
+            bj += bb * (double)bt[o.J + u * NB + c];
+        }
+        for (int j = 0; j < NB; ++j) {
+            hat += Hs[r * NB + j] * Ab[c * NB + j];
+            ah += Ab[r * NB + j] * Hs[j * NB + c];
+        }
+        fused[f.BJ + idx] = (float)bj;
+        fused[f.HAt + idx] = (float)hat;
+        fused[f.AH + idx] = (float)ah;
+        AHs[idx] = ah;
+    }
+    __syncthreads();
+    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+        const int r = idx / NB, c = idx % NB;
+        double s = 0.0;
+        for (int j = 0; j < NB; ++j) s += AHs[r * NB + j] * Ab[c * NB + j];
+        fused[f.AHAt + idx] = (float)s;
+    }
+    for (int r = t; r < NB; r += blockDim.x) {
+        double hq = 0.0, hbq = 0.0, cq = 0.0;
+        for (int j = 0; j < NB; ++j) {
+            const double q = (double)bt[o.qbar + j];
+            hq += Hs[r * NB + j] * q;
+            hbq += (double)bt[o.Hb + r * NB + j] * q;
+            cq += AHs[r * NB + j] * q;
+        }
+        if (r < NX) cq += (double)bt[o.e + r];
+        fused[f.Hq + r] = (float)hq;
+        fused[f.Hbq + r] = (float)hbq;
+        fused[f.cq + r] = (float)cq;
+    }
+}
+
+// Kernel geometry: kRowWaves compute waves per workgroup, plus kRecvWaves
+// receiver waves that poll the global mailboxes of the two neighbouring
+// workgroups and forward each halo word into LDS.  Compute waves then never
+// load from global memory inside the iteration loop: their halo waits are
+// LDS polls, and a poll never sits behind their own outstanding stores (loads
+// and stores share one in-order counter on this architecture), so the halo
+// round trip overlaps the local part of the step.
 constexpr int kRowWaves = 4;
+constexpr int kRecvWaves = 2;
+constexpr int kRowThreads = 64 * (kRowWaves + kRecvWaves);
+
+// Dynamic LDS of one workgroup: per wave, the broadcast rows [3S + 2][NB + 4]
+// and the lane-private rows of the rows lanes (H, BJ, AHAt: NB each; column
+// of [A B]: NX) as float4 [(3 NB + NX) / 4][NB].
+__host__ __device__ constexpr size_t row_lds_bytes(int NX, int NU, int S) {
+    return (size_t)kRowWaves *
+           (4 * (3 * S + 2) * (NX + NU + 4) + 16 * (NX + NU) * ((3 * (NX + NU) + NX) / 4));
+}
+
+extern __shared__ __align__(16) float row_smem[];
 
 template <int NX, int NU, int S>
-__global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __restrict__ ap, int nwaves,
+__global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restrict__ ap, int nwaves,
                                                              int nwg) {
     constexpr int NB = NX + NU;
-    constexpr int LD = NB + 4;  // LDS row pitch of a broadcast vector (16-byte multiple)
+    constexpr int NB4 = NB / 4;
+    constexpr int NX4 = NX / 4;
+    constexpr int LD = NB + 4;       // LDS row pitch of a broadcast vector (16-byte multiple)
+    constexpr int NV = 3 * S + 2;    // broadcast rows: (p, d, w) per stage, then w_R, d_L
+    constexpr int RW = 3 * S;        // row of w_R
+    constexpr int RD = 3 * S + 1;    // row of d_L
     static_assert(NB <= 64, "row kernel needs nx + nu <= 64");
-    static_assert(LD % 4 == 0, "broadcast rows must stay 16-byte aligned");
+    static_assert(NB % 4 == 0 && NX % 4 == 0, "padded sizes must be multiples of 4");
     const RowArgs& a = *ap;
     const InstDev I = a.inst[a.inst_idx];
     const int N = I.N;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     // XCD-aware logical workgroup index: hardware workgroup h runs on XCD h % 8.
     int lwg = blockIdx.x;
     if (nwg % 8 == 0) lwg = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
@@ -152,49 +255,124 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
     const int k0 = gw * S;
     const int ns = max(0, min(S, N - k0));  // stages in this block
     const bool rowl = lane < NB;            // lane carries a (padded) row
-    const int r = lane;
+    const int r = rowl ? lane : 0;
     const float rho = (float)a.rho;
     const float third = 1.0f / 3.0f;
 
-    RowScratch sc = row_scratch((char*)a.scratch + (size_t)I.pad0 * 16, nwaves, NB);
+    const gptr<char> sbase = (gptr<char>)((char*)a.scratch + (size_t)I.pad0 * 16);
+    RowScratch sc = row_scratch(sbase, nwaves, NB);
+    const gptr<const float> F = (gptr<const float>)(sbase + row_clear_size(N, NB));  // same offset as the host side
+    const FusedOffsets fo = fused_offsets(NB);
 
-    // per-wave broadcast rows: [S + 2][LD] (one row per vector of a round)
-    __shared__ __align__(16) float bcast[kRowWaves][S + 2][LD];
-    __shared__ uint64_t lmbox[kRowWaves][2][6][NB];  // intra-workgroup mailboxes
-    for (int i = threadIdx.x; i < kRowWaves * 2 * 6 * NB; i += blockDim.x) (&lmbox[0][0][0][0])[i] = 0;
-    __syncthreads();
-    if (gw >= nwaves) return;  // no workgroup barrier below this point
+    float(*bc)[LD] = (float(*)[LD])(row_smem + (size_t)wv * NV * LD);
+    float4* lrow = (float4*)(row_smem + (size_t)kRowWaves * NV * LD) + (size_t)wv * (3 * NB4 + NX4) * NB;
+#define LH(q) lrow[(q) * NB + r]
+#define LBJ(q) lrow[(NB4 + (q)) * NB + r]
+#define LAHAT(q) lrow[(2 * NB4 + (q)) * NB + r]
+#define LACOL(q) lrow[(3 * NB4 + (q)) * NB + r]
+    __shared__ uint64_t lmbox[kRowWaves][2][kMboxVecs][NB];  // intra-workgroup mailboxes
+    __shared__ uint64_t lin[2][2][NB];  // forwarded external halos: [buf][0: w from the right, 1: d from the left]
+    __shared__ int lstop;               // set by the compute waves when they leave the loop
+    for (int i = threadIdx.x; i < kRowWaves * 2 * kMboxVecs * NB; i += blockDim.x) (&lmbox[0][0][0][0])[i] = 0;
+    for (int i = threadIdx.x; i < 2 * 2 * NB; i += blockDim.x) (&lin[0][0][0])[i] = 0;
+    if (threadIdx.x == 0) lstop = 0;
+    __syncthreads();  // no workgroup barrier below this point
 
-    // ---- per-lane matrix rows (time-invariant data), padded entries are 0
+    if (wv >= kRowWaves) {
+        // ---- receiver wave: side 0 forwards w of the first stage of the right
+        // workgroup, side 1 forwards d of the last stage of the left one, for
+        // every tag the compute waves will consume (1 .. K)
+        const int side = wv - kRowWaves;
+        const int first = lwg * kRowWaves;
+        const int last = min(first + kRowWaves, nwaves) - 1;
+        const int src = side == 0 ? last + 1 : first - 1;
+        const bool has = side == 0 ? (last == first + kRowWaves - 1 && src < nwaves) : (first > 0);
+        if (!has || lane >= NB) return;
+        const int vec = side == 0 ? 0 : 1;
+        for (int t = 1; t <= a.K; ++t) {
+            const gptr<uint64_t> p = sc.mbox + ((size_t)(src * 2 + (t & 1)) * kMboxVecs + vec) * NB + lane;
+            int spins = 0;
+            for (;;) {
+                const uint64_t word = gload(p);
+                if (unpack_tag(word) == (uint32_t)t) {
+                    lstore(&lin[t & 1][side][lane], word);
+                    break;
+                }
+                if ((++spins & 31) == 0) {
+                    if (__hip_atomic_load(&lstop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0 ||
+                        __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                        return;
+                    if (spins > kSpinLimit) {
+                        __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        return;
+                    }
+                }
+            }
+        }
+        return;
+    }
+    if (gw >= nwaves) return;
+
+    // ---- per-lane stage data (time-invariant), padded entries are 0
     const MatOffsets o = mat_offsets(NX, NU, N, 0);
-    const float* M = (const float*)a.mats + I.mat_off;
-    float Hrow[NB], Jrow[NB], Arow[NB], Acol[NX], Brow[NU];
+    const gptr<const float> M = (gptr<const float>)((const float*)a.mats + I.mat_off);
+    float HAr[NB], AHr[NB];  // the two matrices of the halo terms stay in VGPRs
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-        Hrow[j] = rowl ? M[o.H + r * NB + j] : 0.f;
-        Jrow[j] = (r < NU) ? M[o.J + r * NB + j] : 0.f;
-        Arow[j] = (r < NX) ? (j < NX ? M[o.A + r * NX + j] : M[o.B + r * NU + (j - NX)]) : 0.f;
+        HAr[j] = rowl ? F[fo.HAt + r * NB + j] : 0.f;
+        AHr[j] = rowl ? F[fo.AH + r * NB + j] : 0.f;
     }
+    if (rowl) {
+        auto ld4 = [&](gptr<const float> p) { return make_float4(p[0], p[1], p[2], p[3]); };
 #pragma unroll
-    for (int i = 0; i < NX; ++i)  // column r of the top block [A B]
-        Acol[i] = rowl ? (r < NX ? M[o.A + i * NX + r] : M[o.B + i * NU + (r - NX)]) : 0.f;
+        for (int q = 0; q < NB4; ++q) {
+            LH(q) = ld4(M + o.H + r * NB + 4 * q);
+            LBJ(q) = ld4(F + fo.BJ + r * NB + 4 * q);
+            LAHAT(q) = ld4(F + fo.AHAt + r * NB + 4 * q);
+        }
+    }
+    // column r of the top block [A B] (rows i < NX)
+    auto acol = [&](int i) -> float {
+        return rowl ? (r < NX ? M[o.A + i * NX + r] : M[o.B + i * NU + (r - NX)]) : 0.f;
+    };
+    if (rowl) {
 #pragma unroll
-    for (int j = 0; j < NU; ++j) Brow[j] = (r < NX) ? M[o.B + r * NU + j] : 0.f;
-    const float e_r = (r < NX) ? M[o.e + r] : 0.f;
-    const float q_r = rowl ? M[o.qbar + r] : 0.f;
+        for (int q = 0; q < NX4; ++q) LACOL(q) = make_float4(acol(4 * q + 0), acol(4 * q + 1), acol(4 * q + 2), acol(4 * q + 3));
+    }
+    const float e_r = (rowl && r < NX) ? M[o.e + r] : 0.f;  // ebar_r
     const float lb_r = rowl ? M[o.lb + r] : 0.f;
     const float ub_r = rowl ? M[o.ub + r] : 0.f;
     const float hbd_r = rowl ? M[o.Hb + r * NB + r] : 0.f;
+    const float Hq_r = rowl ? F[fo.Hq + r] : 0.f;
+    const float Hbq_r = rowl ? F[fo.Hbq + r] : 0.f;
+    const float cq_r = rowl ? F[fo.cq + r] : 0.f;
     const bool hb_diag = I.hb_diag != 0;
     const bool owns_last = ns > 0 && k0 + ns == N;  // block holds stage N-1 (uses H_{N-1})
 
-    float xb0_r = 0.f;  // row r of xbar_0 = col(x(t), u(t-1))
-    if (r < NX && r < I.nx) xb0_r = ((const float*)a.x0)[I.x_off + r];
-    if (r >= NX && r - NX < I.nu && a.uprev) xb0_r = ((const float*)a.uprev)[I.u_off + r - NX];
+    // c_0 = Abar xbar_0 + ebar (stage 0 only), xbar_0 = col(x(t), u(t-1))
+    float c0_r = 0.f;
+    if (k0 == 0 && ns > 0) {
+        float xb0 = 0.f;
+        if (rowl && r < NX && r < I.nx) xb0 = ((const float*)a.x0)[I.x_off + r];
+        if (rowl && r >= NX && r - NX < I.nu && a.uprev) xb0 = ((const float*)a.uprev)[I.u_off + r - NX];
+        if (rowl) bc[0][r] = xb0;
+        __builtin_amdgcn_wave_barrier();
+        if (rowl) {
+            float s = e_r;
+            if (r < NX) {
+#pragma unroll
+                for (int j = 0; j < NB; ++j) s += (j < NX ? M[o.A + r * NX + j] : M[o.B + r * NU + (j - NX)]) * bc[0][j];
+            } else {
+                s = xb0;
+            }
+            c0_r = s;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 
     // ---- iterate rows of the S stages
-    float v[S], z[S], th[S], be[S], la[S], du[S], xs[S], g[S];
-    float* st = (float*)a.state + I.st_off;
+    float v[S], z[S], th[S], be[S], la[S], pv[S], xs[S];
+    const gptr<float> st = (gptr<float>)((float*)a.state + I.st_off);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const bool ld = a.warm && rowl && s < ns;
@@ -204,214 +382,188 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
         th[s] = ld ? st[(size_t)(2 * NB + r) * N + k] : 0.f;
         be[s] = ld ? st[(size_t)(3 * NB + r) * N + k] : 0.f;
         la[s] = ld ? st[(size_t)(4 * NB + r) * N + k] : 0.f;
-        du[s] = 0.f;
+        pv[s] = 0.f;
         xs[s] = 0.f;
-        g[s] = 0.f;
     }
 
     const bool has_left = ns > 0 && k0 > 0;
     const bool has_right = ns > 0 && k0 + ns < N;
     const bool left_in_wg = wv > 0;
     const bool right_in_wg = wv < kRowWaves - 1;
+    auto mbox_g = [&](int wave, int buf, int vec) -> gptr<uint64_t> {
+        return sc.mbox + ((size_t)(wave * 2 + buf) * kMboxVecs + vec) * NB + r;
+    };
     auto put = [&](bool in_wg, int buf, int vec, uint64_t word) {
         if (in_wg)
             lstore(&lmbox[wv][buf][vec][r], word);
         else
-            gstore(sc.mbox + ((size_t)gw * 12 + buf * 6 + vec) * NB + r, word);
+            gstore(mbox_g(gw, buf, vec), word);
     };
     bool failed = false;
-    auto recv = [&](int nl, int ng, bool in_wg, int vec, uint32_t tag) -> float {
-        if (!rowl) return 0.f;
-        const int buf = tag & 1;
-        if (in_wg) return wait_lds(&lmbox[nl][buf][vec][r], tag, sc.abort, &failed);
-        return wait_glb(sc.mbox + ((size_t)ng * 12 + buf * 6 + vec) * NB + r, tag, sc.abort, &failed);
-    };
-    // left_out (z, v, lambda[, dd]) of the first stage, read by wave gw-1
-    auto publish_left = [&](uint32_t tag, bool with_dd, float dd0) {
-        if (!has_left || !rowl) return;
-        const int buf = tag & 1;
-        put(left_in_wg, buf, 0, pack(z[0], tag));
-        put(left_in_wg, buf, 1, pack(v[0], tag));
-        put(left_in_wg, buf, 2, pack(la[0], tag));
-        if (with_dd) put(left_in_wg, buf, 3, pack(dd0, tag));
-    };
-    // right_out (z, theta) of the last stage, read by wave gw+1
-    auto publish_right = [&](uint32_t tag) {
-        if (!has_right || !rowl) return;
-        const int buf = tag & 1;
-        float zl = z[0], tl = th[0];
+    // Stage vectors of the iterate: w = z - v - ebar + lambda, d = z - theta.
+    auto wvec = [&](int s) { return z[s] - v[s] - e_r + la[s]; };
+    auto dvec = [&](int s) { return z[s] - th[s]; };
+    auto last_of = [&](float* x) {
+        float y = x[0];
 #pragma unroll
         for (int s = 1; s < S; ++s)
-            if (s == ns - 1) {
-                zl = z[s];
-                tl = th[s];
-            }
-        put(right_in_wg, buf, 4, pack(zl, tag));
-        put(right_in_wg, buf, 5, pack(tl, tag));
+            if (s == ns - 1) y = x[s];
+        return y;
+    };
+    // w of the first stage goes left, d of the last stage goes right
+    auto publish = [&](uint32_t tag) {
+        if (!rowl) return;
+        const int buf = tag & 1;
+        if (has_left) put(left_in_wg, buf, 0, pack(wvec(0), tag));
+        if (has_right) {
+            float zl = z[0], tl = th[0];
+#pragma unroll
+            for (int s = 1; s < S; ++s)
+                if (s == ns - 1) {
+                    zl = z[s];
+                    tl = th[s];
+                }
+            put(right_in_wg, buf, 1, pack(zl - tl, tag));
+        }
     };
 
-    float(*bc)[LD] = bcast[wv];
-    // Write this lane's row of up to S + 2 vectors, then make them visible to
-    // the wave (LDS operations of one wave complete in order).
-#define BC_PUT(row, val)                  \
-    do {                                  \
-        if (rowl) bc[(row)][r] = (val);   \
-    } while (0)
-#define BC_SYNC() __builtin_amdgcn_wave_barrier()
-#define DOT(acc, coef, row, n)                                  \
-    _Pragma("unroll") for (int j_ = 0; j_ < (n); ++j_) (acc) += (coef)[j_] * bc[(row)][j_];
-
-    publish_left(1u, false, 0.f);  // initial iterate carries tag 1
-    publish_right(1u);
+    publish(1u);  // the initial iterate carries tag 1
+    // Let every load of the set-up complete here, so the loop header does not
+    // carry a wait for them (which, inside the loop, would also wait for the
+    // previous iteration's halo stores).
+    __builtin_amdgcn_s_waitcnt(0);
 
     int iters = 0;
     double c_last = 0.0, rp_last = 0.0, rd_last = 0.0;
     int status = 0;
     bool stop = false;
 
-    // One update of stage s (steps 2-3) given its xbar_k row `xp`.
-    float cpart = 0.f, rpart = 0.f, rdpart = 0.f;
-    float ddv[S], dzv[S];
-    auto update = [&](int s, bool check) {
-        // round 3 inputs (xp, du) are already in bc rows 0 (xp) and 1 (du)
-        float ci = 0.f, bi = 0.f;
-        DOT(ci, Arow, 0, NB);
-        if (r >= NX) ci = bc[0][r];
-        ci += e_r - la[s];
-        DOT(bi, Brow, 1, NU);
-        if (r >= NX) bi = bc[1][r - NX];
-        bi += be[s];
-        const float gam = bi - ci;
-        const float y = (2.f * (xs[s] + th[s]) + bi + ci) * third;
-        const float zn = y < lb_r ? lb_r : (y > ub_r ? ub_r : y);
-        const float vn = (zn + gam) * 0.5f;
-        const float thn = th[s] + xs[s] - zn;
-        const float ben = bi - vn;
-        const float lan = zn - vn - ci;
-        if (check) {
-            const float dv = rowl ? vn - v[s] : 0.f, dz = rowl ? zn - z[s] : 0.f;
-            const float dth = rowl ? thn - th[s] : 0.f, dbe = rowl ? ben - be[s] : 0.f;
-            const float dla = rowl ? lan - la[s] : 0.f;
-            const float dd = dz - dv;
-            cpart += dth * dth + dbe * dbe + dla * dla + dz * dz + dv * dv + dd * dd;
-            rpart = fmax(rpart, fmax(fabsf(dth), fmax(fabsf(dbe), fabsf(dla))));
-#pragma unroll
-            for (int t = 0; t < S; ++t)
-                if (t == s) {
-                    ddv[t] = dd;
-                    dzv[t] = dz;
-                }
-            // du block of F'G dq: Bbar' dv = u-rows of Abar' dv
-            BC_PUT(2, dv);
-            BC_SYNC();
-            float bt = (r >= NX) ? dv : 0.f;
-            DOT(bt, Acol, 2, NX);
-            if (r >= NX && rowl) rdpart = fmax(rdpart, fabsf(bt));
-        }
-        if (rowl) {
-            v[s] = vn;
-            z[s] = zn;
-            th[s] = thn;
-            be[s] = ben;
-            la[s] = lan;
-        }
-    };
-
 #pragma unroll 1
     for (int it = 0; it < a.K && !stop; ++it) {
         const uint32_t tin = (uint32_t)it + 1;   // tag of the iterate this step reads
         const uint32_t tout = (uint32_t)it + 2;  // tag of the iterate it produces
         const bool check = (a.eps > 0.0 && ((it + 1) % a.check_every) == 0) || (it == a.K - 1);
-        cpart = rpart = rdpart = 0.f;
-#pragma unroll
-        for (int s = 0; s < S; ++s) ddv[s] = dzv[s] = 0.f;
 
-        // ---- round 1 (own data only): du_s = J (v - beta), g_s = Abar' (z - v - ebar + lambda)
+        // ---- halo mailboxes of the iterate entering this step (LDS only): w of
+        // the stage after the block, d of the stage before it, from the
+        // neighbouring wave or, across workgroups, as forwarded by a receiver
+        const int hbuf = tin & 1;
+        uint64_t* pr = right_in_wg ? &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][hbuf][0][r] : &lin[hbuf][0][r];
+        uint64_t* pl = left_in_wg ? &lmbox[wv > 0 ? wv - 1 : 0][hbuf][1][r] : &lin[hbuf][1][r];
+        uint64_t wr = 0, wl = 0;
+        auto poll = [&]() {
+            if (has_right) wr = lload(pr);
+            if (has_left) wl = lload(pl);
+        };
+
+        // ---- local part of the step (no halo needed)
+        float bb[S], xl[S], cl[S];
+        if (rowl) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s < ns) {
-                BC_PUT(0, v[s] - be[s]);
-                BC_PUT(1, z[s] - v[s] - e_r + la[s]);
-                BC_SYNC();
-                float acc = 0.f;
-                DOT(acc, Jrow, 0, NB);
-                du[s] = acc;
-                float gg = (r >= NX) ? bc[1][r] : 0.f;
-                DOT(gg, Acol, 1, NX);
-                g[s] = gg;
-                BC_SYNC();
-            }
-        }
-        // ---- round 2 for stages whose g_{k+1} is inside the block
-#pragma unroll
-        for (int s = 0; s + 1 < S; ++s) {
-            if (s + 1 < ns) {
-                float gn = g[0];
-#pragma unroll
-                for (int t = 1; t < S; ++t)
-                    if (t == s + 1) gn = g[t];
-                BC_PUT(0, q_r + rho * (z[s] - th[s] + gn));
-                BC_SYNC();
-                float acc = 0.f;
-                DOT(acc, Hrow, 0, NB);
-                xs[s] = acc;
-                BC_SYNC();
-            }
-        }
-        // ---- round 3 for interior stages 1 .. ns-2 (xbar_k of the previous stage is inside)
-#pragma unroll
-        for (int s = 1; s + 1 < S; ++s) {
-            if (s + 1 < ns) {
-                float xp = xs[0], dus = du[0];
-#pragma unroll
-                for (int t = 1; t < S; ++t) {
-                    if (t == s - 1) xp = xs[t];
-                    if (t == s) dus = du[t];
+            for (int s = 0; s < S; ++s) {
+                if (s < ns) {
+                    bc[3 * s + 0][r] = v[s] - be[s];
+                    bc[3 * s + 1][r] = dvec(s);
+                    bc[3 * s + 2][r] = wvec(s);
                 }
-                BC_PUT(0, xp);
-                BC_PUT(1, dus);
-                BC_SYNC();
-                update(s, check);
-                BC_SYNC();
             }
         }
+        __builtin_amdgcn_wave_barrier();
+        if (rowl) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (s < ns) {
+                    const int k = k0 + s;
+                    float ab0 = 0.f, ab1 = 0.f, ah0 = 0.f, ah1 = 0.f, ac0 = 0.f, ac1 = 0.f;
+                    // all operands come from LDS; a partly unrolled loop keeps
+                    // the scheduler from hoisting every load (VGPR pressure)
+#pragma unroll 3
+                    for (int q = 0; q < NB4; ++q) {
+                        const float4 p4 = *(const float4*)&bc[3 * s + 0][4 * q];
+                        const float4 d4 = *(const float4*)&bc[3 * s + 1][4 * q];
+                        const float4 w4 = *(const float4*)&bc[3 * s + 2][4 * q];
+                        const float4 g = LBJ(q);
+                        const float4 m = LAHAT(q);
+                        const float4 h = LH(q);
+                        ab0 += g.x * p4.x;
+                        ab1 += g.y * p4.y;
+                        ab0 += g.z * p4.z;
+                        ab1 += g.w * p4.w;
+                        ah0 += h.x * d4.x;
+                        ah1 += h.y * d4.y;
+                        ah0 += h.z * d4.z;
+                        ah1 += h.w * d4.w;
+                        ac0 += m.x * w4.x;
+                        ac1 += m.y * w4.y;
+                        ac0 += m.z * w4.z;
+                        ac1 += m.w * w4.w;
+                    }
+                    bb[s] = be[s] + (ab0 + ab1);
+                    if (k == N - 1) {
+                        // xbar_N = H_{N-1} (q + rho d)
+                        float hb = 0.f;
+                        if (hb_diag) {
+                            hb = hbd_r * bc[3 * s + 1][r];
+                        } else {
+                            const gptr<const float> Hb = M + o.Hb + r * NB;
+#pragma unroll
+                            for (int j = 0; j < NB; ++j) hb += Hb[j] * bc[3 * s + 1][j];
+                        }
+                        xl[s] = Hbq_r + rho * hb;
+                    } else {
+                        xl[s] = Hq_r + rho * (ah0 + ah1);
+                    }
+                    cl[s] = (k == 0) ? c0_r - la[s] : cq_r + rho * (ac0 + ac1) - la[s];
+                } else {
+                    bb[s] = xl[s] = cl[s] = 0.f;
+                }
+            }
+            // neighbours inside the block
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (s + 1 < ns) {  // xbar_{k+1} += rho (H Abar') w_{k+1}
+                    float x0 = 0.f, x1 = 0.f;
+#pragma unroll
+                    for (int q = 0; q < NB4; ++q) {
+                        const float4 w4 = *(const float4*)&bc[3 * (s + 1) + 2][4 * q];
+                        x0 += HAr[4 * q + 0] * w4.x;
+                        x1 += HAr[4 * q + 1] * w4.y;
+                        x0 += HAr[4 * q + 2] * w4.z;
+                        x1 += HAr[4 * q + 3] * w4.w;
+                    }
+                    xl[s] += rho * (x0 + x1);
+                }
+                if (s >= 1 && s < ns) {  // c_k += rho (Abar H) d_{k-1}
+                    float x0 = 0.f, x1 = 0.f;
+#pragma unroll
+                    for (int q = 0; q < NB4; ++q) {
+                        const float4 d4 = *(const float4*)&bc[3 * (s - 1) + 1][4 * q];
+                        x0 += AHr[4 * q + 0] * d4.x;
+                        x1 += AHr[4 * q + 1] * d4.y;
+                        x0 += AHr[4 * q + 2] * d4.z;
+                        x1 += AHr[4 * q + 3] * d4.w;
+                    }
+                    cl[s] += rho * (x0 + x1);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) bb[s] = xl[s] = cl[s] = 0.f;
+        }
 
-        // ---- halos of the previous iterate (needed only by the block's end stages).
-        // All five words are loaded together each poll, so a poll costs one
-        // memory round trip whatever the number of words.
-        float zR = 0.f, vR = 0.f, lR = 0.f, zL = 0.f, tL = 0.f;
+        // ---- halos of the iterate entering this step: w of the stage after
+        // the block, d of the stage before it.  Both words are loaded together
+        // each poll, so a poll costs one memory round trip.
+        float wR = 0.f, dL = 0.f;
         if ((has_right || has_left) && rowl) {
-            const int buf = tin & 1;
-            uint64_t* pr[3];
-            uint64_t* pl[2];
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                pr[q] = right_in_wg ? &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][buf][q][r]
-                                    : sc.mbox + ((size_t)(gw + 1) * 12 + buf * 6 + q) * NB + r;
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-                pl[q] = left_in_wg ? &lmbox[wv > 0 ? wv - 1 : 0][buf][4 + q][r]
-                                   : sc.mbox + ((size_t)(gw > 0 ? gw - 1 : 0) * 12 + buf * 6 + 4 + q) * NB + r;
             int spins = 0;
+            poll();
             for (;;) {
-                uint64_t wr[3] = {0, 0, 0}, wl[2] = {0, 0};
-                if (has_right) {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) wr[q] = right_in_wg ? lload(pr[q]) : gload(pr[q]);
-                }
-                if (has_left) {
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) wl[q] = left_in_wg ? lload(pl[q]) : gload(pl[q]);
-                }
-                const bool okr = !has_right || (unpack_tag(wr[0]) == tin && unpack_tag(wr[1]) == tin &&
-                                                 unpack_tag(wr[2]) == tin);
-                const bool okl = !has_left || (unpack_tag(wl[0]) == tin && unpack_tag(wl[1]) == tin);
+                const bool okr = !has_right || unpack_tag(wr) == tin;
+                const bool okl = !has_left || unpack_tag(wl) == tin;
                 if (okr && okl) {
-                    zR = unpack_val(wr[0]);
-                    vR = unpack_val(wr[1]);
-                    lR = unpack_val(wr[2]);
-                    zL = unpack_val(wl[0]);
-                    tL = unpack_val(wl[1]);
+                    wR = unpack_val(wr);
+                    dL = unpack_val(wl);
                     break;
                 }
                 if ((++spins & 31) == 0) {
@@ -426,84 +578,122 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
                     }
                 }
                 __builtin_amdgcn_s_sleep(1);
+                poll();
             }
         }
         if (__builtin_amdgcn_readfirstlane((int)failed) || wave_any(failed)) {
             status = -5;
             break;
         }
-        // g of the stage after the block (right halo)
-        float gR = 0.f;
-        if (has_right) {
-            BC_PUT(0, zR - vR - e_r + lR);
-            BC_SYNC();
-            gR = (r >= NX) ? bc[0][r] : 0.f;
-            DOT(gR, Acol, 0, NX);
-            BC_SYNC();
+        // ---- halo terms: xbar of the last stage and c of the first stage
+        if (rowl) {
+            bc[RW][r] = wR;
+            bc[RD][r] = dL;
         }
-        // ---- round 2 for the last stage (needs gR) and xbar_{k0} from the left halo
-        const int sl = ns - 1;  // last stage of the block
-        float hlast = 0.f, xlast = 0.f;
-        {
-            float zl = z[0], tl = th[0];
+        __builtin_amdgcn_wave_barrier();
+        if (rowl && (has_right || has_left)) {
+            float x0 = 0.f, x1 = 0.f, y0 = 0.f, y1 = 0.f;
+            float4 wq[NB4], dq[NB4];  // all broadcast reads in flight at once
 #pragma unroll
-            for (int t = 1; t < S; ++t)
-                if (t == sl) {
-                    zl = z[t];
-                    tl = th[t];
+            for (int q = 0; q < NB4; ++q) {
+                wq[q] = *(const float4*)&bc[RW][4 * q];
+                dq[q] = *(const float4*)&bc[RD][4 * q];
+            }
+#pragma unroll
+            for (int q = 0; q < NB4; ++q) {
+                const float4 w4 = wq[q];
+                const float4 d4 = dq[q];
+                x0 += HAr[4 * q + 0] * w4.x;
+                y0 += AHr[4 * q + 0] * d4.x;
+                x1 += HAr[4 * q + 1] * w4.y;
+                y1 += AHr[4 * q + 1] * d4.y;
+                x0 += HAr[4 * q + 2] * w4.z;
+                y0 += AHr[4 * q + 2] * d4.z;
+                x1 += HAr[4 * q + 3] * w4.w;
+                y1 += AHr[4 * q + 3] * d4.w;
+            }
+            if (has_right) {
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (s == ns - 1) xl[s] += rho * (x0 + x1);
+            }
+            if (has_left) cl[0] += rho * (y0 + y1);
+        }
+
+        // ---- steps 2-3 (Theorem 1 closed form, box projection, dual update)
+        float cpart = 0.f, rpart = 0.f;
+        float ddv[S], dzv[S], dvv[S];
+        if (rowl) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                ddv[s] = dzv[s] = dvv[s] = 0.f;
+                if (s < ns) {
+                    const float bi = bb[s], ci = cl[s], xi = xl[s];
+                    const float gam = bi - ci;
+                    const float y = (2.f * (xi + th[s]) + bi + ci) * third;
+                    const float zn = y < lb_r ? lb_r : (y > ub_r ? ub_r : y);
+                    const float vn = (zn + gam) * 0.5f;
+                    const float thn = th[s] + xi - zn;
+                    const float ben = bi - vn;
+                    const float lan = zn - vn - ci;
+                    if (check) {
+                        const float dv = vn - v[s], dz = zn - z[s];
+                        const float dth = thn - th[s], dbe = ben - be[s], dla = lan - la[s];
+                        const float dd = dz - dv;
+                        cpart += dth * dth + dbe * dbe + dla * dla + dz * dz + dv * dv + dd * dd;
+                        rpart = fmax(rpart, fmax(fabsf(dth), fmax(fabsf(dbe), fabsf(dla))));
+                        ddv[s] = dd;
+                        dzv[s] = dz;
+                        dvv[s] = dv;
+                    }
+                    pv[s] = bc[3 * s + 0][r];
+                    xs[s] = xi;
+                    v[s] = vn;
+                    z[s] = zn;
+                    th[s] = thn;
+                    be[s] = ben;
+                    la[s] = lan;
                 }
-            hlast = q_r + rho * (zl - tl + gR);
-            BC_PUT(0, hlast);
-            if (has_left) BC_PUT(1, q_r + rho * (zL - tL + g[0]));
-            BC_SYNC();
-            if (owns_last && hb_diag) {
-                xlast = hbd_r * hlast;
-            } else if (owns_last) {
-                const float* Hb = M + o.Hb + (rowl ? r : 0) * NB;
-#pragma unroll
-                for (int j = 0; j < NB; ++j) xlast += (rowl ? Hb[j] : 0.f) * bc[0][j];
-            } else {
-                DOT(xlast, Hrow, 0, NB);
             }
-            float xsL = xb0_r;
-            if (has_left) {
-                xsL = 0.f;
-                DOT(xsL, Hrow, 1, NB);
-            }
-            BC_SYNC();
+        } else {
 #pragma unroll
-            for (int t = 0; t < S; ++t)
-                if (t == sl) xs[t] = xlast;
-            // ---- round 3 for the first stage (xp = xbar_{k0}) ...
-            BC_PUT(0, xsL);
-            BC_PUT(1, du[0]);
-            BC_SYNC();
-            update(0, check);
-            BC_SYNC();
+            for (int s = 0; s < S; ++s) ddv[s] = dzv[s] = dvv[s] = 0.f;
         }
-        publish_left(tout, false, 0.f);
-        // ... and for the last stage (xp = xbar of the stage before it)
-        if (sl > 0) {
-            float xp = xs[0], dus = du[0];
-#pragma unroll
-            for (int t = 1; t < S; ++t) {
-                if (t == sl - 1) xp = xs[t];
-                if (t == sl) dus = du[t];
-            }
-            BC_PUT(0, xp);
-            BC_PUT(1, dus);
-            BC_SYNC();
-            update(sl, check);
-            BC_SYNC();
-        }
-        publish_right(tout);
-        if (check) publish_left(tout, true, ddv[0]);  // dd of the first stage for the dual residual
+        publish(tout);
+        if (check && has_left && rowl) put(left_in_wg, tout & 1, 2, pack(ddv[0], tout));
         ++iters;
 
         if (check) {
-            // xbar block of F'G dq: dz_{k+1} + Abar_{k+1}' (dz_{k+2} - dv_{k+1})
+            // dual residual (Section IV-B): du block Bbar_k' dv_k and xbar block
+            // dz_{k+1} + Abar_{k+1}' (dz_{k+2} - dv_{k+1}); with the top rows of
+            // Abar' as column r of [A B]: (Abar' x)_r = [r >= NX] x_r + sum_i [A B]_{i r} x_i.
             float ddR = 0.f;
-            if (has_right) ddR = recv(wv + 1, gw + 1, right_in_wg, 3, tout);
+            if (has_right && rowl) {
+                uint64_t* lp = &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][tout & 1][2][r];
+                const gptr<uint64_t> gp = mbox_g(gw + 1 < nwaves ? gw + 1 : gw, tout & 1, 2);
+                int spins = 0;
+                for (;;) {
+                    uint64_t wd;
+                    if (right_in_wg)
+                        wd = lload(lp);
+                    else
+                        wd = gload(gp);
+                    if (unpack_tag(wd) == tout) {
+                        ddR = unpack_val(wd);
+                        break;
+                    }
+                    if ((++spins & 31) == 0) {
+                        if (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                            spins > kSpinLimit) {
+                            __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            failed = true;
+                            break;
+                        }
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            float rdpart = 0.f;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 if (s < ns) {
@@ -512,14 +702,29 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
                     for (int t = 1; t < S; ++t)
                         if (t == s + 1 && t < ns) ddn = ddv[t];
                     const bool hasnext = k0 + s + 1 < N;
-                    BC_PUT(0, ddn);
-                    BC_SYNC();
-                    float tg = (r >= NX) ? bc[0][r] : 0.f;
-                    DOT(tg, Acol, 0, NX);
-                    BC_SYNC();
-                    if (rowl) rdpart = fmax(rdpart, fabsf(dzv[s] + (hasnext ? tg : 0.f)));
+                    if (rowl) {
+                        bc[0][r] = dvv[s];
+                        bc[1][r] = ddn;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (rowl) {
+                        float bt = (r >= NX) ? dvv[s] : 0.f;
+                        float tg = (r >= NX) ? ddn : 0.f;
+#pragma unroll
+                        for (int q = 0; q < NX4; ++q) {
+                            const float4 c4 = LACOL(q);
+                            const float4 x4 = *(const float4*)&bc[0][4 * q];
+                            const float4 y4 = *(const float4*)&bc[1][4 * q];
+                            bt += c4.x * x4.x + c4.y * x4.y + c4.z * x4.z + c4.w * x4.w;
+                            tg += c4.x * y4.x + c4.y * y4.y + c4.z * y4.z + c4.w * y4.w;
+                        }
+                        if (r >= NX) rdpart = fmax(rdpart, fabsf(bt));
+                        rdpart = fmax(rdpart, fabsf(dzv[s] + (hasnext ? tg : 0.f)));
+                    }
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
+            if (!rowl) cpart = rpart = rdpart = 0.f;
             const double csum = wsum((double)cpart);
             const double rpm = wmax((double)rpart);
             const double rdm = wmax((double)rdpart);
@@ -600,7 +805,27 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
         }
     }
 
-    // ---- outputs
+    // leaving before K iterations (stop decision or failure): no compute wave
+    // of this workgroup consumes another halo, so the receivers may end too
+    if (iters < a.K && lane == 0) __hip_atomic_store(&lstop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+    // ---- outputs: final iterate; du_k = J_k (v_k - beta_k) and xbar_{k+1}
+    // of the last step 1
+    float du[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        du[s] = 0.f;
+        if (s < ns) {
+            if (rowl) bc[0][r] = pv[s];
+            __builtin_amdgcn_wave_barrier();
+            if (rowl && r < NU) {
+                float acc = 0.f;
+                for (int j = 0; j < NB; ++j) acc += M[o.J + r * NB + j] * bc[0][j];
+                du[s] = acc;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
     if (rowl) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -612,16 +837,16 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
                 st[(size_t)(3 * NB + r) * N + k] = be[s];
                 st[(size_t)(4 * NB + r) * N + k] = la[s];
                 if (a.write_iters) {
-                    float* io = (float*)a.iters_out + I.it_off;
+                    const gptr<float> io = (gptr<float>)((float*)a.iters_out + I.it_off);
                     if (r < NU) io[(size_t)r * N + k] = du[s];
                     io[(size_t)(NU + r) * N + k] = xs[s];
                 }
             }
         }
     }
-    if (k0 == 0 && ns > 0 && r < I.nu) {
-        const float up = a.uprev ? ((const float*)a.uprev)[I.u_off + r] : 0.f;
-        ((float*)a.u0)[I.u_off + r] = up + du[0];
+    if (k0 == 0 && ns > 0 && lane < I.nu) {
+        const float up = a.uprev ? ((const float*)a.uprev)[I.u_off + lane] : 0.f;
+        ((float*)a.u0)[I.u_off + lane] = up + du[0];
     }
     if (gw == 0 && lane == 0 && a.info) {
         InfoDev rec;
@@ -634,9 +859,10 @@ __global__ void __launch_bounds__(64 * kRowWaves) row_kernel(const RowArgs* __re
         rec.pad = 0;
         a.info[a.inst_idx] = rec;
     }
-#undef BC_PUT
-#undef BC_SYNC
-#undef DOT
+#undef LH
+#undef LBJ
+#undef LAHAT
+#undef LACOL
 }
 
 template <typename T>
@@ -653,10 +879,16 @@ constexpr RowCfg kRowCfgs[] = {{24, 12}, {32, 16}};
 
 template <int NX, int NU, int S>
 hipError_t row_launch_t(const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
-    if (occ) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, row_kernel<NX, NU, S>, 64 * kRowWaves, 0);
+    const size_t lds = row_lds_bytes(NX, NU, S);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)row_kernel<NX, NU, S>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
     }
-    hipLaunchKernelGGL((row_kernel<NX, NU, S>), dim3(nwg), dim3(64 * kRowWaves), 0, s, a_dev, nwaves, nwg);
+    if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, row_kernel<NX, NU, S>, kRowThreads, lds);
+    hipLaunchKernelGGL((row_kernel<NX, NU, S>), dim3(nwg), dim3(kRowThreads), lds, s, a_dev, nwaves, nwg);
     return hipGetLastError();
 }
 
@@ -709,7 +941,8 @@ bool row_supported(int nx, int nu, int N, int tv, int fp64, int* nxp, int* nup) 
 
 size_t row_scratch_bytes(const InstDev& I, int fp64) {
     (void)fp64;
-    return align16(row_scratch_size(I.N, I.nbp));  // sized for one stage per wave
+    // sized for one stage per wave, plus the fused stage data
+    return align16(row_clear_size(I.N, I.nbp)) + align16(4 * row_fused_floats(I.nbp));
 }
 
 // Choose the blocking S (stages per wave): the smallest S whose grid stays
@@ -730,11 +963,20 @@ hipError_t row_prepare(int fp64, InstDev& I) {
     return hipErrorInvalidConfiguration;
 }
 
+hipError_t launch_row_fuse(const InstDev* d_inst, int inst_idx, const InstDev& I, const void* mats,
+                           void* scratch_base, hipStream_t s) {
+    if (I.nbp > kFuseMax) return hipErrorInvalidValue;
+    char* scr = (char*)scratch_base + (size_t)I.pad0 * 16;
+    float* fused = (float*)(scr + row_clear_size(I.N, I.nbp));
+    hipLaunchKernelGGL(row_fuse_kernel, dim3(1), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats, fused);
+    return hipGetLastError();
+}
+
 hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, void* scratch_base, hipStream_t s) {
     (void)fp64;
     const int S = I.pad1 > 0 ? I.pad1 : 1;
     char* scr = (char*)scratch_base + (size_t)I.pad0 * 16;
-    hipError_t e = launch_fill<int32_t>((int32_t*)scr, (int64_t)(row_scratch_bytes(I, 0) / 4), 0, s);
+    hipError_t e = launch_fill<int32_t>((int32_t*)scr, (int64_t)(row_clear_size(I.N, I.nbp) / 4), 0, s);
     if (e != hipSuccess) return e;
     return row_launch_any(I, S, a_dev, s, nullptr);
 }

@@ -33,7 +33,12 @@ size_t row_scratch_bytes(const InstDev& I, int fp64);
 // Pick the stage blocking (stored in I.pad1) so the grid stays co-resident;
 // I.pad1 > 0 on entry is the preferred blocking.
 hipError_t row_prepare(int fp64, InstDev& I);
-// Enqueue the solve of one row-family instance (clears its scratch first).
+// Form the fused stage data of a row-family instance in its scratch (after
+// every factorisation; reads the T block written by the factor kernel).
+hipError_t launch_row_fuse(const InstDev* d_inst, int inst_idx, const InstDev& I, const void* mats,
+                           void* scratch_base, hipStream_t s);
+// Enqueue the solve of one row-family instance (clears the cleared part of its
+// scratch first).
 hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, void* scratch_base, hipStream_t s);
 
 }  // namespace pimpc

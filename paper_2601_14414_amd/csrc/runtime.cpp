@@ -312,6 +312,16 @@ static int upload_t_block(pimpc_ctx ctx, const double* qbar, const double* xmin,
     return PIMPC_OK;
 }
 
+// Fused stage data of the row-family instances (once their scratch exists).
+static hipError_t fuse_rows(pimpc_ctx ctx, hipStream_t s) {
+    if (!ctx->d_row_scratch) return hipSuccess;
+    for (int i : ctx->row_insts) {
+        hipError_t e = launch_row_fuse(ctx->d_inst, i, ctx->inst[i], ctx->d_mats, ctx->d_row_scratch, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Expand the FP64 stage data into the T layout, factor, check the SPD flags.
 static int refactor(pimpc_ctx ctx, bool sync_check) {
     hipStream_t s = ctx->stream;
@@ -325,6 +335,7 @@ static int refactor(pimpc_ctx ctx, bool sync_check) {
         HIPCHK(ctx, launch_factor<float>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->d_mats64,
                                          (float*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, s));
     }
+    HIPCHK(ctx, fuse_rows(ctx, s));
     if (sync_check) {
         std::vector<int32_t> bad(std::max(ctx->ntasks, 1));
         HIPCHK(ctx, hipMemcpyAsync(bad.data(), ctx->d_bad, bad.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -900,6 +911,9 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
         }
         HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipDeviceSynchronize());  // the scratch clear above is complete
+        HIPCHK(ctx, fuse_rows(ctx, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
     if (o->ckpt_every > 0) {
         if (ctx->fp64 || tv || !ctx->row_insts.empty())
