@@ -221,12 +221,12 @@ constexpr int kRowWaves = 4;
 constexpr int kRecvWaves = 2;
 constexpr int kRowThreads = 64 * (kRowWaves + kRecvWaves);
 
-// Dynamic LDS of one workgroup: per wave, the broadcast rows [3S + 2][NB + 4]
+// Dynamic LDS of one workgroup: per wave, the broadcast rows [3S][NB + 4]
 // and the lane-private rows of the rows lanes (H, BJ, AHAt: NB each; column
 // of [A B]: NX) as float4 [(3 NB + NX) / 4][NB].
 __host__ __device__ constexpr size_t row_lds_bytes(int NX, int NU, int S) {
     return (size_t)kRowWaves *
-           (4 * (3 * S + 2) * (NX + NU + 4) + 16 * (NX + NU) * ((3 * (NX + NU) + NX) / 4));
+           (4 * (3 * S) * (NX + NU + 4) + 16 * (NX + NU) * ((3 * (NX + NU) + NX) / 4));
 }
 
 extern __shared__ __align__(16) float row_smem[];
@@ -238,9 +238,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     constexpr int NB4 = NB / 4;
     constexpr int NX4 = NX / 4;
     constexpr int LD = NB + 4;       // LDS row pitch of a broadcast vector (16-byte multiple)
-    constexpr int NV = 3 * S + 2;    // broadcast rows: (p, d, w) per stage, then w_R, d_L
-    constexpr int RW = 3 * S;        // row of w_R
-    constexpr int RD = 3 * S + 1;    // row of d_L
+    constexpr int NV = 3 * S;        // broadcast rows: (p, d, w) per stage
     static_assert(NB <= 64, "row kernel needs nx + nu <= 64");
     static_assert(NB % 4 == 0 && NX % 4 == 0, "padded sizes must be multiples of 4");
     const RowArgs& a = *ap;
@@ -270,8 +268,9 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
 #define LBJ(q) lrow[(NB4 + (q)) * NB + r]
 #define LAHAT(q) lrow[(2 * NB4 + (q)) * NB + r]
 #define LACOL(q) lrow[(3 * NB4 + (q)) * NB + r]
-    __shared__ uint64_t lmbox[kRowWaves][2][kMboxVecs][NB];  // intra-workgroup mailboxes
-    __shared__ uint64_t lin[2][2][NB];  // forwarded external halos: [buf][0: w from the right, 1: d from the left]
+    // (16-byte aligned: a halo vector is also read whole, two words per float4)
+    __shared__ __align__(16) uint64_t lmbox[kRowWaves][2][kMboxVecs][NB];  // intra-workgroup mailboxes
+    __shared__ __align__(16) uint64_t lin[2][2][NB];  // forwarded external halos: [buf][0: w from the right, 1: d from the left]
     __shared__ int lstop;               // set by the compute waves when they leave the loop
     for (int i = threadIdx.x; i < kRowWaves * 2 * kMboxVecs * NB; i += blockDim.x) (&lmbox[0][0][0][0])[i] = 0;
     for (int i = threadIdx.x; i < 2 * 2 * NB; i += blockDim.x) (&lin[0][0][0])[i] = 0;
@@ -448,8 +447,10 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         // the stage after the block, d of the stage before it, from the
         // neighbouring wave or, across workgroups, as forwarded by a receiver
         const int hbuf = tin & 1;
-        uint64_t* pr = right_in_wg ? &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][hbuf][0][r] : &lin[hbuf][0][r];
-        uint64_t* pl = left_in_wg ? &lmbox[wv > 0 ? wv - 1 : 0][hbuf][1][r] : &lin[hbuf][1][r];
+        uint64_t* prb = right_in_wg ? &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][hbuf][0][0] : &lin[hbuf][0][0];
+        uint64_t* plb = left_in_wg ? &lmbox[wv > 0 ? wv - 1 : 0][hbuf][1][0] : &lin[hbuf][1][0];
+        uint64_t* pr = prb + r;
+        uint64_t* pl = plb + r;
         uint64_t wr = 0, wl = 0;
         auto poll = [&]() {
             if (has_right) wr = lload(pr);
@@ -461,8 +462,9 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         if (rowl) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (s < ns) {
-                    bc[3 * s + 0][r] = v[s] - be[s];
+                if (S == 1 || s < ns) {
+                    pv[s] = v[s] - be[s];
+                    bc[3 * s + 0][r] = pv[s];
                     bc[3 * s + 1][r] = dvec(s);
                     bc[3 * s + 2][r] = wvec(s);
                 }
@@ -472,7 +474,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         if (rowl) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (s < ns) {
+                if (S == 1 || s < ns) {
                     const int k = k0 + s;
                     float ab0 = 0.f, ab1 = 0.f, ah0 = 0.f, ah1 = 0.f, ac0 = 0.f, ac1 = 0.f;
                     // all operands come from LDS; a partly unrolled loop keeps
@@ -554,18 +556,13 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         // ---- halos of the iterate entering this step: w of the stage after
         // the block, d of the stage before it.  Both words are loaded together
         // each poll, so a poll costs one memory round trip.
-        float wR = 0.f, dL = 0.f;
         if ((has_right || has_left) && rowl) {
             int spins = 0;
             poll();
             for (;;) {
                 const bool okr = !has_right || unpack_tag(wr) == tin;
                 const bool okl = !has_left || unpack_tag(wl) == tin;
-                if (okr && okl) {
-                    wR = unpack_val(wr);
-                    dL = unpack_val(wl);
-                    break;
-                }
+                if (okr && okl) break;
                 if ((++spins & 31) == 0) {
                     if (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                         failed = true;
@@ -585,32 +582,26 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             status = -5;
             break;
         }
-        // ---- halo terms: xbar of the last stage and c of the first stage
-        if (rowl) {
-            bc[RW][r] = wR;
-            bc[RD][r] = dL;
-        }
-        __builtin_amdgcn_wave_barrier();
+        // ---- halo terms: xbar of the last stage and c of the first stage.
+        // Every lane has seen its own word of both halo vectors carry the tag,
+        // so the whole vectors are read straight from the mailboxes (two
+        // (value, tag) words per float4, the same address in every lane).
+        // Both products are always formed (a missing side reads a harmless
+        // mailbox) and only the existing sides are added.
         if (rowl && (has_right || has_left)) {
             float x0 = 0.f, x1 = 0.f, y0 = 0.f, y1 = 0.f;
-            float4 wq[NB4], dq[NB4];  // all broadcast reads in flight at once
+            float4 wq[NB / 2], dq[NB / 2];  // all reads in flight at once
 #pragma unroll
-            for (int q = 0; q < NB4; ++q) {
-                wq[q] = *(const float4*)&bc[RW][4 * q];
-                dq[q] = *(const float4*)&bc[RD][4 * q];
+            for (int q = 0; q < NB / 2; ++q) {
+                wq[q] = *(const float4*)(prb + 2 * q);
+                dq[q] = *(const float4*)(plb + 2 * q);
             }
 #pragma unroll
-            for (int q = 0; q < NB4; ++q) {
-                const float4 w4 = wq[q];
-                const float4 d4 = dq[q];
-                x0 += HAr[4 * q + 0] * w4.x;
-                y0 += AHr[4 * q + 0] * d4.x;
-                x1 += HAr[4 * q + 1] * w4.y;
-                y1 += AHr[4 * q + 1] * d4.y;
-                x0 += HAr[4 * q + 2] * w4.z;
-                y0 += AHr[4 * q + 2] * d4.z;
-                x1 += HAr[4 * q + 3] * w4.w;
-                y1 += AHr[4 * q + 3] * d4.w;
+            for (int q = 0; q < NB / 2; ++q) {
+                x0 += HAr[2 * q + 0] * wq[q].x;
+                y0 += AHr[2 * q + 0] * dq[q].x;
+                x1 += HAr[2 * q + 1] * wq[q].z;
+                y1 += AHr[2 * q + 1] * dq[q].z;
             }
             if (has_right) {
 #pragma unroll
@@ -621,43 +612,38 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         }
 
         // ---- steps 2-3 (Theorem 1 closed form, box projection, dual update)
+        // (lanes without a row hold zeros throughout: their bounds are [0, 0])
         float cpart = 0.f, rpart = 0.f;
         float ddv[S], dzv[S], dvv[S];
-        if (rowl) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                ddv[s] = dzv[s] = dvv[s] = 0.f;
-                if (s < ns) {
-                    const float bi = bb[s], ci = cl[s], xi = xl[s];
-                    const float gam = bi - ci;
-                    const float y = (2.f * (xi + th[s]) + bi + ci) * third;
-                    const float zn = y < lb_r ? lb_r : (y > ub_r ? ub_r : y);
-                    const float vn = (zn + gam) * 0.5f;
-                    const float thn = th[s] + xi - zn;
-                    const float ben = bi - vn;
-                    const float lan = zn - vn - ci;
-                    if (check) {
-                        const float dv = vn - v[s], dz = zn - z[s];
-                        const float dth = thn - th[s], dbe = ben - be[s], dla = lan - la[s];
-                        const float dd = dz - dv;
-                        cpart += dth * dth + dbe * dbe + dla * dla + dz * dz + dv * dv + dd * dd;
-                        rpart = fmax(rpart, fmax(fabsf(dth), fmax(fabsf(dbe), fabsf(dla))));
-                        ddv[s] = dd;
-                        dzv[s] = dz;
-                        dvv[s] = dv;
-                    }
-                    pv[s] = bc[3 * s + 0][r];
-                    xs[s] = xi;
-                    v[s] = vn;
-                    z[s] = zn;
-                    th[s] = thn;
-                    be[s] = ben;
-                    la[s] = lan;
+        for (int s = 0; s < S; ++s) {
+            ddv[s] = dzv[s] = dvv[s] = 0.f;
+            if (S == 1 || s < ns) {  // a compute wave has at least one stage
+                const float bi = bb[s], ci = cl[s], xi = xl[s];
+                const float gam = bi - ci;
+                const float y = (2.f * (xi + th[s]) + bi + ci) * third;
+                const float zn = y < lb_r ? lb_r : (y > ub_r ? ub_r : y);
+                const float vn = (zn + gam) * 0.5f;
+                const float thn = th[s] + xi - zn;
+                const float ben = bi - vn;
+                const float lan = zn - vn - ci;
+                if (check) {
+                    const float dv = vn - v[s], dz = zn - z[s];
+                    const float dth = thn - th[s], dbe = ben - be[s], dla = lan - la[s];
+                    const float dd = dz - dv;
+                    cpart += dth * dth + dbe * dbe + dla * dla + dz * dz + dv * dv + dd * dd;
+                    rpart = fmax(rpart, fmax(fabsf(dth), fmax(fabsf(dbe), fabsf(dla))));
+                    ddv[s] = dd;
+                    dzv[s] = dz;
+                    dvv[s] = dv;
                 }
+                xs[s] = xi;
+                v[s] = vn;
+                z[s] = zn;
+                th[s] = thn;
+                be[s] = ben;
+                la[s] = lan;
             }
-        } else {
-#pragma unroll
-            for (int s = 0; s < S; ++s) ddv[s] = dzv[s] = dvv[s] = 0.f;
         }
         publish(tout);
         if (check && has_left && rowl) put(left_in_wg, tout & 1, 2, pack(ddv[0], tout));
