@@ -8,11 +8,14 @@
 //   * an instance occupies ceil(N/64) consecutive waves of a 512-thread
 //     workgroup; several instances share a workgroup ("bin");
 //   * time-invariant stage data (J, H, A, B, e, bounds) is uniform across the
-//     wave, read through the scalar data cache into SGPRs (scalar *loads*
-//     only), so every mat-vec FMA takes a matrix operand from an SGPR;
-//     time-varying stage data is loaded once into VGPRs per lane;
+//     wave and is streamed row by row through SGPRs with scalar loads, one row
+//     ahead of its use (each row's load overlaps the previous row's FMAs), so
+//     every mat-vec FMA takes its matrix operand from an SGPR; time-varying
+//     stage data is loaded once into VGPRs per lane;
 //   * the two one-stage halos of an iteration (g_{k+1} for step 1 and
-//     xbar_k for step 2) go through LDS between two workgroup barriers;
+//     xbar_k for step 2) move between neighbouring lanes with DPP wavefront
+//     shifts; only the value crossing a wave boundary goes through a small
+//     LDS slot, between two workgroup barriers;
 //   * residuals (Algorithm 1 step 4 and Section IV-B) are reduced with
 //     cross-lane shuffles, then across the instance's waves in LDS, in a
 //     fixed order (deterministic);
@@ -25,10 +28,6 @@
 #include "lane_common.hpp"
 
 namespace pimpc {
-
-constexpr int kBD = kBinThreads;  // LDS row stride of the halo buffers
-
-extern __shared__ __align__(16) unsigned char lane_smem[];
 
 template <typename T>
 __device__ inline T wave_sum(T v) {
@@ -49,39 +48,118 @@ __device__ inline T clampv(T y, T lo, T hi) {
     return y < lo ? lo : (y > hi ? hi : y);
 }
 
+// DPP wavefront shifts by one lane (32-bit moves; a double moves as two
+// halves).  shl1: lane i receives lane i + 1 (lane 63 receives 0);
+// shr1: lane i receives lane i - 1 (lane 0 receives 0).
+__device__ __forceinline__ int dpp_shl1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shr1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ float shl1(float x) { return __int_as_float(dpp_shl1(__float_as_int(x))); }
+__device__ __forceinline__ float shr1(float x) { return __int_as_float(dpp_shr1(__float_as_int(x))); }
+__device__ __forceinline__ double shl1(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_shl1((int)(b & 0xffffffffll)), hi = dpp_shl1((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double shr1(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_shr1((int)(b & 0xffffffffll)), hi = dpp_shr1((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---- streaming of uniform rows through SGPRs
+template <typename T, int W>
+struct SRow {
+    T x[W];
+};
+
+// Scalar-load W consecutive values at p (uniform).  The opaque copy of the
+// pointer keeps the load where it is written (not hoisted ahead of earlier
+// rows, which would overflow the SGPRs).
+template <typename T, int W>
+__device__ __forceinline__ void sload_into(T* dst, cptr<T> p) {
+    asm volatile("" : "+s"(p));
+#pragma unroll
+    for (int j = 0; j < W; ++j) dst[j] = p[j];
+}
+
+// Every scalar load issued so far has landed (scalar loads return out of
+// order, so only a full wait on the counter is meaningful): lgkmcnt(0).
+__device__ __forceinline__ void swait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Rows 0..R-1 of a uniform stream: load(r) returns row r, body(r, row)
+// consumes it.  With PF, row r + 1 is requested right after row r has landed,
+// so its load overlaps body(r); without, each row is loaded, awaited and used
+// (fewer SGPRs held, for the widest stages whose registers are full).
+template <typename RowT, int R, bool PF, typename L, typename B>
+__device__ __forceinline__ void stream_rows(L&& load, B&& body) {
+    if constexpr (PF) {
+        RowT cur = load(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            swait();
+            RowT nxt;
+            if (r + 1 < R) nxt = load(r + 1);
+            body(r, cur);
+            cur = nxt;
+        }
+    } else {
+        // two rows per wait: half the exposed latencies for one extra row of SGPRs
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            RowT c0 = load(r), c1;
+            if (r + 1 < R) c1 = load(r + 1);
+            swait();
+            body(r, c0);
+            if (r + 1 < R) body(r + 1, c1);
+        }
+    }
+}
+
 // Run (or, with have = false, only shadow the barrier sequence of) one
 // instance on the waves [gw0, gw0 + gnw) of the workgroup.
 template <typename T, int NX, int NU, bool TV>
 __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bool have, int gw0,
-                                      unsigned leader_mask) {
+                                         unsigned leader_mask, T (*bnd_g)[NX + NU], T (*bnd_x)[NX + NU],
+                                         T (*dzl)[kBinThreads], T (*ddl)[kBinThreads], double* red,
+                                         int* gdone) {
     inst_idx = __builtin_amdgcn_readfirstlane(inst_idx);
     gw0 = __builtin_amdgcn_readfirstlane(gw0);
     have = __builtin_amdgcn_readfirstlane((int)have) != 0;
     leader_mask = __builtin_amdgcn_readfirstlane(leader_mask);
+    // SGPRs are the scarce resource of this kernel (every matrix row streams
+    // through them): launch parameters are re-read where they are used, via
+    // an opaque copy of the pointer (scalar loads that hit the scalar cache),
+    // instead of being held in SGPRs across the iteration loop.
     const cptr<LaneArgs> ap = (cptr<LaneArgs>)uniform_ptr(ap_in);
-    const LaneArgs a = *ap;
-    const InstDev I = ((cptr<InstDev>)uniform_ptr(a.inst))[have ? inst_idx : 0];
-    T* xg = (T*)lane_smem;
-    T* xx = xg + (size_t)a.nbmax * kBD;
-    T* xd = xx + (size_t)a.nbmax * kBD;
-    double* red = (double*)(xd + (size_t)a.nbmax * kBD);
-    int* gdone = (int*)(red + kBinWaves * 4);
+    const cptr<InstDev> ip = ((cptr<InstDev>)uniform_ptr((*ap).inst)) + (have ? inst_idx : 0);
+    auto AP = [&]() {
+        cptr<LaneArgs> p = ap;
+        asm volatile("" : "+s"(p));
+        return p;
+    };
+    auto IP = [&]() {
+        cptr<InstDev> p = ip;
+        asm volatile("" : "+s"(p));
+        return p;
+    };
     constexpr int NB = NX + NU;
+    constexpr bool kPF = NB <= 16;  // row prefetch (see stream_rows)
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int k = tid - gw0 * 64;  // stage owned by this lane
-    const int N = have ? I.N : 0;
+    const int N = have ? (*ip).N : 0;
     const bool act = have && k >= 0 && k < N;
     const bool leader = have && k == 0;
-    const T rho = (T)a.rho;
+    const T rho = (T)(*ap).rho;
     const T third = (T)(1.0 / 3.0);
 
     const MatOffsets o = mat_offsets(NX, NU, have ? N : 1, TV);
-    const cptr<T> M0 = (cptr<T>)uniform_ptr(have ? (const T*)a.mats + I.mat_off : (const T*)a.mats);
-    // Uniform stage data is re-read through the scalar cache each iteration;
-    // an opaque copy of the base pointer keeps the compiler from hoisting
-    // hundreds of loads out of the loop (which would overflow the SGPRs).
+    // matrix block of the instance (re-derived each iteration, see above)
+    auto MB = [&]() {
+        const T* m = (const T*)(*AP()).mats;
+        return (cptr<T>)uniform_ptr(have ? m + (*IP()).mat_off : m);
+    };
 #define PIMPC_MAT_PTRS(Mp)                          \
     const cptr<T> Jm = (Mp) + o.J;                 \
     const cptr<T> Hm = (Mp) + o.H;                 \
@@ -98,7 +176,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     T Jr[TV ? NU * NB : 1], Hr[TV ? NB * NB : 1], Ar[TV ? NX * NX : 1], Br[TV ? NX * NU : 1],
         er[TV ? NX : 1];
     if constexpr (TV) {
-        PIMPC_MAT_PTRS(M0)
+        PIMPC_MAT_PTRS(MB())
 #pragma unroll
         for (int q = 0; q < NU * NB; ++q) Jr[q] = act ? Jm[(int64_t)q * N + k] : T(0);
 #pragma unroll
@@ -110,54 +188,57 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 #pragma unroll
         for (int q = 0; q < NX; ++q) er[q] = act ? em[(int64_t)q * N + k] : T(0);
     }
-#define JM(r, c) (TV ? Jr[(r) * NB + (c)] : Jm[(r) * NB + (c)])
-#define HM(r, c) (TV ? Hr[(r) * NB + (c)] : Hm[(r) * NB + (c)])
-#define AM(r, c) (TV ? Ar[(r) * NX + (c)] : Am[(r) * NX + (c)])
-#define BM(r, c) (TV ? Br[(r) * NU + (c)] : Bm[(r) * NU + (c)])
-#define EM(r) (TV ? er[(r)] : em[(r)])
 
     // xbar_0 = col(x(t), u(t-1)): uniform over the instance, read through the
     // scalar cache where lane k = 0 needs it.
-    const cptr<T> x0p = (cptr<T>)uniform_ptr((const T*)a.x0 + (have ? I.x_off : 0));
-    const cptr<T> upp = (cptr<T>)uniform_ptr(a.uprev ? (const T*)a.uprev + (have ? I.u_off : 0) : nullptr);
-    const int nx_real = have ? I.nx : 0, nu_real = have ? I.nu : 0;
 #define XB0(i) ((i) < NX ? ((i) < nx_real ? x0p[(i)] : T(0)) \
                          : ((upp && (i) - NX < nu_real) ? upp[(i) - NX] : T(0)))
 
     // iterate (v, z, theta, beta, lambda) of this stage
     T v[NB], z[NB], th[NB], be[NB], la[NB];
-    const gptr<T> st = (gptr<T>)(have ? (T*)a.state + I.st_off : (T*)a.state);
+    auto ST = [&]() { return (gptr<T>)(have ? (T*)(*AP()).state + (*IP()).st_off : (T*)(*AP()).state); };
+    const gptr<T> st = ST();
+    const bool warm = (*ap).warm != 0;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const bool ld = act && a.warm;
+        const bool ld = act && warm;
         v[i] = ld ? st[(int64_t)(0 * NB + i) * N + k] : T(0);
         z[i] = ld ? st[(int64_t)(1 * NB + i) * N + k] : T(0);
         th[i] = ld ? st[(int64_t)(2 * NB + i) * N + k] : T(0);
         be[i] = ld ? st[(int64_t)(3 * NB + i) * N + k] : T(0);
         la[i] = ld ? st[(int64_t)(4 * NB + i) * N + k] : T(0);
     }
-    T du[NU], xs[NB];
+    // du of the last step 1 is kept for u0; the step-1 outputs of an iteration
+    // (du, xbar) are written out on check iterations, which include the last
+    // one, so xbar need not stay in registers across iterations
+    T du[NU];
 #pragma unroll
     for (int i = 0; i < NU; ++i) du[i] = T(0);
-#pragma unroll
-    for (int i = 0; i < NB; ++i) xs[i] = T(0);
 
     const bool last_wave = have && ((N - 1) >> 6) == (k >> 6) && k >= 0;
     const bool is_last = act && k == N - 1;
-    const bool hb_diag = have && I.hb_diag;
+    const bool hb_diag = have && (*ip).hb_diag;
+    const bool hasnext = act && k + 1 < N;
+    const bool from_next_wave = hasnext && lane == 63;  // stage k + 1 is lane 0 of the next wave
+    const bool from_prev_wave = act && k > 0 && lane == 0;
 
     int iters = 0;
     bool done = !have;
     double c_last = 0.0, rp_last = 0.0, rd_last = 0.0;
     int status = 0;
 
+    const int K = (*ap).K;
+    const bool use_eps = (*ap).eps > 0.0;
+    const int check_every = (*ap).check_every;
+    const int ckpt_every = (*ap).ckpt_every;
 #pragma unroll 1
-    for (int it = 0; it < a.K; ++it) {
-        const bool check = (a.eps > 0.0 && ((it + 1) % a.check_every) == 0) || (it == a.K - 1);
+    for (int it = 0; it < K; ++it) {
+        const bool check = (use_eps && ((it + 1) % check_every) == 0) || (it == K - 1);
         const bool run = !done;
         // taped forward: keep the iterate entering this iteration every ckpt_every steps
-        if (a.ckpt_every > 0 && (it % a.ckpt_every) == 0 && act) {
-            const gptr<T> ck = (gptr<T>)((T*)a.ckpt + I.ck_off + (int64_t)(it / a.ckpt_every) * 5 * NB * N);
+        if (ckpt_every > 0 && (it % ckpt_every) == 0 && act) {
+            const gptr<T> ck =
+                (gptr<T>)((T*)(*AP()).ckpt + (*IP()).ck_off + (int64_t)(it / ckpt_every) * 5 * NB * N);
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 ck[(int64_t)(0 * NB + i) * N + k] = v[i];
@@ -167,117 +248,190 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                 ck[(int64_t)(4 * NB + i) * N + k] = la[i];
             }
         }
-        // Row pointers are re-made opaque before use so that the scalar loads
-        // of one matrix row cannot be hoisted ahead of earlier rows.
-#define ROW(base, r, ld) ([&]() { cptr<T> p_ = (base) + (r) * (ld); asm volatile("" : "+s"(p_)); return p_; }())
-        cptr<T> Mi = M0;
-        asm volatile("" : "+s"(Mi));
+        const cptr<T> Mi = MB();
         PIMPC_MAT_PTRS(Mi)
 
         // ---- step 1a: du_k = J_k (v_k - beta_k); g_k = Abar_k' (z_{k+1} - v_k - ebar_k + lambda_k)
+        T g[NB], xs[NB];
         if (run) {
 #pragma unroll
-            for (int r = 0; r < NU; ++r) {
-                const cptr<T> Jrow = ROW(Jm, r, NB);
-                T s = T(0);
-#pragma unroll
-                for (int j = 0; j < NB; ++j) s += (TV ? Jr[r * NB + j] : Jrow[j]) * (v[j] - be[j]);
-                du[r] = s;
-            }
-            T g[NB];
-#pragma unroll
             for (int c = 0; c < NB; ++c) g[c] = (c < NX) ? T(0) : (z[c] - v[c] + la[c]);
+            if constexpr (TV) {
 #pragma unroll
-            for (int r = 0; r < NX; ++r) {
-                const T w = z[r] - v[r] - EM(r) + la[r];
-                const cptr<T> Arow = ROW(Am, r, NX);
-                const cptr<T> Brow = ROW(Bm, r, NU);
+                for (int r = 0; r < NU; ++r) {
+                    T s = T(0);
 #pragma unroll
-                for (int c = 0; c < NX; ++c) g[c] += (TV ? Ar[r * NX + c] : Arow[c]) * w;
+                    for (int j = 0; j < NB; ++j) s += Jr[r * NB + j] * (v[j] - be[j]);
+                    du[r] = s;
+                }
 #pragma unroll
-                for (int c = 0; c < NU; ++c) g[NX + c] += (TV ? Br[r * NU + c] : Brow[c]) * w;
+                for (int r = 0; r < NX; ++r) {
+                    const T w = z[r] - v[r] - er[r] + la[r];
+#pragma unroll
+                    for (int c = 0; c < NX; ++c) g[c] += Ar[r * NX + c] * w;
+#pragma unroll
+                    for (int c = 0; c < NU; ++c) g[NX + c] += Br[r * NU + c] * w;
+                }
+            } else {
+                // one stream: rows of J (du), then rows [A_r B_r e_r] (g)
+                using Row = SRow<T, NB + 1>;
+                stream_rows<Row, NU + NX, kPF>(
+                    [&](int r) {
+                        Row x;
+                        if (r < NU) {
+                            sload_into<T, NB>(x.x, Jm + r * NB);
+                        } else {
+                            sload_into<T, NX>(x.x, Am + (r - NU) * NX);
+                            sload_into<T, NU>(x.x + NX, Bm + (r - NU) * NU);
+                            sload_into<T, 1>(x.x + NB, em + (r - NU));
+                        }
+                        return x;
+                    },
+                    [&](int r, const Row& x) {
+                        if (r < NU) {
+                            T s = T(0);
+#pragma unroll
+                            for (int j = 0; j < NB; ++j) s += x.x[j] * (v[j] - be[j]);
+                            du[r] = s;
+                        } else {
+                            const int i = r - NU;
+                            const T w = z[i] - v[i] - x.x[NB] + la[i];
+#pragma unroll
+                            for (int c = 0; c < NB; ++c) g[c] += x.x[c] * w;
+                        }
+                    });
             }
+            // g moves one lane down (stage k + 1 -> k); lane 0 of the wave
+            // hands its g to the previous wave through LDS
+            if (lane == 0) {
 #pragma unroll
-            for (int c = 0; c < NB; ++c) xg[c * kBD + tid] = g[c];
+                for (int c = 0; c < NB; ++c) bnd_g[wave][c] = g[c];
+            }
         }
         __syncthreads();
+        if (run) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) g[c] = shl1(g[c]);  // g[] now holds g_{k+1}
+        }
 
         // ---- step 1b: h_k = qbar + rho (z_{k+1} - theta_k + g_{k+1}); xbar_{k+1} = H_k h_k
         if (run) {
-            const bool hasnext = act && (k + 1 < N);
             T h[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                // the read stays inside the LDS allocation for every tid (xx follows xg)
-                const T gv = xg[i * kBD + tid + 1];
-                const T gn = hasnext ? gv : T(0);
-                h[i] = qb[i] + rho * (z[i] - th[i] + gn);
-            }
-#pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const cptr<T> Hrow = ROW(Hm, r, NB);
-                T s = T(0);
-#pragma unroll
-                for (int j = 0; j < NB; ++j) s += (TV ? Hr[r * NB + j] : Hrow[j]) * h[j];
-                xs[r] = s;
-            }
             if constexpr (!TV) {
+                T q[NB];
+                sload_into<T, NB>(q, qb);
+                swait();
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const T gn = from_next_wave ? bnd_g[wave + 1 < kBinWaves ? wave + 1 : wave][i] : g[i];
+                    h[i] = q[i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
+                }
+                using Row = SRow<T, NB>;
+                stream_rows<Row, NB, kPF>(
+                    [&](int r) {
+                        Row x;
+                        sload_into<T, NB>(x.x, Hm + r * NB);
+                        return x;
+                    },
+                    [&](int r, const Row& x) {
+                        T s = T(0);
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
+                        xs[r] = s;
+                    });
                 if (last_wave) {  // wave-uniform: only the wave holding stage N-1
                     if (hb_diag) {
-#pragma unroll
-                        for (int r = 0; r < NB; ++r) xs[r] = is_last ? Hbm[r * NB + r] * h[r] : xs[r];
-                    } else {
+                        T d[NB];
+                        cptr<T> Hbp = Hbm;
 #pragma unroll
                         for (int r = 0; r < NB; ++r) {
-                            const cptr<T> Hrow = ROW(Hbm, r, NB);
-                            T s = T(0);
-#pragma unroll
-                            for (int j = 0; j < NB; ++j) s += Hrow[j] * h[j];
-                            xs[r] = is_last ? s : xs[r];
+                            asm volatile("" : "+s"(Hbp));
+                            d[r] = Hbp[r * NB + r];
                         }
+                        swait();
+#pragma unroll
+                        for (int r = 0; r < NB; ++r) xs[r] = is_last ? d[r] * h[r] : xs[r];
+                    } else {
+                        stream_rows<Row, NB, kPF>(
+                            [&](int r) {
+                                Row x;
+                                sload_into<T, NB>(x.x, Hbm + r * NB);
+                                return x;
+                            },
+                            [&](int r, const Row& x) {
+                                T s = T(0);
+#pragma unroll
+                                for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
+                                xs[r] = is_last ? s : xs[r];
+                            });
                     }
                 }
-            }
+            } else {
 #pragma unroll
-            for (int i = 0; i < NB; ++i) xx[i * kBD + tid] = xs[i];
+                for (int i = 0; i < NB; ++i) {
+                    const T gn = from_next_wave ? bnd_g[wave + 1 < kBinWaves ? wave + 1 : wave][i] : g[i];
+                    h[i] = qb[i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
+                }
+#pragma unroll
+                for (int r = 0; r < NB; ++r) {
+                    T s = T(0);
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s += Hr[r * NB + j] * h[j];
+                    xs[r] = s;
+                }
+            }
+            // xbar moves one lane up (stage k -> k + 1); lane 63 hands its
+            // xbar to the next wave through LDS
+            if (lane == 63) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) bnd_x[wave][c] = xs[c];
+            }
         }
         __syncthreads();
 
         // ---- steps 2-3: Theorem 1 closed form, box projection, dual update
         T rdu[NU];
         T cpart = T(0), rpart = T(0);
+        // check iterations: dz and dd = dz - dv of every component go to LDS planes
         if (run) {
+            // shift first, with every lane active (a DPP source lane that is
+            // masked off reads as 0), then take the boundary value
             T xp[NB];
 #pragma unroll
+            for (int i = 0; i < NB; ++i) xp[i] = shr1(xs[i]);
+            // xbar_0 = col(x(t), u(t-1)) for stage 0 (uniform, scalar loads)
+            const cptr<T> x0p = (cptr<T>)uniform_ptr((const T*)(*AP()).x0 + (have ? (*IP()).x_off : 0));
+            const T* upraw = (const T*)(*AP()).uprev;
+            const cptr<T> upp = (cptr<T>)uniform_ptr(upraw ? upraw + (have ? (*IP()).u_off : 0) : nullptr);
+            const int nx_real = have ? (*IP()).nx : 0, nu_real = have ? (*IP()).nu : 0;
+            const int wprev = wave > 0 ? wave - 1 : 0;
+#pragma unroll
             for (int i = 0; i < NB; ++i) {
-                // tid - 1 >= -1: the read stays inside the LDS allocation (xg precedes xx)
-                const T xv = xx[i * kBD + tid - 1];
+                const T xv = from_prev_wave ? bnd_x[wprev][i] : xp[i];
                 xp[i] = (k == 0) ? XB0(i) : (act ? xv : T(0));
             }
 #pragma unroll
             for (int c = 0; c < NU; ++c) rdu[c] = T(0);
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                // b_i = (Bbar du)_i + beta_i;  c_i = (Abar xbar_k)_i + ebar_i - lambda_i
+            // component i: b_i = (Bbar du)_i + beta_i;  c_i = (Abar xbar_k)_i + ebar_i - lambda_i
+            // (rows are passed as accessors, never as addresses, so that they stay in registers)
+            auto comp = [&](int i, auto&& arow, auto&& brow, T ei, T lo, T hi) {
                 T bi, ci;
                 if (i < NX) {
-                    const cptr<T> Arow = ROW(Am, i, NX);
-                    const cptr<T> Brow = ROW(Bm, i, NU);
                     bi = be[i];
 #pragma unroll
-                    for (int j = 0; j < NU; ++j) bi += (TV ? Br[i * NU + j] : Brow[j]) * du[j];
-                    ci = EM(i) - la[i];
+                    for (int j = 0; j < NU; ++j) bi += brow(j) * du[j];
+                    ci = ei - la[i];
 #pragma unroll
-                    for (int j = 0; j < NX; ++j) ci += (TV ? Ar[i * NX + j] : Arow[j]) * xp[j];
+                    for (int j = 0; j < NX; ++j) ci += arow(j) * xp[j];
 #pragma unroll
-                    for (int j = 0; j < NU; ++j) ci += (TV ? Br[i * NU + j] : Brow[j]) * xp[NX + j];
+                    for (int j = 0; j < NU; ++j) ci += brow(j) * xp[NX + j];
                 } else {
                     bi = du[i - NX] + be[i];
                     ci = xp[i] - la[i];
                 }
                 const T gam = bi - ci;
                 const T y = (T(2) * (xs[i] + th[i]) + bi + ci) * third;
-                const T zn = clampv(y, lbm[i], ubm[i]);
+                const T zn = clampv(y, lo, hi);
                 const T vn = (zn + gam) * T(0.5);
                 const T thn = th[i] + xs[i] - zn;
                 const T ben = bi - vn;
@@ -290,55 +444,108 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     rpart = fmax(rpart, fmax(fabs(dth), fmax(fabs(dbe), fabs(dla))));
                     // du block of F'G dq: Bbar_k' dv
                     if (i < NX) {
-                        const cptr<T> Brow = ROW(Bm, i, NU);
 #pragma unroll
-                        for (int c = 0; c < NU; ++c) rdu[c] += (TV ? Br[i * NU + c] : Brow[c]) * dv;
+                        for (int c = 0; c < NU; ++c) rdu[c] += brow(c) * dv;
                     } else {
                         rdu[i - NX] += dv;
                     }
-                    xd[i * kBD + tid] = dz;  // own slot
-                    xg[i * kBD + tid] = dd;  // own slot; nobody reads xg until the next barrier
+                    dzl[i][tid] = dz;
+                    ddl[i][tid] = dd;
                 }
                 v[i] = vn;
                 z[i] = zn;
                 th[i] = thn;
                 be[i] = ben;
                 la[i] = lan;
+            };
+            if constexpr (TV) {
+                const cptr<T> lbq = lbm, ubq = ubm;
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    comp(
+                        i, [&](int j) { return Ar[(i < NX ? i : 0) * NX + j]; },
+                        [&](int j) { return Br[(i < NX ? i : 0) * NU + j]; }, i < NX ? er[i] : T(0), lbq[i], ubq[i]);
+            } else {
+                // one stream over the components: [A_i B_i e_i lb_i ub_i] (i < NX), [lb_i ub_i]
+                using Row = SRow<T, NB + 3>;
+                stream_rows<Row, NB, kPF>(
+                    [&](int i) {
+                        Row x;
+                        if (i < NX) {
+                            sload_into<T, NX>(x.x, Am + i * NX);
+                            sload_into<T, NU>(x.x + NX, Bm + i * NU);
+                            sload_into<T, 1>(x.x + NB, em + i);
+                        }
+                        sload_into<T, 1>(x.x + NB + 1, lbm + i);
+                        sload_into<T, 1>(x.x + NB + 2, ubm + i);
+                        return x;
+                    },
+                    [&](int i, const Row& x) {
+                        comp(
+                            i, [&](int j) { return x.x[j]; }, [&](int j) { return x.x[NX + j]; },
+                            i < NX ? x.x[NB] : T(0), x.x[NB + 1], x.x[NB + 2]);
+                    });
             }
             ++iters;
+            if (check && act && (*AP()).write_iters) {
+                const gptr<T> io = (gptr<T>)((T*)(*AP()).iters_out + (*IP()).it_off);
+#pragma unroll
+                for (int i = 0; i < NU; ++i) io[(int64_t)i * N + k] = du[i];
+#pragma unroll
+                for (int i = 0; i < NB; ++i) io[(int64_t)(NU + i) * N + k] = xs[i];
+            }
         }
 
         if (check) {
             // dual residual, xbar block: dz_{k+1} + Abar_{k+1}' (dz_{k+2} - dv_{k+1})
             T rdpart = T(0);
+            T tg[NB];
             if (run) {
 #pragma unroll
                 for (int c = 0; c < NU; ++c) rdpart = fmax(rdpart, fabs(rdu[c]));
-                T tg[NB];
+                // Abar_k' dd_k (its next-stage copy enters the xbar block)
 #pragma unroll
-                for (int c = 0; c < NB; ++c) tg[c] = (c < NX) ? T(0) : xg[c * kBD + tid];
+                for (int c = 0; c < NB; ++c) tg[c] = (c < NX) ? T(0) : ddl[c][tid];
+                if constexpr (TV) {
 #pragma unroll
-                for (int r = 0; r < NX; ++r) {
-                    const T dd = xg[r * kBD + tid];
-                    const cptr<T> Arow = ROW(Am, r, NX);
-                    const cptr<T> Brow = ROW(Bm, r, NU);
+                    for (int r = 0; r < NX; ++r) {
+                        const T dd = ddl[r][tid];
 #pragma unroll
-                    for (int c = 0; c < NX; ++c) tg[c] += (TV ? Ar[r * NX + c] : Arow[c]) * dd;
+                        for (int c = 0; c < NX; ++c) tg[c] += Ar[r * NX + c] * dd;
 #pragma unroll
-                    for (int c = 0; c < NU; ++c) tg[NX + c] += (TV ? Br[r * NU + c] : Brow[c]) * dd;
+                        for (int c = 0; c < NU; ++c) tg[NX + c] += Br[r * NU + c] * dd;
+                    }
+                } else {
+                    PIMPC_MAT_PTRS(MB())
+                    using Row = SRow<T, NB>;
+                    stream_rows<Row, NX, kPF>(
+                        [&](int r) {
+                            Row x;
+                            sload_into<T, NX>(x.x, Am + r * NX);
+                            sload_into<T, NU>(x.x + NX, Bm + r * NU);
+                            return x;
+                        },
+                        [&](int r, const Row& x) {
+                            const T dd = ddl[r][tid];
+#pragma unroll
+                            for (int c = 0; c < NB; ++c) tg[c] += x.x[c] * dd;
+                        });
                 }
+                if (lane == 0) {  // the g slots are free again (read before the last barrier)
 #pragma unroll
-                for (int c = 0; c < NB; ++c) xg[c * kBD + tid] = tg[c];
+                    for (int c = 0; c < NB; ++c) bnd_g[wave][c] = tg[c];
+                }
             }
             __syncthreads();
             double csum = 0.0, rpm = 0.0, rdm = 0.0;
             if (run) {
-                const bool hasnext = act && (k + 1 < N);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) tg[i] = shl1(tg[i]);  // every lane active (see step 2)
+                const int wnext = wave + 1 < kBinWaves ? wave + 1 : wave;
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
-                    const T tv = xg[i * kBD + tid + 1];
-                    const T tn = hasnext ? tv : T(0);
-                    rdpart = fmax(rdpart, fabs(xd[i * kBD + tid] + tn));
+                    const T tn = from_next_wave ? bnd_g[wnext][i] : tg[i];
+                    rdpart = fmax(rdpart, fabs(dzl[i][tid] + (hasnext ? tn : T(0))));
                 }
                 if (!act) {
                     cpart = T(0);
@@ -363,15 +570,16 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     rp = fmax(rp, red[w * 4 + 1]);
                     rd = fmax(rd, red[w * 4 + 2]);
                 }
-                c_last = a.rho * cs;
+                const double rho64 = (*AP()).rho;
+                c_last = rho64 * cs;
                 rp_last = rp;
-                rd_last = a.rho * rd;
+                rd_last = rho64 * rd;
                 bool stop = false;
                 if (!(c_last < INFINITY)) {  // NaN or Inf
                     status = -4;
                     stop = true;
                 }
-                if (a.eps > 0.0 && c_last <= a.eps) stop = true;
+                if (use_eps && c_last <= (*AP()).eps) stop = true;
                 gdone[gw0] = stop ? 1 : 0;
             }
             __syncthreads();
@@ -380,28 +588,28 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             for (unsigned m = leader_mask; m; m &= m - 1) all_done = all_done && (gdone[__ffs(m) - 1] != 0);
             if (all_done) break;
         }
-#undef ROW
     }
 
     // ---- outputs: final iterate, last step-1 results, u0, info
     if (act) {
+        const gptr<T> sto = ST();
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            st[(int64_t)(0 * NB + i) * N + k] = v[i];
-            st[(int64_t)(1 * NB + i) * N + k] = z[i];
-            st[(int64_t)(2 * NB + i) * N + k] = th[i];
-            st[(int64_t)(3 * NB + i) * N + k] = be[i];
-            st[(int64_t)(4 * NB + i) * N + k] = la[i];
+            sto[(int64_t)(0 * NB + i) * N + k] = v[i];
+            sto[(int64_t)(1 * NB + i) * N + k] = z[i];
+            sto[(int64_t)(2 * NB + i) * N + k] = th[i];
+            sto[(int64_t)(3 * NB + i) * N + k] = be[i];
+            sto[(int64_t)(4 * NB + i) * N + k] = la[i];
         }
-        if (a.write_iters) {
-            const gptr<T> io = (gptr<T>)((T*)a.iters_out + I.it_off);
+        if (iters == 0 && (*AP()).write_iters) {  // no step was taken
+            const gptr<T> io = (gptr<T>)((T*)(*AP()).iters_out + (*IP()).it_off);
 #pragma unroll
-            for (int i = 0; i < NU; ++i) io[(int64_t)i * N + k] = du[i];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) io[(int64_t)(NU + i) * N + k] = xs[i];
+            for (int i = 0; i < NU + NB; ++i) io[(int64_t)i * N + k] = T(0);
         }
     }
     if (leader) {
+        const LaneArgs a = *AP();
+        const InstDev I = *IP();
         const gptr<T> u0 = (gptr<T>)(T*)a.u0;
         const gptr<T> up = (gptr<T>)(T*)a.uprev;
         for (int i = 0; i < I.nu; ++i) u0[I.u_off + i] = (up ? up[I.u_off + i] : T(0)) + du[i];
@@ -417,11 +625,6 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             ((gptr<InfoDev>)a.info)[inst_idx] = r;
         }
     }
-#undef JM
-#undef HM
-#undef AM
-#undef BM
-#undef EM
 #undef XB0
 #undef PIMPC_MAT_PTRS
 }
@@ -429,10 +632,21 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 // One persistent kernel per class (each gets the whole register file; the
 // classes of a batch run as concurrent branches of one graph).  Workgroups
 // claim bins of this class from a counter, largest first.
+// Narrow stages fit two 512-thread workgroups per CU (<= 128 VGPRs a lane);
+// wider ones take the whole register file with one.
+constexpr int lane_waves_per_eu(int nb, int tsize) { return (tsize == 4 && nb <= 7) ? 4 : 2; }
+
 template <typename T, int NX, int NU, bool TV>
-__global__ void __launch_bounds__(kBinThreads) lane_kernel(const LaneArgs* __restrict__ ap) {
+__global__ void __launch_bounds__(kBinThreads)
+    __attribute__((amdgpu_waves_per_eu(lane_waves_per_eu(NX + NU, sizeof(T)))))
+    lane_kernel(const LaneArgs* __restrict__ ap) {
     const LaneArgs& a = *ap;
-    int* gdone = (int*)((double*)((T*)lane_smem + (size_t)3 * a.nbmax * kBD) + kBinWaves * 4);
+    __shared__ T bnd_g[kBinWaves][NX + NU];  // g (and the dual-residual term) crossing a wave boundary
+    __shared__ T bnd_x[kBinWaves][NX + NU];  // xbar crossing a wave boundary
+    __shared__ T dzl[NX + NU][kBinThreads];  // check iterations: dz of every lane
+    __shared__ T ddl[NX + NU][kBinThreads];  // check iterations: dz - dv of every lane
+    __shared__ double red[kBinWaves * 4];   // per-wave residual partials
+    __shared__ int gdone[kBinWaves];        // per-instance stop flags (indexed by first wave)
     __shared__ int s_bin;
     const int wave = threadIdx.x >> 6;
     for (int j = 0;; ++j) {
@@ -457,40 +671,24 @@ __global__ void __launch_bounds__(kBinThreads) lane_kernel(const LaneArgs* __res
         if (threadIdx.x < kBinWaves) gdone[threadIdx.x] = 1;
         __syncthreads();
         if (my >= 0)
-            lane_run<T, NX, NU, TV>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask);
+            lane_run<T, NX, NU, TV>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g, bnd_x, dzl,
+                                    ddl, red, gdone);
         else
-            lane_run<T, NX, NU, TV>(ap, 0, false, wave, leader_mask);
+            lane_run<T, NX, NU, TV>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone);
         __syncthreads();
     }
 }
 
-// Raise the kernel's dynamic-LDS limit to what this launch needs (only ever
-// upwards; the default limit is 64 KiB).
 template <typename T, int NX, int NU, bool TV>
-hipError_t lane_lds_attr(size_t lds) {
-    static size_t set_to = 64 * 1024;
-    if (lds <= set_to) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)lane_kernel<T, NX, NU, TV>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess) set_to = lds;
-    return e;
-}
-
-template <typename T, int NX, int NU, bool TV>
-hipError_t launch_lane_cls(const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s) {
-    const size_t lds = lane_lds_bytes(nbmax, sizeof(T));
-    hipError_t e = lane_lds_attr<T, NX, NU, TV>(lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV>), dim3(grid), dim3(kBinThreads), lds, s, a_dev);
+hipError_t launch_lane_cls(const LaneArgs* a_dev, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV>), dim3(grid), dim3(kBinThreads), 0, s, a_dev);
     return hipGetLastError();
 }
 
 template <typename T, int NX, int NU, bool TV>
-int lane_occupancy(int nbmax) {
-    const size_t lds = lane_lds_bytes(nbmax, sizeof(T));
-    if (lane_lds_attr<T, NX, NU, TV>(lds) != hipSuccess) return -1;
+int lane_occupancy() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV>, kBinThreads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV>, kBinThreads, 0) !=
         hipSuccess)
         return -1;
     return nb > 0 ? nb : 1;
@@ -501,18 +699,24 @@ int lane_occupancy(int nbmax) {
 template <int P>
 hipError_t lane_dispatch(int fp64, int cls, const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s,
                          int* occ, bool* handled) {
+    (void)nbmax;
     *handled = false;
 #define PIMPC_CASE(id, nx, nu, tv)                                                           \
     if constexpr ((id) % PIMPC_LANE_NPARTS == P) {                                          \
         if (cls == (id)) {                                                                  \
             *handled = true;                                                                \
             if (occ) {                                                                      \
-                *occ = fp64 ? lane_occupancy<double, nx, nu, tv>(nbmax)                     \
-                            : lane_occupancy<float, nx, nu, tv>(nbmax);                     \
+                if (!fp64)                                                                  \
+                    *occ = lane_occupancy<float, nx, nu, tv>();                             \
+                else if constexpr (lane_fp64_class(nx + nu))                                \
+                    *occ = lane_occupancy<double, nx, nu, tv>();                            \
+                else                                                                        \
+                    *occ = -1;                                                              \
                 return *occ > 0 ? hipSuccess : hipErrorInvalidValue;                        \
             }                                                                               \
-            return fp64 ? launch_lane_cls<double, nx, nu, tv>(a_dev, nbmax, grid, s)        \
-                        : launch_lane_cls<float, nx, nu, tv>(a_dev, nbmax, grid, s);        \
+            if (!fp64) return launch_lane_cls<float, nx, nu, tv>(a_dev, grid, s);           \
+            if constexpr (lane_fp64_class(nx + nu)) return launch_lane_cls<double, nx, nu, tv>(a_dev, grid, s); \
+            return hipErrorInvalidValue;                                                    \
         }                                                                                   \
     }
 #define PIMPC_CASE_TI(id, nx, nu) PIMPC_CASE(id, nx, nu, false)

@@ -37,10 +37,10 @@ template <int P>
 hipError_t lane_dispatch(int fp64, int cls, const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s,
                          int* occ, bool* handled);
 
-// Dynamic LDS of a lane workgroup: three halo/scratch planes [nbmax][512]
-// plus the per-wave residual partials and the per-group stop flags.
-inline size_t lane_lds_bytes(int nbmax, size_t tsize) {
-    return (size_t)3 * nbmax * kBinThreads * tsize + kBinWaves * 4 * sizeof(double) + kBinWaves * sizeof(int);
-}
+// Whether a class of padded stage size nb fits the lane kernel in this
+// precision: the iterate, the step-1 outputs and the temporaries of one
+// stage live in the registers of one lane, which bounds FP64 classes.
+constexpr bool lane_fp64_class(int nb) { return nb <= 13; }
+inline bool lane_class_fits(int nb, size_t tsize) { return tsize == 4 || lane_fp64_class(nb); }
 
 }  // namespace pimpc

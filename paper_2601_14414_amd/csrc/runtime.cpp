@@ -218,7 +218,7 @@ int pick_class(int nx, int nu, int tv, size_t tsize) {
     int64_t best_cost = 0;
     for (const ClassDesc& c : kClassTable) {
         if (c.tv != tv || c.nx < nx || c.nu < nu) continue;
-        if (lane_lds_bytes(c.nx + c.nu, tsize) > 160 * 1024) continue;  // does not fit one CU's LDS
+        if (!lane_class_fits(c.nx + c.nu, tsize)) continue;
         const int64_t cost = stage_fma(c.nx, c.nu);
         if (best < 0 || cost < best_cost) {
             best = c.id;
