@@ -226,6 +226,21 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     bool done = !have;
     double c_last = 0.0, rp_last = 0.0, rd_last = 0.0;
     int status = 0;
+    // restart acceleration state of the instance (the same in all its lanes)
+    const bool accel = (*ap).accel != 0;
+    double alpha = 1.0, c_prev = 1.0, coef = 0.0;
+    int restarts = 0;
+    if (accel && act) {  // the iterate entering the first step is the first "previous" one
+        const gptr<T> pv = (gptr<T>)((T*)(*AP()).prev + (*IP()).st_off);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            pv[(int64_t)(0 * NB + i) * N + k] = v[i];
+            pv[(int64_t)(1 * NB + i) * N + k] = z[i];
+            pv[(int64_t)(2 * NB + i) * N + k] = th[i];
+            pv[(int64_t)(3 * NB + i) * N + k] = be[i];
+            pv[(int64_t)(4 * NB + i) * N + k] = la[i];
+        }
+    }
 
     const int K = (*ap).K;
     const bool use_eps = (*ap).eps > 0.0;
@@ -234,6 +249,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 #pragma unroll 1
     for (int it = 0; it < K; ++it) {
         const bool check = (use_eps && ((it + 1) % check_every) == 0) || (it == K - 1);
+        const bool need_c = check || accel;  // c^{i+1} is needed (accel decides every step)
         const bool run = !done;
         // taped forward: keep the iterate entering this iteration every ckpt_every steps
         if (ckpt_every > 0 && (it % ckpt_every) == 0 && act) {
@@ -436,11 +452,12 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                 const T thn = th[i] + xs[i] - zn;
                 const T ben = bi - vn;
                 const T lan = zn - vn - ci;
-                if (check) {
+                if (need_c) {
                     const T dv = vn - v[i], dz = zn - z[i], dth = thn - th[i], dbe = ben - be[i],
                             dla = lan - la[i];
                     const T dd = dz - dv;
                     cpart += dth * dth + dbe * dbe + dla * dla + dz * dz + dv * dv + dd * dd;
+                  if (check) {
                     rpart = fmax(rpart, fmax(fabs(dth), fmax(fabs(dbe), fabs(dla))));
                     // du block of F'G dq: Bbar_k' dv
                     if (i < NX) {
@@ -451,6 +468,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     }
                     dzl[i][tid] = dz;
                     ddl[i][tid] = dd;
+                  }
                 }
                 v[i] = vn;
                 z[i] = zn;
@@ -496,65 +514,71 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             }
         }
 
-        if (check) {
-            // dual residual, xbar block: dz_{k+1} + Abar_{k+1}' (dz_{k+2} - dv_{k+1})
+        if (check || accel) {  // residuals (uniform over the workgroup: check, accel, K)
             T rdpart = T(0);
             T tg[NB];
-            if (run) {
+            if (check) {
+                // dual residual, xbar block: dz_{k+1} + Abar_{k+1}' (dz_{k+2} - dv_{k+1})
+                if (run) {
 #pragma unroll
-                for (int c = 0; c < NU; ++c) rdpart = fmax(rdpart, fabs(rdu[c]));
-                // Abar_k' dd_k (its next-stage copy enters the xbar block)
+                    for (int c = 0; c < NU; ++c) rdpart = fmax(rdpart, fabs(rdu[c]));
+                    // Abar_k' dd_k (its next-stage copy enters the xbar block)
 #pragma unroll
-                for (int c = 0; c < NB; ++c) tg[c] = (c < NX) ? T(0) : ddl[c][tid];
-                if constexpr (TV) {
+                    for (int c = 0; c < NB; ++c) tg[c] = (c < NX) ? T(0) : ddl[c][tid];
+                    if constexpr (TV) {
 #pragma unroll
-                    for (int r = 0; r < NX; ++r) {
-                        const T dd = ddl[r][tid];
-#pragma unroll
-                        for (int c = 0; c < NX; ++c) tg[c] += Ar[r * NX + c] * dd;
-#pragma unroll
-                        for (int c = 0; c < NU; ++c) tg[NX + c] += Br[r * NU + c] * dd;
-                    }
-                } else {
-                    PIMPC_MAT_PTRS(MB())
-                    using Row = SRow<T, NB>;
-                    stream_rows<Row, NX, kPF>(
-                        [&](int r) {
-                            Row x;
-                            sload_into<T, NX>(x.x, Am + r * NX);
-                            sload_into<T, NU>(x.x + NX, Bm + r * NU);
-                            return x;
-                        },
-                        [&](int r, const Row& x) {
+                        for (int r = 0; r < NX; ++r) {
                             const T dd = ddl[r][tid];
 #pragma unroll
-                            for (int c = 0; c < NB; ++c) tg[c] += x.x[c] * dd;
-                        });
-                }
-                if (lane == 0) {  // the g slots are free again (read before the last barrier)
+                            for (int c = 0; c < NX; ++c) tg[c] += Ar[r * NX + c] * dd;
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) bnd_g[wave][c] = tg[c];
+                            for (int c = 0; c < NU; ++c) tg[NX + c] += Br[r * NU + c] * dd;
+                        }
+                    } else {
+                        PIMPC_MAT_PTRS(MB())
+                        using Row = SRow<T, NB>;
+                        stream_rows<Row, NX, kPF>(
+                            [&](int r) {
+                                Row x;
+                                sload_into<T, NX>(x.x, Am + r * NX);
+                                sload_into<T, NU>(x.x + NX, Bm + r * NU);
+                                return x;
+                            },
+                            [&](int r, const Row& x) {
+                                const T dd = ddl[r][tid];
+#pragma unroll
+                                for (int c = 0; c < NB; ++c) tg[c] += x.x[c] * dd;
+                            });
+                    }
+                    if (lane == 0) {  // the g slots are free again (read before the last barrier)
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) bnd_g[wave][c] = tg[c];
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
-            double csum = 0.0, rpm = 0.0, rdm = 0.0;
             if (run) {
+                if (check) {
 #pragma unroll
-                for (int i = 0; i < NB; ++i) tg[i] = shl1(tg[i]);  // every lane active (see step 2)
-                const int wnext = wave + 1 < kBinWaves ? wave + 1 : wave;
+                    for (int i = 0; i < NB; ++i) tg[i] = shl1(tg[i]);  // every lane active (see step 2)
+                    const int wnext = wave + 1 < kBinWaves ? wave + 1 : wave;
 #pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                    const T tn = from_next_wave ? bnd_g[wnext][i] : tg[i];
-                    rdpart = fmax(rdpart, fabs(dzl[i][tid] + (hasnext ? tn : T(0))));
+                    for (int i = 0; i < NB; ++i) {
+                        const T tn = from_next_wave ? bnd_g[wnext][i] : tg[i];
+                        rdpart = fmax(rdpart, fabs(dzl[i][tid] + (hasnext ? tn : T(0))));
+                    }
                 }
                 if (!act) {
                     cpart = T(0);
                     rpart = T(0);
                     rdpart = T(0);
                 }
-                csum = wave_sum((double)cpart);
-                rpm = wave_max((double)rpart);
-                rdm = wave_max((double)rdpart);
+                const double csum = wave_sum((double)cpart);
+                double rpm = 0.0, rdm = 0.0;
+                if (check) {
+                    rpm = wave_max((double)rpart);
+                    rdm = wave_max((double)rdpart);
+                }
                 if (lane == 0) {
                     red[wave * 4 + 0] = csum;
                     red[wave * 4 + 1] = rpm;
@@ -562,7 +586,9 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                 }
             }
             __syncthreads();
-            if (run && leader) {
+            if (run) {
+                // every wave of the instance sums the same partials in the same
+                // order, so all of them take the same decisions
                 const int nw = (N + 63) >> 6;
                 double cs = 0.0, rp = 0.0, rd = 0.0;
                 for (int w = gw0; w < gw0 + nw; ++w) {
@@ -571,22 +597,63 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     rd = fmax(rd, red[w * 4 + 2]);
                 }
                 const double rho64 = (*AP()).rho;
-                c_last = rho64 * cs;
-                rp_last = rp;
-                rd_last = rho64 * rd;
+                const double c_now = rho64 * cs;
                 bool stop = false;
-                if (!(c_last < INFINITY)) {  // NaN or Inf
-                    status = -4;
-                    stop = true;
+                if (check) {
+                    c_last = c_now;
+                    rp_last = rp;
+                    rd_last = rho64 * rd;
+                    if (!(c_now < INFINITY)) {  // NaN or Inf
+                        status = -4;
+                        stop = true;
+                    }
+                    if (use_eps && c_now <= (*AP()).eps) stop = true;
                 }
-                if (use_eps && c_last <= (*AP()).eps) stop = true;
-                gdone[gw0] = stop ? 1 : 0;
+                // steps 6-7 (restart acceleration): momentum while c keeps
+                // falling by the factor eta, else restart (alpha = 1, hats =
+                // current iterate); c_prev starts at 1
+                if (accel && !stop) {
+                    if (c_now <= (*AP()).eta * c_prev) {
+                        const double a1 = 0.5 + 0.5 * sqrt(1.0 + 4.0 * alpha * alpha);
+                        coef = (alpha - 1.0) / a1;
+                        alpha = a1;
+                    } else {
+                        alpha = 1.0;
+                        coef = 0.0;
+                        ++restarts;
+                    }
+                    c_prev = c_now;
+                }
+                if (leader) gdone[gw0] = stop ? 1 : 0;
             }
             __syncthreads();
             if (run) done = gdone[gw0] != 0;
             bool all_done = true;
             for (unsigned m = leader_mask; m; m &= m - 1) all_done = all_done && (gdone[__ffs(m) - 1] != 0);
             if (all_done) break;
+            // hats for the next iteration: new + coef (new - previous); the
+            // previous actual iterate moves to `prev` (not after the last step)
+            if (accel && run && !done && it + 1 < K && act) {
+                const gptr<T> pv = (gptr<T>)((T*)(*AP()).prev + (*IP()).st_off);
+                const T cf = (T)coef;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const int64_t o0 = (int64_t)(0 * NB + i) * N + k, o1 = (int64_t)(1 * NB + i) * N + k,
+                                  o2 = (int64_t)(2 * NB + i) * N + k, o3 = (int64_t)(3 * NB + i) * N + k,
+                                  o4 = (int64_t)(4 * NB + i) * N + k;
+                    const T p0 = pv[o0], p1 = pv[o1], p2 = pv[o2], p3 = pv[o3], p4 = pv[o4];
+                    pv[o0] = v[i];
+                    pv[o1] = z[i];
+                    pv[o2] = th[i];
+                    pv[o3] = be[i];
+                    pv[o4] = la[i];
+                    v[i] += cf * (v[i] - p0);
+                    z[i] += cf * (z[i] - p1);
+                    th[i] += cf * (th[i] - p2);
+                    be[i] += cf * (be[i] - p3);
+                    la[i] += cf * (la[i] - p4);
+                }
+            }
         }
     }
 
@@ -616,7 +683,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
         if (a.info) {
             InfoDev r;
             r.iters = iters;
-            r.restarts = 0;
+            r.restarts = restarts;
             r.c = c_last;
             r.r_prim = rp_last;
             r.r_dual = rd_last;

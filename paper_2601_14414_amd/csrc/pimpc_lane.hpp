@@ -31,6 +31,10 @@ struct LaneArgs {
     int32_t write_iters;
     int32_t ckpt_every;  // > 0: store the iterate entering every ckpt_every-th iteration
     void* ckpt;          // checkpoint buffer (T), per instance at InstDev::ck_off
+    int32_t accel;       // 1: restart acceleration (Algorithm 1 steps 6-7)
+    int32_t pad_;
+    double eta;          // restart threshold
+    void* prev;          // accel: previous actual iterate (T, state layout)
 };
 
 template <int P>

@@ -130,6 +130,7 @@ struct pimpc_ctx_s {
     void* d_mats = nullptr;
     double* d_mats64 = nullptr;
     void* d_state = nullptr;
+    void* d_prev = nullptr;  // restart acceleration: the previous actual iterate (state layout)
     void* d_iters = nullptr;
     void* d_x0 = nullptr;
     void* d_up = nullptr;
@@ -436,6 +437,9 @@ static int fill_set_args(pimpc_ctx ctx, LaunchSet* ls) {
         a.write_iters = ls->write_iters;
         a.ckpt_every = ctx->opt.ckpt_every;
         a.ckpt = ctx->d_ckpt;
+        a.accel = ctx->opt.accel;
+        a.eta = ctx->opt.eta;
+        a.prev = ctx->d_prev;
     }
     if (!args.empty())
         HIPCHK(ctx, hipMemcpy(ls->d_args, args.data(), args.size() * sizeof(LaneArgs), hipMemcpyHostToDevice));
@@ -678,6 +682,7 @@ static void destroy_ctx(pimpc_ctx ctx) {
     rel(ctx->d_mats);
     rel(ctx->d_mats64);
     rel(ctx->d_state);
+    rel(ctx->d_prev);
     rel(ctx->d_iters);
     rel(ctx->d_x0);
     rel(ctx->d_up);
@@ -718,7 +723,9 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     if (o->precision != PIMPC_FP32 && o->precision != PIMPC_FP64)
         return ctx->fail(PIMPC_E_ARG, "precision must be PIMPC_FP32 or PIMPC_FP64");
     if (o->accel != 0 && o->accel != 1) return ctx->fail(PIMPC_E_ARG, "accel must be 0 or 1");
-    if (o->accel == 1) return ctx->fail(PIMPC_E_UNSUPPORTED, "restart acceleration is not built in this version");
+    if (o->accel == 1 && !(o->eta > 0.0 && o->eta <= 1.0)) return ctx->fail(PIMPC_E_ARG, "eta must be in (0, 1]");
+    if (o->accel == 1 && o->ckpt_every > 0)
+        return ctx->fail(PIMPC_E_UNSUPPORTED, "the taped forward differentiates plain ADMM (accel = 0)");
     if (o->warm_start != 0 && o->warm_start != 1) return ctx->fail(PIMPC_E_ARG, "warm_start must be 0 or 1");
     if (o->ckpt_every < 0) return ctx->fail(PIMPC_E_ARG, "ckpt_every must be >= 0");
     if (o->schedule < 0) return ctx->fail(PIMPC_E_ARG, "schedule must be >= 0");
@@ -794,6 +801,11 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             I.cls = -1;
             I.nxp = rnx;
             I.nup = rnu;
+            if (o->accel == 1)
+                return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                 "instance %d (nx=%d, nu=%d, N=%d): restart acceleration needs the lane family "
+                                 "(a per-iteration residual reduction across the row family's workgroups is "
+                                 "not built)", i, I.nx, I.nu, I.N);
             ctx->row_insts.push_back(i);
         }
         I.nbp = I.nxp + I.nup;
@@ -869,6 +881,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(ctx->d_tasks, tasks.data(), tasks.size() * sizeof(FactorTask), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemset(ctx->d_state, 0, ctx->st_elems * ts));
+    if (o->accel == 1) DALLOC(ctx->d_prev, char, ctx->st_elems * ts);
     HIPCHK(ctx, hipMemset(ctx->d_iters, 0, ctx->it_elems * ts));
     HIPCHK(ctx, hipMemset(ctx->d_up, 0, ctx->sum_nu * ts));
 

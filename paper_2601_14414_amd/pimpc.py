@@ -251,11 +251,13 @@ class Solver:
 
     def __init__(self, problems: Sequence, rho: float = 1.0, max_iter: int = 200, eps: float = 0.0,
                  check_every: int = 1, precision: int = PIMPC_FP32, warm_start: bool = False,
-                 ckpt_every: int = 0, schedule: int = 0, stream: Optional[int] = None):
+                 ckpt_every: int = 0, schedule: int = 0, stream: Optional[int] = None,
+                 accel: bool = False, eta: float = 0.999):
         self.problems = list(problems)
         o = pimpc_default_options()
         o.rho, o.max_iter, o.eps, o.check_every = rho, max_iter, eps, check_every
         o.precision, o.warm_start, o.ckpt_every, o.schedule = precision, int(warm_start), ckpt_every, schedule
+        o.accel, o.eta = int(bool(accel)), eta
         self.opts = o
         self.ctx, self._keep = pimpc_setup(self.problems, o, stream)
         self.count = len(self.problems)

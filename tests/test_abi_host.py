@@ -82,7 +82,18 @@ def test_bad_problem_data_rejected():
 
 
 def test_unsupported_requests_are_reported():
-    assert _setup_code([W.plain_fp64_problem(0)], accel=1)[0] == P.PIMPC_E_UNSUPPORTED
+    # restart acceleration runs on the lane family only (a long wide horizon
+    # goes to the row family), and the taped forward differentiates plain ADMM
+    lh = W.long_horizon_problem(0, N=256, K=10)
+    code, msg = _setup_code([lh], accel=1)
+    assert code == P.PIMPC_E_UNSUPPORTED and "restart" in msg
+    code, msg = _setup_code([W.plain_fp64_problem(0)], accel=1, ckpt_every=20)
+    assert code == P.PIMPC_E_UNSUPPORTED and "accel" in msg
+
+
+@pytest.mark.parametrize("eta", [0.0, -0.5, 1.5, float("nan")])
+def test_bad_restart_threshold_rejected(eta):
+    assert _setup_code([W.plain_fp64_problem(0)], accel=1, eta=eta)[0] == P.PIMPC_E_ARG
 
 
 def test_error_text_available_without_context():
