@@ -1,14 +1,16 @@
 """Benchmark: ADMM stage-iterations/s of the piMPC hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--no-accel]
 
 A step is one full solve (all iterations) of the long-horizon workload: the
 12-mass chain (nx=24, nu=11), horizon N=1024, 500 plain ADMM iterations, FP32
 iteration arithmetic with the FP64 stage factorisation done at setup.
 Inputs are resident in HBM before timing starts; the timed region is the
 graph-replayed solve on the current torch stream.  value = N * iterations *
-steps / seconds.  Extra keys report the 4096-instance uneven batch and the
-CPU oracle timed on the host.  Prints one JSON line.
+steps / seconds.  Extra keys report the 4096-instance uneven batch, the
+differentiable batch (forward + backward against the plain forward), restart
+acceleration against plain ADMM to a tolerance on the batch, and the CPU
+oracle timed on the host.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -104,6 +106,37 @@ def bench_batch(torch, P, W, steps, warmup):
             "iterations": 300, "achieved_tflops": flops / (min(per) / 1e3) / 1e12}
 
 
+def bench_accel(torch, P, W, steps, warmup):
+    """Time to solution on the 4096-instance batch, plain ADMM against restart
+    acceleration (Algorithm 1 steps 6-7): both stop each instance at
+    c <= 1e-8 (checked every 10 iterations), at most 6000 iterations."""
+    import numpy as np
+    problems = W.random_batch(4096, base_seed=1000, K=6000)
+    stream = torch.cuda.current_stream().cuda_stream
+    dev = torch.device("cuda")
+    x0 = torch.tensor(np.concatenate([p.x0 for p in problems]), dtype=torch.float32, device=dev)
+    Ns = np.array([p.N for p in problems])
+    res = {}
+    for name, accel in (("plain", False), ("accel", True)):
+        s = P.Solver(problems, max_iter=6000, eps=1e-8, check_every=10, precision=P.PIMPC_FP32,
+                     accel=accel, stream=stream)
+        u0 = torch.empty(s.sum_nu, dtype=torch.float32, device=dev)
+        info = torch.zeros(40 * len(problems), dtype=torch.uint8, device=dev)
+        fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream)
+        ms, per = time_solves(torch, fn, steps, warmup)
+        rec = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
+        its = rec["iters"].astype(np.int64)
+        res[name] = {"ms_per_solve": ms / steps, "mean_iters": float(its.mean()), "max_iters": int(its.max()),
+                     "converged": int((rec["c"] <= 1e-8).sum()),
+                     "stage_iterations_per_s": float((Ns * its).sum() / (min(per) / 1e3))}
+        if accel:
+            res[name]["mean_restarts"] = float(rec["restarts"].mean())
+        s.close()
+    res["speedup"] = res["plain"]["ms_per_solve"] / res["accel"]["ms_per_solve"]
+    res["workload"] = "4096 random instances (batch recipe), FP32, to c <= 1e-8, check every 10, max 6000"
+    return res
+
+
 def bench_diff(torch, P, W, steps, warmup):
     """Differentiable batch: 1024 chains (nx=8, nu=3, N=128), 200 iterations,
     checkpoints every 20.  Returns the time of (taped forward + backward) over
@@ -152,6 +185,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-accel", action="store_true", help="skip the restart-acceleration extra")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -212,6 +246,8 @@ def main():
     if not args.no_extra:
         out["batch_4096"] = bench_batch(torch, P, W, max(3, args.steps // 4), 1)
         out["differentiable_1024"] = bench_diff(torch, P, W, max(3, args.steps // 4), 1)
+        if not args.no_accel:
+            out["restart_accel_4096"] = bench_accel(torch, P, W, 2, 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
