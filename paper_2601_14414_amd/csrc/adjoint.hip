@@ -555,22 +555,43 @@ __global__ void __launch_bounds__(kBwdThreads) lane_bwd_kernel(BwdArgs a) {
 
 constexpr int kCh = 17;  // LDS pitch of the 16 x 16 work matrices
 
-__device__ void ch_inverse(double* M, double* Out, int n) {
-    // Gauss-Jordan on an SPD matrix (thread 0; n <= 16): Out = M^-1
-    double W[16][32];
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < 2 * n; ++j) W[i][j] = j < n ? M[i * kCh + j] : (j - n == i ? 1.0 : 0.0);
-    for (int c = 0; c < n; ++c) {
-        const double p = W[c][c];
-        for (int j = 0; j < 2 * n; ++j) W[c][j] /= p;
-        for (int r = 0; r < n; ++r)
-            if (r != c) {
-                const double f = W[r][c];
-                for (int j = 0; j < 2 * n; ++j) W[r][j] -= f * W[c][j];
-            }
+// In-place Gauss-Jordan inverses of the two stage matrices (order nb) and of G (order nu), all three at once
+// by the threads of the workgroup.  The matrices are symmetric positive definite, so no pivoting is needed.
+// Each pivot step keeps the old pivot row and column in pr / pc ([3][16]) and then rewrites every element:
+// pivot p = 1 / a_kk, row k scaled by p, column k scaled by -p, the rest a_ij - a_ik a_kj p.
+__device__ void ch_inverse3(double* M0, double* M1, double* M2, int nb, int nu, double* pr, double* pc) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < nb; ++k) {
+        const int nm = k < nu ? 3 : 2;
+        for (int e = t; e < nm * nb; e += blockDim.x) {
+            const int m = e / nb, x = e % nb;
+            if (m == 2 && x >= nu) continue;
+            const double* M = m == 0 ? M0 : (m == 1 ? M1 : M2);
+            pr[m * 16 + x] = M[k * kCh + x];
+            pc[m * 16 + x] = M[x * kCh + k];
+        }
+        __syncthreads();
+        const int tot = 2 * nb * nb + (nm == 3 ? nu * nu : 0);
+        for (int e = t; e < tot; e += blockDim.x) {
+            const int m = e < 2 * nb * nb ? e / (nb * nb) : 2;
+            const int n = m == 2 ? nu : nb;
+            const int r = m == 2 ? e - 2 * nb * nb : e - m * nb * nb;
+            const int i = r / n, j = r % n;
+            double* M = m == 0 ? M0 : (m == 1 ? M1 : M2);
+            const double p = 1.0 / pc[m * 16 + k];
+            double v;
+            if (i == k && j == k)
+                v = p;
+            else if (i == k)
+                v = pr[m * 16 + j] * p;
+            else if (j == k)
+                v = -pc[m * 16 + i] * p;
+            else
+                v = M[i * kCh + j] - pc[m * 16 + i] * pr[m * 16 + j] * p;
+            M[i * kCh + j] = v;
+        }
+        __syncthreads();
     }
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) Out[i * kCh + j] = W[i][j + n];
 }
 
 __global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ inst, int count,
@@ -588,8 +609,12 @@ __global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ i
     const double* Q = mats64 + I.mat64_off + o.Q64;
     const double* R = mats64 + I.mat64_off + o.R64;
     const float* gr = grads + I.gr_off;
-    __shared__ double Ab[16 * kCh], Ma[16 * kCh], Mb[16 * kCh], Ha[16 * kCh], Hb[16 * kCh], G[16 * kCh],
-        Gi[16 * kCh], Jm[16 * kCh], T1[16 * kCh], Mba[16 * kCh], Mbb[16 * kCh], Gb[16 * kCh];
+    __shared__ double Ab[16 * kCh], Ha[16 * kCh], Hb[16 * kCh], Gi[16 * kCh], Jm[16 * kCh], T1[16 * kCh],
+        Mba[16 * kCh], Mbb[16 * kCh], Gb[16 * kCh], pr[3 * 16], pc[3 * 16];
+    // the stage matrices and G are built in Ha, Hb, Gi and inverted in place
+    double* Ma = Ha;
+    double* Mb = Hb;
+    double* G = Gi;
     const int t = threadIdx.x;
     // Abar rows (all NB rows) and the two M matrices
     for (int e = t; e < NB * NB; e += blockDim.x) {
@@ -614,12 +639,7 @@ __global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ i
         G[i * kCh + j] = s;
     }
     __syncthreads();
-    if (t == 0) {
-        ch_inverse(Ma, Ha, NB);
-        ch_inverse(Mb, Hb, NB);
-        ch_inverse(G, Gi, NU);
-    }
-    __syncthreads();
+    ch_inverse3(Ma, Mb, G, NB, NU, pr, pc);
     // J = G^-1 [B' I]
     for (int e = t; e < NU * NB; e += blockDim.x) {
         const int i = e / NB, j = e % NB;
