@@ -32,12 +32,12 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.orc_factor.restype = ctypes.c_int
-    lib.orc_factor.argtypes = [ctypes.c_int] * 3 + [_dp] * 4 + [ctypes.c_double, _dp, _dp]
+    lib.orc_factor.argtypes = [ctypes.c_int] * 3 + [_dp] * 5 + [ctypes.c_double, _dp, _dp]
     lib.orc_solve.restype = ctypes.c_int
-    lib.orc_solve.argtypes = ([ctypes.c_int] * 3 + [_dp] * 9 + [ctypes.c_double, ctypes.c_int,
+    lib.orc_solve.argtypes = ([ctypes.c_int] * 3 + [_dp] * 10 + [ctypes.c_double, ctypes.c_int,
                               ctypes.c_double, ctypes.c_int, ctypes.c_double] + [_dp] * 4 + [_ip])
     lib.orc_grad.restype = ctypes.c_int
-    lib.orc_grad.argtypes = ([ctypes.c_int] * 3 + [_dp] * 7 + [ctypes.c_double, ctypes.c_int]
+    lib.orc_grad.argtypes = ([ctypes.c_int] * 3 + [_dp] * 8 + [ctypes.c_double, ctypes.c_int]
                              + [_dp] * 7)
     _lib = lib
     return lib
@@ -57,6 +57,12 @@ class OracleError(RuntimeError):
     pass
 
 
+def _wdu(p):
+    """Input-rate weight W_du of problem `p` as (m, m) float64, or None (= 0)."""
+    W = getattr(p, "Wdu", None)
+    return None if W is None else _c(W)
+
+
 def factor(p):
     """Stage caches (H_k, J_k) of Algorithm 1 for problem `p` (FP64)."""
     lib = _load()
@@ -64,7 +70,7 @@ def factor(p):
     H = np.zeros((p.N, nb, nb))
     J = np.zeros((p.N, p.nu, nb))
     rc = lib.orc_factor(p.nx, p.nu, p.N, _ptr(_c(p.stage_A())), _ptr(_c(p.stage_B())),
-                        _ptr(_c(p.Q)), _ptr(_c(p.R)), float(p.rho), _ptr(H), _ptr(J))
+                        _ptr(_c(p.Q)), _ptr(_c(p.R)), _ptr(_wdu(p)), float(p.rho), _ptr(H), _ptr(J))
     if rc != 0:
         raise OracleError("stage matrix not positive definite")
     return H, J
@@ -95,7 +101,8 @@ def solve(p, K: Optional[int] = None, eps: float = 0.0, accel: bool = False, eta
     qbar = None if p.qbar is None else _c(p.qbar)
     xb0 = _c(p.xbar0() if xbar0 is None else xbar0)
     rc = lib.orc_solve(p.nx, p.nu, p.N, _ptr(_c(p.stage_A())), _ptr(_c(p.stage_B())), _ptr(e),
-                       _ptr(_c(p.Q)), _ptr(_c(p.R)), _ptr(qbar), _ptr(_c(p.lb())), _ptr(_c(p.ub())),
+                       _ptr(_c(p.Q)), _ptr(_c(p.R)), _ptr(_wdu(p)), _ptr(qbar), _ptr(_c(p.lb())),
+                       _ptr(_c(p.ub())),
                        _ptr(xb0), float(p.rho), int(K), float(eps), int(bool(accel)), float(eta),
                        _ptr(st), _ptr(du), _ptr(xs), _ptr(hist), ctypes.byref(it))
     if rc != 0:
@@ -105,13 +112,15 @@ def solve(p, K: Optional[int] = None, eps: float = 0.0, accel: bool = False, eta
                 u0=np.asarray(p.u_prev, np.float64) + du[0])
 
 
-def grad(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ubar) -> dict:
+def grad(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ubar, Wdu=None) -> dict:
     """Vector-Jacobian product of u_0 (output of the K-th step 1, cold start,
-    u_prev = 0, e = 0) with respect to (x0, diag Q, diag R, A, B)."""
+    u_prev = 0, e = 0) with respect to (x0, diag Q, diag R, A, B); Wdu is a
+    fixed input-rate weight (None = 0)."""
     lib = _load()
     out = dict(u0=np.zeros(nu), dA=np.zeros((nx, nx)), dB=np.zeros((nx, nu)),
                dQd=np.zeros(nx), dRd=np.zeros(nu), dx0=np.zeros(nx))
-    rc = lib.orc_grad(nx, nu, N, _ptr(_c(A)), _ptr(_c(B)), _ptr(_c(Qd)), _ptr(_c(Rd)),
+    W = None if Wdu is None else _c(Wdu)
+    rc = lib.orc_grad(nx, nu, N, _ptr(_c(A)), _ptr(_c(B)), _ptr(_c(Qd)), _ptr(_c(Rd)), _ptr(W),
                       _ptr(_c(lb)), _ptr(_c(ub)), _ptr(_c(x0)), float(rho), int(K), _ptr(_c(ubar)),
                       _ptr(out["u0"]), _ptr(out["dA"]), _ptr(out["dB"]), _ptr(out["dQd"]),
                       _ptr(out["dRd"]), _ptr(out["dx0"]))

@@ -14,6 +14,12 @@
  *   - the stage caches of Algorithm 1 ("cache"): J_k = (Bbar_k' Bbar_k)^-1 Bbar_k'
  *     and H_k = (Qbar + rho I + rho Abar_{k+1}' Abar_{k+1})^-1 (k < N-1),
  *     H_{N-1} = (Qbar + rho I)^-1 (proof of Theorem 2, eqn. (8));
+ *   - optionally the input-rate weight W_du of the experiments (Section V:
+ *     AFTI-16 and CSTR), a term 1/2 ||du_k||^2_{W_du} added to the cost of
+ *     Theorem 2.  It enters only the du sub-problem of eqn. (8), which becomes
+ *     argmin 1/2 du' W_du du + rho/2 ||Bbar_k du - v_k + beta_k||^2, so
+ *     J_k = (W_du + rho Bbar_k' Bbar_k)^-1 rho Bbar_k' (W_du = 0 gives the
+ *     paper's J_k);
  *   - the closed-form iteration of eqn. (8) / Algorithm 1 steps 1-3, the
  *     residual c^{i+1} of step 4, the eps stop of step 5 and (optionally) the
  *     restart acceleration of steps 6-7;
@@ -38,6 +44,7 @@
  *
  * Layouts (all row-major, double):
  *   A [N][n][n], B [N][n][m], e [N][n] (NULL = 0), Q [n][n], R [m][m],
+ *   Wdu [m][m] (NULL = 0),
  *   qbar [nb] (NULL = 0), lb/ub [nb] (+-INFINITY allowed), xbar0 [nb],
  *   state [5][N][nb] = (v, z, theta, beta, lambda); z[k] holds z_{k+1}.
  */
@@ -130,17 +137,19 @@ typedef struct {
     double *ebar;  /* [N][nb]     */
     double *Qbar;  /* [nb][nb]    */
     double *qbar;  /* [nb]        */
+    double *W;     /* [m][m] input-rate weight (zero if absent) */
     double *H;     /* [N][nb][nb] */
     double *J;     /* [N][m][nb]  */
 } vform_t;
 
 static void vform_free(vform_t *V) {
-    free(V->Abar); free(V->Bbar); free(V->ebar); free(V->Qbar); free(V->qbar);
+    free(V->Abar); free(V->Bbar); free(V->ebar); free(V->Qbar); free(V->qbar); free(V->W);
     free(V->H); free(V->J);
 }
 
 static void vform_build(vform_t *V, int n, int m, int N, const double *A, const double *B,
-                        const double *e, const double *Q, const double *R, const double *qbar) {
+                        const double *e, const double *Q, const double *R, const double *W,
+                        const double *qbar) {
     int nb = n + m;
     V->n = n; V->m = m; V->nb = nb; V->N = N;
     V->Abar = (double *)calloc((size_t)N * nb * nb, sizeof(double));
@@ -148,6 +157,8 @@ static void vform_build(vform_t *V, int n, int m, int N, const double *A, const 
     V->ebar = (double *)calloc((size_t)N * nb, sizeof(double));
     V->Qbar = (double *)calloc((size_t)nb * nb, sizeof(double));
     V->qbar = (double *)calloc((size_t)nb, sizeof(double));
+    V->W = (double *)calloc((size_t)m * m, sizeof(double));
+    if (W) memcpy(V->W, W, sizeof(double) * (size_t)m * m);
     V->H = (double *)calloc((size_t)N * nb * nb, sizeof(double));
     V->J = (double *)calloc((size_t)N * m * nb, sizeof(double));
     for (int k = 0; k < N; ++k) {
@@ -197,13 +208,13 @@ static int vform_factor(vform_t *V, double rho) {
             }
         rc = spd_inverse(nb, M, V->H + (size_t)k * nb * nb);
         if (rc) break;
-        /* G_k = Bbar_k' Bbar_k,  J_k = G_k^-1 Bbar_k' */
+        /* G_k = W_du + rho Bbar_k' Bbar_k,  J_k = G_k^-1 rho Bbar_k' */
         const double *Bb = V->Bbar + (size_t)k * nb * m;
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) {
                 double t = 0.0;
                 for (int r = 0; r < nb; ++r) t += Bb[IDX2(r, i, m)] * Bb[IDX2(r, j, m)];
-                G[IDX2(i, j, m)] = t;
+                G[IDX2(i, j, m)] = V->W[IDX2(i, j, m)] + rho * t;
             }
         rc = spd_inverse(m, G, Gi);
         if (rc) break;
@@ -211,7 +222,7 @@ static int vform_factor(vform_t *V, double rho) {
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < nb; ++j) {
                 double t = 0.0;
-                for (int r = 0; r < m; ++r) t += Gi[IDX2(i, r, m)] * Bb[IDX2(j, r, m)];
+                for (int r = 0; r < m; ++r) t += Gi[IDX2(i, r, m)] * rho * Bb[IDX2(j, r, m)];
                 Jk[IDX2(i, j, nb)] = t;
             }
     }
@@ -331,9 +342,9 @@ static void residuals(const vform_t *V, double rho, const double *const hat[5],
 
 /* Stage caches only: H [N][nb][nb], J [N][m][nb].  0 or -1 (not SPD). */
 int orc_factor(int n, int m, int N, const double *A, const double *B, const double *Q,
-               const double *R, double rho, double *H, double *J) {
+               const double *R, const double *Wdu, double rho, double *H, double *J) {
     vform_t V;
-    vform_build(&V, n, m, N, A, B, NULL, Q, R, NULL);
+    vform_build(&V, n, m, N, A, B, NULL, Q, R, Wdu, NULL);
     int rc = vform_factor(&V, rho);
     if (rc == 0) {
         memcpy(H, V.H, sizeof(double) * (size_t)N * V.nb * V.nb);
@@ -354,14 +365,15 @@ int orc_factor(int n, int m, int N, const double *A, const double *B, const doub
  * Returns 0, -1 if a stage matrix is not SPD, -2 on bad arguments.
  */
 int orc_solve(int n, int m, int N, const double *A, const double *B, const double *e,
-              const double *Q, const double *R, const double *qbar, const double *lb,
-              const double *ub, const double *xbar0, double rho, int K, double eps, int accel,
-              double eta, double *state, double *du, double *xs, double *hist, int *iters) {
+              const double *Q, const double *R, const double *Wdu, const double *qbar,
+              const double *lb, const double *ub, const double *xbar0, double rho, int K, double eps,
+              int accel, double eta, double *state, double *du, double *xs, double *hist,
+              int *iters) {
     if (n <= 0 || m <= 0 || N <= 0 || K < 0 || !(rho > 0.0)) return -2;
     int nb = n + m;
     size_t S = (size_t)N * nb;
     vform_t V;
-    vform_build(&V, n, m, N, A, B, e, Q, R, qbar);
+    vform_build(&V, n, m, N, A, B, e, Q, R, Wdu, qbar);
     int rc = vform_factor(&V, rho);
     if (rc) { vform_free(&V); return -1; }
 
@@ -426,7 +438,8 @@ int orc_solve(int n, int m, int N, const double *A, const double *B, const doubl
 
 /*
  * Loss gradient for a time-invariant instance with diagonal weights, e = 0,
- * qbar = 0, u_prev = 0 and a cold start.  The output u_0 = du_0 of the K-th
+ * qbar = 0, u_prev = 0 and a cold start; Wdu [m][m] (NULL = 0) is a fixed,
+ * non-differentiated input-rate weight.  The output u_0 = du_0 of the K-th
  * step 1 (Algorithm 1 output) is a function of (x0, diag Q, diag R, A, B);
  * given ubar = dL/du_0 this returns the vector-Jacobian products.
  *   A [n][n], B [n][m], Qd [n], Rd [m], lb/ub [nb], x0 [n], ubar [m]
@@ -434,7 +447,7 @@ int orc_solve(int n, int m, int N, const double *A, const double *B, const doubl
  * The whole tape (K states) is kept in memory.  Returns 0, -1 (not SPD), -2.
  */
 int orc_grad(int n, int m, int N, const double *A, const double *B, const double *Qd,
-             const double *Rd, const double *lb, const double *ub, const double *x0, double rho,
+             const double *Rd, const double *Wdu, const double *lb, const double *ub, const double *x0, double rho,
              int K, const double *ubar, double *u0, double *dA, double *dB, double *dQd,
              double *dRd, double *dx0) {
     if (n <= 0 || m <= 0 || N <= 0 || K < 1 || !(rho > 0.0)) return -2;
@@ -451,7 +464,7 @@ int orc_grad(int n, int m, int N, const double *A, const double *B, const double
     for (int i = 0; i < n; ++i) Q[IDX2(i, i, n)] = Qd[i];
     for (int i = 0; i < m; ++i) R[IDX2(i, i, m)] = Rd[i];
     vform_t V;
-    vform_build(&V, n, m, N, Aall, Ball, NULL, Q, R, NULL);
+    vform_build(&V, n, m, N, Aall, Ball, NULL, Q, R, Wdu, NULL);
     if (vform_factor(&V, rho)) {
         vform_free(&V); free(Aall); free(Ball); free(Q); free(R);
         return -1;
@@ -663,7 +676,8 @@ int orc_grad(int n, int m, int N, const double *A, const double *B, const double
                 }
         }
     }
-    /* J = G^-1 Bbar', G = Bbar' Bbar:  Gbar = -G^-1 Jbar J',  Bbar_bar += Jbar' G^-1 + Bbar (Gbar + Gbar') */
+    /* J = G^-1 rho Bbar', G = W_du + rho Bbar' Bbar:  Gbar = -G^-1 Jbar J',
+     * Bbar_bar += rho Jbar' G^-1 + rho Bbar (Gbar + Gbar') */
     {
         double *G = (double *)malloc(sizeof(double) * (size_t)m * m);
         double *Gi = (double *)malloc(sizeof(double) * (size_t)m * m);
@@ -673,7 +687,7 @@ int orc_grad(int n, int m, int N, const double *A, const double *B, const double
             for (int j = 0; j < m; ++j) {
                 double t = 0.0;
                 for (int r = 0; r < nb; ++r) t += V.Bbar[IDX2(r, i, m)] * V.Bbar[IDX2(r, j, m)];
-                G[IDX2(i, j, m)] = t;
+                G[IDX2(i, j, m)] = V.W[IDX2(i, j, m)] + rho * t;
             }
         spd_inverse(m, G, Gi);
         for (int i = 0; i < m; ++i)
@@ -693,7 +707,7 @@ int orc_grad(int n, int m, int N, const double *A, const double *B, const double
                 double t = GiJb[IDX2(j, i, nb)];
                 for (int r = 0; r < m; ++r)
                     t += V.Bbar[IDX2(i, r, m)] * (Gb[IDX2(r, j, m)] + Gb[IDX2(j, r, m)]);
-                Bbb[IDX2(i, j, m)] += t;
+                Bbb[IDX2(i, j, m)] += rho * t;
             }
         free(G); free(Gi); free(Gb); free(GiJb);
     }

@@ -31,6 +31,8 @@ class Problem:
     A: (n, n) time-invariant or (N, n, n) time-varying; B likewise (n, m) or
     (N, n, m); e: None or (n,) / (N, n).  Q (n, n), R (m, m) symmetric PSD.
     qbar: None or (n+m,) linear term of the velocity-form cost (Theorem 2).
+    Wdu: None or (m, m) symmetric PSD input-rate weight, cost term
+    1/2 ||u_k - u_{k-1}||^2_{Wdu} (used by the paper's experiments, Section V).
     Bounds are per-component boxes; +-inf allowed.  x0 = x(t), u_prev = u(t-1).
     """
 
@@ -51,6 +53,7 @@ class Problem:
     K: int = 200
     e: Optional[np.ndarray] = None
     qbar: Optional[np.ndarray] = None
+    Wdu: Optional[np.ndarray] = None
 
     @property
     def nb(self) -> int:

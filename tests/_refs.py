@@ -80,6 +80,9 @@ def velocity_dense(p):
     for k in range(1, N + 1):
         P[xb(k), xb(k)] = Qbar
         qv[xb(k)] = qbar
+    if getattr(p, "Wdu", None) is not None:
+        for k in range(N):
+            P[du(k), du(k)] = p.Wdu
     lo = np.concatenate([np.full(N * nb, -np.inf), np.tile(p.lb(), N)])
     hi = np.concatenate([np.full(N * nb, np.inf), np.tile(p.ub(), N)])
     return dict(F=F, G=G, h=h, P=P, qv=qv, lo=lo, hi=hi, Abar=Abar, Bbar=Bbar, ebar=ebar)
@@ -141,17 +144,30 @@ def lqr(A, B, Q, R, x0, N):
 
 def original_qp(p):
     """Sparse QP (2) of problem (1) in original coordinates y = col(u_0, x_1,
-    ..., u_{N-1}, x_N): cost 1/2 y'Hy, equality rows Aeq y = beq (dynamics),
-    box rows on every u and x.  Returns dict."""
+    ..., u_{N-1}, x_N): cost 1/2 y'Hy + f'y, equality rows Aeq y = beq
+    (dynamics), box rows on every u and x.  An input-rate weight Wdu adds
+    sum_k 1/2 (u_k - u_{k-1})'Wdu(u_k - u_{k-1}) with u_{-1} = u_prev.
+    Returns dict."""
     n, m, N = p.nx, p.nu, p.N
     A, B, e = p.stage_A(), p.stage_B(), p.stage_e()
     ny = N * (n + m)
     uu = lambda k: slice(k * (n + m), k * (n + m) + m)
     xx = lambda k: slice(k * (n + m) + m, (k + 1) * (n + m))  # x_{k+1}
     H = np.zeros((ny, ny))
+    f = np.zeros(ny)
     for k in range(N):
         H[uu(k), uu(k)] = p.R
         H[xx(k), xx(k)] = p.Q
+    Wd = getattr(p, "Wdu", None)
+    if Wd is not None:
+        for k in range(N):
+            H[uu(k), uu(k)] += Wd
+            if k >= 1:
+                H[uu(k - 1), uu(k - 1)] += Wd
+                H[uu(k), uu(k - 1)] -= Wd
+                H[uu(k - 1), uu(k)] -= Wd
+            else:
+                f[uu(0)] -= Wd @ np.asarray(p.u_prev, np.float64)
     Aeq = np.zeros((N * n, ny))
     beq = np.zeros(N * n)
     for k in range(N):
@@ -168,7 +184,7 @@ def original_qp(p):
     for k in range(N):
         lo[uu(k)], hi[uu(k)] = p.umin, p.umax
         lo[xx(k)], hi[xx(k)] = p.xmin, p.xmax
-    return dict(H=H, Aeq=Aeq, beq=beq, lo=lo, hi=hi, uu=uu, xx=xx)
+    return dict(H=H, f=f, Aeq=Aeq, beq=beq, lo=lo, hi=hi, uu=uu, xx=xx)
 
 
 def eq_qp_original(p):
@@ -177,7 +193,7 @@ def eq_qp_original(p):
     H, Aeq, beq = D["H"], D["Aeq"], D["beq"]
     ny, ne = H.shape[0], Aeq.shape[0]
     K = np.block([[H, Aeq.T], [Aeq, np.zeros((ne, ne))]])
-    rhs = np.concatenate([np.zeros(ny), beq])
+    rhs = np.concatenate([-D["f"], beq])
     sol = np.linalg.solve(K, rhs)
     y = sol[:ny]
     N = p.N
@@ -201,7 +217,7 @@ def qp_admm(p, rho=1.0, iters=60000, tol=1e-12):
     y = np.zeros(ny)
     it = 0
     for it in range(1, iters + 1):
-        y = Minv @ (rho * E.T @ (w - lam))
+        y = Minv @ (-D["f"] + rho * E.T @ (w - lam))
         Ey = E @ y
         w_new = np.clip(Ey + lam, Ylo, Yhi)
         lam = lam + Ey - w_new
@@ -213,4 +229,5 @@ def qp_admm(p, rho=1.0, iters=60000, tol=1e-12):
     N = p.N
     us = np.array([y[D["uu"](k)] for k in range(N)])
     xs = np.array([y[D["xx"](k)] for k in range(N)])
-    return dict(xs=xs, us=us, y=y, w=w, lam=lam, iters=it, E=E, H=H, Ylo=Ylo, Yhi=Yhi, rho=rho)
+    return dict(xs=xs, us=us, y=y, w=w, lam=lam, iters=it, E=E, H=H, f=D["f"], Ylo=Ylo, Yhi=Yhi,
+                rho=rho)

@@ -99,6 +99,45 @@ def test_dual_update_and_residual_definitions(seed):
     assert c == pytest.approx(c_dense, rel=1e-12)
 
 
+def _rate_weight(seed, m):
+    rng = np.random.default_rng(50 + seed)
+    Wh = rng.standard_normal((m, m))
+    return Wh @ Wh.T / m + 0.1 * np.eye(m)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_p_update_with_rate_weight_equals_dense_subproblem(seed):
+    """With the input-rate weight of Section V the du block of the first ADMM
+    sub-problem gains 1/2 du'W du; the oracle's stage closed forms must still
+    equal the dense minimiser over the whole horizon."""
+    p = tiny_tv_problem(seed)
+    p = p.copy(Wdu=_rate_weight(seed, p.nu))
+    st0 = random_state(p, 150 + seed)
+    r = oracle.solve(p, K=1, state=st0)
+    D = _refs.velocity_dense(p)
+    q, s = _refs.state_to_qs(st0)
+    pv = _refs.p_subproblem(D, p.rho, q, s)
+    N, m = p.N, p.nu
+    np.testing.assert_allclose(r["du"].ravel(), pv[: N * m], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(r["xs"].ravel(), pv[N * m:], rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_rate_weight_fixed_point_is_kkt(seed):
+    """Time-varying affine data, no active bounds, input-rate weight and
+    u(t-1) != 0: the fixed point equals the KKT solution of problem (1) with
+    the rate term sum_k 1/2 (u_k - u_{k-1})'W(u_k - u_{k-1}) added."""
+    p = tiny_tv_problem(seed, bounded=False)
+    p = p.copy(qbar=None, Wdu=_rate_weight(seed, p.nu))
+    r = oracle.solve(p, K=80000, eps=1e-28)
+    xs_k, us_k = _refs.eq_qp_original(p)
+    np.testing.assert_allclose(r["xs"][:, :p.nx], xs_k, rtol=0, atol=1e-8)
+    np.testing.assert_allclose(r["xs"][:, p.nx:], us_k, rtol=0, atol=1e-8)
+    # the rate weight changes the optimum (so the test sees it)
+    xs_0, us_0 = _refs.eq_qp_original(p.copy(Wdu=None))
+    assert np.max(np.abs(us_0 - us_k)) > 1e-3
+
+
 # --- fixed points ------------------------------------------------------------
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -155,18 +194,26 @@ def _x_bound_case(seed):
                      rho=1.0, K=0)
 
 
-@pytest.mark.parametrize("case,seed", [("u", 0), ("u", 1), ("x", 0), ("x", 1)])
+def _u_bound_rate_case(seed):
+    """The input-bound case with an input-rate weight and u(t-1) != 0, so the
+    rate term couples u_0 to u(t-1) and the bound is still active."""
+    p = _u_bound_case(seed)
+    return p.copy(Wdu=0.5 * np.eye(1), u_prev=np.array([0.1]))
+
+
+@pytest.mark.parametrize("case,seed", [("u", 0), ("u", 1), ("x", 0), ("x", 1), ("uw", 0), ("uw", 1)])
 def test_constrained_fixed_point_matches_qp_admm(case, seed):
     """Active bounds: the converged oracle equals the optimum found by the
     general-QP ADMM of eqn. (3) (an independent algorithm on the sparse QP
-    (2)), whose own convergence, feasibility and KKT conditions are checked."""
-    p = _u_bound_case(seed) if case == "u" else _x_bound_case(seed)
+    (2)), whose own convergence, feasibility and KKT conditions are checked.
+    Case "uw" adds the input-rate weight of Section V."""
+    p = {"u": _u_bound_case, "x": _x_bound_case, "uw": _u_bound_rate_case}[case](seed)
     ref = _refs.qp_admm(p, rho=1.0, iters=100000, tol=1e-13)
     assert ref["iters"] < 100000
     E, y, w = ref["E"], ref["y"], ref["w"]
     assert np.max(np.abs(E @ y - w)) < 1e-11
     mu = ref["rho"] * ref["lam"]
-    assert np.max(np.abs(ref["H"] @ y + E.T @ mu)) < 1e-9
+    assert np.max(np.abs(ref["H"] @ y + ref["f"] + E.T @ mu)) < 1e-9
     at_lo = np.isclose(w, ref["Ylo"], atol=1e-10)
     at_hi = np.isclose(w, ref["Yhi"], atol=1e-10)
     free = ~(at_lo | at_hi)
@@ -232,11 +279,11 @@ def test_residuals_at_fixed_iterations_plain_fp64_problem():
 
 # --- adjoint vs central finite differences -------------------------------------
 
-def _loss_and_grad_fd(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ut, h=1e-6):
+def _loss_and_grad_fd(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ut, h=1e-6, Wdu=None):
     def loss(A_, B_, Qd_, Rd_, x0_):
         p = W.Problem(nx=nx, nu=nu, N=N, A=A_, B=B_, Q=np.diag(Qd_), R=np.diag(Rd_),
                       xmin=lb[:nx], xmax=ub[:nx], umin=lb[nx:], umax=ub[nx:], x0=x0_,
-                      u_prev=np.zeros(nu), rho=rho, K=K)
+                      u_prev=np.zeros(nu), rho=rho, K=K, Wdu=Wdu)
         u0 = oracle.solve(p)["u0"]
         return float(np.sum((u0 - ut) ** 2))
 
@@ -255,13 +302,16 @@ def _loss_and_grad_fd(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ut, h=1e-6):
     return grads
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_oracle_adjoint_matches_finite_differences(seed):
+@pytest.mark.parametrize("seed,masses,rho,rate", [(0, 2, 1.0, False), (1, 2, 1.0, False),
+                                                  (2, 3, 1.7, True)])
+def test_oracle_adjoint_matches_finite_differences(seed, masses, rho, rate):
     """Reverse mode through the unrolled iteration (differentiable layer)
-    equals central differences (h = 1e-6, FP64) of the oracle's own loss."""
+    equals central differences (h = 1e-6, FP64) of the oracle's own loss;
+    the last case adds a fixed input-rate weight and rho != 1."""
     rng = np.random.default_rng(seed)
-    A, B = W.mass_spring(2)
-    nx, nu, N, K, rho = 4, 1, 6, 25, 1.0
+    A, B = W.mass_spring(masses)
+    nx, nu, N, K = 2 * masses, masses - 1, 6, 25
+    Wdu = _rate_weight(seed, nu) if rate else None
     Qd = rng.uniform(0.5, 1.5, nx)
     Rd = rng.uniform(0.05, 0.2, nu)
     x0 = rng.uniform(-1, 1, nx)
@@ -270,10 +320,10 @@ def test_oracle_adjoint_matches_finite_differences(seed):
     ut = rng.normal(0, 0.1, nu)
     p = W.Problem(nx=nx, nu=nu, N=N, A=A, B=B, Q=np.diag(Qd), R=np.diag(Rd), xmin=lb[:nx],
                   xmax=ub[:nx], umin=lb[nx:], umax=ub[nx:], x0=x0, u_prev=np.zeros(nu),
-                  rho=rho, K=K)
+                  rho=rho, K=K, Wdu=Wdu)
     u0 = oracle.solve(p)["u0"]
-    g = oracle.grad(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, 2 * (u0 - ut))
+    g = oracle.grad(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, 2 * (u0 - ut), Wdu=Wdu)
     np.testing.assert_allclose(g["u0"], u0, atol=1e-14)
-    fd = _loss_and_grad_fd(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ut)
+    fd = _loss_and_grad_fd(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ut, Wdu=Wdu)
     for name, key in [("A", "dA"), ("B", "dB"), ("Qd", "dQd"), ("Rd", "dRd"), ("x0", "dx0")]:
         np.testing.assert_allclose(g[key], fd[name], rtol=1e-5, atol=1e-7, err_msg=name)
