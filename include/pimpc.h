@@ -67,8 +67,9 @@ extern "C" {
 typedef struct pimpc_ctx_s *pimpc_ctx;
 
 /*
- * Problem data, eqn. (1) with C = I, W_y = Q, W_u = R (Section II) and the
- * velocity-form linear term qbar of Theorem 2.
+ * Problem data, eqn. (1) with C = I, W_y = Q, W_u = R (Section II), the
+ * velocity-form linear term qbar of Theorem 2 and the input-rate weight
+ * W_du of the experiments (Section V).
  *   count          number of instances (>= 1)
  *   nx, nu, N      per-instance state/input sizes and horizon (count entries each)
  *   time_varying   0: one (A, B, e) per instance; 1: N stage copies per instance
@@ -77,6 +78,9 @@ typedef struct pimpc_ctx_s *pimpc_ctx;
  *   Q, R           nx*nx and nu*nu symmetric PSD weights per instance
  *   qbar           (nx+nu) linear cost term per instance, NULL = 0
  *   xmin, xmax     nx per instance; umin, umax nu per instance; +-INFINITY allowed
+ *   Wdu            nu*nu symmetric PSD input-rate weight per instance (cost term
+ *                  1/2 ||u_k - u_{k-1}||^2_Wdu), NULL = 0.  It changes only the
+ *                  du cache: J_k = (Wdu / rho + Bbar_k' Bbar_k)^-1 Bbar_k'.
  */
 typedef struct {
     int32_t count;
@@ -94,6 +98,7 @@ typedef struct {
     const double *xmax;
     const double *umin;
     const double *umax;
+    const double *Wdu;
 } pimpc_problem;
 
 /*

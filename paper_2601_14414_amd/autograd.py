@@ -51,12 +51,13 @@ class PiMPCLayer(torch.nn.Module):
     solved with `iters` plain ADMM iterations and differentiated through them."""
 
     def __init__(self, count: int, nx: int, nu: int, N: int, iters: int = 200, ckpt_every: int = 20,
-                 rho: float = 1.0, xbound: float = 4.0, ubound: float = 0.5):
+                 rho: float = 1.0, xbound: float = 4.0, ubound: float = 0.5, Wdu=None):
         super().__init__()
+        # Wdu: optional fixed (nu, nu) input-rate weight shared by the instances
         proto = W.Problem(nx=nx, nu=nu, N=N, A=np.eye(nx) * 0.9, B=np.ones((nx, nu)) / nx, Q=np.eye(nx),
                           R=0.1 * np.eye(nu), xmin=-xbound * np.ones(nx), xmax=xbound * np.ones(nx),
                           umin=-ubound * np.ones(nu), umax=ubound * np.ones(nu), x0=np.zeros(nx),
-                          u_prev=np.zeros(nu), rho=rho, K=iters)
+                          u_prev=np.zeros(nu), rho=rho, K=iters, Wdu=Wdu)
         self.solver = P.Solver([proto] * count, rho=rho, max_iter=iters, precision=P.PIMPC_FP32,
                                ckpt_every=ckpt_every,
                                stream=torch.cuda.current_stream().cuda_stream)

@@ -632,9 +632,10 @@ __global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ i
         Ma[i * kCh + j] = q + rho * s;
         Mb[i * kCh + j] = q;
     }
+    const double* Wd = mats64 + I.mat64_off + o.W64;
     for (int e = t; e < NU * NU; e += blockDim.x) {
         const int i = e / NU, j = e % NU;
-        double s = (i == j) ? 1.0 : 0.0;
+        double s = ((i == j) ? 1.0 : 0.0) + Wd[i * NU + j] / rho;
         for (int r = 0; r < NX; ++r) s += B[r * NU + i] * B[r * NU + j];
         G[i * kCh + j] = s;
     }

@@ -4,6 +4,9 @@
 //   H_k = (Qbar + rho I + rho Abar_{k+1}' Abar_{k+1})^-1   (k < N-1)
 //   H_{N-1} = (Qbar + rho I)^-1
 //   J_k = (Bbar_k' Bbar_k)^-1 Bbar_k' = (B_k' B_k + I)^-1 [B_k'  I]
+// or, with an input-rate weight W (cost 1/2 du' W du, Section V), the minimiser
+// of 1/2 du' W du + rho/2 ||Bbar du - (v - beta)||^2:
+//   J_k = (W / rho + B_k' B_k + I)^-1 [B_k'  I]
 // with Abar = [[A, B], [0, I]], Bbar = [[B], [I]], Qbar = blkdiag(Q, R).
 // One 64-thread workgroup builds one matrix in LDS, factors it by a
 // right-looking Cholesky (pivot-column scaling and trailing update spread
@@ -121,12 +124,13 @@ __global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ 
             }
         }
     } else {
-        // G = B' B + I (NU x NU); J = G^-1 [B' I]
+        // G = W / rho + B' B + I (NU x NU); J = G^-1 [B' I]
         const int sk = I.tv ? tk.stage : 0;
         const double* Bk = b64 + o.B64 + (int64_t)sk * NX * NU;
+        const double* Wd = b64 + o.W64;
         for (int idx = t; idx < NU * NU; idx += blockDim.x) {
             const int i = idx / NU, j = idx % NU;
-            double s = (i == j) ? 1.0 : 0.0;
+            double s = ((i == j) ? 1.0 : 0.0) + Wd[i * NU + j] / rho;
             for (int r = 0; r < NX; ++r) s += Bk[r * NU + i] * Bk[r * NU + j];
             M[i * kLd + j] = s;
         }

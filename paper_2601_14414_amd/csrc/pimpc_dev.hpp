@@ -53,16 +53,17 @@ __host__ __device__ inline int64_t mat_block_size(int32_t NX, int32_t NU, int32_
 }
 
 // FP64 factorisation inputs of one instance (padded):
-//   A [S][NX][NX] | B [S][NX][NU] | e [S][NX] | Q [NX][NX] | R [NU][NU]   with S = tv ? N : 1
+//   A [S][NX][NX] | B [S][NX][NU] | e [S][NX] | Q [NX][NX] | R [NU][NU] | Wdu [NU][NU]
+// with S = tv ? N : 1 (Wdu = input-rate weight, zero when absent).
 __host__ __device__ inline int64_t mat64_block_size(int32_t NX, int32_t NU, int32_t N, int32_t tv) {
     const int64_t S = tv ? N : 1;
-    return S * (NX * NX + NX * NU + NX) + NX * NX + NU * NU;
+    return S * (NX * NX + NX * NU + NX) + NX * NX + 2 * NU * NU;
 }
 
 // Offsets inside the blocks above.
 struct MatOffsets {
     int64_t J, H, Hb, A, B, e, qbar, lb, ub;  // T block (Hb unused when tv)
-    int64_t A64, B64, e64, Q64, R64;          // FP64 block
+    int64_t A64, B64, e64, Q64, R64, W64;     // FP64 block
 };
 
 __host__ __device__ inline MatOffsets mat_offsets(int32_t NX, int32_t NU, int32_t N, int32_t tv) {
@@ -93,6 +94,7 @@ __host__ __device__ inline MatOffsets mat_offsets(int32_t NX, int32_t NU, int32_
     o.e64 = o.B64 + S * NX * NU;
     o.Q64 = o.e64 + S * NX;
     o.R64 = o.Q64 + NX * NX;
+    o.W64 = o.R64 + NU * NU;
     return o;
 }
 

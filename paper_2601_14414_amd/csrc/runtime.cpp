@@ -239,10 +239,11 @@ const ClassDesc* class_desc(int id) {
 
 // --------------------------------------------------------------- data upload
 
-// Build the padded FP64 block (A, B, e, Q, R) of every instance from packed
-// caller arrays; only the stage data (A, B, e) when `stage_only`.
+// Build the padded FP64 block (A, B, e, Q, R, Wdu) of every instance from
+// packed caller arrays; only the stage data (A, B, e) when `stage_only`.
 static void build_mats64(pimpc_ctx ctx, const double* A, const double* B, const double* e,
-                         const double* Q, const double* R, std::vector<double>& out, bool stage_only) {
+                         const double* Q, const double* R, const double* Wdu, std::vector<double>& out,
+                         bool stage_only) {
     if (!stage_only) out.assign(ctx->mat64_elems, 0.0);
     int64_t oa = 0, ob = 0, oe = 0, oq = 0, orr = 0;
     for (int i = 0; i < ctx->count; ++i) {
@@ -272,6 +273,9 @@ static void build_mats64(pimpc_ctx ctx, const double* A, const double* B, const 
             for (int r = 0; r < NU; ++r)
                 for (int c = 0; c < NU; ++c)
                     b[o.R64 + r * NU + c] = (r < nu && c < nu) ? R[orr + r * nu + c] : (r == c ? 1.0 : 0.0);
+            for (int r = 0; r < NU; ++r)
+                for (int c = 0; c < NU; ++c)
+                    b[o.W64 + r * NU + c] = (Wdu && r < nu && c < nu) ? Wdu[orr + r * nu + c] : 0.0;
             oq += (int64_t)nx * nx;
             orr += (int64_t)nu * nu;
         }
@@ -748,7 +752,8 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         snu += nu;
     }
     if (!finite_arr(p->A, sA) || !finite_arr(p->B, sB) || (p->e && !finite_arr(p->e, se)) ||
-        !finite_arr(p->Q, sQ) || !finite_arr(p->R, sR) || (p->qbar && !finite_arr(p->qbar, snx + snu)))
+        !finite_arr(p->Q, sQ) || !finite_arr(p->R, sR) || (p->qbar && !finite_arr(p->qbar, snx + snu)) ||
+        (p->Wdu && !finite_arr(p->Wdu, sR)))
         return ctx->fail(PIMPC_E_NONFINITE, "problem data contains NaN or Inf");
     for (int64_t j = 0; j < snx; ++j)
         if (std::isnan(p->xmin[j]) || std::isnan(p->xmax[j]) || p->xmin[j] > p->xmax[j])
@@ -764,6 +769,8 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
                 return ctx->fail(PIMPC_E_NOT_PSD, "instance %d: Q is not %s", i, sym ? "PSD" : "symmetric");
             if (!sym_psd(p->R + orr, p->nu[i], &sym))
                 return ctx->fail(PIMPC_E_NOT_PSD, "instance %d: R is not %s", i, sym ? "PSD" : "symmetric");
+            if (p->Wdu && !sym_psd(p->Wdu + orr, p->nu[i], &sym))
+                return ctx->fail(PIMPC_E_NOT_PSD, "instance %d: Wdu is not %s", i, sym ? "PSD" : "symmetric");
             oq += (int64_t)p->nx[i] * p->nx[i];
             orr += (int64_t)p->nu[i] * p->nu[i];
         }
@@ -886,7 +893,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     HIPCHK(ctx, hipMemset(ctx->d_up, 0, ctx->sum_nu * ts));
 
     std::vector<double> m64v;
-    build_mats64(ctx, p->A, p->B, p->e, p->Q, p->R, m64v, false);
+    build_mats64(ctx, p->A, p->B, p->e, p->Q, p->R, p->Wdu, m64v, false);
     HIPCHK(ctx, hipMemcpy(ctx->d_mats64, m64v.data(), m64v.size() * sizeof(double), hipMemcpyHostToDevice));
     int rc = ctx->fp64 ? upload_t_block<double>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax)
                        : upload_t_block<float>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax);
@@ -1015,7 +1022,7 @@ int32_t pimpc_linearize(pimpc_ctx ctx, const double* A, const double* B, const d
         return ctx->fail(PIMPC_E_NONFINITE, "stage data contains NaN or Inf");
     std::vector<double> m64v(ctx->mat64_elems);
     HIPCHK(ctx, hipMemcpy(m64v.data(), ctx->d_mats64, m64v.size() * sizeof(double), hipMemcpyDeviceToHost));
-    build_mats64(ctx, pA, pB, pe, nullptr, nullptr, m64v, true);
+    build_mats64(ctx, pA, pB, pe, nullptr, nullptr, nullptr, m64v, true);
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_mats64, m64v.data(), m64v.size() * sizeof(double), hipMemcpyHostToDevice,
                                ctx->stream));
     int rc = refactor(ctx, true);

@@ -43,7 +43,7 @@ class pimpc_problem(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("nx", _ip), ("nu", _ip), ("N", _ip),
                 ("time_varying", ctypes.c_int32), ("A", _dp), ("B", _dp), ("e", _dp),
                 ("Q", _dp), ("R", _dp), ("qbar", _dp), ("xmin", _dp), ("xmax", _dp),
-                ("umin", _dp), ("umax", _dp)]
+                ("umin", _dp), ("umax", _dp), ("Wdu", _dp)]
 
 
 class pimpc_options(ctypes.Structure):
@@ -172,12 +172,16 @@ def pimpc_setup(problems: Sequence, opts: pimpc_options, stream: Optional[int] =
     xmax = _f64(np.concatenate([p.xmax for p in problems]))
     umin = _f64(np.concatenate([p.umin for p in problems]))
     umax = _f64(np.concatenate([p.umax for p in problems]))
+    Wdu = None
+    if any(getattr(p, "Wdu", None) is not None for p in problems):
+        Wdu = _f64(np.concatenate([(np.zeros((p.nu, p.nu)) if getattr(p, "Wdu", None) is None
+                                    else np.asarray(p.Wdu)).ravel() for p in problems]))
     keep.update(nx=nx, nu=nu, N=N, A=A, B=B, e=e, Q=Q, R=R, qbar=qbar, xmin=xmin, xmax=xmax,
-                umin=umin, umax=umax)
+                umin=umin, umax=umax, Wdu=Wdu)
     prob = pimpc_problem(count=len(problems), nx=nx.ctypes.data_as(_ip), nu=nu.ctypes.data_as(_ip),
                          N=N.ctypes.data_as(_ip), time_varying=tv, A=_p(A), B=_p(B), e=_p(e),
                          Q=_p(Q), R=_p(R), qbar=_p(qbar), xmin=_p(xmin), xmax=_p(xmax),
-                         umin=_p(umin), umax=_p(umax))
+                         umin=_p(umin), umax=_p(umax), Wdu=_p(Wdu))
     ctx = ctypes.c_void_p()
     rc = lib().pimpc_setup(ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opts), stream)
     _check(rc, None)

@@ -81,6 +81,19 @@ def test_bad_problem_data_rejected():
     assert _setup_code([q])[0] == P.PIMPC_E_DIM
 
 
+def test_bad_rate_weight_rejected():
+    p = W.plain_fp64_problem(0)
+    Wd = 0.1 * np.eye(3)
+    Wd[0, 2] = 0.05  # not symmetric
+    code, msg = _setup_code([p.copy(Wdu=Wd)])
+    assert code == P.PIMPC_E_NOT_PSD and "Wdu" in msg and "symmetric" in msg
+    code, msg = _setup_code([p.copy(Wdu=np.diag([0.1, -0.2, 0.1]))])
+    assert code == P.PIMPC_E_NOT_PSD and "Wdu" in msg
+    Wd = 0.1 * np.eye(3)
+    Wd[1, 1] = np.nan
+    assert _setup_code([p.copy(Wdu=Wd)])[0] == P.PIMPC_E_NONFINITE
+
+
 def test_unsupported_requests_are_reported():
     # restart acceleration runs on the lane family only (a long wide horizon
     # goes to the row family), and the taped forward differentiates plain ADMM
