@@ -861,7 +861,9 @@ namespace {
 struct RowCfg {
     int nx, nu;
 };
-constexpr RowCfg kRowCfgs[] = {{24, 12}, {32, 16}};
+// Padded stage classes of the row family, narrowest first: (4, 4) serves long
+// horizons of small stages (e.g. the 2-state, 1-input reactor at N = 5000).
+constexpr RowCfg kRowCfgs[] = {{4, 4}, {24, 12}, {32, 16}};
 
 template <int NX, int NU, int S>
 hipError_t row_launch_t(const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
@@ -887,6 +889,10 @@ hipError_t row_launch_s(int S, const RowArgs* a_dev, int nwaves, int nwg, hipStr
             return row_launch_t<NX, NU, 2>(a_dev, nwaves, nwg, s, occ);
         case 4:
             return row_launch_t<NX, NU, 4>(a_dev, nwaves, nwg, s, occ);
+        case 8:
+            // eight stages per wave only for narrow stages (register budget)
+            if constexpr (NX + NU <= 8) return row_launch_t<NX, NU, 8>(a_dev, nwaves, nwg, s, occ);
+            return hipErrorInvalidValue;
         default:
             return hipErrorInvalidValue;
     }
@@ -895,6 +901,7 @@ hipError_t row_launch_s(int S, const RowArgs* a_dev, int nwaves, int nwg, hipStr
 hipError_t row_launch_any(const InstDev& I, int S, const RowArgs* a_dev, hipStream_t s, int* occ) {
     const int nwaves = (I.N + S - 1) / S;
     const int nwg = (nwaves + kRowWaves - 1) / kRowWaves;
+    if (I.nxp == 4 && I.nup == 4) return row_launch_s<4, 4>(S, a_dev, nwaves, nwg, s, occ);
     if (I.nxp == 24 && I.nup == 12) return row_launch_s<24, 12>(S, a_dev, nwaves, nwg, s, occ);
     if (I.nxp == 32 && I.nup == 16) return row_launch_s<32, 16>(S, a_dev, nwaves, nwg, s, occ);
     return hipErrorInvalidValue;
@@ -936,7 +943,8 @@ size_t row_scratch_bytes(const InstDev& I, int fp64) {
 hipError_t row_prepare(int fp64, InstDev& I) {
     (void)fp64;
     const int want = I.pad1 > 0 ? I.pad1 : 1;
-    for (int S : {want, 1, 2, 4}) {
+    for (int S : {want, 1, 2, 4, 8}) {
+        if (S == 8 && I.nbp > 8) break;
         int occ = 0;
         hipError_t e = row_launch_any(I, S, nullptr, nullptr, &occ);
         if (e != hipSuccess) return e;

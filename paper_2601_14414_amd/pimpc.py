@@ -86,6 +86,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2601_14414_amd.build` (no CPU fallback exists)")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+    # soname).  Loading it first lets libpimpc bind to that copy, so device
+    # pointers and streams from torch tensors are valid here; loading libpimpc
+    # first would pull in a second HIP / HSA runtime next to torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     L.pimpc_default_options.argtypes = [ctypes.POINTER(pimpc_options)]

@@ -64,3 +64,43 @@ def run_cartpole_rti(steps: int = 20, N: int = 256, iters: int = 100, precision:
     finally:
         solver.close()
     return log
+
+
+@dataclasses.dataclass
+class CSTRStep:
+    t: int
+    x: np.ndarray          # plant state before applying u0
+    u0: np.ndarray
+    u_prev: np.ndarray
+    info: np.ndarray
+    solve_s: float         # wall time of pimpc_linearize + pimpc_solve
+
+
+def run_cstr_nmpc(steps: int = 20, N: int = 5000, iters: int = 1000, rho: float = 0.1,
+                  precision: int = P.PIMPC_FP32, stream: Optional[int] = None) -> List[CSTRStep]:
+    """Online-linearised NMPC of the reactor of Section V: at every sample the
+    Euler model is linearised at the current state and input (the same stage
+    data for the whole horizon), the device refactors (pimpc_linearize) and
+    runs `iters` warm-started iterations, and the first input drives the RK4
+    plant under the inlet-temperature disturbance."""
+    import time
+    p = W.cstr_problem(N=N, K=iters, rho=rho)
+    solver = P.Solver([p], rho=rho, max_iter=iters, precision=precision, warm_start=True, stream=stream)
+    x = p.x0.copy()
+    u_prev = p.u_prev.copy()
+    log: List[CSTRStep] = []
+    try:
+        for t in range(steps):
+            tm = t * W.CSTR_TS
+            t0 = time.perf_counter()
+            A, B, e = W.cstr_linearize(x, u_prev, W.cstr_ti(tm))
+            solver.linearize(A.ravel(), B.ravel(), e.ravel())
+            u0, info = solver.solve(x0=x, u_prev=u_prev)
+            dt = time.perf_counter() - t0
+            log.append(CSTRStep(t=t, x=x.copy(), u0=u0.copy(), u_prev=u_prev.copy(), info=info.copy(),
+                                solve_s=dt))
+            x = W.cstr_plant(x, u0, tm)
+            u_prev = u0
+    finally:
+        solver.close()
+    return log

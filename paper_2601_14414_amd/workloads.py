@@ -431,3 +431,88 @@ def pack(problems: Sequence[Problem]) -> PackedBatch:
         xmin=cat([p.xmin for p in problems]), xmax=cat([p.xmax for p in problems]),
         umin=cat([p.umin for p in problems]), umax=cat([p.umax for p in problems]),
         x0=cat([p.x0 for p in problems]), u_prev=cat([p.u_prev for p in problems]))
+
+
+# --------------------------------------------------------------------- CSTR
+# Continuous stirred-tank reactor of Section V (online-linearised NMPC):
+# state (C_A [kgmol/m^3], T [K]), input the coolant temperature T_c [K],
+# output y = C_A.  Constants as printed; inlet temperature disturbance
+# T_i(t) = 298.15 + 5 sin(0.05 t), t in minutes.
+CSTR_CAI = 10.0
+CSTR_K0 = 34930800.0
+CSTR_EAR = 5963.6
+CSTR_TS = 0.5
+
+
+def cstr_ti(t_min: float) -> float:
+    return 298.15 + 5.0 * math.sin(0.05 * t_min)
+
+
+def cstr_f(x, u, Ti):
+    """Right-hand side of the CSTR model (works on complex inputs)."""
+    ca, T = x[0], x[1]
+    kappa = CSTR_K0 * np.exp(-CSTR_EAR / T)
+    return np.array([CSTR_CAI - ca - kappa * ca,
+                     Ti + 0.3 * u[0] - 1.3 * T + 11.92 * kappa * ca], dtype=np.result_type(x, u, 1.0))
+
+
+def cstr_linearize(x, u, Ti, dt=CSTR_TS, h=1e-30):
+    """Forward-Euler map x + dt f(x, u) linearised at (x, u) by complex step:
+    returns (A, B, e) with e = f_d(x, u) - A x - B u."""
+    x = np.asarray(x, np.float64)
+    u = np.asarray(u, np.float64)
+    fd = lambda xx, uu: xx + dt * cstr_f(xx, uu, Ti)
+    A = np.zeros((2, 2))
+    B = np.zeros((2, 1))
+    for j in range(2):
+        xc = x.astype(np.complex128)
+        xc[j] += 1j * h
+        A[:, j] = np.imag(fd(xc, u.astype(np.complex128))) / h
+    uc = u.astype(np.complex128)
+    uc[0] += 1j * h
+    B[:, 0] = np.imag(fd(x.astype(np.complex128), uc)) / h
+    e = fd(x, u) - A @ x - B @ u
+    return A, B, e
+
+
+def cstr_plant(x, u, t_min, dt=CSTR_TS, substeps=20):
+    """Plant: RK4 integration of the continuous model over one sample, with
+    the inlet disturbance evaluated along the way."""
+    h = dt / substeps
+    t = t_min
+    for _ in range(substeps):
+        k1 = cstr_f(x, u, cstr_ti(t))
+        k2 = cstr_f(x + 0.5 * h * k1, u, cstr_ti(t + 0.5 * h))
+        k3 = cstr_f(x + 0.5 * h * k2, u, cstr_ti(t + 0.5 * h))
+        k4 = cstr_f(x + h * k3, u, cstr_ti(t + h))
+        x = x + (h / 6.0) * (k1 + 2 * k2 + 2 * k3 + k4)
+        t += h
+    return x
+
+
+CSTR_X0 = np.array([8.57, 311.0])
+CSTR_REF = 2.0
+
+
+def cstr_steady_input(x) -> float:
+    """Coolant temperature that holds dT/dt = 0 at state x (T_i nominal)."""
+    ca, T = x
+    kappa = CSTR_K0 * math.exp(-CSTR_EAR / T)
+    return (1.3 * T - 298.15 - 11.92 * kappa * ca) / 0.3
+
+
+def cstr_problem(N: int = 5000, K: int = 1000, rho: float = 1.0, t_min: float = 0.0,
+                 x=None, u_prev=None) -> Problem:
+    """CSTR tracking MPC in the form of eqn. (1): W_y = 1 on y = C_A (so
+    Q = diag(1, 0) and qbar = (W_y r_y, 0, 0) with r_y = 2), W_u = 0,
+    W_du = 0.1, horizon N.  The stage data are the Euler linearisation at
+    (x, u_prev) (same for every stage).  Bounds (not printed in the paper):
+    0 <= C_A <= 10, T unbounded, 280 K <= T_c <= 330 K."""
+    x = CSTR_X0.copy() if x is None else np.asarray(x, np.float64)
+    u_prev = np.array([cstr_steady_input(CSTR_X0)]) if u_prev is None else np.asarray(u_prev, np.float64)
+    A, B, e = cstr_linearize(x, u_prev, cstr_ti(t_min))
+    inf = np.inf
+    return Problem(nx=2, nu=1, N=N, A=A, B=B, e=e, Q=np.diag([1.0, 0.0]), R=np.zeros((1, 1)),
+                   qbar=np.array([CSTR_REF, 0.0, 0.0]), Wdu=np.array([[0.1]]),
+                   xmin=np.array([0.0, -inf]), xmax=np.array([10.0, inf]),
+                   umin=np.array([280.0]), umax=np.array([330.0]), x0=x, u_prev=u_prev, rho=rho, K=K)

@@ -1,0 +1,66 @@
+"""Long-horizon online-linearised NMPC of the reactor of Section V (N = 5000,
+1000 iterations per sample, input-rate weight 0.1, FP32): the horizon is
+longer than one workgroup of the lane family, so it runs on the row family's
+narrow (4 + 4) class with eight stages per wave.
+
+Per-sample parity: the oracle runs the NMPC loop (it decides the inputs);
+the GPU solver gets the same linearisations, x(t) and u(t-1) and keeps its
+own warm start.  Tolerance 1e-4 of max(1, |oracle|_inf) as for every FP32
+iteration (temperatures are ~300-375 K, so this is ~0.04 K / 4e-4 kgmol/m^3
+in absolute terms)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_14414_amd import pimpc as P
+from paper_2601_14414_amd import rti
+from paper_2601_14414_amd import workloads as W
+
+from test_gpu_lane import TOL32, check_info, compare, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+RHO = 0.1
+
+
+def oracle_loop(steps, N, iters):
+    x = W.CSTR_X0.copy()
+    up = np.array([W.cstr_steady_input(x)])
+    st = None
+    log = []
+    for t in range(steps):
+        p = W.cstr_problem(N=N, K=iters, rho=RHO, t_min=t * W.CSTR_TS, x=x, u_prev=up)
+        r = oracle.solve(p, state=st)
+        log.append((p, r))
+        st = r["state"]
+        x = W.cstr_plant(x, r["u0"], t * W.CSTR_TS)
+        up = r["u0"]
+    return log
+
+
+@pytest.mark.parametrize("N,iters,steps", [(5000, 1000, 3), (1500, 300, 4)])
+def test_cstr_per_sample_parity(N, iters, steps):
+    log = oracle_loop(steps, N, iters)
+    s = P.Solver([log[0][0]], rho=RHO, max_iter=iters, precision=P.PIMPC_FP32, warm_start=True)
+    try:
+        for t, (p, r) in enumerate(log):
+            s.linearize(p.A.ravel(), p.B.ravel(), p.e.ravel())
+            u0, info = s.solve(x0=p.x0, u_prev=p.u_prev)
+            assert scaled_err(u0, r["u0"]) <= TOL32, t
+            compare(s, [p], [r], TOL32)
+            assert info["status"][0] == 0
+    finally:
+        s.close()
+
+
+def test_cstr_closed_loop_driver():
+    """The GPU-driven loop moves the reactor from low to high conversion:
+    C_A falls from 8.57 towards the reference 2 within 30 samples, and every
+    input stays inside the coolant bounds (up to the FP32 / finite-iteration
+    slack of the u part of xbar)."""
+    log = rti.run_cstr_nmpc(steps=30, N=5000, iters=1000, rho=RHO)
+    ca = np.array([st.x[0] for st in log])
+    u = np.array([st.u0[0] for st in log])
+    assert np.all(np.isfinite(u)) and np.all(u >= 280.0 - 0.1) and np.all(u <= 330.0 + 0.1)
+    assert ca[0] > 8.0 and ca[-1] < 2.5
+    assert all(st.info["status"][0] == 0 for st in log)
