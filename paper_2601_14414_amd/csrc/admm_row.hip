@@ -5,8 +5,12 @@
 // for instances whose horizon is long and whose stage is wide (e.g. nx = 24,
 // nu = 11, N = 1024), where one lane per stage would leave most of the chip
 // idle:
-//   * a wave owns a block of S consecutive stages; lane r owns row r of
-//     every stage vector;
+//   * a wave owns a block of consecutive stages; lane r owns row r of
+//     every stage vector.  Wide stages (more than 16 padded rows) give a wave
+//     S stages, processed in turn; narrow stages pack G = 64 / NB stages side
+//     by side in the lanes of a wave (lane = g NB + r), so a long horizon of
+//     small stages (e.g. the 2-state reactor at N = 5000) costs one stage of
+//     work per wave and iteration;
 //   * the iteration is evaluated in an algebraically equivalent "fused" form
 //     whose only dependence on a neighbouring stage is ONE vector each way:
 //       with w_k = z_k - v_k - ebar + lambda_k and d_k = z_k - theta_k of the
@@ -221,12 +225,15 @@ constexpr int kRowWaves = 4;
 constexpr int kRecvWaves = 2;
 constexpr int kRowThreads = 64 * (kRowWaves + kRecvWaves);
 
-// Dynamic LDS of one workgroup: per wave, the broadcast rows [3S][NB + 4]
+// Stage groups per wave: narrow stages (NB <= 16) share a wave side by side.
+__host__ __device__ constexpr int row_groups(int nb) { return nb <= 16 ? 64 / nb : 1; }
+
+// Dynamic LDS of one workgroup: per wave, the broadcast rows [3 S G][NB + 4]
 // and the lane-private rows of the rows lanes (H, BJ, AHAt: NB each; column
 // of [A B]: NX) as float4 [(3 NB + NX) / 4][NB].
 __host__ __device__ constexpr size_t row_lds_bytes(int NX, int NU, int S) {
     return (size_t)kRowWaves *
-           (4 * (3 * S) * (NX + NU + 4) + 16 * (NX + NU) * ((3 * (NX + NU) + NX) / 4));
+           (4 * (3 * S * row_groups(NX + NU)) * (NX + NU + 4) + 16 * (NX + NU) * ((3 * (NX + NU) + NX) / 4));
 }
 
 extern __shared__ __align__(16) float row_smem[];
@@ -238,8 +245,10 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     constexpr int NB4 = NB / 4;
     constexpr int NX4 = NX / 4;
     constexpr int LD = NB + 4;       // LDS row pitch of a broadcast vector (16-byte multiple)
-    constexpr int NV = 3 * S;        // broadcast rows: (p, d, w) per stage
+    constexpr int G = row_groups(NB);  // stage groups side by side in a wave
+    constexpr int NV = 3 * S * G;      // broadcast rows: (p, d, w) per stage
     static_assert(NB <= 64, "row kernel needs nx + nu <= 64");
+    static_assert(G == 1 || S == 1, "packed narrow stages take one stage per group");
     static_assert(NB % 4 == 0 && NX % 4 == 0, "padded sizes must be multiples of 4");
     const RowArgs& a = *ap;
     const InstDev I = a.inst[a.inst_idx];
@@ -250,10 +259,15 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     int lwg = blockIdx.x;
     if (nwg % 8 == 0) lwg = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
     const int gw = lwg * kRowWaves + wv;  // logical wave (block) index
-    const int k0 = gw * S;
-    const int ns = max(0, min(S, N - k0));  // stages in this block
-    const bool rowl = lane < NB;            // lane carries a (padded) row
-    const int r = rowl ? lane : 0;
+    const int k0 = gw * S * G;
+    // stages in this block (a compute wave, gw < nwaves, has at least one)
+    const int ns = (S * G == 1) ? 1 : max(0, min(S * G, N - k0));
+    const bool rowl = lane < G * NB;            // lane carries a (padded) row
+    const int grp = G > 1 ? lane / NB : 0;      // stage group of the lane
+    const int r = rowl ? lane - grp * NB : 0;
+    const int tb = grp * S;                     // block position of the lane's first stage
+    const int nsl = max(0, min(S, ns - tb));    // stages the lane holds
+    const int kl = k0 + tb;                     // index of the lane's first stage
     const float rho = (float)a.rho;
     const float third = 1.0f / 3.0f;
 
@@ -346,7 +360,6 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     const float Hbq_r = rowl ? F[fo.Hbq + r] : 0.f;
     const float cq_r = rowl ? F[fo.cq + r] : 0.f;
     const bool hb_diag = I.hb_diag != 0;
-    const bool owns_last = ns > 0 && k0 + ns == N;  // block holds stage N-1 (uses H_{N-1})
 
     // c_0 = Abar xbar_0 + ebar (stage 0 only), xbar_0 = col(x(t), u(t-1))
     float c0_r = 0.f;
@@ -374,8 +387,8 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     const gptr<float> st = (gptr<float>)((float*)a.state + I.st_off);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const bool ld = a.warm && rowl && s < ns;
-        const int k = k0 + s;
+        const bool ld = a.warm && rowl && s < nsl;
+        const int k = kl + s;
         v[s] = ld ? st[(size_t)(0 * NB + r) * N + k] : 0.f;
         z[s] = ld ? st[(size_t)(1 * NB + r) * N + k] : 0.f;
         th[s] = ld ? st[(size_t)(2 * NB + r) * N + k] : 0.f;
@@ -402,23 +415,18 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     // Stage vectors of the iterate: w = z - v - ebar + lambda, d = z - theta.
     auto wvec = [&](int s) { return z[s] - v[s] - e_r + la[s]; };
     auto dvec = [&](int s) { return z[s] - th[s]; };
-    auto last_of = [&](float* x) {
-        float y = x[0];
-#pragma unroll
-        for (int s = 1; s < S; ++s)
-            if (s == ns - 1) y = x[s];
-        return y;
-    };
-    // w of the first stage goes left, d of the last stage goes right
+    // w of the first stage goes left, d of the last stage goes right (each
+    // written by the lanes that hold that stage)
+    const int sl = ns - 1 - tb;  // the block's last stage, as an index into the lane's stages
     auto publish = [&](uint32_t tag) {
         if (!rowl) return;
         const int buf = tag & 1;
-        if (has_left) put(left_in_wg, buf, 0, pack(wvec(0), tag));
-        if (has_right) {
+        if (has_left && tb == 0) put(left_in_wg, buf, 0, pack(wvec(0), tag));
+        if (has_right && sl >= 0 && sl < S) {
             float zl = z[0], tl = th[0];
 #pragma unroll
             for (int s = 1; s < S; ++s)
-                if (s == ns - 1) {
+                if (s == sl) {
                     zl = z[s];
                     tl = th[s];
                 }
@@ -462,11 +470,11 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         if (rowl) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (S == 1 || s < ns) {
+                if (s < nsl) {
                     pv[s] = v[s] - be[s];
-                    bc[3 * s + 0][r] = pv[s];
-                    bc[3 * s + 1][r] = dvec(s);
-                    bc[3 * s + 2][r] = wvec(s);
+                    bc[3 * (tb + s) + 0][r] = pv[s];
+                    bc[3 * (tb + s) + 1][r] = dvec(s);
+                    bc[3 * (tb + s) + 2][r] = wvec(s);
                 }
             }
         }
@@ -474,16 +482,17 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         if (rowl) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (S == 1 || s < ns) {
-                    const int k = k0 + s;
+                if (s < nsl) {
+                    const int k = kl + s;
+                    const int t = tb + s;
                     float ab0 = 0.f, ab1 = 0.f, ah0 = 0.f, ah1 = 0.f, ac0 = 0.f, ac1 = 0.f;
                     // all operands come from LDS; a partly unrolled loop keeps
                     // the scheduler from hoisting every load (VGPR pressure)
 #pragma unroll 3
                     for (int q = 0; q < NB4; ++q) {
-                        const float4 p4 = *(const float4*)&bc[3 * s + 0][4 * q];
-                        const float4 d4 = *(const float4*)&bc[3 * s + 1][4 * q];
-                        const float4 w4 = *(const float4*)&bc[3 * s + 2][4 * q];
+                        const float4 p4 = *(const float4*)&bc[3 * t + 0][4 * q];
+                        const float4 d4 = *(const float4*)&bc[3 * t + 1][4 * q];
+                        const float4 w4 = *(const float4*)&bc[3 * t + 2][4 * q];
                         const float4 g = LBJ(q);
                         const float4 m = LAHAT(q);
                         const float4 h = LH(q);
@@ -505,11 +514,11 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                         // xbar_N = H_{N-1} (q + rho d)
                         float hb = 0.f;
                         if (hb_diag) {
-                            hb = hbd_r * bc[3 * s + 1][r];
+                            hb = hbd_r * bc[3 * t + 1][r];
                         } else {
                             const gptr<const float> Hb = M + o.Hb + r * NB;
 #pragma unroll
-                            for (int j = 0; j < NB; ++j) hb += Hb[j] * bc[3 * s + 1][j];
+                            for (int j = 0; j < NB; ++j) hb += Hb[j] * bc[3 * t + 1][j];
                         }
                         xl[s] = Hbq_r + rho * hb;
                     } else {
@@ -523,11 +532,12 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             // neighbours inside the block
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (s + 1 < ns) {  // xbar_{k+1} += rho (H Abar') w_{k+1}
+                const int t = tb + s;
+                if (s < nsl && t + 1 < ns) {  // xbar_{k+1} += rho (H Abar') w_{k+1}
                     float x0 = 0.f, x1 = 0.f;
 #pragma unroll
                     for (int q = 0; q < NB4; ++q) {
-                        const float4 w4 = *(const float4*)&bc[3 * (s + 1) + 2][4 * q];
+                        const float4 w4 = *(const float4*)&bc[3 * (t + 1) + 2][4 * q];
                         x0 += HAr[4 * q + 0] * w4.x;
                         x1 += HAr[4 * q + 1] * w4.y;
                         x0 += HAr[4 * q + 2] * w4.z;
@@ -535,11 +545,11 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                     }
                     xl[s] += rho * (x0 + x1);
                 }
-                if (s >= 1 && s < ns) {  // c_k += rho (Abar H) d_{k-1}
+                if (s < nsl && t >= 1) {  // c_k += rho (Abar H) d_{k-1}
                     float x0 = 0.f, x1 = 0.f;
 #pragma unroll
                     for (int q = 0; q < NB4; ++q) {
-                        const float4 d4 = *(const float4*)&bc[3 * (s - 1) + 1][4 * q];
+                        const float4 d4 = *(const float4*)&bc[3 * (t - 1) + 1][4 * q];
                         x0 += AHr[4 * q + 0] * d4.x;
                         x1 += AHr[4 * q + 1] * d4.y;
                         x0 += AHr[4 * q + 2] * d4.z;
@@ -606,9 +616,9 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             if (has_right) {
 #pragma unroll
                 for (int s = 0; s < S; ++s)
-                    if (s == ns - 1) xl[s] += rho * (x0 + x1);
+                    if (s == sl) xl[s] += rho * (x0 + x1);
             }
-            if (has_left) cl[0] += rho * (y0 + y1);
+            if (has_left && tb == 0) cl[0] += rho * (y0 + y1);
         }
 
         // ---- steps 2-3 (Theorem 1 closed form, box projection, dual update)
@@ -618,7 +628,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             ddv[s] = dzv[s] = dvv[s] = 0.f;
-            if (S == 1 || s < ns) {  // a compute wave has at least one stage
+            if (s < nsl) {
                 const float bi = bb[s], ci = cl[s], xi = xl[s];
                 const float gam = bi - ci;
                 const float y = (2.f * (xi + th[s]) + bi + ci) * third;
@@ -646,7 +656,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             }
         }
         publish(tout);
-        if (check && has_left && rowl) put(left_in_wg, tout & 1, 2, pack(ddv[0], tout));
+        if (check && has_left && rowl && tb == 0) put(left_in_wg, tout & 1, 2, pack(ddv[0], tout));
         ++iters;
 
         if (check) {
@@ -680,17 +690,20 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                 }
             }
             float rdpart = 0.f;
+            // dd of the next stage when it sits in the next group of lanes
+            const float ddg = (G > 1) ? __shfl(ddv[0], lane + NB < 64 ? lane + NB : lane, 64) : 0.f;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (s < ns) {
-                    float ddn = (s + 1 < ns) ? 0.f : ddR;
+                if (s < nsl) {
+                    const int t = tb + s;
+                    float ddn = (t + 1 < ns) ? (G > 1 ? ddg : 0.f) : ddR;
 #pragma unroll
-                    for (int t = 1; t < S; ++t)
-                        if (t == s + 1 && t < ns) ddn = ddv[t];
-                    const bool hasnext = k0 + s + 1 < N;
+                    for (int u = 1; u < S; ++u)
+                        if (u == s + 1 && t + 1 < ns) ddn = ddv[u];
+                    const bool hasnext = kl + s + 1 < N;
                     if (rowl) {
-                        bc[0][r] = dvv[s];
-                        bc[1][r] = ddn;
+                        bc[3 * tb + 0][r] = dvv[s];
+                        bc[3 * tb + 1][r] = ddn;
                     }
                     __builtin_amdgcn_wave_barrier();
                     if (rowl) {
@@ -699,8 +712,8 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
 #pragma unroll
                         for (int q = 0; q < NX4; ++q) {
                             const float4 c4 = LACOL(q);
-                            const float4 x4 = *(const float4*)&bc[0][4 * q];
-                            const float4 y4 = *(const float4*)&bc[1][4 * q];
+                            const float4 x4 = *(const float4*)&bc[3 * tb + 0][4 * q];
+                            const float4 y4 = *(const float4*)&bc[3 * tb + 1][4 * q];
                             bt += c4.x * x4.x + c4.y * x4.y + c4.z * x4.z + c4.w * x4.w;
                             tg += c4.x * y4.x + c4.y * y4.y + c4.z * y4.z + c4.w * y4.w;
                         }
@@ -801,12 +814,12 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         du[s] = 0.f;
-        if (s < ns) {
-            if (rowl) bc[0][r] = pv[s];
+        if (s < nsl) {
+            if (rowl) bc[3 * tb][r] = pv[s];
             __builtin_amdgcn_wave_barrier();
             if (rowl && r < NU) {
                 float acc = 0.f;
-                for (int j = 0; j < NB; ++j) acc += M[o.J + r * NB + j] * bc[0][j];
+                for (int j = 0; j < NB; ++j) acc += M[o.J + r * NB + j] * bc[3 * tb][j];
                 du[s] = acc;
             }
             __builtin_amdgcn_wave_barrier();
@@ -815,8 +828,8 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     if (rowl) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            if (s < ns) {
-                const int k = k0 + s;
+            if (s < nsl) {
+                const int k = kl + s;
                 st[(size_t)(0 * NB + r) * N + k] = v[s];
                 st[(size_t)(1 * NB + r) * N + k] = z[s];
                 st[(size_t)(2 * NB + r) * N + k] = th[s];
@@ -861,9 +874,10 @@ namespace {
 struct RowCfg {
     int nx, nu;
 };
-// Padded stage classes of the row family, narrowest first: (4, 4) serves long
-// horizons of small stages (e.g. the 2-state, 1-input reactor at N = 5000).
-constexpr RowCfg kRowCfgs[] = {{4, 4}, {24, 12}, {32, 16}};
+// Padded stage classes of the row family, narrowest first: (4, 4) and (8, 8)
+// pack 8 and 4 stages per wave and serve long horizons of small stages (e.g.
+// the 2-state, 1-input reactor at N = 5000).
+constexpr RowCfg kRowCfgs[] = {{4, 4}, {8, 8}, {24, 12}, {32, 16}};
 
 template <int NX, int NU, int S>
 hipError_t row_launch_t(const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
@@ -882,26 +896,29 @@ hipError_t row_launch_t(const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s
 
 template <int NX, int NU>
 hipError_t row_launch_s(int S, const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
-    switch (S) {
-        case 1:
-            return row_launch_t<NX, NU, 1>(a_dev, nwaves, nwg, s, occ);
-        case 2:
-            return row_launch_t<NX, NU, 2>(a_dev, nwaves, nwg, s, occ);
-        case 4:
-            return row_launch_t<NX, NU, 4>(a_dev, nwaves, nwg, s, occ);
-        case 8:
-            // eight stages per wave only for narrow stages (register budget)
-            if constexpr (NX + NU <= 8) return row_launch_t<NX, NU, 8>(a_dev, nwaves, nwg, s, occ);
-            return hipErrorInvalidValue;
-        default:
-            return hipErrorInvalidValue;
+    if constexpr (row_groups(NX + NU) > 1) {  // packed narrow stages: one stage per group
+        if (S != 1) return hipErrorInvalidValue;
+        return row_launch_t<NX, NU, 1>(a_dev, nwaves, nwg, s, occ);
+    } else {
+        switch (S) {
+            case 1:
+                return row_launch_t<NX, NU, 1>(a_dev, nwaves, nwg, s, occ);
+            case 2:
+                return row_launch_t<NX, NU, 2>(a_dev, nwaves, nwg, s, occ);
+            case 4:
+                return row_launch_t<NX, NU, 4>(a_dev, nwaves, nwg, s, occ);
+            default:
+                return hipErrorInvalidValue;
+        }
     }
 }
 
 hipError_t row_launch_any(const InstDev& I, int S, const RowArgs* a_dev, hipStream_t s, int* occ) {
-    const int nwaves = (I.N + S - 1) / S;
+    const int per = S * row_groups(I.nbp);  // stages per wave
+    const int nwaves = (I.N + per - 1) / per;
     const int nwg = (nwaves + kRowWaves - 1) / kRowWaves;
     if (I.nxp == 4 && I.nup == 4) return row_launch_s<4, 4>(S, a_dev, nwaves, nwg, s, occ);
+    if (I.nxp == 8 && I.nup == 8) return row_launch_s<8, 8>(S, a_dev, nwaves, nwg, s, occ);
     if (I.nxp == 24 && I.nup == 12) return row_launch_s<24, 12>(S, a_dev, nwaves, nwg, s, occ);
     if (I.nxp == 32 && I.nup == 16) return row_launch_s<32, 16>(S, a_dev, nwaves, nwg, s, occ);
     return hipErrorInvalidValue;
@@ -943,12 +960,13 @@ size_t row_scratch_bytes(const InstDev& I, int fp64) {
 hipError_t row_prepare(int fp64, InstDev& I) {
     (void)fp64;
     const int want = I.pad1 > 0 ? I.pad1 : 1;
-    for (int S : {want, 1, 2, 4, 8}) {
-        if (S == 8 && I.nbp > 8) break;
+    for (int S : {want, 1, 2, 4}) {
+        if (S > 1 && row_groups(I.nbp) > 1) break;  // packed narrow stages: S = 1 only
         int occ = 0;
         hipError_t e = row_launch_any(I, S, nullptr, nullptr, &occ);
         if (e != hipSuccess) return e;
-        const int nwg = ((I.N + S - 1) / S + kRowWaves - 1) / kRowWaves;
+        const int per = S * row_groups(I.nbp);
+        const int nwg = ((I.N + per - 1) / per + kRowWaves - 1) / kRowWaves;
         if (occ > 0 && nwg <= occ * num_cus()) {
             I.pad1 = S;
             return hipSuccess;
