@@ -1,6 +1,7 @@
 """Benchmark: ADMM stage-iterations/s of the piMPC hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--no-accel]
+    python bench.py --only {batch,diff,accel,cstr}   (one extra workload, for profiling)
 
 A step is one full solve (all iterations) of the long-horizon workload: the
 12-mass chain (nx=24, nu=11), horizon N=1024, 500 plain ADMM iterations, FP32
@@ -204,6 +205,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-accel", action="store_true", help="skip the restart-acceleration extra")
+    ap.add_argument("--only", choices=["batch", "diff", "accel", "cstr"],
+                    help="run one extra workload alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -215,6 +218,16 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": a.numel() * 4, "launches": 3}))
+        return
+    if args.only:
+        import torch
+        from paper_2601_14414_amd import pimpc as P
+        from paper_2601_14414_amd import workloads as W
+        torch.cuda.set_device(0)
+        n = max(3, args.steps // 4)
+        res = {"batch": lambda: bench_batch(torch, P, W, n, 1), "diff": lambda: bench_diff(torch, P, W, n, 1),
+               "accel": lambda: bench_accel(torch, P, W, 2, 1), "cstr": lambda: bench_cstr()}[args.only]()
+        print(json.dumps({args.only: res}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
