@@ -34,8 +34,11 @@ def _load():
     lib.orc_factor.restype = ctypes.c_int
     lib.orc_factor.argtypes = [ctypes.c_int] * 3 + [_dp] * 5 + [ctypes.c_double, _dp, _dp]
     lib.orc_solve.restype = ctypes.c_int
-    lib.orc_solve.argtypes = ([ctypes.c_int] * 3 + [_dp] * 10 + [ctypes.c_double, ctypes.c_int,
+    lib.orc_solve.argtypes = ([ctypes.c_int] * 3 + [_dp] * 9 + [ctypes.c_int, _dp, ctypes.c_int, _dp]
+                              + [_dp] + [ctypes.c_double, ctypes.c_int,
                               ctypes.c_double, ctypes.c_int, ctypes.c_double] + [_dp] * 4 + [_ip])
+    lib.orc_project.restype = None
+    lib.orc_project.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
     lib.orc_grad.restype = ctypes.c_int
     lib.orc_grad.argtypes = ([ctypes.c_int] * 3 + [_dp] * 8 + [ctypes.c_double, ctypes.c_int]
                              + [_dp] * 7)
@@ -61,6 +64,36 @@ def _wdu(p):
     """Input-rate weight W_du of problem `p` as (m, m) float64, or None (= 0)."""
     W = getattr(p, "Wdu", None)
     return None if W is None else _c(W)
+
+
+SET_KINDS = {"box": 0, "halfspace": 1, "hyperplane": 2, "soc": 3, "l1ball": 4}
+
+
+def _set_spec(spec, n):
+    """(kind, par[n+1]) of a factor set: None / ("box",) / ("halfspace", a, b) /
+    ("hyperplane", a, b) / ("soc",) / ("l1ball", r)."""
+    if spec is None or spec[0] == "box":
+        return 0, None
+    kind = SET_KINDS[spec[0]]
+    par = np.zeros(n + 1)
+    if spec[0] in ("halfspace", "hyperplane"):
+        par[:n] = np.asarray(spec[1], np.float64)
+        par[n] = float(spec[2])
+    elif spec[0] == "l1ball":
+        par[n] = float(spec[1])
+    return kind, par
+
+
+def project(spec, w, lo=None, hi=None):
+    """Projection of w onto one factor set, by the oracle's own routine (test use)."""
+    lib = _load()
+    w = _c(w).copy()
+    n = w.size
+    kind, par = _set_spec(spec, n)
+    lo = _c(np.full(n, -np.inf) if lo is None else lo)
+    hi = _c(np.full(n, np.inf) if hi is None else hi)
+    lib.orc_project(kind, n, _ptr(par), _ptr(lo), _ptr(hi), _ptr(w))
+    return w
 
 
 def factor(p):
@@ -100,9 +133,11 @@ def solve(p, K: Optional[int] = None, eps: float = 0.0, accel: bool = False, eta
     e = None if p.e is None else _c(p.stage_e())
     qbar = None if p.qbar is None else _c(p.qbar)
     xb0 = _c(p.xbar0() if xbar0 is None else xbar0)
+    xkind, xpar = _set_spec(getattr(p, "xset", None), p.nx)
+    ukind, upar = _set_spec(getattr(p, "uset", None), p.nu)
     rc = lib.orc_solve(p.nx, p.nu, p.N, _ptr(_c(p.stage_A())), _ptr(_c(p.stage_B())), _ptr(e),
                        _ptr(_c(p.Q)), _ptr(_c(p.R)), _ptr(_wdu(p)), _ptr(qbar), _ptr(_c(p.lb())),
-                       _ptr(_c(p.ub())),
+                       _ptr(_c(p.ub())), xkind, _ptr(xpar), ukind, _ptr(upar),
                        _ptr(xb0), float(p.rho), int(K), float(eps), int(bool(accel)), float(eta),
                        _ptr(st), _ptr(du), _ptr(xs), _ptr(hist), ctypes.byref(it))
     if rc != 0:

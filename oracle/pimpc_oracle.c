@@ -40,6 +40,10 @@
  *   R8  rho multiplies all six terms of c^{i+1}; the z difference is taken on
  *       z_{k+1};
  *   R11 restart follows Algorithm 1: alpha = 1 and hats = current iterate.
+ *   Sets: Xbar = X x U (Theorem 2); each factor is a box or one of the other
+ *       closed convex sets the proof of Theorem 1 lists (halfspace, affine
+ *       hyperplane, second-order cone, l1 ball), so the projection of the z
+ *       update is taken factor by factor.
  *   Terminal stage: Qbar applies to xbar_N as to every other stage.
  *
  * Layouts (all row-major, double):
@@ -138,12 +142,15 @@ typedef struct {
     double *Qbar;  /* [nb][nb]    */
     double *qbar;  /* [nb]        */
     double *W;     /* [m][m] input-rate weight (zero if absent) */
+    int xkind, ukind;      /* set kinds of the X and U factors (ORC_SET_*) */
+    double *xpar, *upar;   /* [n+1], [m+1]: (a, b) or (., r) of the factor set */
     double *H;     /* [N][nb][nb] */
     double *J;     /* [N][m][nb]  */
 } vform_t;
 
 static void vform_free(vform_t *V) {
     free(V->Abar); free(V->Bbar); free(V->ebar); free(V->Qbar); free(V->qbar); free(V->W);
+    free(V->xpar); free(V->upar);
     free(V->H); free(V->J);
 }
 
@@ -159,6 +166,9 @@ static void vform_build(vform_t *V, int n, int m, int N, const double *A, const 
     V->qbar = (double *)calloc((size_t)nb, sizeof(double));
     V->W = (double *)calloc((size_t)m * m, sizeof(double));
     if (W) memcpy(V->W, W, sizeof(double) * (size_t)m * m);
+    V->xkind = V->ukind = 0;
+    V->xpar = (double *)calloc((size_t)n + 1, sizeof(double));
+    V->upar = (double *)calloc((size_t)m + 1, sizeof(double));
     V->H = (double *)calloc((size_t)N * nb * nb, sizeof(double));
     V->J = (double *)calloc((size_t)N * m * nb, sizeof(double));
     for (int k = 0; k < N; ++k) {
@@ -231,6 +241,71 @@ static int vform_factor(vform_t *V, double rho) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Euclidean projections onto the factor sets (proof of Theorem 1; formulas   */
+/* of Parikh and Boyd, "Proximal Algorithms", Ch. 6)                          */
+/* ------------------------------------------------------------------------- */
+
+#define ORC_SET_BOX 0        /* lo <= w <= hi                         */
+#define ORC_SET_HALFSPACE 1  /* a'w <= b                              */
+#define ORC_SET_HYPERPLANE 2 /* a'w = b                               */
+#define ORC_SET_SOC 3        /* ||(w_1..w_{n-1})||_2 <= w_n           */
+#define ORC_SET_L1BALL 4     /* ||w||_1 <= r  (r = par[n])            */
+
+static int cmp_desc(const void *x, const void *y) {
+    double a = *(const double *)x, b = *(const double *)y;
+    return (a < b) - (a > b);
+}
+
+/* Project w (n entries) onto the set; par = (a_1..a_n, b) or (., r). */
+static void project_set(int kind, int n, const double *par, const double *lo, const double *hi, double *w) {
+    if (kind == ORC_SET_BOX) {
+        for (int i = 0; i < n; ++i) w[i] = w[i] < lo[i] ? lo[i] : (w[i] > hi[i] ? hi[i] : w[i]);
+    } else if (kind == ORC_SET_HALFSPACE || kind == ORC_SET_HYPERPLANE) {
+        double s = 0.0, aa = 0.0;
+        for (int i = 0; i < n; ++i) {
+            s += par[i] * w[i];
+            aa += par[i] * par[i];
+        }
+        s -= par[n];
+        if (kind == ORC_SET_HYPERPLANE || s > 0.0)
+            for (int i = 0; i < n; ++i) w[i] -= s / aa * par[i];
+    } else if (kind == ORC_SET_SOC) {
+        double t = w[n - 1], nx2 = 0.0;
+        for (int i = 0; i < n - 1; ++i) nx2 += w[i] * w[i];
+        double nx = sqrt(nx2);
+        if (nx <= t) return;
+        if (nx <= -t) {
+            for (int i = 0; i < n; ++i) w[i] = 0.0;
+            return;
+        }
+        double al = 0.5 * (nx + t);
+        for (int i = 0; i < n - 1; ++i) w[i] = al * w[i] / nx;
+        w[n - 1] = al;
+    } else if (kind == ORC_SET_L1BALL) {
+        double r = par[n], l1 = 0.0;
+        for (int i = 0; i < n; ++i) l1 += fabs(w[i]);
+        if (l1 <= r) return;
+        /* soft threshold at theta with sum max(|w_i| - theta, 0) = r:
+         * sort |w| descending, theta = (sum of the rho largest - r) / rho with
+         * rho the last index whose entry stays above its running threshold */
+        double *mu = (double *)malloc(sizeof(double) * (size_t)n);
+        for (int i = 0; i < n; ++i) mu[i] = fabs(w[i]);
+        qsort(mu, (size_t)n, sizeof(double), cmp_desc);
+        double cs = 0.0, theta = 0.0;
+        for (int j = 0; j < n; ++j) {
+            cs += mu[j];
+            double tj = (cs - r) / (double)(j + 1);
+            if (mu[j] - tj > 0.0) theta = tj;
+        }
+        free(mu);
+        for (int i = 0; i < n; ++i) {
+            double a = fabs(w[i]) - theta;
+            w[i] = a > 0.0 ? (w[i] > 0.0 ? a : -a) : 0.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* one ADMM iteration (eqn. (8), Algorithm 1 steps 1-3)                       */
 /* ------------------------------------------------------------------------- */
 
@@ -247,6 +322,7 @@ static void admm_iteration(const vform_t *V, double rho, const double *lb, const
     double *d = (double *)malloc(sizeof(double) * nb);
     double *b = (double *)malloc(sizeof(double) * nb);
     double *c = (double *)malloc(sizeof(double) * nb);
+    double *y = (double *)malloc(sizeof(double) * nb);
 
     /* step 1: du_k = J_k (v_k - beta_k);  xbar_{k+1} = H_k h_k with
      * h_k = qbar + rho (z_{k+1} - theta_k + Abar_{k+1}' (z_{k+2} - v_{k+1} - ebar_{k+1} + lambda_{k+1})) */
@@ -266,7 +342,9 @@ static void admm_iteration(const vform_t *V, double rho, const double *lb, const
         matvec(nb, nb, V->H + (size_t)k * nb * nb, h, xs + (size_t)k * nb);
     }
 
-    /* steps 2-3 (Theorem 1 closed form, then the scaled dual updates) */
+    /* steps 2-3 (Theorem 1 closed form: z = Proj_Xbar((2 (xbar + theta) + b + c) / 3),
+     * Xbar = X x U projected factor by factor; then the scaled dual updates) */
+    int n = V->n;
     for (int k = 0; k < N; ++k) {
         const double *xp = (k == 0) ? xbar0 : xs + (size_t)(k - 1) * nb;
         const double *xk = xs + (size_t)k * nb;
@@ -274,11 +352,17 @@ static void admm_iteration(const vform_t *V, double rho, const double *lb, const
         matvec(nb, nb, V->Abar + (size_t)k * nb * nb, xp, c);
         for (int i = 0; i < nb; ++i) {
             size_t o = (size_t)k * nb + i;
-            double bi = b[i] + be[o];
-            double ci = c[i] + V->ebar[o] - la[o];
+            b[i] += be[o];
+            c[i] += V->ebar[o] - la[o];
+            y[i] = (2.0 * (xk[i] + th[o]) + b[i] + c[i]) / 3.0;
+        }
+        project_set(V->xkind, n, V->xpar, lb, ub, y);
+        project_set(V->ukind, m, V->upar, lb + n, ub + n, y + n);
+        for (int i = 0; i < nb; ++i) {
+            size_t o = (size_t)k * nb + i;
+            double bi = b[i], ci = c[i];
             double gam = bi - ci;
-            double y = (2.0 * (xk[i] + th[o]) + bi + ci) / 3.0;
-            double zn = y < lb[i] ? lb[i] : (y > ub[i] ? ub[i] : y);
+            double zn = y[i];
             double vn = 0.5 * (zn + gam);
             out[0][o] = vn;
             out[1][o] = zn;
@@ -287,7 +371,7 @@ static void admm_iteration(const vform_t *V, double rho, const double *lb, const
             out[4][o] = zn - vn - ci;
         }
     }
-    free(w); free(g); free(h); free(d); free(b); free(c);
+    free(w); free(g); free(h); free(d); free(b); free(c); free(y);
 }
 
 /* c^{i+1} (Algorithm 1 step 4), primal residual ||s^{i+1}-s^i||_inf and dual
@@ -356,7 +440,9 @@ int orc_factor(int n, int m, int N, const double *A, const double *B, const doub
 
 /*
  * Run Algorithm 1 for at most K iterations from `state` (in: initial iterate,
- * out: final iterate).  eps <= 0 disables the stop of step 5.  accel = 0 runs
+ * out: final iterate).  The X and U factors of the constraint set are of kind
+ * xkind / ukind (ORC_SET_*) with parameters xpar [n+1] / upar [m+1] (NULL =
+ * zeros); box factors use lb / ub.  eps <= 0 disables the stop of step 5.  accel = 0 runs
  * plain ADMM (hats = previous iterate); accel = 1 adds steps 6-7 with the
  * given eta.  Outputs (any may be NULL except state):
  *   du [N][m], xs [N][nb]  step-1 results of the last iteration run
@@ -366,14 +452,21 @@ int orc_factor(int n, int m, int N, const double *A, const double *B, const doub
  */
 int orc_solve(int n, int m, int N, const double *A, const double *B, const double *e,
               const double *Q, const double *R, const double *Wdu, const double *qbar,
-              const double *lb, const double *ub, const double *xbar0, double rho, int K, double eps,
+              const double *lb, const double *ub, int xkind, const double *xpar, int ukind,
+              const double *upar, const double *xbar0, double rho, int K, double eps,
               int accel, double eta, double *state, double *du, double *xs, double *hist,
               int *iters) {
     if (n <= 0 || m <= 0 || N <= 0 || K < 0 || !(rho > 0.0)) return -2;
+    if (xkind < 0 || xkind > 4 || ukind < 0 || ukind > 4) return -2;
+    if ((xkind == ORC_SET_SOC && n < 2) || (ukind == ORC_SET_SOC && m < 2)) return -2;
     int nb = n + m;
     size_t S = (size_t)N * nb;
     vform_t V;
     vform_build(&V, n, m, N, A, B, e, Q, R, Wdu, qbar);
+    V.xkind = xkind;
+    V.ukind = ukind;
+    if (xpar) memcpy(V.xpar, xpar, sizeof(double) * ((size_t)n + 1));
+    if (upar) memcpy(V.upar, upar, sizeof(double) * ((size_t)m + 1));
     int rc = vform_factor(&V, rho);
     if (rc) { vform_free(&V); return -1; }
 
@@ -726,4 +819,10 @@ int orc_grad(int n, int m, int N, const double *A, const double *B, const double
     free(tape); free(du); free(xs); free(dlast); free(xbar0);
     vform_free(&V); free(Aall); free(Ball); free(Q); free(R);
     return 0;
+}
+
+/* Projection of w (n entries) onto one factor set (exported for the pins). */
+void orc_project(int kind, int n, const double *par, const double *lo, const double *hi, double *w) {
+    static const double zero[1] = {0.0};
+    project_set(kind, n, par ? par : zero, lo, hi, w);
 }

@@ -33,6 +33,10 @@ class Problem:
     qbar: None or (n+m,) linear term of the velocity-form cost (Theorem 2).
     Wdu: None or (m, m) symmetric PSD input-rate weight, cost term
     1/2 ||u_k - u_{k-1}||^2_{Wdu} (used by the paper's experiments, Section V).
+    xset / uset: None (the box xmin..xmax / umin..umax) or another closed
+    convex set for every x_k / u_k (the sets the proof of Theorem 1 lists):
+    ("halfspace", a, b) = {a'w <= b}, ("hyperplane", a, b) = {a'w = b},
+    ("soc",) = {||w[:-1]||_2 <= w[-1]}, ("l1ball", r) = {||w||_1 <= r}.
     Bounds are per-component boxes; +-inf allowed.  x0 = x(t), u_prev = u(t-1).
     """
 
@@ -54,6 +58,8 @@ class Problem:
     e: Optional[np.ndarray] = None
     qbar: Optional[np.ndarray] = None
     Wdu: Optional[np.ndarray] = None
+    xset: Optional[tuple] = None
+    uset: Optional[tuple] = None
 
     @property
     def nb(self) -> int:
