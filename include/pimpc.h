@@ -51,6 +51,20 @@ extern "C" {
 #define PIMPC_FP64 0
 #define PIMPC_FP32 1
 
+/* Constraint set of the x_k or of the u_k factor of Xbar = X x U (the z update
+ * of Theorem 1 projects onto it; the proof of Theorem 1 lists these sets).
+ * Parameters per instance, w = the factor (nx or nu entries), par = (a, b):
+ *   BOX         xmin <= w <= xmax (the problem's bounds; par unused)
+ *   HALFSPACE   a'w <= b           (a != 0)
+ *   HYPERPLANE  a'w = b            (a != 0)
+ *   SOC         ||(w_1..w_{n-1})||_2 <= w_n   (n >= 2; par unused)
+ *   L1BALL      ||w||_1 <= r, r = par[n] >= 0 (a unused) */
+#define PIMPC_SET_BOX 0
+#define PIMPC_SET_HALFSPACE 1
+#define PIMPC_SET_HYPERPLANE 2
+#define PIMPC_SET_SOC 3
+#define PIMPC_SET_L1BALL 4
+
 /* where a pointer lives */
 #define PIMPC_MEM_HOST 0
 #define PIMPC_MEM_DEVICE 1
@@ -81,6 +95,13 @@ typedef struct pimpc_ctx_s *pimpc_ctx;
  *   Wdu            nu*nu symmetric PSD input-rate weight per instance (cost term
  *                  1/2 ||u_k - u_{k-1}||^2_Wdu), NULL = 0.  It changes only the
  *                  du cache: J_k = (Wdu / rho + Bbar_k' Bbar_k)^-1 Bbar_k'.
+ *   xset, uset     per-instance PIMPC_SET_* kind of the X and U factors, NULL =
+ *                  all boxes.  For a non-box factor the matching xmin/xmax (or
+ *                  umin/umax) entries are ignored.  Non-box sets run on the
+ *                  lane family (N <= 512) without a tape; other requests
+ *                  return PIMPC_E_UNSUPPORTED.
+ *   xset_par       (nx + 1) values per instance: (a, b) or (., r); may be NULL
+ *   uset_par       (nu + 1) values per instance, likewise
  */
 typedef struct {
     int32_t count;
@@ -99,6 +120,10 @@ typedef struct {
     const double *umin;
     const double *umax;
     const double *Wdu;
+    const int32_t *xset;
+    const int32_t *uset;
+    const double *xset_par;
+    const double *uset_par;
 } pimpc_problem;
 
 /*

@@ -48,6 +48,82 @@ __device__ inline T clampv(T y, T lo, T hi) {
     return y < lo ? lo : (y > hi ? hi : y);
 }
 
+// Euclidean projection of the factor y[OFF .. OFF + n) (n <= NP real entries
+// of a padded factor of NP) onto a non-box set of the proof of Theorem 1
+// (closed forms as in Parikh and Boyd, "Proximal Algorithms", Ch. 6); the
+// padded entries are left to the box clamp.  par = (a [NP], b) or (., r).
+//   1 halfspace a'w <= b, 2 hyperplane a'w = b: w -= (a'w - b)_(+) / |a|^2 a
+//   3 second-order cone |w_1..n-1| <= w_n: scale onto the cone surface
+//   4 l1 ball |w|_1 <= r: soft threshold at theta = max over j of
+//     (sum of the |w_i| >= |w_j|, minus r) / (their count)
+template <typename T, int NP, int OFF, int NBT>
+__device__ inline void project_factor(T (&y)[NBT], int kind, int n, cptr<T> par) {
+    if (kind == 1 || kind == 2) {
+        T s = T(0), aa = T(0);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const T a = par[i];  // zero beyond n
+            s += a * y[OFF + i];
+            aa += a * a;
+        }
+        s -= par[NP];
+        if (kind == 2 || s > T(0)) {
+            const T f = s / aa;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) y[OFF + i] -= f * par[i];
+        }
+    } else if (kind == 3) {
+        T t = T(0), q = T(0);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            if (i == n - 1) t = y[OFF + i];
+            if (i < n - 1) q += y[OFF + i] * y[OFF + i];
+        }
+        const T nq = sqrt(q);
+        if (nq <= t) return;
+        const bool zero = nq <= -t;
+        const T al = (nq + t) * T(0.5);
+        const T sc = zero ? T(0) : al / nq;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            if (i < n - 1) y[OFF + i] *= sc;
+            if (i == n - 1) y[OFF + i] = zero ? T(0) : al;
+        }
+    } else if (kind == 4) {
+        const T r = par[NP];
+        T l1 = T(0);
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            if (i < n) l1 += fabs(y[OFF + i]);
+        if (l1 <= r) return;
+        T theta = T(0);
+        bool first = true;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            if (j >= n) continue;
+            const T mj = fabs(y[OFF + j]);
+            T sj = T(0), cj = T(0);
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const T mi = fabs(y[OFF + i]);
+                if (i < n && mi >= mj) {
+                    sj += mi;
+                    cj += T(1);
+                }
+            }
+            const T tj = (sj - r) / cj;
+            theta = (first || tj > theta) ? tj : theta;
+            first = false;
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            if (i >= n) continue;
+            const T a = fabs(y[OFF + i]) - theta;
+            y[OFF + i] = a > T(0) ? (y[OFF + i] > T(0) ? a : -a) : T(0);
+        }
+    }
+}
+
 // DPP wavefront shifts by one lane (32-bit moves; a double moves as two
 // halves).  shl1: lane i receives lane i + 1 (lane 63 receives 0);
 // shr1: lane i receives lane i - 1 (lane 0 receives 0).
@@ -117,7 +193,7 @@ __device__ __forceinline__ void stream_rows(L&& load, B&& body) {
 
 // Run (or, with have = false, only shadow the barrier sequence of) one
 // instance on the waves [gw0, gw0 + gnw) of the workgroup.
-template <typename T, int NX, int NU, bool TV>
+template <typename T, int NX, int NU, bool TV, bool GS>
 __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bool have, int gw0,
                                          unsigned leader_mask, T (*bnd_g)[NX + NU], T (*bnd_x)[NX + NU],
                                          T (*dzl)[kBinThreads], T (*ddl)[kBinThreads], double* red,
@@ -428,26 +504,9 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             }
 #pragma unroll
             for (int c = 0; c < NU; ++c) rdu[c] = T(0);
-            // component i: b_i = (Bbar du)_i + beta_i;  c_i = (Abar xbar_k)_i + ebar_i - lambda_i
-            // (rows are passed as accessors, never as addresses, so that they stay in registers)
-            auto comp = [&](int i, auto&& arow, auto&& brow, T ei, T lo, T hi) {
-                T bi, ci;
-                if (i < NX) {
-                    bi = be[i];
-#pragma unroll
-                    for (int j = 0; j < NU; ++j) bi += brow(j) * du[j];
-                    ci = ei - la[i];
-#pragma unroll
-                    for (int j = 0; j < NX; ++j) ci += arow(j) * xp[j];
-#pragma unroll
-                    for (int j = 0; j < NU; ++j) ci += brow(j) * xp[NX + j];
-                } else {
-                    bi = du[i - NX] + be[i];
-                    ci = xp[i] - la[i];
-                }
+            // the new iterate of component i from b_i, c_i and the projected z_i
+            auto finish = [&](int i, T bi, T ci, T zn, auto&& brow) {
                 const T gam = bi - ci;
-                const T y = (T(2) * (xs[i] + th[i]) + bi + ci) * third;
-                const T zn = clampv(y, lo, hi);
                 const T vn = (zn + gam) * T(0.5);
                 const T thn = th[i] + xs[i] - zn;
                 const T ben = bi - vn;
@@ -476,6 +535,36 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                 be[i] = ben;
                 la[i] = lan;
             };
+            // general sets: y, b, c of every component, projected after the stream
+            T gy[GS ? NB : 1], gbv[GS ? NB : 1], gcv[GS ? NB : 1];
+            // component i: b_i = (Bbar du)_i + beta_i;  c_i = (Abar xbar_k)_i + ebar_i - lambda_i
+            // (rows are passed as accessors, never as addresses, so that they stay in registers)
+            auto comp = [&](int i, auto&& arow, auto&& brow, T ei, T lo, T hi) {
+                T bi, ci;
+                if (i < NX) {
+                    bi = be[i];
+#pragma unroll
+                    for (int j = 0; j < NU; ++j) bi += brow(j) * du[j];
+                    ci = ei - la[i];
+#pragma unroll
+                    for (int j = 0; j < NX; ++j) ci += arow(j) * xp[j];
+#pragma unroll
+                    for (int j = 0; j < NU; ++j) ci += brow(j) * xp[NX + j];
+                } else {
+                    bi = du[i - NX] + be[i];
+                    ci = xp[i] - la[i];
+                }
+                const T y = (T(2) * (xs[i] + th[i]) + bi + ci) * third;
+                if constexpr (GS) {
+                    gy[i] = y;
+                    gbv[i] = bi;
+                    gcv[i] = ci;
+                    (void)lo;
+                    (void)hi;
+                } else {
+                    finish(i, bi, ci, clampv(y, lo, hi), brow);
+                }
+            };
             if constexpr (TV) {
                 const cptr<T> lbq = lbm, ubq = ubm;
 #pragma unroll
@@ -503,6 +592,23 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                             i, [&](int j) { return x.x[j]; }, [&](int j) { return x.x[NX + j]; },
                             i < NX ? x.x[NB] : T(0), x.x[NB + 1], x.x[NB + 2]);
                     });
+            }
+            if constexpr (GS) {
+                // z = Proj_{X x U}(y): the non-box factor (if any) first, then the
+                // box clamp (the identity on a non-box factor's real entries,
+                // whose bounds are stored as -inf / +inf; zero on padding)
+                const int xk = have ? (*IP()).xset : 0, uk = have ? (*IP()).uset : 0;
+                const int nxr = have ? (*IP()).nx : 0, nur = have ? (*IP()).nu : 0;
+                project_factor<T, NX, 0>(gy, xk, nxr, Mi + o.sx);
+                project_factor<T, NU, NX>(gy, uk, nur, Mi + o.su);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const T zn = clampv(gy[i], (T)lbm[i], (T)ubm[i]);
+                    if constexpr (TV)
+                        finish(i, gbv[i], gcv[i], zn, [&](int j) { return Br[(i < NX ? i : 0) * NU + j]; });
+                    else
+                        finish(i, gbv[i], gcv[i], zn, [&](int j) { return (T)Bm[(i < NX ? i : 0) * NU + j]; });
+                }
             }
             ++iters;
             if (check && act && (*AP()).write_iters) {
@@ -703,7 +809,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 // wider ones take the whole register file with one.
 constexpr int lane_waves_per_eu(int nb, int tsize) { return (tsize == 4 && nb <= 7) ? 4 : 2; }
 
-template <typename T, int NX, int NU, bool TV>
+template <typename T, int NX, int NU, bool TV, bool GS>
 __global__ void __launch_bounds__(kBinThreads)
     __attribute__((amdgpu_waves_per_eu(lane_waves_per_eu(NX + NU, sizeof(T)))))
     lane_kernel(const LaneArgs* __restrict__ ap) {
@@ -738,33 +844,37 @@ __global__ void __launch_bounds__(kBinThreads)
         if (threadIdx.x < kBinWaves) gdone[threadIdx.x] = 1;
         __syncthreads();
         if (my >= 0)
-            lane_run<T, NX, NU, TV>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g, bnd_x, dzl,
-                                    ddl, red, gdone);
+            lane_run<T, NX, NU, TV, GS>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g, bnd_x,
+                                        dzl, ddl, red, gdone);
         else
-            lane_run<T, NX, NU, TV>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone);
+            lane_run<T, NX, NU, TV, GS>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone);
         __syncthreads();
     }
 }
 
 template <typename T, int NX, int NU, bool TV>
-hipError_t launch_lane_cls(const LaneArgs* a_dev, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV>), dim3(grid), dim3(kBinThreads), 0, s, a_dev);
+hipError_t launch_lane_cls(const LaneArgs* a_dev, int grid, hipStream_t s, bool gs) {
+    if (gs)
+        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, true>), dim3(grid), dim3(kBinThreads), 0, s, a_dev);
+    else
+        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, false>), dim3(grid), dim3(kBinThreads), 0, s, a_dev);
     return hipGetLastError();
 }
 
 template <typename T, int NX, int NU, bool TV>
-int lane_occupancy() {
+int lane_occupancy(bool gs) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV>, kBinThreads, 0) !=
-        hipSuccess)
-        return -1;
+    const hipError_t e =
+        gs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, true>, kBinThreads, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, false>, kBinThreads, 0);
+    if (e != hipSuccess) return -1;
     return nb > 0 ? nb : 1;
 }
 
 // Class dispatch, split into parts compiled separately (PIMPC_LANE_PART of
 // PIMPC_LANE_NPARTS) so the per-class kernels build in parallel.
 template <int P>
-hipError_t lane_dispatch(int fp64, int cls, const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s,
+hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s,
                          int* occ, bool* handled) {
     (void)nbmax;
     *handled = false;
@@ -774,15 +884,16 @@ hipError_t lane_dispatch(int fp64, int cls, const LaneArgs* a_dev, int nbmax, in
             *handled = true;                                                                \
             if (occ) {                                                                      \
                 if (!fp64)                                                                  \
-                    *occ = lane_occupancy<float, nx, nu, tv>();                             \
+                    *occ = lane_occupancy<float, nx, nu, tv>(gs != 0);                      \
                 else if constexpr (lane_fp64_class(nx + nu))                                \
-                    *occ = lane_occupancy<double, nx, nu, tv>();                            \
+                    *occ = lane_occupancy<double, nx, nu, tv>(gs != 0);                     \
                 else                                                                        \
                     *occ = -1;                                                              \
                 return *occ > 0 ? hipSuccess : hipErrorInvalidValue;                        \
             }                                                                               \
-            if (!fp64) return launch_lane_cls<float, nx, nu, tv>(a_dev, grid, s);           \
-            if constexpr (lane_fp64_class(nx + nu)) return launch_lane_cls<double, nx, nu, tv>(a_dev, grid, s); \
+            if (!fp64) return launch_lane_cls<float, nx, nu, tv>(a_dev, grid, s, gs != 0);  \
+            if constexpr (lane_fp64_class(nx + nu))                                         \
+                return launch_lane_cls<double, nx, nu, tv>(a_dev, grid, s, gs != 0);        \
             return hipErrorInvalidValue;                                                    \
         }                                                                                   \
     }
@@ -797,8 +908,8 @@ hipError_t lane_dispatch(int fp64, int cls, const LaneArgs* a_dev, int nbmax, in
 }
 
 #ifdef PIMPC_LANE_PART
-template hipError_t lane_dispatch<PIMPC_LANE_PART>(int, int, const LaneArgs*, int, int, hipStream_t, int*,
-                                                   bool*);
+template hipError_t lane_dispatch<PIMPC_LANE_PART>(int, int, int, const LaneArgs*, int, int, hipStream_t,
+                                                   int*, bool*);
 #endif
 
 }  // namespace pimpc

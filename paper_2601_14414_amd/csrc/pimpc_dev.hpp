@@ -23,6 +23,7 @@ struct InstDev {
     int32_t tv;                // time-varying stage data
     int32_t hb_diag;           // H_{N-1} is diagonal (time-invariant only)
     int32_t pad0, pad1;
+    int32_t xset, uset;        // constraint-set kinds of the x and u factors (PIMPC_SET_*)
     int64_t mat_off;           // T matrix block (see layout below)
     int64_t mat64_off;         // FP64 factorisation inputs
     int64_t st_off;            // iterate block [5][nbp][N]
@@ -42,14 +43,15 @@ constexpr int kGradStride = kGradBlocks * 256 + 16;
 // T matrix block of one instance (padded sizes NX, NU, NB = NX + NU).
 // Time-invariant (tv = 0), row-major:
 //   J [NU][NB] | Ha [NB][NB] | Hb [NB][NB] | A [NX][NX] | B [NX][NU] | e [NX] |
-//   qbar [NB] | lb [NB] | ub [NB]
+//   qbar [NB] | lb [NB] | ub [NB] | sx [NX + 1] | su [NU + 1]
 // Time-varying (tv = 1), stage-minor ("SoA": element q of stage k at q*N + k):
 //   J [NU*NB][N] | H [NB*NB][N] | A [NX*NX][N] | B [NX*NU][N] | e [NX][N] |
-//   qbar [NB] | lb [NB] | ub [NB]
+//   qbar [NB] | lb [NB] | ub [NB] | sx [NX + 1] | su [NU + 1]
+// sx / su: parameters (a padded with zeros, then b or r) of non-box x / u sets.
 __host__ __device__ inline int64_t mat_block_size(int32_t NX, int32_t NU, int32_t N, int32_t tv) {
     const int64_t NB = NX + NU;
-    if (!tv) return NU * NB + 2 * NB * NB + NX * NX + NX * NU + NX + 3 * NB;
-    return (int64_t)N * (NU * NB + NB * NB + NX * NX + NX * NU + NX) + 3 * NB;
+    if (!tv) return NU * NB + 2 * NB * NB + NX * NX + NX * NU + NX + 4 * NB + 2;
+    return (int64_t)N * (NU * NB + NB * NB + NX * NX + NX * NU + NX) + 4 * NB + 2;
 }
 
 // FP64 factorisation inputs of one instance (padded):
@@ -62,7 +64,7 @@ __host__ __device__ inline int64_t mat64_block_size(int32_t NX, int32_t NU, int3
 
 // Offsets inside the blocks above.
 struct MatOffsets {
-    int64_t J, H, Hb, A, B, e, qbar, lb, ub;  // T block (Hb unused when tv)
+    int64_t J, H, Hb, A, B, e, qbar, lb, ub, sx, su;  // T block (Hb unused when tv)
     int64_t A64, B64, e64, Q64, R64, W64;     // FP64 block
 };
 
@@ -88,6 +90,8 @@ __host__ __device__ inline MatOffsets mat_offsets(int32_t NX, int32_t NU, int32_
     }
     o.lb = o.qbar + NB;
     o.ub = o.lb + NB;
+    o.sx = o.ub + NB;
+    o.su = o.sx + NX + 1;
     const int64_t S = tv ? N : 1;
     o.A64 = 0;
     o.B64 = o.A64 + S * NX * NX;

@@ -59,12 +59,12 @@ inline int64_t stage_fma(int nx, int nu) {
     return nb * nb + nu * nb + 2LL * nx * nx + 3LL * nx * nu;
 }
 
-hipError_t lane_dispatch_any(int fp64, int cls, const LaneArgs* a, int nbmax, int grid, hipStream_t s,
+hipError_t lane_dispatch_any(int fp64, int cls, int gs, const LaneArgs* a, int nbmax, int grid, hipStream_t s,
                              int* occ) {
     bool handled = false;
     hipError_t e;
-#define PIMPC_TRY(P)                                                        \
-    e = lane_dispatch<P>(fp64, cls, a, nbmax, grid, s, occ, &handled);     \
+#define PIMPC_TRY(P)                                                            \
+    e = lane_dispatch<P>(fp64, cls, gs, a, nbmax, grid, s, occ, &handled);     \
     if (handled) return e;
     PIMPC_TRY(0)
     PIMPC_TRY(1)
@@ -108,6 +108,7 @@ struct ClassRun {
     int bin_first = 0;
     int nbins = 0;
     int occ = 1;
+    int gs = 0;        // some instance of the class has a non-box constraint set
     int64_t cost = 0;  // sum over bins of waves * stage FMAs (for stream balancing)
 };
 
@@ -284,7 +285,7 @@ static void build_mats64(pimpc_ctx ctx, const double* A, const double* B, const 
 
 template <typename T>
 static int upload_t_block(pimpc_ctx ctx, const double* qbar, const double* xmin, const double* xmax,
-                          const double* umin, const double* umax) {
+                          const double* umin, const double* umax, const double* xpar, const double* upar) {
     std::vector<T> h(ctx->mat_elems, T(0));
     int64_t ox = 0, ou = 0;
     for (int i = 0; i < ctx->count; ++i) {
@@ -300,10 +301,23 @@ static int upload_t_block(pimpc_ctx ctx, const double* qbar, const double* xmin,
             if (real) {
                 lo = isx ? xmin[ox + rr] : umin[ou + rr];
                 hi = isx ? xmax[ox + rr] : umax[ou + rr];
+                if ((isx ? I.xset : I.uset) != PIMPC_SET_BOX) {  // the set's own projection applies
+                    lo = -INFINITY;
+                    hi = INFINITY;
+                }
             }
             b[o.lb + r] = (T)lo;
             b[o.ub + r] = (T)hi;
             b[o.qbar + r] = (T)q;
+        }
+        // non-box set parameters: (a, b) or (., r), a padded with zeros
+        if (I.xset != PIMPC_SET_BOX && xpar) {
+            for (int r = 0; r < nx; ++r) b[o.sx + r] = (T)xpar[ox + i + r];
+            b[o.sx + NX] = (T)xpar[ox + i + nx];
+        }
+        if (I.uset != PIMPC_SET_BOX && upar) {
+            for (int r = 0; r < nu; ++r) b[o.su + r] = (T)upar[ou + i + r];
+            b[o.su + NU] = (T)upar[ou + i + nu];
         }
         if (qbar) {
             const int64_t qo = ox + ou;  // qbar packed as (nx + nu) per instance
@@ -395,6 +409,8 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassR
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return used[a] > used[b]; });
         ClassRun run;
         run.cls = cd.id;
+        for (int i : members)
+            if (ctx->inst[i].xset != 0 || ctx->inst[i].uset != 0) run.gs = 1;
         run.nbmax = cd.nx + cd.nu;
         run.bin_first = (int)bins.size();
         run.nbins = (int)cb.size();
@@ -541,7 +557,7 @@ static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
         const ClassRun& r = ctx->runs[c];
         const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[j] += r.cost;
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, ls->d_args + c, r.nbmax, class_grid(ctx, r),
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, ls->d_args + c, r.nbmax, class_grid(ctx, r),
                                       stream_of(j), nullptr));
     }
     if (ns > 1) {
@@ -775,6 +791,39 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             orr += (int64_t)p->nu[i] * p->nu[i];
         }
     }
+    {  // constraint sets of the x and u factors
+        int64_t ox = 0, ou = 0;
+        for (int i = 0; i < count; ++i) {
+            for (int side = 0; side < 2; ++side) {
+                const int kind = side == 0 ? (p->xset ? p->xset[i] : 0) : (p->uset ? p->uset[i] : 0);
+                const int n = side == 0 ? p->nx[i] : p->nu[i];
+                const double* par = side == 0 ? (p->xset_par ? p->xset_par + ox + i : nullptr)
+                                              : (p->uset_par ? p->uset_par + ou + i : nullptr);
+                const char* nm = side == 0 ? "xset" : "uset";
+                if (kind < PIMPC_SET_BOX || kind > PIMPC_SET_L1BALL)
+                    return ctx->fail(PIMPC_E_ARG, "instance %d: unknown %s kind %d", i, nm, kind);
+                if (kind == PIMPC_SET_BOX) continue;
+                if (kind == PIMPC_SET_SOC && n < 2)
+                    return ctx->fail(PIMPC_E_DIM, "instance %d: a second-order cone %s needs >= 2 entries", i, nm);
+                if (kind != PIMPC_SET_SOC && !par)
+                    return ctx->fail(PIMPC_E_ARG, "instance %d: %s_par is required for this set", i, nm);
+                if (par && !finite_arr(par, n + 1))
+                    return ctx->fail(PIMPC_E_NONFINITE, "instance %d: %s_par contains NaN or Inf", i, nm);
+                if (kind == PIMPC_SET_HALFSPACE || kind == PIMPC_SET_HYPERPLANE) {
+                    double aa = 0.0;
+                    for (int r = 0; r < n; ++r) aa += par[r] * par[r];
+                    if (!(aa > 0.0)) return ctx->fail(PIMPC_E_ARG, "instance %d: %s normal a is zero", i, nm);
+                }
+                if (kind == PIMPC_SET_L1BALL && !(par[n] >= 0.0))
+                    return ctx->fail(PIMPC_E_ARG, "instance %d: %s radius must be >= 0", i, nm);
+                if (o->ckpt_every > 0)
+                    return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                     "instance %d: the taped forward differentiates box constraints only", i);
+            }
+            ox += p->nx[i];
+            ou += p->nu[i];
+        }
+    }
 
     // ---------------- layout
     ctx->opt = *o;
@@ -793,6 +842,8 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         I.nb = I.nx + I.nu;
         I.N = p->N[i];
         I.tv = tv;
+        I.xset = p->xset ? p->xset[i] : PIMPC_SET_BOX;
+        I.uset = p->uset ? p->uset[i] : PIMPC_SET_BOX;
         const int cls = (I.N <= kBinThreads) ? pick_class(I.nx, I.nu, tv, ctx->fp64 ? 8 : 4) : -1;
         if (cls >= 0) {
             const ClassDesc* cd = class_desc(cls);
@@ -808,6 +859,10 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             I.cls = -1;
             I.nxp = rnx;
             I.nup = rnu;
+            if (I.xset != PIMPC_SET_BOX || I.uset != PIMPC_SET_BOX)
+                return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                 "instance %d (nx=%d, nu=%d, N=%d): non-box constraint sets need the lane family "
+                                 "(N <= 512)", i, I.nx, I.nu, I.N);
             if (o->accel == 1)
                 return ctx->fail(PIMPC_E_UNSUPPORTED,
                                  "instance %d (nx=%d, nu=%d, N=%d): restart acceleration needs the lane family "
@@ -895,8 +950,9 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     std::vector<double> m64v;
     build_mats64(ctx, p->A, p->B, p->e, p->Q, p->R, p->Wdu, m64v, false);
     HIPCHK(ctx, hipMemcpy(ctx->d_mats64, m64v.data(), m64v.size() * sizeof(double), hipMemcpyHostToDevice));
-    int rc = ctx->fp64 ? upload_t_block<double>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax)
-                       : upload_t_block<float>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax);
+    int rc = ctx->fp64
+                 ? upload_t_block<double>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax, p->xset_par, p->uset_par)
+                 : upload_t_block<float>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax, p->xset_par, p->uset_par);
     if (rc != PIMPC_OK) return rc;
     rc = refactor(ctx, true);
     if (rc != PIMPC_OK) return rc;
@@ -911,7 +967,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     DALLOC(ctx->d_counters, int32_t, std::max<size_t>(ctx->runs.size(), 1));
     for (ClassRun& r : ctx->runs) {
         int occ = 1;
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, nullptr, r.nbmax, 0, ctx->stream, &occ));
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, nullptr, r.nbmax, 0, ctx->stream, &occ));
         r.occ = occ;
     }
     if (!ctx->row_insts.empty()) {

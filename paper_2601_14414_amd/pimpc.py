@@ -33,6 +33,7 @@ PIMPC_FP64 = 0
 PIMPC_FP32 = 1
 PIMPC_MEM_HOST = 0
 PIMPC_MEM_DEVICE = 1
+PIMPC_SET_BOX, PIMPC_SET_HALFSPACE, PIMPC_SET_HYPERPLANE, PIMPC_SET_SOC, PIMPC_SET_L1BALL = 0, 1, 2, 3, 4
 IT_V, IT_Z, IT_THETA, IT_BETA, IT_LAMBDA, IT_DU, IT_XBAR = range(7)
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -43,7 +44,8 @@ class pimpc_problem(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("nx", _ip), ("nu", _ip), ("N", _ip),
                 ("time_varying", ctypes.c_int32), ("A", _dp), ("B", _dp), ("e", _dp),
                 ("Q", _dp), ("R", _dp), ("qbar", _dp), ("xmin", _dp), ("xmax", _dp),
-                ("umin", _dp), ("umax", _dp), ("Wdu", _dp)]
+                ("umin", _dp), ("umax", _dp), ("Wdu", _dp), ("xset", _ip), ("uset", _ip),
+                ("xset_par", _dp), ("uset_par", _dp)]
 
 
 class pimpc_options(ctypes.Structure):
@@ -151,6 +153,32 @@ def pimpc_default_options() -> pimpc_options:
     return o
 
 
+SET_KINDS = {"box": PIMPC_SET_BOX, "halfspace": PIMPC_SET_HALFSPACE, "hyperplane": PIMPC_SET_HYPERPLANE,
+             "soc": PIMPC_SET_SOC, "l1ball": PIMPC_SET_L1BALL}
+
+
+def _set_arrays(specs, sizes):
+    """Packed kinds (int32 per instance) and parameters ((n + 1) per instance)
+    of the x or u factor sets; (None, None) when every factor is a box.  A
+    spec is None / ("box",) / ("halfspace", a, b) / ("hyperplane", a, b) /
+    ("soc",) / ("l1ball", r)."""
+    if all(sp is None or sp[0] == "box" for sp in specs):
+        return None, None
+    kinds = np.zeros(len(specs), np.int32)
+    pars = []
+    for i, (sp, n) in enumerate(zip(specs, sizes)):
+        par = np.zeros(n + 1)
+        if sp is not None:
+            kinds[i] = SET_KINDS[sp[0]]
+            if sp[0] in ("halfspace", "hyperplane"):
+                par[:n] = np.asarray(sp[1], np.float64)
+                par[n] = float(sp[2])
+            elif sp[0] == "l1ball":
+                par[n] = float(sp[1])
+        pars.append(par)
+    return kinds, _f64(np.concatenate(pars))
+
+
 def pimpc_setup(problems: Sequence, opts: pimpc_options, stream: Optional[int] = None):
     """Create a context for a list of workloads.Problem (all time-invariant or
     all time-varying).  Returns (ctx, keepalive)."""
@@ -184,12 +212,17 @@ def pimpc_setup(problems: Sequence, opts: pimpc_options, stream: Optional[int] =
     if any(getattr(p, "Wdu", None) is not None for p in problems):
         Wdu = _f64(np.concatenate([(np.zeros((p.nu, p.nu)) if getattr(p, "Wdu", None) is None
                                     else np.asarray(p.Wdu)).ravel() for p in problems]))
+    xk, xpar = _set_arrays([getattr(p, "xset", None) for p in problems], [p.nx for p in problems])
+    uk, upar = _set_arrays([getattr(p, "uset", None) for p in problems], [p.nu for p in problems])
     keep.update(nx=nx, nu=nu, N=N, A=A, B=B, e=e, Q=Q, R=R, qbar=qbar, xmin=xmin, xmax=xmax,
-                umin=umin, umax=umax, Wdu=Wdu)
+                umin=umin, umax=umax, Wdu=Wdu, xk=xk, xpar=xpar, uk=uk, upar=upar)
     prob = pimpc_problem(count=len(problems), nx=nx.ctypes.data_as(_ip), nu=nu.ctypes.data_as(_ip),
                          N=N.ctypes.data_as(_ip), time_varying=tv, A=_p(A), B=_p(B), e=_p(e),
                          Q=_p(Q), R=_p(R), qbar=_p(qbar), xmin=_p(xmin), xmax=_p(xmax),
-                         umin=_p(umin), umax=_p(umax), Wdu=_p(Wdu))
+                         umin=_p(umin), umax=_p(umax), Wdu=_p(Wdu),
+                         xset=None if xk is None else xk.ctypes.data_as(_ip),
+                         uset=None if uk is None else uk.ctypes.data_as(_ip), xset_par=_p(xpar),
+                         uset_par=_p(upar))
     ctx = ctypes.c_void_p()
     rc = lib().pimpc_setup(ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opts), stream)
     _check(rc, None)

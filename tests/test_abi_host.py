@@ -81,6 +81,27 @@ def test_bad_problem_data_rejected():
     assert _setup_code([q])[0] == P.PIMPC_E_DIM
 
 
+def test_bad_constraint_sets_rejected():
+    p = W.plain_fp64_problem(0)
+    assert _setup_code([p.copy(uset=("soc",))])[0] not in (P.PIMPC_E_ARG, P.PIMPC_E_DIM)
+    q = W.Problem(**{**p.__dict__, "uset": ("halfspace", np.zeros(3), 1.0)})
+    code, msg = _setup_code([q])
+    assert code == P.PIMPC_E_ARG and "normal" in msg
+    code, msg = _setup_code([p.copy(uset=("l1ball", -0.1))])
+    assert code == P.PIMPC_E_ARG and "radius" in msg
+    code, msg = _setup_code([p.copy(xset=("l1ball", float("nan")))])
+    assert code == P.PIMPC_E_NONFINITE
+    # a cone needs two entries
+    one = W.cartpole_problem(N=16, K=5).copy(uset=("soc",))
+    assert _setup_code([one])[0] == P.PIMPC_E_DIM
+    # non-box sets: lane family only, and no tape
+    lh = W.long_horizon_problem(0, N=600, K=10).copy(uset=("l1ball", 1.0))
+    code, msg = _setup_code([lh])
+    assert code == P.PIMPC_E_UNSUPPORTED and "lane family" in msg
+    code, msg = _setup_code([p.copy(uset=("soc",))], ckpt_every=20)
+    assert code == P.PIMPC_E_UNSUPPORTED and "box" in msg
+
+
 def test_bad_rate_weight_rejected():
     p = W.plain_fp64_problem(0)
     Wd = 0.1 * np.eye(3)
