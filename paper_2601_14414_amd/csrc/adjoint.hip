@@ -149,27 +149,36 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
         MATS()
 #pragma unroll
         for (int i = 0; i < NB; ++i) d[i] = v[i] - be[i];
-#pragma unroll
-        for (int r = 0; r < NU; ++r) {
-            const cptr<float> Jr = ROWP(Jm, r, NB);
-            float s = 0.f;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) s += Jr[j] * d[j];
-            du[r] = s;
-        }
         float g[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) g[c] = (c < NX) ? 0.f : (z[c] - v[c] + la[c]);
+        // one stream of rows: J (du = J d), then [A_r B_r e_r] (g = Abar' w)
+        using RowJA = SRow<float, NB + 1>;
+        stream_rows<RowJA, NU + NX, true>(
+            [&](int r) {
+                RowJA x;
+                if (r < NU) {
+                    sload_into<float, NB>(x.x, Jm + r * NB);
+                } else {
+                    sload_into<float, NX>(x.x, Am + (r - NU) * NX);
+                    sload_into<float, NU>(x.x + NX, Bm + (r - NU) * NU);
+                    sload_into<float, 1>(x.x + NB, em + (r - NU));
+                }
+                return x;
+            },
+            [&](int r, const RowJA& x) {
+                if (r < NU) {
+                    float s = 0.f;
 #pragma unroll
-        for (int r = 0; r < NX; ++r) {
-            const float w = z[r] - v[r] - em[r] + la[r];
-            const cptr<float> Ar = ROWP(Am, r, NX);
-            const cptr<float> Br = ROWP(Bm, r, NU);
+                    for (int j = 0; j < NB; ++j) s += x.x[j] * d[j];
+                    du[r] = s;
+                } else {
+                    const int rr = r - NU;
+                    const float w = z[rr] - v[rr] - x.x[NB] + la[rr];
 #pragma unroll
-            for (int c = 0; c < NX; ++c) g[c] += Ar[c] * w;
-#pragma unroll
-            for (int c = 0; c < NU; ++c) g[NX + c] += Br[c] * w;
-        }
+                    for (int c = 0; c < NB; ++c) g[c] += x.x[c] * w;
+                }
+            });
 #pragma unroll
         for (int c = 0; c < NB; ++c) xg[c * kBBD + tid] = g[c];
         __syncthreads();
@@ -179,72 +188,93 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             const float gv = xg[i * kBBD + tid + 1];
             h[i] = qb[i] + rho * (z[i] - th[i] + (hasnext ? gv : 0.f));
         }
+        using RowH = SRow<float, NB>;
+        stream_rows<RowH, NB, true>(
+            [&](int r) {
+                RowH x;
+                sload_into<float, NB>(x.x, Hm + r * NB);
+                return x;
+            },
+            [&](int r, const RowH& x) {
+                float s = 0.f;
 #pragma unroll
-        for (int r = 0; r < NB; ++r) {
-            const cptr<float> Hr = ROWP(Hm, r, NB);
-            float s = 0.f;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) s += Hr[j] * h[j];
-            xs[r] = s;
-        }
+                for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
+                xs[r] = s;
+            });
         if (is_last) {
             if (hb_diag) {
 #pragma unroll
                 for (int r = 0; r < NB; ++r) xs[r] = Hbm[r * NB + r] * h[r];
             } else {
+                stream_rows<RowH, NB, true>(
+                    [&](int r) {
+                        RowH x;
+                        sload_into<float, NB>(x.x, Hbm + r * NB);
+                        return x;
+                    },
+                    [&](int r, const RowH& x) {
+                        float s = 0.f;
 #pragma unroll
-                for (int r = 0; r < NB; ++r) {
-                    float s = 0.f;
-#pragma unroll
-                    for (int j = 0; j < NB; ++j) s += Hbm[r * NB + j] * h[j];
-                    xs[r] = s;
-                }
+                        for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
+                        xs[r] = s;
+                    });
             }
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) xx[i * kBBD + tid] = xs[i];
         __syncthreads();
     };
-    // b, c of steps 2-3 given xbar_k (xp); optionally the new iterate.
-    auto step23 = [&](const float (&xp)[NB], float (&b)[NB], float (&c)[NB], bool advance) {
+    // Steps 2-3 given xbar_k (xp): b, c, the projection argument y and its box
+    // mask (bit i: lb_i < y_i < ub_i); with `advance`, also the new iterate.
+    // One stream of rows [A_i B_i e_i lb_i ub_i] (i < NX), [lb_i ub_i] (i >= NX).
+    auto step23 = [&](const float (&xp)[NB], bool advance, uint32_t& mask) {
         MATS()
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            if (i < NX) {
-                const cptr<float> Ar = ROWP(Am, i, NX);
-                const cptr<float> Br = ROWP(Bm, i, NU);
-                float sb = be[i];
-#pragma unroll
-                for (int j = 0; j < NU; ++j) sb += Br[j] * du[j];
-                float sc = em[i] - la[i];
-#pragma unroll
-                for (int j = 0; j < NX; ++j) sc += Ar[j] * xp[j];
-#pragma unroll
-                for (int j = 0; j < NU; ++j) sc += Br[j] * xp[NX + j];
-                b[i] = sb;
-                c[i] = sc;
-            } else {
-                b[i] = du[i - NX] + be[i];
-                c[i] = xp[i] - la[i];
-            }
-        }
-        if (advance) {
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const float gam = b[i] - c[i];
-                const float y = (2.f * (xs[i] + th[i]) + b[i] + c[i]) * third;
-                const float zn = y < lbm[i] ? lbm[i] : (y > ubm[i] ? ubm[i] : y);
-                const float vn = (zn + gam) * 0.5f;
-                const float thn = th[i] + xs[i] - zn;
-                if (act) {
-                    v[i] = vn;
-                    th[i] = thn;
-                    be[i] = b[i] - vn;
-                    la[i] = zn - vn - c[i];
-                    z[i] = zn;
+        mask = 0u;
+        using Row = SRow<float, NB + 3>;
+        stream_rows<Row, NB, true>(
+            [&](int i) {
+                Row x;
+                if (i < NX) {
+                    sload_into<float, NX>(x.x, Am + i * NX);
+                    sload_into<float, NU>(x.x + NX, Bm + i * NU);
+                    sload_into<float, 1>(x.x + NB, em + i);
                 }
-            }
-        }
+                sload_into<float, 1>(x.x + NB + 1, lbm + i);
+                sload_into<float, 1>(x.x + NB + 2, ubm + i);
+                return x;
+            },
+            [&](int i, const Row& x) {
+                float bi, ci;
+                if (i < NX) {
+                    bi = be[i];
+#pragma unroll
+                    for (int j = 0; j < NU; ++j) bi += x.x[NX + j] * du[j];
+                    ci = x.x[NB] - la[i];
+#pragma unroll
+                    for (int j = 0; j < NX; ++j) ci += x.x[j] * xp[j];
+#pragma unroll
+                    for (int j = 0; j < NU; ++j) ci += x.x[NX + j] * xp[NX + j];
+                } else {
+                    bi = du[i - NX] + be[i];
+                    ci = xp[i] - la[i];
+                }
+                const float lo = x.x[NB + 1], hi = x.x[NB + 2];
+                const float y = (2.f * (xs[i] + th[i]) + bi + ci) * third;
+                if (y > lo && y < hi) mask |= 1u << i;
+                if (advance) {
+                    const float gam = bi - ci;
+                    const float zn = y < lo ? lo : (y > hi ? hi : y);
+                    const float vn = (zn + gam) * 0.5f;
+                    const float thn = th[i] + xs[i] - zn;
+                    if (act) {
+                        v[i] = vn;
+                        th[i] = thn;
+                        be[i] = bi - vn;
+                        la[i] = zn - vn - ci;
+                        z[i] = zn;
+                    }
+                }
+            });
     };
     auto get_xp = [&](float (&xp)[NB]) {
 #pragma unroll
@@ -269,9 +299,10 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             store_state(tape + (int64_t)(i - i0) * 5 * NB * N);
             if (i + 1 < i1) {
                 step1();
-                float xp[NB], b[NB], c[NB];
+                float xp[NB];
+                uint32_t mask;
                 get_xp(xp);
-                step23(xp, b, c, true);
+                step23(xp, true, mask);
             }
         }
         // reverse sweep
@@ -302,16 +333,16 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             }
             // ---- recompute the step's intermediates
             step1();
-            float xp[NB], b[NB], c[NB];
+            float xp[NB];
+            uint32_t mask;
             get_xp(xp);
-            step23(xp, b, c, false);
+            step23(xp, false, mask);
             MATS()
             // ---- transpose of steps 2-3 (sv.. hold the adjoint of the new iterate)
             float nth[NB], xsb[NB], bb[NB], cb[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                const float y = (2.f * (xs[i] + th[i]) + b[i] + c[i]) * third;
-                const bool inside = y > lbm[i] && y < ubm[i];
+                const bool inside = (mask >> i) & 1u;
                 float znb = sz[i] - sth[i];
                 nth[i] = sth[i];
                 xsb[i] = sth[i];
@@ -342,30 +373,27 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 nla[i] = -cb[i];
             }
             // xbar_k adjoint = Abar' cb (to stage k-1, or to xbar_0 at k = 0)
-            float xpb[NB];
+            // and du adjoint = Bbar' bb, from one stream of rows [A_r B_r]
+            float xpb[NB], dub[NU];
 #pragma unroll
             for (int cc = 0; cc < NB; ++cc) xpb[cc] = (cc < NX) ? 0.f : cb[cc];
 #pragma unroll
-            for (int r = 0; r < NX; ++r) {
-                const cptr<float> Ar = ROWP(Am, r, NX);
-                const cptr<float> Br = ROWP(Bm, r, NU);
+            for (int cc = 0; cc < NU; ++cc) dub[cc] = bb[NX + cc];
+            using RowAB = SRow<float, NB>;
+            auto load_ab = [&](int r) {
+                RowAB x;
+                sload_into<float, NX>(x.x, Am + r * NX);
+                sload_into<float, NU>(x.x + NX, Bm + r * NU);
+                return x;
+            };
+            stream_rows<RowAB, NX, true>(load_ab, [&](int r, const RowAB& x) {
 #pragma unroll
-                for (int cc = 0; cc < NX; ++cc) xpb[cc] += Ar[cc] * cb[r];
+                for (int cc = 0; cc < NB; ++cc) xpb[cc] += x.x[cc] * cb[r];
 #pragma unroll
-                for (int cc = 0; cc < NU; ++cc) xpb[NX + cc] += Br[cc] * cb[r];
-            }
+                for (int cc = 0; cc < NU; ++cc) dub[cc] += x.x[NX + cc] * bb[r];
+            });
 #pragma unroll
             for (int i = 0; i < NB; ++i) xg[i * kBBD + tid] = xpb[i];
-            // du adjoint = Bbar' bb
-            float dub[NU];
-#pragma unroll
-            for (int cc = 0; cc < NU; ++cc) dub[cc] = bb[NX + cc];
-#pragma unroll
-            for (int r = 0; r < NX; ++r) {
-                const cptr<float> Br = ROWP(Bm, r, NU);
-#pragma unroll
-                for (int cc = 0; cc < NU; ++cc) dub[cc] += Br[cc] * bb[r];
-            }
             {  // Abar += cb xbar_k' (top rows), Bbar += bb du' (top rows)
                 float v1[16], v2[16];
 #pragma unroll
@@ -392,21 +420,36 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             }
             // h adjoint = H' xsb (H symmetric)
             float hb[NB];
-#pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const cptr<float> Hr = ROWP(Hm, r, NB);
-                float s = 0.f;
-#pragma unroll
-                for (int j = 0; j < NB; ++j) s += Hr[j] * xsb[j];
-                hb[r] = s;
-            }
-            if (is_last) {
-#pragma unroll
-                for (int r = 0; r < NB; ++r) {
+            using RowH = SRow<float, NB>;
+            stream_rows<RowH, NB, true>(
+                [&](int r) {
+                    RowH x;
+                    sload_into<float, NB>(x.x, Hm + r * NB);
+                    return x;
+                },
+                [&](int r, const RowH& x) {
                     float s = 0.f;
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) s += Hbm[j * NB + r] * xsb[j];
+                    for (int j = 0; j < NB; ++j) s += x.x[j] * xsb[j];
                     hb[r] = s;
+                });
+            if (is_last) {  // H_{N-1}' xsb (H_{N-1} is symmetric; diagonal for diagonal Q, R)
+                if (hb_diag) {
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) hb[r] = Hbm[r * NB + r] * xsb[r];
+                } else {
+                    stream_rows<RowH, NB, true>(
+                        [&](int r) {
+                            RowH x;
+                            sload_into<float, NB>(x.x, Hbm + r * NB);
+                            return x;
+                        },
+                        [&](int r, const RowH& x) {
+                            float s = 0.f;
+#pragma unroll
+                            for (int j = 0; j < NB; ++j) s += x.x[j] * xsb[j];
+                            hb[r] = s;
+                        });
                 }
             }
             {  // H_a += xsb h' (k < N-1), H_{N-1} += xsb h' (k = N-1)
@@ -439,17 +482,12 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             float wb[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) wb[i] = (i < NX) ? 0.f : gr[i];
-#pragma unroll
-            for (int r = 0; r < NX; ++r) {
-                const cptr<float> Ar = ROWP(Am, r, NX);
-                const cptr<float> Br = ROWP(Bm, r, NU);
+            stream_rows<RowAB, NX, true>(load_ab, [&](int r, const RowAB& x) {
                 float s = 0.f;
 #pragma unroll
-                for (int cc = 0; cc < NX; ++cc) s += Ar[cc] * gr[cc];
-#pragma unroll
-                for (int cc = 0; cc < NU; ++cc) s += Br[cc] * gr[NX + cc];
+                for (int cc = 0; cc < NB; ++cc) s += x.x[cc] * gr[cc];
                 wb[r] = s;
-            }
+            });
             {  // Abar += w_k g_bar' (top rows)
                 float v1[16], v2[16];
 #pragma unroll
@@ -475,13 +513,26 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 }
                 stage_accum(CJ, v1, v2, stg, lane);
             }
+            {  // J' dub, one stream of J rows
+                float jt[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                float t = 0.f;
+                for (int j = 0; j < NB; ++j) jt[j] = 0.f;
+                using RowJ = SRow<float, NB>;
+                stream_rows<RowJ, NU, true>(
+                    [&](int r) {
+                        RowJ x;
+                        sload_into<float, NB>(x.x, Jm + r * NB);
+                        return x;
+                    },
+                    [&](int r, const RowJ& x) {
 #pragma unroll
-                for (int r = 0; r < NU; ++r) t += Jm[r * NB + j] * dub[r];
-                nv[j] += t;
-                nbe[j] -= t;
+                        for (int j = 0; j < NB; ++j) jt[j] += x.x[j] * dub[r];
+                    });
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    nv[j] += jt[j];
+                    nbe[j] -= jt[j];
+                }
             }
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
