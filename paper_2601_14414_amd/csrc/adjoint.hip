@@ -594,10 +594,9 @@ __global__ void __launch_bounds__(kBwdThreads) lane_bwd_kernel(BwdArgs a) {
             if (wave >= bin.e[e].wave0 && wave < bin.e[e].wave0 + bin.e[e].nwaves) my = e;
         }
         my = __builtin_amdgcn_readfirstlane(my);
-        if (my >= 0)
-            bwd_run<NX, NU>(a, bin.e[my].inst, true, bin.e[my].wave0, leader_mask);
-        else
-            bwd_run<NX, NU>(a, 0, false, wave, leader_mask);
+        // one inlined copy: a wave without an instance shadows the barriers
+        const bool have = my >= 0;
+        bwd_run<NX, NU>(a, have ? bin.e[my].inst : 0, have, have ? bin.e[my].wave0 : wave, leader_mask);
         __syncthreads();
     }
 }
