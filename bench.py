@@ -110,74 +110,66 @@ def bench_batch(torch, P, W, steps, warmup):
 
 def bench_accel(torch, P, W, steps, warmup):
     """Time to solution on the 4096-instance batch, plain ADMM against restart
-    acceleration (Algorithm 1 steps 6-7): both stop each instance at
-    c <= 1e-8 (checked every 10 iterations), at most 6000 iterations."""
+    acceleration (Algorithm 1 steps 6-7): both stop each instance at c <= eps
+    (checked every 10 iterations), at most 6000 iterations, eps = 1e-6; and
+    the same on 1024 4-mass chains (N = 128) to eps = 1e-5, at most 20000.
+    A batched solve ends with its slowest instance.  The levels keep the
+    iterate differences that make up c well above FP32 resolution."""
     import numpy as np
     problems = W.random_batch(4096, base_seed=1000, K=6000)
     stream = torch.cuda.current_stream().cuda_stream
     dev = torch.device("cuda")
     x0 = torch.tensor(np.concatenate([p.x0 for p in problems]), dtype=torch.float32, device=dev)
     Ns = np.array([p.N for p in problems])
+    out = {}
+    for eps in (1e-6,):
+        res = {}
+        for name, accel in (("plain", False), ("accel", True)):
+            s = P.Solver(problems, max_iter=6000, eps=eps, check_every=10, precision=P.PIMPC_FP32,
+                         accel=accel, stream=stream)
+            u0 = torch.empty(s.sum_nu, dtype=torch.float32, device=dev)
+            info = torch.zeros(40 * len(problems), dtype=torch.uint8, device=dev)
+            fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream)
+            ms, per = time_solves(torch, fn, steps, warmup)
+            rec = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
+            its = rec["iters"].astype(np.int64)
+            res[name] = {"ms_per_solve": ms / steps, "mean_iters": float(its.mean()),
+                         "max_iters": int(its.max()), "converged": int((rec["c"] <= eps).sum()),
+                         "stage_iterations_per_s": float((Ns * its).sum() / (min(per) / 1e3))}
+            if accel:
+                res[name]["mean_restarts"] = float(rec["restarts"].mean())
+            s.close()
+        res["speedup"] = res["plain"]["ms_per_solve"] / res["accel"]["ms_per_solve"]
+        res["iteration_ratio"] = res["accel"]["mean_iters"] / res["plain"]["mean_iters"]
+        out[f"eps_{eps:g}"] = res
+    out["workload"] = ("4096 random instances (batch recipe), FP32, to c <= eps, check every 10, max 6000; "
+                       "about a tenth of the instances never reach eps with either method (their box is "
+                       "infeasible for the dynamics), so both batched solves run 6000 iterations on those")
+    # a batch where every instance converges: 1024 perturbed 4-mass chains, N=128
+    eps_c = 1e-5
+    db = W.diff_batch(count=1024, seed=7, N=128, K=20000)
+    chains = [db.instance(i) for i in range(1024)]
+    x0c = torch.tensor(np.concatenate([p.x0 for p in chains]), dtype=torch.float32, device=dev)
     res = {}
     for name, accel in (("plain", False), ("accel", True)):
-        s = P.Solver(problems, max_iter=6000, eps=1e-8, check_every=10, precision=P.PIMPC_FP32,
-                     accel=accel, stream=stream)
+        s = P.Solver(chains, max_iter=20000, eps=eps_c, check_every=10, precision=P.PIMPC_FP32, accel=accel,
+                     stream=stream)
         u0 = torch.empty(s.sum_nu, dtype=torch.float32, device=dev)
-        info = torch.zeros(40 * len(problems), dtype=torch.uint8, device=dev)
-        fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream)
+        info = torch.zeros(40 * len(chains), dtype=torch.uint8, device=dev)
+        fn = lambda: P.pimpc_solve_batch(s.ctx, x0c, None, u0, info, stream)
         ms, per = time_solves(torch, fn, steps, warmup)
         rec = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
         its = rec["iters"].astype(np.int64)
         res[name] = {"ms_per_solve": ms / steps, "mean_iters": float(its.mean()), "max_iters": int(its.max()),
-                     "converged": int((rec["c"] <= 1e-8).sum()),
-                     "stage_iterations_per_s": float((Ns * its).sum() / (min(per) / 1e3))}
+                     "converged": int((rec["c"] <= eps_c).sum())}
         if accel:
             res[name]["mean_restarts"] = float(rec["restarts"].mean())
         s.close()
     res["speedup"] = res["plain"]["ms_per_solve"] / res["accel"]["ms_per_solve"]
-    res["workload"] = "4096 random instances (batch recipe), FP32, to c <= 1e-8, check every 10, max 6000"
-    return res
-
-
-def bench_diff(torch, P, W, steps, warmup):
-    """Differentiable batch: 1024 chains (nx=8, nu=3, N=128), 200 iterations,
-    checkpoints every 20.  Returns the time of (taped forward + backward) over
-    the time of the plain forward on the same batch."""
-    import numpy as np
-    from paper_2601_14414_amd.autograd import PiMPCFunction
-    db = W.diff_batch(count=1024, seed=7, N=128, K=200)
-    dev = torch.device("cuda")
-    stream = torch.cuda.current_stream().cuda_stream
-    problems = [db.instance(i) for i in range(1024)]
-    plain = P.Solver(problems, max_iter=200, precision=P.PIMPC_FP32, stream=stream)
-    taped = P.Solver(problems, max_iter=200, precision=P.PIMPC_FP32, ckpt_every=20, stream=stream)
-    f = lambda a, g=False: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev,
-                                        requires_grad=g)
-    x0 = f(db.x0)
-    u0 = torch.empty(1024 * 3, dtype=torch.float32, device=dev)
-    ms_plain, per_plain = time_solves(torch, lambda: P.pimpc_solve_batch(plain.ctx, x0, None, u0, None, stream),
-                                      steps, warmup)
-    xq, Qd, Rd, A, B = f(db.x0, True), f(db.Qdiag, True), f(db.Rdiag, True), f(db.A, True), f(db.Bm, True)
-    target = f(db.u_target)
-
-    def fwd_bwd():
-        u = PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
-        ((u - target) ** 2).sum().backward()
-
-    ms_fb, per_fb = time_solves(torch, fwd_bwd, steps, warmup)
-
-    def fwd_only():
-        with torch.no_grad():
-            PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
-
-    ms_f, _ = time_solves(torch, fwd_only, steps, warmup)
-    plain.close()
-    taped.close()
-    return {"fwd_bwd_over_plain": ms_fb / ms_plain, "plain_fwd_ms": ms_plain / steps,
-            "taped_fwd_ms": ms_f / steps, "fwd_bwd_ms": ms_fb / steps,
-            "workload": "1024 x 4-mass chain (nx=8, nu=3), N=128, 200 iterations, checkpoints every 20, "
-                        "loss sum ||u0 - u_target||^2, gradients w.r.t. x0, diag Q, diag R, A, B",
-            "plain_stage_iterations_per_s": 1024 * 128 * 200 * steps / (ms_plain / 1e3)}
+    res["iteration_ratio"] = res["accel"]["mean_iters"] / res["plain"]["mean_iters"]
+    res["workload"] = "1024 4-mass chains (nx=8, nu=3), N=128, FP32, to c <= 1e-5, check every 10, max 20000"
+    out["chains_1024"] = res
+    return out
 
 
 def bench_cstr(steps=21):
