@@ -11,9 +11,11 @@
 //     iteration; the backward re-runs each segment from its checkpoint into a
 //     per-instance tape, then walks it in reverse;
 //   * per reverse step it recomputes the step's intermediates (du, g, h,
-//     xbar, b, c, the box mask), applies the exact transpose of steps 2-3,
-//     then of step 1; the halo directions are reversed (the adjoint of
-//     xbar_k goes to stage k-1, the adjoint of g_{k+1} to stage k+1);
+//     xbar and the box mask of the projection), applies the exact transpose
+//     of steps 2-3, then of step 1; the halo directions are reversed (the
+//     adjoint of xbar_k goes to stage k-1, the adjoint of g_{k+1} to stage
+//     k+1); the uniform matrix rows stream through SGPRs one row ahead of
+//     their use, as in the forward kernel;
 //   * parameter adjoints are sums over stages and iterations of outer
 //     products (e.g. Hbar += xbar_bar h^T).  Each wave stages the two vectors
 //     of its 64 stages in LDS and contracts over the stages with FP32 MFMA
@@ -97,7 +99,6 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     const bool is_last = act && k == N - 1;
     const bool hb_diag = have && I.hb_diag;
 
-#define ROWP(base, r, ld) ([&]() { cptr<float> p_ = (base) + (r) * (ld); asm volatile("" : "+s"(p_)); return p_; }())
 #define MATS()                           \
     cptr<float> Mi = M0;                 \
     asm volatile("" : "+s"(Mi));         \
@@ -567,7 +568,6 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     }
     __syncthreads();
     (void)leader_mask;
-#undef ROWP
 #undef MATS
 }
 

@@ -21,6 +21,12 @@
 //     fixed order (deterministic);
 //   * the kernel is persistent: each workgroup claims bins from a counter
 //     until none is left (largest-cost bins first).
+//   * restart acceleration (Algorithm 1 steps 6-7), when on, reduces c every
+//     iteration and extrapolates the hats in registers from the previous
+//     iterate, kept in a global buffer;
+//   * a kernel variant per class (GS) projects onto non-box factor sets
+//     (halfspace, hyperplane, second-order cone, l1 ball) once the whole
+//     projection argument of a stage is known.
 #include <hip/hip_runtime.h>
 
 #include "pimpc_dev.hpp"
