@@ -285,6 +285,10 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     // (16-byte aligned: a halo vector is also read whole, two words per float4)
     __shared__ __align__(16) uint64_t lmbox[kRowWaves][2][kMboxVecs][NB];  // intra-workgroup mailboxes
     __shared__ __align__(16) uint64_t lin[2][2][NB];  // forwarded external halos: [buf][0: w from the right, 1: d from the left]
+    // plain values of the w and d halos, written before their tagged words (LDS
+    // operations of one wave complete in order), read whole by the consumer
+    __shared__ __align__(16) float lmv[kRowWaves][2][2][NB];
+    __shared__ __align__(16) float linv[2][2][NB];
     __shared__ int lstop;               // set by the compute waves when they leave the loop
     for (int i = threadIdx.x; i < kRowWaves * 2 * kMboxVecs * NB; i += blockDim.x) (&lmbox[0][0][0][0])[i] = 0;
     for (int i = threadIdx.x; i < 2 * 2 * NB; i += blockDim.x) (&lin[0][0][0])[i] = 0;
@@ -308,6 +312,8 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             for (;;) {
                 const uint64_t word = gload(p);
                 if (unpack_tag(word) == (uint32_t)t) {
+                    linv[t & 1][side][lane] = unpack_val(word);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // value before tag (in-order LDS)
                     lstore(&lin[t & 1][side][lane], word);
                     break;
                 }
@@ -406,10 +412,15 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         return sc.mbox + ((size_t)(wave * 2 + buf) * kMboxVecs + vec) * NB + r;
     };
     auto put = [&](bool in_wg, int buf, int vec, uint64_t word) {
-        if (in_wg)
+        if (in_wg) {
+            if (vec < 2) {
+                lmv[wv][buf][vec][r] = unpack_val(word);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);  // value before tag (in-order LDS)
+            }
             lstore(&lmbox[wv][buf][vec][r], word);
-        else
+        } else {
             gstore(mbox_g(gw, buf, vec), word);
+        }
     };
     bool failed = false;
     // Stage vectors of the iterate: w = z - v - ebar + lambda, d = z - theta.
@@ -457,6 +468,8 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         const int hbuf = tin & 1;
         uint64_t* prb = right_in_wg ? &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][hbuf][0][0] : &lin[hbuf][0][0];
         uint64_t* plb = left_in_wg ? &lmbox[wv > 0 ? wv - 1 : 0][hbuf][1][0] : &lin[hbuf][1][0];
+        const float* prv = right_in_wg ? &lmv[wv + 1 < kRowWaves ? wv + 1 : wv][hbuf][0][0] : &linv[hbuf][0][0];
+        const float* plv = left_in_wg ? &lmv[wv > 0 ? wv - 1 : 0][hbuf][1][0] : &linv[hbuf][1][0];
         uint64_t* pr = prb + r;
         uint64_t* pl = plb + r;
         uint64_t wr = 0, wl = 0;
@@ -594,31 +607,37 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         }
         // ---- halo terms: xbar of the last stage and c of the first stage.
         // Every lane has seen its own word of both halo vectors carry the tag,
-        // so the whole vectors are read straight from the mailboxes (two
-        // (value, tag) words per float4, the same address in every lane).
-        // Both products are always formed (a missing side reads a harmless
-        // mailbox) and only the existing sides are added.
+        // and each word's plain value was stored before it by the same wave,
+        // so the value arrays are read whole (four values per float4, the
+        // same address in every lane).  Both products are always formed (a
+        // missing side reads a harmless buffer) and only the existing sides
+        // are added.
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the value reads stay after the polls
         if (rowl && (has_right || has_left)) {
-            float x0 = 0.f, x1 = 0.f, y0 = 0.f, y1 = 0.f;
-            float4 wq[NB / 2], dq[NB / 2];  // all reads in flight at once
+            float x0 = 0.f, x1 = 0.f, x2 = 0.f, x3 = 0.f, y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f;
+            float4 wq[NB4], dq[NB4];  // all reads in flight at once
 #pragma unroll
-            for (int q = 0; q < NB / 2; ++q) {
-                wq[q] = *(const float4*)(prb + 2 * q);
-                dq[q] = *(const float4*)(plb + 2 * q);
+            for (int q = 0; q < NB4; ++q) {
+                wq[q] = *(const float4*)(prv + 4 * q);
+                dq[q] = *(const float4*)(plv + 4 * q);
             }
 #pragma unroll
-            for (int q = 0; q < NB / 2; ++q) {
-                x0 += HAr[2 * q + 0] * wq[q].x;
-                y0 += AHr[2 * q + 0] * dq[q].x;
-                x1 += HAr[2 * q + 1] * wq[q].z;
-                y1 += AHr[2 * q + 1] * dq[q].z;
+            for (int q = 0; q < NB4; ++q) {
+                x0 += HAr[4 * q + 0] * wq[q].x;
+                y0 += AHr[4 * q + 0] * dq[q].x;
+                x1 += HAr[4 * q + 1] * wq[q].y;
+                y1 += AHr[4 * q + 1] * dq[q].y;
+                x2 += HAr[4 * q + 2] * wq[q].z;
+                y2 += AHr[4 * q + 2] * dq[q].z;
+                x3 += HAr[4 * q + 3] * wq[q].w;
+                y3 += AHr[4 * q + 3] * dq[q].w;
             }
             if (has_right) {
 #pragma unroll
                 for (int s = 0; s < S; ++s)
-                    if (s == sl) xl[s] += rho * (x0 + x1);
+                    if (s == sl) xl[s] += rho * ((x0 + x1) + (x2 + x3));
             }
-            if (has_left && tb == 0) cl[0] += rho * (y0 + y1);
+            if (has_left && tb == 0) cl[0] += rho * ((y0 + y1) + (y2 + y3));
         }
 
         // ---- steps 2-3 (Theorem 1 closed form, box projection, dual update)
