@@ -190,6 +190,47 @@ def bench_accel(torch, P, W, steps, warmup):
     return out
 
 
+def bench_diff(torch, P, W, steps, warmup):
+    """Differentiable batch: 1024 chains (nx=8, nu=3, N=128), 200 iterations,
+    checkpoints every 20.  Returns the time of (taped forward + backward) over
+    the time of the plain forward on the same batch."""
+    import numpy as np
+    from paper_2601_14414_amd.autograd import PiMPCFunction
+    db = W.diff_batch(count=1024, seed=7, N=128, K=200)
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    problems = [db.instance(i) for i in range(1024)]
+    plain = P.Solver(problems, max_iter=200, precision=P.PIMPC_FP32, stream=stream)
+    taped = P.Solver(problems, max_iter=200, precision=P.PIMPC_FP32, ckpt_every=20, stream=stream)
+    f = lambda a, g=False: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev,
+                                        requires_grad=g)
+    x0 = f(db.x0)
+    u0 = torch.empty(1024 * 3, dtype=torch.float32, device=dev)
+    ms_plain, per_plain = time_solves(torch, lambda: P.pimpc_solve_batch(plain.ctx, x0, None, u0, None, stream),
+                                      steps, warmup)
+    xq, Qd, Rd, A, B = f(db.x0, True), f(db.Qdiag, True), f(db.Rdiag, True), f(db.A, True), f(db.Bm, True)
+    target = f(db.u_target)
+
+    def fwd_bwd():
+        u = PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
+        ((u - target) ** 2).sum().backward()
+
+    ms_fb, per_fb = time_solves(torch, fwd_bwd, steps, warmup)
+
+    def fwd_only():
+        with torch.no_grad():
+            PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
+
+    ms_f, _ = time_solves(torch, fwd_only, steps, warmup)
+    plain.close()
+    taped.close()
+    return {"fwd_bwd_over_plain": ms_fb / ms_plain, "plain_fwd_ms": ms_plain / steps,
+            "taped_fwd_ms": ms_f / steps, "fwd_bwd_ms": ms_fb / steps,
+            "workload": "1024 x 4-mass chain (nx=8, nu=3), N=128, 200 iterations, checkpoints every 20, "
+                        "loss sum ||u0 - u_target||^2, gradients w.r.t. x0, diag Q, diag R, A, B",
+            "plain_stage_iterations_per_s": 1024 * 128 * 200 * steps / (ms_plain / 1e3)}
+
+
 def bench_cstr(steps=21):
     """Reactor NMPC of Section V: N=5000, 1000 warm-started iterations per
     sample, re-linearised every sample.  Per-sample time = pimpc_linearize
