@@ -1,0 +1,48 @@
+"""Host-side checks of bench.py (no GPU): the contract's refusal of more than
+one GPU, the flop model, and that every name the measurement legs call exists
+(a static check over the module's own syntax tree)."""
+import ast
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_every_called_module_function_exists():
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    defined = {n.name for n in tree.body if isinstance(n, ast.FunctionDef)}
+    called = {n.func.id for n in ast.walk(tree) if isinstance(n, ast.Call) and isinstance(n.func, ast.Name)}
+    local_names = set()
+    for n in ast.walk(tree):
+        if isinstance(n, (ast.Assign, ast.AugAssign)):
+            for t in (n.targets if isinstance(n, ast.Assign) else [n.target]):
+                for m in ast.walk(t):
+                    if isinstance(m, ast.Name):
+                        local_names.add(m.id)
+        elif isinstance(n, ast.FunctionDef):
+            local_names.update(a.arg for a in n.args.args)
+            for m in ast.walk(n):
+                if isinstance(m, ast.FunctionDef):
+                    local_names.add(m.name)
+    missing = {c for c in called if c not in defined and c not in local_names and not hasattr(bench, c)
+               and c not in dir(__import__("builtins"))}
+    assert not missing, missing
+    for leg in ("bench_batch", "bench_diff", "bench_accel", "bench_cstr", "cpu_baseline", "measured_traffic"):
+        assert leg in defined, leg
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_stage_flop_model():
+    # 2 F + 25 nb with F = nb^2 + nu nb + 2 nx^2 + 3 nx nu (the 12-mass chain: nx = 24, nu = 11)
+    nb = 35
+    F = nb * nb + 11 * nb + 2 * 24 * 24 + 3 * 24 * 11
+    assert bench.stage_flops(24, 11) == 2 * F + 25 * nb
