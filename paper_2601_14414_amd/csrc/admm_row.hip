@@ -214,6 +214,100 @@ __global__ void __launch_bounds__(256) row_fuse_kernel(const InstDev* __restrict
     }
 }
 
+// Time-varying stage data: one fused block per stage k (workgroup k), from the
+// stage-minor T block (element q of stage k at q N + k):
+//   BJ_k = Bbar_k J_k, HAt_k = H_k Abar_{k+1}' (k < N-1), AH_k = Abar_k H_{k-1},
+//   AHAt_k = Abar_k H_{k-1} Abar_k', cq_k = Abar_k H_{k-1} qbar + ebar_k (k >= 1),
+//   Hq_k = H_k qbar (H_{N-1} qbar for the last stage); Hbq is not used.
+__global__ void __launch_bounds__(256) row_fuse_tv_kernel(const InstDev* __restrict__ inst, int inst_idx,
+                                                          const float* __restrict__ mats,
+                                                          float* __restrict__ fused_all) {
+    __shared__ double Ab[kFuseMax * kFuseMax];
+    __shared__ double Hs[kFuseMax * kFuseMax];
+    __shared__ double AHs[kFuseMax * kFuseMax];
+    const InstDev I = inst[inst_idx];
+    const int NX = I.nxp, NU = I.nup, NB = I.nbp, N = I.N;
+    const int k = blockIdx.x;
+    if (NB > kFuseMax || k >= N) return;  // host side never launches such a shape
+    const MatOffsets o = mat_offsets(NX, NU, N, 1);
+    const float* bt = mats + I.mat_off;
+    const FusedOffsets f = fused_offsets(NB);
+    float* fused = fused_all + (size_t)k * row_fused_floats(NB);
+    const int t = threadIdx.x;
+    auto abar = [&](int st, int r, int c) -> double {
+        if (r < NX)
+            return (c < NX) ? (double)bt[o.A + (int64_t)(r * NX + c) * N + st]
+                            : (double)bt[o.B + (int64_t)(r * NU + (c - NX)) * N + st];
+        return (r == c) ? 1.0 : 0.0;
+    };
+    auto hmat = [&](int st, int r, int c) -> double { return (double)bt[o.H + (int64_t)(r * NB + c) * N + st]; };
+    // BJ_k
+    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+        const int r = idx / NB, c = idx % NB;
+        double bj = 0.0;
+        for (int u = 0; u < NU; ++u) {
+            const double bb = (r < NX) ? (double)bt[o.B + (int64_t)(r * NU + u) * N + k] : ((r - NX) == u ? 1.0 : 0.0);
+            bj += bb * (double)bt[o.J + (int64_t)(u * NB + c) * N + k];
+        }
+        fused[f.BJ + idx] = (float)bj;
+    }
+    // AH_k, AHAt_k, cq_k from Abar_k and H_{k-1}
+    if (k >= 1) {
+        for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+            const int r = idx / NB, c = idx % NB;
+            Ab[idx] = abar(k, r, c);
+            Hs[idx] = hmat(k - 1, r, c);
+        }
+        __syncthreads();
+        for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+            const int r = idx / NB, c = idx % NB;
+            double ah = 0.0;
+            for (int j = 0; j < NB; ++j) ah += Ab[r * NB + j] * Hs[j * NB + c];
+            AHs[idx] = ah;
+            fused[f.AH + idx] = (float)ah;
+        }
+        __syncthreads();
+        for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+            const int r = idx / NB, c = idx % NB;
+            double s = 0.0;
+            for (int j = 0; j < NB; ++j) s += AHs[r * NB + j] * Ab[c * NB + j];
+            fused[f.AHAt + idx] = (float)s;
+        }
+        for (int r = t; r < NB; r += blockDim.x) {
+            double cq = 0.0;
+            for (int j = 0; j < NB; ++j) cq += AHs[r * NB + j] * (double)bt[o.qbar + j];
+            if (r < NX) cq += (double)bt[o.e + (int64_t)r * N + k];
+            fused[f.cq + r] = (float)cq;
+        }
+    } else {
+        for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+            fused[f.AH + idx] = 0.f;
+            fused[f.AHAt + idx] = 0.f;
+        }
+        for (int r = t; r < NB; r += blockDim.x) fused[f.cq + r] = 0.f;
+    }
+    __syncthreads();
+    // HAt_k from H_k and Abar_{k+1}; Hq_k
+    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+        const int r = idx / NB, c = idx % NB;
+        Hs[idx] = hmat(k, r, c);
+        Ab[idx] = (k + 1 < N) ? abar(k + 1, r, c) : 0.0;
+    }
+    __syncthreads();
+    for (int idx = t; idx < NB * NB; idx += blockDim.x) {
+        const int r = idx / NB, c = idx % NB;
+        double hat = 0.0;
+        for (int j = 0; j < NB; ++j) hat += Hs[r * NB + j] * Ab[c * NB + j];
+        fused[f.HAt + idx] = (float)hat;
+    }
+    for (int r = t; r < NB; r += blockDim.x) {
+        double hq = 0.0;
+        for (int j = 0; j < NB; ++j) hq += Hs[r * NB + j] * (double)bt[o.qbar + j];
+        fused[f.Hq + r] = (float)hq;
+        fused[f.Hbq + r] = 0.f;
+    }
+}
+
 // Kernel geometry: kRowWaves compute waves per workgroup, plus kRecvWaves
 // receiver waves that poll the global mailboxes of the two neighbouring
 // workgroups and forward each halo word into LDS.  Compute waves then never
@@ -230,15 +324,18 @@ __host__ __device__ constexpr int row_groups(int nb) { return nb <= 16 ? 64 / nb
 
 // Dynamic LDS of one workgroup: per wave, the broadcast rows [3 S G][NB + 4]
 // and the lane-private rows of the rows lanes (H, BJ, AHAt: NB each; column
-// of [A B]: NX) as float4 [(3 NB + NX) / 4][NB].
-__host__ __device__ constexpr size_t row_lds_bytes(int NX, int NU, int S) {
-    return (size_t)kRowWaves *
-           (4 * (3 * S * row_groups(NX + NU)) * (NX + NU + 4) + 16 * (NX + NU) * ((3 * (NX + NU) + NX) / 4));
+// of [A B]: NX; time-varying data adds the column of the stage's own [A B])
+// as float4 [(3 NB + NX (+ NX)) / 4][groups][NB]; time-invariant stage data
+// is the same for every group of a wave, so it is held once.
+__host__ __device__ constexpr size_t row_lds_bytes(int NX, int NU, int S, bool TV) {
+    return (size_t)kRowWaves * (4 * (3 * S * row_groups(NX + NU)) * (NX + NU + 4) +
+                                16 * (NX + NU) * ((3 * (NX + NU) + NX + (TV ? NX : 0)) / 4) *
+                                    (TV ? row_groups(NX + NU) : 1));
 }
 
 extern __shared__ __align__(16) float row_smem[];
 
-template <int NX, int NU, int S>
+template <int NX, int NU, int S, bool TV>
 __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restrict__ ap, int nwaves,
                                                              int nwg) {
     constexpr int NB = NX + NU;
@@ -249,6 +346,9 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     constexpr int NV = 3 * S * G;      // broadcast rows: (p, d, w) per stage
     static_assert(NB <= 64, "row kernel needs nx + nu <= 64");
     static_assert(G == 1 || S == 1, "packed narrow stages take one stage per group");
+    static_assert(!TV || S == 1, "time-varying stage data: one stage per wave or group");
+    constexpr int LG = TV ? G : 1;     // groups with their own lane-private rows
+    constexpr int NL4 = 3 * NB4 + NX4 + (TV ? NX4 : 0);  // float4 rows per lane
     static_assert(NB % 4 == 0 && NX % 4 == 0, "padded sizes must be multiples of 4");
     const RowArgs& a = *ap;
     const InstDev I = a.inst[a.inst_idx];
@@ -277,11 +377,14 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     const FusedOffsets fo = fused_offsets(NB);
 
     float(*bc)[LD] = (float(*)[LD])(row_smem + (size_t)wv * NV * LD);
-    float4* lrow = (float4*)(row_smem + (size_t)kRowWaves * NV * LD) + (size_t)wv * (3 * NB4 + NX4) * NB;
-#define LH(q) lrow[(q) * NB + r]
-#define LBJ(q) lrow[(NB4 + (q)) * NB + r]
-#define LAHAT(q) lrow[(2 * NB4 + (q)) * NB + r]
-#define LACOL(q) lrow[(3 * NB4 + (q)) * NB + r]
+    float4* lrow = (float4*)(row_smem + (size_t)kRowWaves * NV * LD) + (size_t)wv * NL4 * LG * NB;
+    const int lg = TV ? grp : 0;
+#define LROW(q) lrow[((q) * LG + lg) * NB + r]
+#define LH(q) LROW(q)
+#define LBJ(q) LROW(NB4 + (q))
+#define LAHAT(q) LROW(2 * NB4 + (q))
+#define LACOL(q) LROW(3 * NB4 + (q))
+#define LBCOL(q) LROW(3 * NB4 + NX4 + (q))
     // (16-byte aligned: a halo vector is also read whole, two words per float4)
     __shared__ __align__(16) uint64_t lmbox[kRowWaves][2][kMboxVecs][NB];  // intra-workgroup mailboxes
     __shared__ __align__(16) uint64_t lin[2][2][NB];  // forwarded external halos: [buf][0: w from the right, 1: d from the left]
@@ -332,39 +435,56 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     }
     if (gw >= nwaves) return;
 
-    // ---- per-lane stage data (time-invariant), padded entries are 0
-    const MatOffsets o = mat_offsets(NX, NU, N, 0);
+    // ---- per-lane stage data, padded entries are 0.  Time-varying data is
+    // that of the lane's own stage ks (its fused block, and element q of the
+    // stage-minor T block at q N + ks); a group past the horizon reads the
+    // last stage and never uses it.
+    const MatOffsets o = mat_offsets(NX, NU, N, TV);
     const gptr<const float> M = (gptr<const float>)((const float*)a.mats + I.mat_off);
+    const int ks = TV ? min(kl, N - 1) : 0;
+    const int kn = TV ? min(ks + 1, N - 1) : 0;  // the next stage (its Abar enters the dual residual)
+    const gptr<const float> Fk = F + (size_t)ks * row_fused_floats(NB);
+    auto tvi = [&](int64_t base, int q, int st) -> float {  // element q of a stage-minor block, or row-major
+        return TV ? M[base + (int64_t)q * N + st] : M[base + q];
+    };
     float HAr[NB], AHr[NB];  // the two matrices of the halo terms stay in VGPRs
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-        HAr[j] = rowl ? F[fo.HAt + r * NB + j] : 0.f;
-        AHr[j] = rowl ? F[fo.AH + r * NB + j] : 0.f;
+        HAr[j] = rowl ? Fk[fo.HAt + r * NB + j] : 0.f;
+        AHr[j] = rowl ? Fk[fo.AH + r * NB + j] : 0.f;
     }
     if (rowl) {
         auto ld4 = [&](gptr<const float> p) { return make_float4(p[0], p[1], p[2], p[3]); };
 #pragma unroll
         for (int q = 0; q < NB4; ++q) {
-            LH(q) = ld4(M + o.H + r * NB + 4 * q);
-            LBJ(q) = ld4(F + fo.BJ + r * NB + 4 * q);
-            LAHAT(q) = ld4(F + fo.AHAt + r * NB + 4 * q);
+            LH(q) = make_float4(tvi(o.H, r * NB + 4 * q + 0, ks), tvi(o.H, r * NB + 4 * q + 1, ks),
+                                tvi(o.H, r * NB + 4 * q + 2, ks), tvi(o.H, r * NB + 4 * q + 3, ks));
+            LBJ(q) = ld4(Fk + fo.BJ + r * NB + 4 * q);
+            LAHAT(q) = ld4(Fk + fo.AHAt + r * NB + 4 * q);
         }
     }
-    // column r of the top block [A B] (rows i < NX)
-    auto acol = [&](int i) -> float {
-        return rowl ? (r < NX ? M[o.A + i * NX + r] : M[o.B + i * NU + (r - NX)]) : 0.f;
+    // column r of the top block [A B] (rows i < NX) of stage st
+    auto acol = [&](int i, int st) -> float {
+        return rowl ? (r < NX ? tvi(o.A, i * NX + r, st) : tvi(o.B, i * NU + (r - NX), st)) : 0.f;
     };
     if (rowl) {
 #pragma unroll
-        for (int q = 0; q < NX4; ++q) LACOL(q) = make_float4(acol(4 * q + 0), acol(4 * q + 1), acol(4 * q + 2), acol(4 * q + 3));
+        for (int q = 0; q < NX4; ++q)
+            LACOL(q) = make_float4(acol(4 * q + 0, kn), acol(4 * q + 1, kn), acol(4 * q + 2, kn), acol(4 * q + 3, kn));
+        if constexpr (TV) {
+#pragma unroll
+            for (int q = 0; q < NX4; ++q)
+                LBCOL(q) =
+                    make_float4(acol(4 * q + 0, ks), acol(4 * q + 1, ks), acol(4 * q + 2, ks), acol(4 * q + 3, ks));
+        }
     }
-    const float e_r = (rowl && r < NX) ? M[o.e + r] : 0.f;  // ebar_r
+    const float e_r = (rowl && r < NX) ? tvi(o.e, r, ks) : 0.f;  // ebar_r of the stage
     const float lb_r = rowl ? M[o.lb + r] : 0.f;
     const float ub_r = rowl ? M[o.ub + r] : 0.f;
-    const float hbd_r = rowl ? M[o.Hb + r * NB + r] : 0.f;
-    const float Hq_r = rowl ? F[fo.Hq + r] : 0.f;
-    const float Hbq_r = rowl ? F[fo.Hbq + r] : 0.f;
-    const float cq_r = rowl ? F[fo.cq + r] : 0.f;
+    const float hbd_r = (rowl && !TV) ? M[o.Hb + r * NB + r] : 0.f;
+    const float Hq_r = rowl ? Fk[fo.Hq + r] : 0.f;
+    const float Hbq_r = rowl ? Fk[fo.Hbq + r] : 0.f;
+    const float cq_r = rowl ? Fk[fo.cq + r] : 0.f;
     const bool hb_diag = I.hb_diag != 0;
 
     // c_0 = Abar xbar_0 + ebar (stage 0 only), xbar_0 = col(x(t), u(t-1))
@@ -379,7 +499,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             float s = e_r;
             if (r < NX) {
 #pragma unroll
-                for (int j = 0; j < NB; ++j) s += (j < NX ? M[o.A + r * NX + j] : M[o.B + r * NU + (j - NX)]) * bc[0][j];
+                for (int j = 0; j < NB; ++j) s += (j < NX ? tvi(o.A, r * NX + j, 0) : tvi(o.B, r * NU + (j - NX), 0)) * bc[0][j];
             } else {
                 s = xb0;
             }
@@ -523,7 +643,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                         ac1 += m.w * w4.w;
                     }
                     bb[s] = be[s] + (ab0 + ab1);
-                    if (k == N - 1) {
+                    if (!TV && k == N - 1) {  // time-varying: the last stage's own H is H_{N-1}
                         // xbar_N = H_{N-1} (q + rho d)
                         float hb = 0.f;
                         if (hb_diag) {
@@ -730,10 +850,12 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                         float tg = (r >= NX) ? ddn : 0.f;
 #pragma unroll
                         for (int q = 0; q < NX4; ++q) {
-                            const float4 c4 = LACOL(q);
+                            const float4 c4 = LACOL(q);  // Abar_{k+1} (the next stage's)
+                            float4 b4 = c4;                // Bbar_k (this stage's)
+                            if constexpr (TV) b4 = LBCOL(q);
                             const float4 x4 = *(const float4*)&bc[3 * tb + 0][4 * q];
                             const float4 y4 = *(const float4*)&bc[3 * tb + 1][4 * q];
-                            bt += c4.x * x4.x + c4.y * x4.y + c4.z * x4.z + c4.w * x4.w;
+                            bt += b4.x * x4.x + b4.y * x4.y + b4.z * x4.z + b4.w * x4.w;
                             tg += c4.x * y4.x + c4.y * y4.y + c4.z * y4.z + c4.w * y4.w;
                         }
                         if (r >= NX) rdpart = fmax(rdpart, fabsf(bt));
@@ -838,7 +960,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             __builtin_amdgcn_wave_barrier();
             if (rowl && r < NU) {
                 float acc = 0.f;
-                for (int j = 0; j < NB; ++j) acc += M[o.J + r * NB + j] * bc[3 * tb][j];
+                for (int j = 0; j < NB; ++j) acc += tvi(o.J, r * NB + j, min(kl + s, N - 1)) * bc[3 * tb][j];
                 du[s] = acc;
             }
             __builtin_amdgcn_wave_barrier();
@@ -881,6 +1003,8 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
 #undef LBJ
 #undef LAHAT
 #undef LACOL
+#undef LBCOL
+#undef LROW
 }
 
 template <typename T>
@@ -898,34 +1022,38 @@ struct RowCfg {
 // the 2-state, 1-input reactor at N = 5000).
 constexpr RowCfg kRowCfgs[] = {{4, 4}, {8, 8}, {24, 12}, {32, 16}};
 
-template <int NX, int NU, int S>
+template <int NX, int NU, int S, bool TV>
 hipError_t row_launch_t(const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
-    const size_t lds = row_lds_bytes(NX, NU, S);
+    const size_t lds = row_lds_bytes(NX, NU, S, TV);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)row_kernel<NX, NU, S>,
+        hipError_t e = hipFuncSetAttribute((const void*)row_kernel<NX, NU, S, TV>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, row_kernel<NX, NU, S>, kRowThreads, lds);
-    hipLaunchKernelGGL((row_kernel<NX, NU, S>), dim3(nwg), dim3(kRowThreads), lds, s, a_dev, nwaves, nwg);
+    if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, row_kernel<NX, NU, S, TV>, kRowThreads, lds);
+    hipLaunchKernelGGL((row_kernel<NX, NU, S, TV>), dim3(nwg), dim3(kRowThreads), lds, s, a_dev, nwaves, nwg);
     return hipGetLastError();
 }
 
 template <int NX, int NU>
-hipError_t row_launch_s(int S, const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
+hipError_t row_launch_s(int S, bool tv, const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
+    if (tv) {  // time-varying stage data: one stage per wave or group
+        if (S != 1) return hipErrorInvalidValue;
+        return row_launch_t<NX, NU, 1, true>(a_dev, nwaves, nwg, s, occ);
+    }
     if constexpr (row_groups(NX + NU) > 1) {  // packed narrow stages: one stage per group
         if (S != 1) return hipErrorInvalidValue;
-        return row_launch_t<NX, NU, 1>(a_dev, nwaves, nwg, s, occ);
+        return row_launch_t<NX, NU, 1, false>(a_dev, nwaves, nwg, s, occ);
     } else {
         switch (S) {
             case 1:
-                return row_launch_t<NX, NU, 1>(a_dev, nwaves, nwg, s, occ);
+                return row_launch_t<NX, NU, 1, false>(a_dev, nwaves, nwg, s, occ);
             case 2:
-                return row_launch_t<NX, NU, 2>(a_dev, nwaves, nwg, s, occ);
+                return row_launch_t<NX, NU, 2, false>(a_dev, nwaves, nwg, s, occ);
             case 4:
-                return row_launch_t<NX, NU, 4>(a_dev, nwaves, nwg, s, occ);
+                return row_launch_t<NX, NU, 4, false>(a_dev, nwaves, nwg, s, occ);
             default:
                 return hipErrorInvalidValue;
         }
@@ -936,10 +1064,11 @@ hipError_t row_launch_any(const InstDev& I, int S, const RowArgs* a_dev, hipStre
     const int per = S * row_groups(I.nbp);  // stages per wave
     const int nwaves = (I.N + per - 1) / per;
     const int nwg = (nwaves + kRowWaves - 1) / kRowWaves;
-    if (I.nxp == 4 && I.nup == 4) return row_launch_s<4, 4>(S, a_dev, nwaves, nwg, s, occ);
-    if (I.nxp == 8 && I.nup == 8) return row_launch_s<8, 8>(S, a_dev, nwaves, nwg, s, occ);
-    if (I.nxp == 24 && I.nup == 12) return row_launch_s<24, 12>(S, a_dev, nwaves, nwg, s, occ);
-    if (I.nxp == 32 && I.nup == 16) return row_launch_s<32, 16>(S, a_dev, nwaves, nwg, s, occ);
+    const bool tv = I.tv != 0;
+    if (I.nxp == 4 && I.nup == 4) return row_launch_s<4, 4>(S, tv, a_dev, nwaves, nwg, s, occ);
+    if (I.nxp == 8 && I.nup == 8) return row_launch_s<8, 8>(S, tv, a_dev, nwaves, nwg, s, occ);
+    if (I.nxp == 24 && I.nup == 12) return row_launch_s<24, 12>(S, tv, a_dev, nwaves, nwg, s, occ);
+    if (I.nxp == 32 && I.nup == 16) return row_launch_s<32, 16>(S, tv, a_dev, nwaves, nwg, s, occ);
     return hipErrorInvalidValue;
 }
 
@@ -958,7 +1087,8 @@ int num_cus() {
 
 bool row_supported(int nx, int nu, int N, int tv, int fp64, int* nxp, int* nup) {
     (void)N;
-    if (tv || fp64) return false;
+    (void)tv;
+    if (fp64) return false;
     for (const RowCfg& c : kRowCfgs)
         if (nx <= c.nx && nu <= c.nu) {
             *nxp = c.nx;
@@ -970,8 +1100,9 @@ bool row_supported(int nx, int nu, int N, int tv, int fp64, int* nxp, int* nup) 
 
 size_t row_scratch_bytes(const InstDev& I, int fp64) {
     (void)fp64;
-    // sized for one stage per wave, plus the fused stage data
-    return align16(row_clear_size(I.N, I.nbp)) + align16(4 * row_fused_floats(I.nbp));
+    // sized for one stage per wave, plus the fused stage data (one block per
+    // stage when the stage data is time-varying)
+    return align16(row_clear_size(I.N, I.nbp)) + align16(4 * row_fused_floats(I.nbp) * (I.tv ? I.N : 1));
 }
 
 // Choose the blocking S (stages per wave): the smallest S whose grid stays
@@ -980,7 +1111,7 @@ hipError_t row_prepare(int fp64, InstDev& I) {
     (void)fp64;
     const int want = I.pad1 > 0 ? I.pad1 : 1;
     for (int S : {want, 1, 2, 4}) {
-        if (S > 1 && row_groups(I.nbp) > 1) break;  // packed narrow stages: S = 1 only
+        if (S > 1 && (row_groups(I.nbp) > 1 || I.tv)) break;  // packed narrow stages, time-varying data: S = 1
         int occ = 0;
         hipError_t e = row_launch_any(I, S, nullptr, nullptr, &occ);
         if (e != hipSuccess) return e;
@@ -999,7 +1130,11 @@ hipError_t launch_row_fuse(const InstDev* d_inst, int inst_idx, const InstDev& I
     if (I.nbp > kFuseMax) return hipErrorInvalidValue;
     char* scr = (char*)scratch_base + (size_t)I.pad0 * 16;
     float* fused = (float*)(scr + row_clear_size(I.N, I.nbp));
-    hipLaunchKernelGGL(row_fuse_kernel, dim3(1), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats, fused);
+    if (I.tv)
+        hipLaunchKernelGGL(row_fuse_tv_kernel, dim3(I.N), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats,
+                           fused);
+    else
+        hipLaunchKernelGGL(row_fuse_kernel, dim3(1), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats, fused);
     return hipGetLastError();
 }
 
