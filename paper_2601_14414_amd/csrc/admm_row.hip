@@ -2,9 +2,11 @@
 //
 // Same iteration as the lane kernel (eqn. (8), Algorithm 1 steps 1-5 of
 // arXiv 2601.14414, velocity form of Theorem 2) with a different mapping,
-// for instances whose horizon is long and whose stage is wide (e.g. nx = 24,
-// nu = 11, N = 1024), where one lane per stage would leave most of the chip
-// idle:
+// for horizons longer than one lane-family workgroup (e.g. nx = 24, nu = 11,
+// N = 1024, where one lane per stage would also leave most of the chip idle,
+// or nx = 2, nu = 1, N = 5000); time-invariant or time-varying stage data
+// (with time-varying data each wave or group holds its own stage's rows,
+// read once per solve):
 //   * a wave owns a block of consecutive stages; lane r owns row r of
 //     every stage vector.  Wide stages (more than 16 padded rows) give a wave
 //     S stages, processed in turn; narrow stages pack G = 64 / NB stages side
