@@ -125,6 +125,22 @@ def test_unsupported_requests_are_reported():
     assert code == P.PIMPC_E_UNSUPPORTED and "accel" in msg
 
 
+def test_shapes_without_a_kernel_are_reported():
+    """Valid problems no compiled kernel serves: a stage wider than the widest
+    long-horizon class, and a long horizon in FP64 (the long-horizon family
+    iterates in FP32)."""
+    rng = np.random.default_rng(0)
+    nx, nu = 40, 10
+    wide = W.Problem(nx=nx, nu=nu, N=600, A=np.eye(nx) * 0.9, B=rng.standard_normal((nx, nu)) * 0.1,
+                     Q=np.eye(nx), R=np.eye(nu), xmin=-np.ones(nx), xmax=np.ones(nx), umin=-np.ones(nu),
+                     umax=np.ones(nu), x0=np.zeros(nx), u_prev=np.zeros(nu), K=10)
+    code, msg = _setup_code([wide])
+    assert code == P.PIMPC_E_UNSUPPORTED and "no compiled kernel" in msg
+    lh = W.long_horizon_problem(0, N=600, K=10)
+    code, msg = _setup_code([lh], precision=P.PIMPC_FP64)
+    assert code == P.PIMPC_E_UNSUPPORTED and "fp64" in msg
+
+
 @pytest.mark.parametrize("eta", [0.0, -0.5, 1.5, float("nan")])
 def test_bad_restart_threshold_rejected(eta):
     assert _setup_code([W.plain_fp64_problem(0)], accel=1, eta=eta)[0] == P.PIMPC_E_ARG
