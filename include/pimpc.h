@@ -7,12 +7,23 @@
  * Section IV (eqn. (8) and Algorithm 1):
  *
  *   min  sum_{k<N} 1/2 x_{k+1}' Q x_{k+1} + 1/2 u_k' R u_k - qbar' xbar_{k+1}
- *   s.t. x_{k+1} = A_k x_k + B_k u_k + e_k,  xmin <= x_{k+1} <= xmax,
- *        umin <= u_k <= umax,  x_0 = x(t)
+ *                  + 1/2 (u_k - u_{k-1})' Wdu (u_k - u_{k-1})
+ *   s.t. x_{k+1} = A_k x_k + B_k u_k + e_k,  x_{k+1} in X,  u_k in U,
+ *        x_0 = x(t),  u_{-1} = u(t-1)
  *
- * in the velocity form of Theorem 2 (xbar_k = col(x_k, u_{k-1}), input du_k),
- * with the stage caches J_k, H_k of Algorithm 1 factorised in FP64 on the
- * device and the iteration run in the precision chosen by the caller.
+ * (X, U boxes by default, or a halfspace, hyperplane, second-order cone or l1
+ * ball) in the velocity form of Theorem 2 (xbar_k = col(x_k, u_{k-1}), input
+ * du_k), with the stage caches J_k, H_k of Algorithm 1 factorised in FP64 on
+ * the device and the iteration run in the precision chosen by the caller.
+ *
+ * Which kernel family serves an instance, and what it supports:
+ *   - N <= 512: one lane per stage (FP32 or FP64 iteration, time-invariant or
+ *     time-varying data, restart acceleration, non-box sets, and the taped
+ *     forward / pimpc_backward for FP32 time-invariant instances with
+ *     nx + nu <= 16 after padding to a compiled class and N <= 256);
+ *   - N > 512: one row per lane, one block of stages per wave (FP32,
+ *     time-invariant or time-varying data, box sets, plain ADMM).
+ * A request outside these returns PIMPC_E_UNSUPPORTED from pimpc_setup.
  *
  * Conventions common to every entry point:
  *   - every call returns an int32 status: PIMPC_OK (0) or a negative error;
