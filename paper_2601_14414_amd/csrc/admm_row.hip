@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     const float rho = (float)a.rho;
     const float third = 1.0f / 3.0f;
 
-    const gptr<char> sbase = (gptr<char>)((char*)a.scratch + (size_t)I.pad0 * 16);
+    const gptr<char> sbase = (gptr<char>)((char*)a.scratch + (size_t)I.row_scr16 * 16);
     RowScratch sc = row_scratch(sbase, nwaves, NB);
     const gptr<const float> F = (gptr<const float>)(sbase + row_clear_size(N, NB));  // same offset as the host side
     const FusedOffsets fo = fused_offsets(NB);
@@ -1111,7 +1111,7 @@ size_t row_scratch_bytes(const InstDev& I, int fp64) {
 // co-resident (every workgroup must be running for the halo waits to end).
 hipError_t row_prepare(int fp64, InstDev& I) {
     (void)fp64;
-    const int want = I.pad1 > 0 ? I.pad1 : 1;
+    const int want = I.row_s > 0 ? I.row_s : 1;
     for (int S : {want, 1, 2, 4}) {
         if (S > 1 && (row_groups(I.nbp) > 1 || I.tv)) break;  // packed narrow stages, time-varying data: S = 1
         int occ = 0;
@@ -1120,7 +1120,7 @@ hipError_t row_prepare(int fp64, InstDev& I) {
         const int per = S * row_groups(I.nbp);
         const int nwg = ((I.N + per - 1) / per + kRowWaves - 1) / kRowWaves;
         if (occ > 0 && nwg <= occ * num_cus()) {
-            I.pad1 = S;
+            I.row_s = S;
             return hipSuccess;
         }
     }
@@ -1130,7 +1130,7 @@ hipError_t row_prepare(int fp64, InstDev& I) {
 hipError_t launch_row_fuse(const InstDev* d_inst, int inst_idx, const InstDev& I, const void* mats,
                            void* scratch_base, hipStream_t s) {
     if (I.nbp > kFuseMax) return hipErrorInvalidValue;
-    char* scr = (char*)scratch_base + (size_t)I.pad0 * 16;
+    char* scr = (char*)scratch_base + (size_t)I.row_scr16 * 16;
     float* fused = (float*)(scr + row_clear_size(I.N, I.nbp));
     if (I.tv)
         hipLaunchKernelGGL(row_fuse_tv_kernel, dim3(I.N), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats,
@@ -1142,8 +1142,8 @@ hipError_t launch_row_fuse(const InstDev* d_inst, int inst_idx, const InstDev& I
 
 hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, void* scratch_base, hipStream_t s) {
     (void)fp64;
-    const int S = I.pad1 > 0 ? I.pad1 : 1;
-    char* scr = (char*)scratch_base + (size_t)I.pad0 * 16;
+    const int S = I.row_s > 0 ? I.row_s : 1;
+    char* scr = (char*)scratch_base + (size_t)I.row_scr16 * 16;
     hipError_t e = launch_fill<int32_t>((int32_t*)scr, (int64_t)(row_clear_size(I.N, I.nbp) / 4), 0, s);
     if (e != hipSuccess) return e;
     return row_launch_any(I, S, a_dev, s, nullptr);

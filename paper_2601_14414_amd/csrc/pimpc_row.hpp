@@ -30,8 +30,8 @@ struct RowArgs {
 bool row_supported(int nx, int nu, int N, int tv, int fp64, int* nxp, int* nup);
 // Device scratch bytes the instance needs (halo mailboxes, partials).
 size_t row_scratch_bytes(const InstDev& I, int fp64);
-// Pick the stage blocking (stored in I.pad1) so the grid stays co-resident;
-// I.pad1 > 0 on entry is the preferred blocking.
+// Pick the stage blocking (stored in I.row_s) so the grid stays co-resident;
+// I.row_s > 0 on entry is the preferred blocking.
 hipError_t row_prepare(int fp64, InstDev& I);
 // Form the fused stage data of a row-family instance in its scratch (after
 // every factorisation; reads the T block written by the factor kernel).

@@ -978,12 +978,12 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         HIPCHK(ctx, hipMemset(ctx->d_row_scratch, 0, bytes));
         size_t off = 0;
         for (int i : ctx->row_insts) {
-            ctx->inst[i].pad0 = (int32_t)(off / 16);  // scratch offset in 16-byte units
+            ctx->inst[i].row_scr16 = (int32_t)(off / 16);  // scratch offset in 16-byte units
             off += row_scratch_bytes(ctx->inst[i], ctx->fp64);
         }
         const char* env_s = getenv("PIMPC_ROW_STAGES");
         for (int i : ctx->row_insts) {
-            ctx->inst[i].pad1 = env_s ? atoi(env_s) : 1;
+            ctx->inst[i].row_s = env_s ? atoi(env_s) : 1;
             HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
         }
         HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
