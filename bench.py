@@ -281,8 +281,9 @@ def main():
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: this benchmark runs on one GPU only (asked for {args.gpus}); "
+              "more GPUs would shard the batch by instance and a long horizon by stage blocks, "
+              "which is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
