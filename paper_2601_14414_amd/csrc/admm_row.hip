@@ -1087,12 +1087,22 @@ int num_cus() {
 
 }  // namespace
 
+// LDS of one row-kernel workgroup: the dynamic part plus the static mailboxes
+// (lmbox, lin, lmv, linv, lstop as declared in the kernel).
+constexpr size_t row_total_lds(int NX, int NU, bool tv) {
+    const size_t NB = (size_t)(NX + NU);
+    return row_lds_bytes(NX, NU, 1, tv) + 8 * NB * (kRowWaves * 2 * kMboxVecs + 4) + 4 * NB * (kRowWaves * 4 + 4) + 16;
+}
+constexpr size_t kRowLdsLimit = 160 * 1024;  // per workgroup on gfx950
+
 bool row_supported(int nx, int nu, int N, int tv, int fp64, int* nxp, int* nup) {
     (void)N;
-    (void)tv;
     if (fp64) return false;
     for (const RowCfg& c : kRowCfgs)
         if (nx <= c.nx && nu <= c.nu) {
+            // time-varying data keeps a second column set per lane; the widest
+            // class then exceeds the workgroup's LDS
+            if (tv && row_total_lds(c.nx, c.nu, true) > kRowLdsLimit) return false;
             *nxp = c.nx;
             *nup = c.nu;
             return true;

@@ -139,6 +139,20 @@ def test_shapes_without_a_kernel_are_reported():
     lh = W.long_horizon_problem(0, N=600, K=10)
     code, msg = _setup_code([lh], precision=P.PIMPC_FP64)
     assert code == P.PIMPC_E_UNSUPPORTED and "fp64" in msg
+    # a long time-varying horizon with stages wider than 24 + 12
+    rng2 = np.random.default_rng(1)
+    nx2, nu2, N2 = 30, 14, 600
+    tvw = W.Problem(nx=nx2, nu=nu2, N=N2, A=np.broadcast_to(np.eye(nx2) * 0.9, (N2, nx2, nx2)).copy(),
+                    B=rng2.standard_normal((N2, nx2, nu2)) * 0.1, Q=np.eye(nx2), R=np.eye(nu2),
+                    xmin=-np.ones(nx2), xmax=np.ones(nx2), umin=-np.ones(nu2), umax=np.ones(nu2),
+                    x0=np.zeros(nx2), u_prev=np.zeros(nu2), K=10)
+    code, msg = _setup_code([tvw])
+    assert code == P.PIMPC_E_UNSUPPORTED and "no compiled kernel" in msg
+    # FP64 lane classes stop at nx + nu = 13 (padded), where the stage still fits a lane's registers
+    big = W.random_batch(64, base_seed=1000, K=10)
+    big = [p for p in big if p.nx + p.nu > 13][0]
+    code, msg = _setup_code([big], precision=P.PIMPC_FP64)
+    assert code == P.PIMPC_E_UNSUPPORTED and "no compiled kernel" in msg
 
 
 @pytest.mark.parametrize("eta", [0.0, -0.5, 1.5, float("nan")])

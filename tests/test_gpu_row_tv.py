@@ -18,7 +18,9 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("n,m,N,K", [(3, 2, 700, 60), (2, 1, 1029, 50), (6, 3, 600, 60), (20, 6, 520, 40)])
 def test_row_time_varying_parity(n, m, N, K):
     """Narrow (4+4, 8+8: stages packed per wave) and wide (24+12) classes,
-    affine time-varying stage data, linear term, dense Q and R, u_prev != 0."""
+    affine time-varying stage data, linear term, dense Q and R, u_prev != 0.
+    (The 32+16 class has no time-varying variant: its second column set
+    would exceed the workgroup's LDS; pimpc_setup reports that.)"""
     p = tiny_problem(7 * N + n, n, m, N, 1)
     s = P.Solver([p], rho=p.rho, max_iter=K, precision=P.PIMPC_FP32)
     u0, info = s.solve()
