@@ -97,3 +97,39 @@ def test_backward_without_tape_is_an_error():
     with pytest.raises(P.PimpcError) as ei:
         P.pimpc_backward(s.ctx, g)
     assert ei.value.code == P.PIMPC_E_STATE
+
+
+@pytest.mark.parametrize("nx,nu,N,K,ck", [(4, 2, 40, 20, 6), (12, 4, 70, 16, 5), (6, 1, 130, 12, 4)])
+def test_adjoint_other_classes(nx, nu, N, K, ck):
+    """Backward kernels of other (nx, nu) classes (padded 4+2, 12+4 and 8+1)
+    and horizons over one and two waves, against the oracle's reverse mode."""
+    from paper_2601_14414_amd.autograd import PiMPCLayer
+    rng = np.random.default_rng(nx * 100 + nu)
+    count = 5
+    A = np.stack([np.eye(nx) * 0.95 + 0.05 * rng.standard_normal((nx, nx)) for _ in range(count)])
+    B = rng.standard_normal((count, nx, nu)) / np.sqrt(nx)
+    Qd = rng.uniform(0.5, 1.5, (count, nx))
+    Rd = rng.uniform(0.05, 0.2, (count, nu))
+    x0 = rng.uniform(-1, 1, (count, nx))
+    ut = rng.normal(0, 0.1, (count, nu))
+    dev = torch.device("cuda")
+    layer = PiMPCLayer(count, nx, nu, N, iters=K, ckpt_every=ck, xbound=1.5, ubound=0.4)
+    f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev, requires_grad=True)
+    tx0, tQ, tR, tA, tB = f(x0), f(Qd), f(Rd), f(A), f(B)
+    u0 = layer(tx0, tQ, tR, tA, tB)
+    ((u0 - torch.tensor(ut, dtype=torch.float32, device=dev)) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    got = {k: t.grad.detach().cpu().numpy().astype(np.float64) for k, t in
+           dict(dx0=tx0, dQd=tQ, dRd=tR, dA=tA, dB=tB).items()}
+    u0n = u0.detach().cpu().numpy().astype(np.float64).reshape(count, nu)
+    layer.solver.close()
+    lb = np.concatenate([-1.5 * np.ones(nx), -0.4 * np.ones(nu)])
+    ub = -lb
+    for i in range(count):
+        p = W.Problem(nx=nx, nu=nu, N=N, A=A[i], B=B[i], Q=np.diag(Qd[i]), R=np.diag(Rd[i]), xmin=lb[:nx],
+                      xmax=ub[:nx], umin=lb[nx:], umax=ub[nx:], x0=x0[i], u_prev=np.zeros(nu), rho=1.0, K=K)
+        r = oracle.solve(p)
+        assert rel(u0n[i], r["u0"]) <= 1e-4
+        g = oracle.grad(nx, nu, N, A[i], B[i], Qd[i], Rd[i], lb, ub, x0[i], 1.0, K, 2 * (r["u0"] - ut[i]))
+        for key in ("dx0", "dQd", "dRd", "dA", "dB"):
+            assert rel(got[key][i], g[key]) <= TOLG, (i, key, rel(got[key][i], g[key]))

@@ -174,3 +174,14 @@ def test_linearize_equals_fresh_setup_fp64():
     s.linearize(A.ravel(), B.ravel(), e.ravel())
     s.solve()
     compare(s, [p1], [oracle.solve(p1, K=50)], TOL64)
+
+
+@pytest.mark.parametrize("n,m,N,tv", [(7, 6, 150, 0), (14, 7, 90, 0), (6, 5, 70, 1)])
+def test_wide_input_classes_fp32(n, m, N, tv):
+    """Classes with up to eight inputs (padded 8+8 and 16+8), FP32 against
+    the FP64 oracle; the time-varying case has no lane class that wide and
+    runs on the row family's 8+8 class with a short horizon."""
+    p = tiny_problem(100 + n + m, n, m, N, tv)
+    s, u0, info, refs = run_both([p], P.PIMPC_FP32)
+    compare(s, [p], refs, TOL32)
+    check_info(info, refs, 1e-4)
