@@ -17,12 +17,14 @@
  * the device and the iteration run in the precision chosen by the caller.
  *
  * Which kernel family serves an instance, and what it supports:
- *   - N <= 512: one lane per stage (FP32 or FP64 iteration, time-invariant or
- *     time-varying data, restart acceleration, non-box sets, and the taped
- *     forward / pimpc_backward for FP32 time-invariant instances with
- *     nx + nu <= 16 after padding to a compiled class and N <= 256);
- *   - N > 512: one row per lane, one block of stages per wave (FP32,
- *     time-invariant or time-varying data, box sets, plain ADMM).
+ *   - one lane per stage, when N <= 512 and a compiled class holds the stage
+ *     (time-invariant: nx <= 16, nu <= 8; time-varying: nx <= 4, nu <= 2;
+ *     FP64 up to nx + nu = 13 after padding): FP32 or FP64 iteration,
+ *     restart acceleration, non-box sets, and the taped forward /
+ *     pimpc_backward for FP32 time-invariant instances with N <= 256;
+ *   - otherwise one row per lane, one block of stages per wave (FP32, nx <= 32,
+ *     nu <= 16; time-varying data up to nx <= 24, nu <= 12; box sets, plain
+ *     ADMM).
  * A request outside these returns PIMPC_E_UNSUPPORTED from pimpc_setup.
  *
  * Conventions common to every entry point:
