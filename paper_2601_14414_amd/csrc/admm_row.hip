@@ -134,6 +134,16 @@ __device__ inline uint64_t lload(uint64_t* p) {
 
 __device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
 
+// A wave-uniform loop invariant held in scalar registers.  The argument block
+// is constant memory, so without this the compiler may re-load a value from
+// it inside the iteration loop (and wait for that load every iteration)
+// rather than keep it live.
+template <typename T>
+__device__ inline T keep_sgpr(T x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 template <typename T>
 __device__ inline T wsum(T v) {
 #pragma unroll
@@ -372,6 +382,10 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     const int kl = k0 + tb;                     // index of the lane's first stage
     const float rho = (float)a.rho;
     const float third = 1.0f / 3.0f;
+    const int K = keep_sgpr(a.K);
+    const double eps = keep_sgpr(a.eps);
+    const double rho_d = keep_sgpr(a.rho);
+    const int check_every = keep_sgpr(a.check_every);
 
     const gptr<char> sbase = (gptr<char>)((char*)a.scratch + (size_t)I.row_scr16 * 16);
     RowScratch sc = row_scratch(sbase, nwaves, NB);
@@ -411,7 +425,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         const bool has = side == 0 ? (last == first + kRowWaves - 1 && src < nwaves) : (first > 0);
         if (!has || lane >= NB) return;
         const int vec = side == 0 ? 0 : 1;
-        for (int t = 1; t <= a.K; ++t) {
+        for (int t = 1; t <= K; ++t) {
             const gptr<uint64_t> p = sc.mbox + ((size_t)(src * 2 + (t & 1)) * kMboxVecs + vec) * NB + lane;
             int spins = 0;
             for (;;) {
@@ -455,14 +469,28 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         HAr[j] = rowl ? Fk[fo.HAt + r * NB + j] : 0.f;
         AHr[j] = rowl ? Fk[fo.AH + r * NB + j] : 0.f;
     }
+    // With one stage per wave and at most 36 rows, the lane's row of H is
+    // held in VGPRs as well (H_{N-1} in the wave of the last stage), so that
+    // the local part of a step reads two lane-private rows from LDS instead
+    // of three: LDS bandwidth bounds that part, since every compute wave of a
+    // CU reads its own rows each iteration.
+    constexpr bool RH = S == 1 && NB <= 36;
+    const bool last_h = !TV && kl == N - 1;  // time-varying: stage N-1's own H is H_{N-1}
+    float Hr[RH ? NB : 1];
+    if constexpr (RH) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            Hr[j] = rowl ? (last_h ? M[o.Hb + r * NB + j] : tvi(o.H, r * NB + j, ks)) : 0.f;
+    }
     if (rowl) {
         auto ld4 = [&](gptr<const float> p) { return make_float4(p[0], p[1], p[2], p[3]); };
 #pragma unroll
         for (int q = 0; q < NB4; ++q) {
-            LH(q) = make_float4(tvi(o.H, r * NB + 4 * q + 0, ks), tvi(o.H, r * NB + 4 * q + 1, ks),
-                                tvi(o.H, r * NB + 4 * q + 2, ks), tvi(o.H, r * NB + 4 * q + 3, ks));
-            LBJ(q) = ld4(Fk + fo.BJ + r * NB + 4 * q);
+            if constexpr (!RH)
+                LH(q) = make_float4(tvi(o.H, r * NB + 4 * q + 0, ks), tvi(o.H, r * NB + 4 * q + 1, ks),
+                                    tvi(o.H, r * NB + 4 * q + 2, ks), tvi(o.H, r * NB + 4 * q + 3, ks));
             LAHAT(q) = ld4(Fk + fo.AHAt + r * NB + 4 * q);
+            LBJ(q) = ld4(Fk + fo.BJ + r * NB + 4 * q);
         }
     }
     // column r of the top block [A B] (rows i < NX) of stage st
@@ -578,11 +606,18 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     int status = 0;
     bool stop = false;
 
+    int ck = check_every;  // iterations left until the next residual check
 #pragma unroll 1
-    for (int it = 0; it < a.K && !stop; ++it) {
+    for (int it = 0; it < K && !stop; ++it) {
         const uint32_t tin = (uint32_t)it + 1;   // tag of the iterate this step reads
         const uint32_t tout = (uint32_t)it + 2;  // tag of the iterate it produces
-        const bool check = (a.eps > 0.0 && ((it + 1) % a.check_every) == 0) || (it == a.K - 1);
+        // residuals every check_every-th iteration when stopping on eps, and
+        // after the last one
+        bool check = it == K - 1;
+        if (eps > 0.0 && --ck == 0) {
+            check = true;
+            ck = check_every;
+        }
 
         // ---- halo mailboxes of the iterate entering this step (LDS only): w of
         // the stage after the block, d of the stage before it, from the
@@ -621,6 +656,31 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                     const int k = kl + s;
                     const int t = tb + s;
                     float ab0 = 0.f, ab1 = 0.f, ah0 = 0.f, ah1 = 0.f, ac0 = 0.f, ac1 = 0.f;
+                    if constexpr (RH) {
+#pragma unroll
+                        for (int q = 0; q < NB4; ++q) {
+                            const float4 p4 = *(const float4*)&bc[3 * t + 0][4 * q];
+                            const float4 d4 = *(const float4*)&bc[3 * t + 1][4 * q];
+                            const float4 w4 = *(const float4*)&bc[3 * t + 2][4 * q];
+                            const float4 g = LBJ(q);
+                            const float4 m = LAHAT(q);
+                            ab0 += g.x * p4.x;
+                            ab1 += g.y * p4.y;
+                            ab0 += g.z * p4.z;
+                            ab1 += g.w * p4.w;
+                            ah0 += Hr[4 * q + 0] * d4.x;
+                            ah1 += Hr[4 * q + 1] * d4.y;
+                            ah0 += Hr[4 * q + 2] * d4.z;
+                            ah1 += Hr[4 * q + 3] * d4.w;
+                            ac0 += m.x * w4.x;
+                            ac1 += m.y * w4.y;
+                            ac0 += m.z * w4.z;
+                            ac1 += m.w * w4.w;
+                            // unrolled for the register row; the scheduler may
+                            // not hoist more than three columns of loads
+                            if (q % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+                        }
+                    } else {
                     // all operands come from LDS; a partly unrolled loop keeps
                     // the scheduler from hoisting every load (VGPR pressure)
 #pragma unroll 3
@@ -644,8 +704,11 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                         ac0 += m.z * w4.z;
                         ac1 += m.w * w4.w;
                     }
+                    }
                     bb[s] = be[s] + (ab0 + ab1);
-                    if (!TV && k == N - 1) {  // time-varying: the last stage's own H is H_{N-1}
+                    if (RH) {  // Hr holds H_{N-1} in the last stage's wave
+                        xl[s] = (last_h ? Hbq_r : Hq_r) + rho * (ah0 + ah1);
+                    } else if (!TV && k == N - 1) {  // time-varying: the last stage's own H is H_{N-1}
                         // xbar_N = H_{N-1} (q + rho d)
                         float hb = 0.f;
                         if (hb_diag) {
@@ -908,15 +971,15 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                 rd = wmax(rd);
                 const bool anyfail = wave_any(lfail);
                 if (lane == 0) {
-                    c_last = a.rho * cs;
+                    c_last = rho_d * cs;
                     rp_last = rp;
-                    rd_last = a.rho * rd;
+                    rd_last = rho_d * rd;
                     int dec = 0;
                     if (!(c_last < INFINITY)) {
                         status = -4;
                         dec = 1;
                     }
-                    if (a.eps > 0.0 && c_last <= a.eps) dec = 1;
+                    if (eps > 0.0 && c_last <= eps) dec = 1;
                     if (anyfail) {
                         status = -5;
                         dec = 1;
@@ -925,7 +988,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
                                        __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-            if (a.eps > 0.0) {  // everyone learns the decision (stop or continue)
+            if (eps > 0.0) {  // everyone learns the decision (stop or continue)
                 uint64_t d = 0;
                 if (lane == 0) {
                     int spins = 0;
@@ -949,7 +1012,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
 
     // leaving before K iterations (stop decision or failure): no compute wave
     // of this workgroup consumes another halo, so the receivers may end too
-    if (iters < a.K && lane == 0) __hip_atomic_store(&lstop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (iters < K && lane == 0) __hip_atomic_store(&lstop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 
     // ---- outputs: final iterate; du_k = J_k (v_k - beta_k) and xbar_{k+1}
     // of the last step 1
