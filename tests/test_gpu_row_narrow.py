@@ -1,7 +1,9 @@
 """Row family with narrow stages packed side by side in a wave (padded
 classes 4+4: eight stages per wave, and 8+8: four stages per wave); the
-last two cases are the wide classes 32+16 (one stage per wave) and 24+12
-with two stages per wave (N = 1500 does not fit one stage per wave).  Horizons
+cases from (30, 14) on are the wide classes: 32+16 (one stage per wave),
+24+12 with two stages per wave (N = 1500 does not fit one stage per wave), and
+24+12 with one stage per wave, where the last stage's wave holds the rows of
+a non-diagonal H_{N-1} (dense Q and R) in registers.  Horizons
 beyond one lane-family workgroup (N > 512) with small stages land here.
 
 FP32 iteration vs the FP64 oracle, tolerance 1e-4 of max(1, |oracle|_inf)
@@ -21,7 +23,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("n,m,N,K", [(3, 2, 513, 60), (4, 4, 700, 80), (2, 1, 1029, 60),
                                      (6, 3, 600, 60), (8, 8, 2053, 40), (5, 1, 777, 50),
-                                     (30, 14, 600, 30), (20, 10, 1500, 30)])
+                                     (30, 14, 600, 30), (20, 10, 1500, 30),
+                                     (12, 8, 600, 40), (24, 11, 530, 30)])
 def test_narrow_row_parity(n, m, N, K):
     """Affine stage data, linear term, dense Q and R, u_prev != 0."""
     p = tiny_problem(N + n, n, m, N, 0)
