@@ -248,6 +248,47 @@ def bench_cstr(steps=21):
                         "W_du=0.1, rho=0.1, FP32, online linearisation at each sample"}
 
 
+def bench_rti(steps=21):
+    """Cart-pole swing-up with real-time iterations: N=256, time-varying
+    A_k, B_k, e_k from the Jacobians along the shifted predicted trajectory,
+    100 warm-started iterations per step, FP32 iteration with FP64
+    refactorisation on the device.  Library time per step = pimpc_linearize
+    + pimpc_solve (host pointers, synchronous); the whole step adds the host
+    Jacobians and the read-back of the predicted trajectory.  The first step
+    is dropped."""
+    import numpy as np
+    from paper_2601_14414_amd import rti
+    log = rti.run_cartpole_rti(steps=steps, N=256, iters=100)
+    lib = np.array([st.lib_s for st in log[1:]])
+    step = np.array([st.step_s for st in log[1:]])
+    jac = np.array([st.jac_s for st in log[1:]])
+    return {"median_lib_s_per_step": float(np.median(lib)), "max_lib_s_per_step": float(np.max(lib)),
+            "median_s_per_step": float(np.median(step)), "median_host_jacobian_s": float(np.median(jac)),
+            "stage_iterations_per_s": 256 * 100 / float(np.median(lib)), "steps": len(lib),
+            "theta_start": float(log[0].x[2]), "theta_end": float(log[-1].x[2]),
+            "workload": "cart-pole swing-up RTI, nx=4, nu=1, N=256, 100 iterations per step, "
+                        "Q=diag(10,1,10,1), R=0.01, |u|<=10, FP32 iteration, FP64 refactorisation"}
+
+
+def bench_fp64_chain(torch, P, W, n):
+    """Plain linear MPC in FP64: 4-mass chain (nx=8, nu=3), N=20, 200 fixed
+    iterations, one instance; device-resident solves on the caller's stream."""
+    p = W.plain_fp64_problem(seed=0)
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    s = P.Solver([p], max_iter=p.K, precision=P.PIMPC_FP64, stream=stream)
+    x0 = torch.tensor(p.x0, dtype=torch.float64, device=dev)
+    u0 = torch.empty(p.nu, dtype=torch.float64, device=dev)
+    info = torch.zeros(40, dtype=torch.uint8, device=dev)
+    fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream)
+    ms, per = time_solves(torch, fn, n, 2)
+    s.close()
+    sol_ms = ms / n
+    return {"ms_per_solve": sol_ms, "stage_iterations_per_s": p.N * p.K / (sol_ms / 1e3),
+            "kernel_ms": float(sum(per) / len(per)),
+            "workload": "4-mass chain (nx=8, nu=3), N=20, 200 iterations, rho=1, FP64, one instance"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,7 +297,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-accel", action="store_true", help="skip the restart-acceleration extra")
-    ap.add_argument("--only", choices=["batch", "diff", "accel", "cstr"],
+    ap.add_argument("--only", choices=["batch", "diff", "accel", "cstr", "rti", "fp64"],
                     help="run one extra workload alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
@@ -277,7 +318,8 @@ def main():
         torch.cuda.set_device(0)
         n = max(3, args.steps // 4)
         res = {"batch": lambda: bench_batch(torch, P, W, n, 1), "diff": lambda: bench_diff(torch, P, W, n, 1),
-               "accel": lambda: bench_accel(torch, P, W, 2, 1), "cstr": lambda: bench_cstr()}[args.only]()
+               "accel": lambda: bench_accel(torch, P, W, 2, 1), "cstr": lambda: bench_cstr(),
+               "rti": lambda: bench_rti(), "fp64": lambda: bench_fp64_chain(torch, P, W, 20)}[args.only]()
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.gpus != 1:
@@ -332,6 +374,8 @@ def main():
         if not args.no_accel:
             out["restart_accel_4096"] = bench_accel(torch, P, W, 2, 1)
         out["cstr_nmpc_5000"] = bench_cstr()
+        out["rti_cartpole_256"] = bench_rti()
+        out["fp64_chain_20"] = bench_fp64_chain(torch, P, W, 20)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

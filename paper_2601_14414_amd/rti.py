@@ -34,11 +34,15 @@ class RTIStep:
     u_prev: np.ndarray
     info: np.ndarray
     xbar: np.ndarray       # predicted xbar_{k+1}, (N, nb)
+    jac_s: float = 0.0     # wall time of the host Jacobians along the shifted trajectory
+    lib_s: float = 0.0     # wall time of pimpc_linearize + pimpc_solve
+    step_s: float = 0.0    # whole RTI step: shift, Jacobians, library calls, predicted trajectory read-back
 
 
 def run_cartpole_rti(steps: int = 20, N: int = 256, iters: int = 100, precision: int = P.PIMPC_FP32,
                      plant: Optional[Callable] = None, stream: Optional[int] = None) -> List[RTIStep]:
     """Swing-up of the cart-pole from the hanging position with RTI."""
+    import time
     plant = plant or W.cartpole_rk4
     p = W.cartpole_problem(N=N, K=iters)
     solver = P.Solver([p], max_iter=iters, precision=precision, warm_start=True, stream=stream)
@@ -48,17 +52,22 @@ def run_cartpole_rti(steps: int = 20, N: int = 256, iters: int = 100, precision:
     log: List[RTIStep] = []
     try:
         for t in range(steps):
+            t0 = time.perf_counter()
             if xbar_pred is None:
                 xs = np.broadcast_to(x, (N, 4)).copy()
                 us = np.zeros((N, 1))
             else:
                 xs, us = W.rti_shift(x, xbar_pred)
             A, B, e = W.cartpole_linearize(xs, us)
+            t1 = time.perf_counter()
             solver.linearize(A.ravel(), B.ravel(), e.ravel())
             u0, info = solver.solve(x0=x, u_prev=u_prev)
+            t2 = time.perf_counter()
             xbar_pred = solver.iterate(P.IT_XBAR)[0]
+            t3 = time.perf_counter()
             log.append(RTIStep(t=t, x=x.copy(), u0=u0.copy(), A=A, B=B, e=e, u_prev=u_prev.copy(),
-                               info=info.copy(), xbar=xbar_pred.copy()))
+                               info=info.copy(), xbar=xbar_pred.copy(), jac_s=t1 - t0, lib_s=t2 - t1,
+                               step_s=t3 - t0))
             x = plant(x, u0)
             u_prev = u0
     finally:

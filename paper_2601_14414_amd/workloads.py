@@ -307,17 +307,25 @@ def cartpole_jacobians(x, u, dt=0.02, h=1e-30):
     return A, B
 
 
-def cartpole_linearize(xs: np.ndarray, us: np.ndarray, dt=0.02):
+def cartpole_linearize(xs: np.ndarray, us: np.ndarray, dt=0.02, h=1e-30):
     """Stage data (A_k, B_k, e_k) of the Euler map linearised at the points
-    (xs[k], us[k]), k = 0..N-1, with e_k = f_d(x_k, u_k) - A_k x_k - B_k u_k."""
+    (xs[k], us[k]), k = 0..N-1, with e_k = f_d(x_k, u_k) - A_k x_k - B_k u_k.
+    The complex-step Jacobians of cartpole_jacobians, evaluated for all
+    stages at once (the model works elementwise on (4, N) arrays)."""
+    X = xs.T.astype(np.complex128)
+    U = us.T.astype(np.complex128)
     N = xs.shape[0]
     A = np.zeros((N, 4, 4))
     B = np.zeros((N, 4, 1))
-    e = np.zeros((N, 4))
-    for k in range(N):
-        Ak, Bk = cartpole_jacobians(xs[k], us[k], dt)
-        A[k], B[k] = Ak, Bk
-        e[k] = cartpole_fd(xs[k], us[k], dt) - Ak @ xs[k] - Bk @ us[k]
+    for j in range(4):
+        Xc = X.copy()
+        Xc[j] += 1j * h
+        A[:, :, j] = (np.imag(cartpole_fd(Xc, U, dt)) / h).T
+    Uc = U.copy()
+    Uc[0] += 1j * h
+    B[:, :, 0] = (np.imag(cartpole_fd(X, Uc, dt)) / h).T
+    fd = cartpole_fd(np.asarray(xs, np.float64).T, np.asarray(us, np.float64).T, dt).T
+    e = fd - np.einsum("nij,nj->ni", A, xs) - np.einsum("nij,nj->ni", B, us)
     return A, B, e
 
 

@@ -71,6 +71,10 @@ def test_cartpole_linearization_affine_term():
     for k in range(5):
         np.testing.assert_allclose(A[k] @ xs[k] + B[k] @ us[k] + e[k], W.cartpole_fd(xs[k], us[k]),
                                    atol=1e-13)
+        # all stages at once give the single-point complex-step Jacobians
+        Ak, Bk = W.cartpole_jacobians(xs[k], us[k])
+        np.testing.assert_allclose(A[k], Ak, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(B[k], Bk, rtol=0, atol=1e-15)
 
 
 def test_rti_shift():
