@@ -24,7 +24,9 @@
  *     pimpc_backward for FP32 time-invariant instances with N <= 256;
  *   - otherwise one row per lane, one block of stages per wave (FP32, nx <= 32,
  *     nu <= 16; time-varying data up to nx <= 24, nu <= 12; box sets, plain
- *     ADMM).
+ *     ADMM), as long as the horizon fits one grid whose workgroups are all
+ *     resident at once (up to 4 stages per wave; for the 24 + 12 class
+ *     N <= 4096 on 256 compute units).
  * A request outside these returns PIMPC_E_UNSUPPORTED from pimpc_setup.
  *
  * Conventions common to every entry point:

@@ -984,7 +984,13 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         const char* env_s = getenv("PIMPC_ROW_STAGES");
         for (int i : ctx->row_insts) {
             ctx->inst[i].row_s = env_s ? atoi(env_s) : 1;
-            HIPCHK(ctx, row_prepare(ctx->fp64, ctx->inst[i]));
+            const hipError_t e = row_prepare(ctx->fp64, ctx->inst[i]);
+            if (e == hipErrorInvalidConfiguration)
+                return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                 "instance %d: horizon N=%d does not fit one co-resident grid of the row "
+                                 "family at up to 4 stages per wave",
+                                 i, ctx->inst[i].N);
+            HIPCHK(ctx, e);
         }
         HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
         HIPCHK(ctx, hipDeviceSynchronize());  // the scratch clear above is complete

@@ -3,7 +3,9 @@ classes 4+4: eight stages per wave, and 8+8: four stages per wave); the
 cases from (30, 14) on are the wide classes: 32+16 (one stage per wave),
 24+12 with two stages per wave (N = 1500 does not fit one stage per wave), and
 24+12 with one stage per wave, where the last stage's wave holds the rows of
-a non-diagonal H_{N-1} (dense Q and R) in registers.  Horizons
+a non-diagonal H_{N-1} (dense Q and R) in registers, and 24+12 with four
+stages per wave up to the longest horizon whose grid is co-resident on a
+256-CU part (N = 4096).  Horizons
 beyond one lane-family workgroup (N > 512) with small stages land here.
 
 FP32 iteration vs the FP64 oracle, tolerance 1e-4 of max(1, |oracle|_inf)
@@ -24,7 +26,8 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("n,m,N,K", [(3, 2, 513, 60), (4, 4, 700, 80), (2, 1, 1029, 60),
                                      (6, 3, 600, 60), (8, 8, 2053, 40), (5, 1, 777, 50),
                                      (30, 14, 600, 30), (20, 10, 1500, 30),
-                                     (12, 8, 600, 40), (24, 11, 530, 30)])
+                                     (12, 8, 600, 40), (24, 11, 530, 30),
+                                     (24, 11, 3000, 12), (24, 11, 4096, 8)])
 def test_narrow_row_parity(n, m, N, K):
     """Affine stage data, linear term, dense Q and R, u_prev != 0."""
     p = tiny_problem(N + n, n, m, N, 0)
@@ -63,3 +66,12 @@ def test_narrow_row_eps_stop_and_warm_start(n, m, N):
     s2.solve()
     compare(s2, [p], [oracle.solve(p, K=40)], TOL32)
     s2.close()
+
+
+def test_horizon_beyond_one_resident_grid_is_unsupported():
+    """A horizon that no co-resident row grid holds is refused at setup with
+    PIMPC_E_UNSUPPORTED (no kernel runs)."""
+    p = tiny_problem(7, 24, 11, 20000, 0)
+    with pytest.raises(P.PimpcError) as ei:
+        P.Solver([p], rho=p.rho, max_iter=5, precision=P.PIMPC_FP32)
+    assert ei.value.code == P.PIMPC_E_UNSUPPORTED
