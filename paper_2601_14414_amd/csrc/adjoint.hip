@@ -46,21 +46,30 @@ extern __shared__ __align__(16) unsigned char bwd_smem[];
 // C += V1 V2^T over the 64 stages of this wave.  Each lane passes its stage's
 // two 16-vectors; they are staged as [stage][16] and fed to the MFMA so that
 // lane l supplies V1[l % 16][4t + l / 16] and V2[l % 16][4t + l / 16].
+// The four float4 slots of stage s are rotated by ((s >> 1) + (s >> 3)) mod 4:
+// without it the 16-float rows put the even lanes of a 128-bit write on the
+// same banks (a 4-way conflict); with it every write and read is
+// conflict-free for 32 and for 64 banks.
+__device__ inline int stage_rot(int s) { return ((s >> 1) + (s >> 3)) & 3; }
+
 __device__ inline void stage_accum(floatx4& C, const float (&v1)[16], const float (&v2)[16], float* stg,
                                    int lane) {
     float4* s1 = (float4*)(stg + lane * 16);
     float4* s2 = (float4*)(stg + 1024 + lane * 16);
+    const int wr = stage_rot(lane);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        s1[q] = make_float4(v1[4 * q], v1[4 * q + 1], v1[4 * q + 2], v1[4 * q + 3]);
-        s2[q] = make_float4(v2[4 * q], v2[4 * q + 1], v2[4 * q + 2], v2[4 * q + 3]);
+        s1[(q + wr) & 3] = make_float4(v1[4 * q], v1[4 * q + 1], v1[4 * q + 2], v1[4 * q + 3]);
+        s2[(q + wr) & 3] = make_float4(v2[4 * q], v2[4 * q + 1], v2[4 * q + 2], v2[4 * q + 3]);
     }
     __builtin_amdgcn_wave_barrier();
     const int i = lane & 15, kk = lane >> 4;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-        const float av = stg[(4 * t + kk) * 16 + i];
-        const float bv = stg[1024 + (4 * t + kk) * 16 + i];
+        const int st = 4 * t + kk;  // the stage whose element i this lane supplies
+        const int off = st * 16 + 4 * (((i >> 2) + stage_rot(st)) & 3) + (i & 3);
+        const float av = stg[off];
+        const float bv = stg[1024 + off];
         C = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, C, 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
