@@ -289,6 +289,40 @@ def bench_fp64_chain(torch, P, W, n):
             "workload": "4-mass chain (nx=8, nu=3), N=20, 200 iterations, rho=1, FP64, one instance"}
 
 
+# Table 1 of the paper (random systems of Section V-B, averages over 200 iterations): milliseconds per
+# iteration of piMPC on its GPU (RTX 3080) and CPU (Ryzen 9 5900X), and of OSQP, for the stage sizes
+# this build compiles.  Context only: other hardware, precision not stated.
+PAPER_TABLE1_MS = {  # (n, m): {N: (piMPC GPU, piMPC CPU, OSQP)}
+    (10, 3): {20: (0.53, 0.15, 0.02), 50: (0.55, 0.31, 0.06), 100: (0.54, 0.58, 0.11), 200: (0.55, 1.12, 0.23),
+              500: (0.56, 2.75, 0.59)},
+    (20, 6): {20: (0.56, 0.17, 0.07), 50: (0.56, 0.35, 0.18), 100: (0.55, 0.68, 0.35), 200: (0.55, 1.38, 0.72),
+              500: (0.56, 3.52, 1.85)},
+    (30, 10): {20: (0.54, 0.18, 0.15), 50: (0.54, 0.38, 0.37), 100: (0.58, 0.73, 0.74), 200: (0.56, 1.61, 1.56),
+               500: (0.56, 3.90, 5.78)},
+}
+
+
+def bench_table1(torch, P, W, n_solves=10):
+    """The random-system recipe of the paper's scalability study at the sizes
+    of its Table 1 that this build compiles: one instance per solve, 200
+    iterations, FP32, device pointers; milliseconds per iteration beside the
+    paper's numbers."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for (n, m), row in PAPER_TABLE1_MS.items():
+        for N, (gpu, cpu, osqp) in row.items():
+            p = W.paper_random_system(n, m, N, seed=0, K=200)
+            s = P.Solver([p], rho=p.rho, max_iter=200, precision=P.PIMPC_FP32, stream=stream)
+            x0 = torch.tensor(p.x0, dtype=torch.float32, device=dev)
+            u0 = torch.empty(m, dtype=torch.float32, device=dev)
+            ms, _ = time_solves(torch, lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, None, stream), n_solves, 2)
+            s.close()
+            out[f"n{n}_m{m}_N{N}"] = {"ms_per_iteration": ms / n_solves / 200, "paper_gpu_ms_per_iteration": gpu,
+                                      "paper_cpu_ms_per_iteration": cpu, "paper_osqp_ms_per_iteration": osqp}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,7 +331,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-accel", action="store_true", help="skip the restart-acceleration extra")
-    ap.add_argument("--only", choices=["batch", "diff", "accel", "cstr", "rti", "fp64"],
+    ap.add_argument("--only", choices=["batch", "diff", "accel", "cstr", "rti", "fp64", "table1"],
                     help="run one extra workload alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
@@ -319,7 +353,8 @@ def main():
         n = max(3, args.steps // 4)
         res = {"batch": lambda: bench_batch(torch, P, W, n, 1), "diff": lambda: bench_diff(torch, P, W, n, 1),
                "accel": lambda: bench_accel(torch, P, W, 2, 1), "cstr": lambda: bench_cstr(),
-               "rti": lambda: bench_rti(), "fp64": lambda: bench_fp64_chain(torch, P, W, 20)}[args.only]()
+               "rti": lambda: bench_rti(), "fp64": lambda: bench_fp64_chain(torch, P, W, 20),
+               "table1": lambda: bench_table1(torch, P, W)}[args.only]()
         print(json.dumps({args.only: res}), flush=True)
         return
     if args.gpus != 1:
@@ -376,6 +411,7 @@ def main():
         out["cstr_nmpc_5000"] = bench_cstr()
         out["rti_cartpole_256"] = bench_rti()
         out["fp64_chain_20"] = bench_fp64_chain(torch, P, W, 20)
+        out["paper_table1_context"] = bench_table1(torch, P, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

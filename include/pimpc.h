@@ -16,18 +16,24 @@
  * du_k), with the stage caches J_k, H_k of Algorithm 1 factorised in FP64 on
  * the device and the iteration run in the precision chosen by the caller.
  *
- * Which kernel family serves an instance, and what it supports:
- *   - one lane per stage, when N <= 512 and a compiled class holds the stage
- *     (time-invariant: nx <= 16, nu <= 8; time-varying: nx <= 4, nu <= 2;
- *     FP64 up to nx + nu = 13 after padding): FP32 or FP64 iteration,
- *     restart acceleration, non-box sets, and the taped forward /
+ * The two kernel families and what they support:
+ *   - lane family, one lane per stage, when N <= 512 and a compiled class
+ *     holds the stage (time-invariant: nx <= 16, nu <= 8; time-varying:
+ *     nx <= 4, nu <= 2; FP64 up to nx + nu = 13 after padding): FP32 or FP64
+ *     iteration, restart acceleration, non-box sets, and the taped forward /
  *     pimpc_backward for FP32 time-invariant instances with N <= 256;
- *   - otherwise one row per lane, one block of stages per wave (FP32, nx <= 32,
- *     nu <= 16; time-varying data up to nx <= 24, nu <= 12; box sets, plain
- *     ADMM), as long as the horizon fits one grid whose workgroups are all
- *     resident at once (up to 4 stages per wave; for the 24 + 12 class
- *     N <= 4096 on 256 compute units).
- * A request outside these returns PIMPC_E_UNSUPPORTED from pimpc_setup.
+ *   - row family, one row of a stage per lane, one block of stages per wave
+ *     (FP32, nx <= 32, nu <= 16; time-varying data up to nx <= 24, nu <= 12;
+ *     box sets, plain ADMM), as long as the horizon fits one grid whose
+ *     workgroups are all resident at once (up to 4 stages per wave; for the
+ *     24 + 12 class N <= 4096 on 256 compute units).
+ * With options.family = PIMPC_FAMILY_AUTO, a context of one time-invariant
+ * FP32 instance with box sets, plain ADMM and no tape runs on the row family
+ * whenever a row class holds it (its iteration is several times shorter than
+ * one lane walking all rows of its stage); otherwise, and for every instance
+ * of a batch, the lane family serves what it holds and the row family the
+ * rest.  A request outside these returns
+ * PIMPC_E_UNSUPPORTED from pimpc_setup.
  *
  * Conventions common to every entry point:
  *   - every call returns an int32 status: PIMPC_OK (0) or a negative error;
@@ -153,6 +159,10 @@ typedef struct {
  *   warm_start   1 = start from the previous solve's iterate (unshifted)
  *   ckpt_every   > 0 records a tape for pimpc_backward every that many iterations
  *   schedule     batch schedule: 0 = autotune, > 0 = fixed candidate index
+ *   family       kernel family: PIMPC_FAMILY_AUTO (choose as described at the
+ *                top of this file), PIMPC_FAMILY_LANE or PIMPC_FAMILY_ROW
+ *                (PIMPC_E_UNSUPPORTED when that family cannot serve an
+ *                instance)
  */
 typedef struct {
     double rho;
@@ -165,7 +175,12 @@ typedef struct {
     int32_t warm_start;
     int32_t ckpt_every;
     int32_t schedule;
+    int32_t family;
 } pimpc_options;
+
+#define PIMPC_FAMILY_AUTO 0
+#define PIMPC_FAMILY_LANE 1
+#define PIMPC_FAMILY_ROW 2
 
 /* Per-instance result of a solve (c, r_prim, r_dual of the last residual check). */
 typedef struct {

@@ -676,6 +676,7 @@ void pimpc_default_options(pimpc_options* o) {
     o->warm_start = 0;
     o->ckpt_every = 0;
     o->schedule = 0;
+    o->family = PIMPC_FAMILY_AUTO;
 }
 
 int32_t pimpc_version(void) { return PIMPC_VERSION; }
@@ -749,6 +750,8 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     if (o->warm_start != 0 && o->warm_start != 1) return ctx->fail(PIMPC_E_ARG, "warm_start must be 0 or 1");
     if (o->ckpt_every < 0) return ctx->fail(PIMPC_E_ARG, "ckpt_every must be >= 0");
     if (o->schedule < 0) return ctx->fail(PIMPC_E_ARG, "schedule must be >= 0");
+    if (o->family < PIMPC_FAMILY_AUTO || o->family > PIMPC_FAMILY_ROW)
+        return ctx->fail(PIMPC_E_ARG, "family must be PIMPC_FAMILY_AUTO, _LANE or _ROW");
     const int count = p->count;
     const int tv = p->time_varying;
     int64_t sA = 0, sB = 0, se = 0, sQ = 0, sR = 0, snx = 0, snu = 0;
@@ -845,14 +848,32 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         I.xset = p->xset ? p->xset[i] : PIMPC_SET_BOX;
         I.uset = p->uset ? p->uset[i] : PIMPC_SET_BOX;
         const int cls = (I.N <= kBinThreads) ? pick_class(I.nx, I.nu, tv, ctx->fp64 ? 8 : 4) : -1;
-        if (cls >= 0) {
+        int rnx = 0, rnu = 0;
+        const bool row_ok = row_supported(I.nx, I.nu, I.N, tv, ctx->fp64, &rnx, &rnu);
+        bool lane = cls >= 0;
+        if (o->family == PIMPC_FAMILY_LANE) {
+            if (cls < 0)
+                return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                 "instance %d (nx=%d, nu=%d, N=%d): no lane-family class holds it", i, I.nx,
+                                 I.nu, I.N);
+        } else if (o->family == PIMPC_FAMILY_ROW) {
+            lane = false;
+        } else if (count == 1 && !tv && row_ok && I.xset == PIMPC_SET_BOX && I.uset == PIMPC_SET_BOX &&
+                   o->accel != 1 && o->ckpt_every == 0) {
+            // One time-invariant instance alone: a row of the stage per lane
+            // gives a much shorter iteration than one lane walking every row
+            // of its stage.  (With time-varying data the row family rebuilds a
+            // fused block per stage at every re-linearisation, which costs
+            // back what the shorter iterations save over a few hundred.)
+            lane = false;
+        }
+        if (lane) {
             const ClassDesc* cd = class_desc(cls);
             I.cls = cls;
             I.nxp = cd->nx;
             I.nup = cd->nu;
         } else {
-            int rnx = 0, rnu = 0;
-            if (!row_supported(I.nx, I.nu, I.N, tv, ctx->fp64, &rnx, &rnu))
+            if (!row_ok)
                 return ctx->fail(PIMPC_E_UNSUPPORTED,
                                  "instance %d (nx=%d, nu=%d, N=%d, %s, %s) has no compiled kernel", i, I.nx, I.nu,
                                  I.N, tv ? "time-varying" : "time-invariant", ctx->fp64 ? "fp64" : "fp32");

@@ -33,6 +33,7 @@ PIMPC_FP64 = 0
 PIMPC_FP32 = 1
 PIMPC_MEM_HOST = 0
 PIMPC_MEM_DEVICE = 1
+PIMPC_FAMILY_AUTO, PIMPC_FAMILY_LANE, PIMPC_FAMILY_ROW = 0, 1, 2
 PIMPC_SET_BOX, PIMPC_SET_HALFSPACE, PIMPC_SET_HYPERPLANE, PIMPC_SET_SOC, PIMPC_SET_L1BALL = 0, 1, 2, 3, 4
 IT_V, IT_Z, IT_THETA, IT_BETA, IT_LAMBDA, IT_DU, IT_XBAR = range(7)
 
@@ -52,7 +53,7 @@ class pimpc_options(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_double), ("max_iter", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("accel", ctypes.c_int32), ("eta", ctypes.c_double), ("warm_start", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("schedule", ctypes.c_int32), ("family", ctypes.c_int32)]
 
 
 class pimpc_info(ctypes.Structure):
@@ -297,12 +298,12 @@ class Solver:
     def __init__(self, problems: Sequence, rho: float = 1.0, max_iter: int = 200, eps: float = 0.0,
                  check_every: int = 1, precision: int = PIMPC_FP32, warm_start: bool = False,
                  ckpt_every: int = 0, schedule: int = 0, stream: Optional[int] = None,
-                 accel: bool = False, eta: float = 0.999):
+                 accel: bool = False, eta: float = 0.999, family: int = PIMPC_FAMILY_AUTO):
         self.problems = list(problems)
         o = pimpc_default_options()
         o.rho, o.max_iter, o.eps, o.check_every = rho, max_iter, eps, check_every
         o.precision, o.warm_start, o.ckpt_every, o.schedule = precision, int(warm_start), ckpt_every, schedule
-        o.accel, o.eta = int(bool(accel)), eta
+        o.accel, o.eta, o.family = int(bool(accel)), eta, family
         self.opts = o
         self.ctx, self._keep = pimpc_setup(self.problems, o, stream)
         self.count = len(self.problems)

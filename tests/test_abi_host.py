@@ -56,7 +56,7 @@ def _setup_code(problems, **kw):
 @pytest.mark.parametrize("field,value", [("rho", 0.0), ("rho", -1.0), ("rho", float("inf")),
                                          ("max_iter", 0), ("check_every", 0), ("precision", 7),
                                          ("accel", 3), ("warm_start", 2), ("ckpt_every", -1),
-                                         ("eps", float("nan"))])
+                                         ("eps", float("nan")), ("family", 3), ("family", -1)])
 def test_bad_options_rejected(field, value):
     code, msg = _setup_code([W.plain_fp64_problem(0)], **{field: value})
     assert code == P.PIMPC_E_ARG, (field, value, code, msg)
@@ -164,3 +164,17 @@ def test_error_text_available_without_context():
     code, msg = _setup_code([W.plain_fp64_problem(0)], rho=-2.0)
     assert code == P.PIMPC_E_ARG and "rho" in msg
     assert b"rho" in P.lib().pimpc_last_error(None)
+
+
+def test_requested_family_that_cannot_serve_is_unsupported():
+    """options.family forces a kernel family; setup refuses, before any HIP
+    call, an instance that family cannot serve."""
+    long = W.long_horizon_problem(0, N=600, K=10)  # nx = 24: no lane-family class
+    code, msg = _setup_code([long], family=P.PIMPC_FAMILY_LANE)
+    assert code == P.PIMPC_E_UNSUPPORTED and "lane-family" in msg
+    small = W.plain_fp64_problem(0)
+    code, _ = _setup_code([small], family=P.PIMPC_FAMILY_ROW, precision=P.PIMPC_FP64)  # row: FP32 only
+    assert code == P.PIMPC_E_UNSUPPORTED
+    code, msg = _setup_code([small.copy(uset=("l1ball", 1.0))], family=P.PIMPC_FAMILY_ROW,
+                            precision=P.PIMPC_FP32)
+    assert code == P.PIMPC_E_UNSUPPORTED and "lane family" in msg

@@ -31,7 +31,7 @@ def test_every_called_module_function_exists():
     missing = {c for c in called if c not in defined and c not in local_names and not hasattr(bench, c)
                and c not in dir(__import__("builtins"))}
     assert not missing, missing
-    for leg in ("bench_batch", "bench_diff", "bench_accel", "bench_cstr", "bench_rti", "bench_fp64_chain",
+    for leg in ("bench_batch", "bench_diff", "bench_accel", "bench_cstr", "bench_rti", "bench_fp64_chain", "bench_table1",
                 "cpu_baseline", "measured_traffic"):
         assert leg in defined, leg
 

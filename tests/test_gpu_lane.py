@@ -36,7 +36,10 @@ def compare(solver, problems, refs, tol, which=range(len(P.EXPORTS))):
 
 
 def run_both(problems, precision, K=None, **kw):
+    """Solve on the lane family (requested explicitly: a lone FP32 instance
+    would otherwise run on the row family) and with the oracle."""
     K = K or problems[0].K
+    kw.setdefault("family", P.PIMPC_FAMILY_LANE)
     s = P.Solver(problems, rho=problems[0].rho, max_iter=K, precision=precision, **kw)
     u0, info = s.solve()
     refs = [oracle.solve(p, K=K, eps=kw.get("eps", 0.0)) for p in problems]
@@ -152,10 +155,11 @@ def test_uneven_batch_subset_fp32():
     check_info(info, refs, 1e-4)
 
 
-def test_nonfinite_iterate_reported():
-    """Overflowing FP32 data is reported as PIMPC_E_NONFINITE."""
+@pytest.mark.parametrize("family", [P.PIMPC_FAMILY_LANE, P.PIMPC_FAMILY_ROW])
+def test_nonfinite_iterate_reported(family):
+    """Overflowing FP32 data is reported as PIMPC_E_NONFINITE by both families."""
     p = W.plain_fp64_problem(0)
-    s = P.Solver([p], precision=P.PIMPC_FP32)
+    s = P.Solver([p], precision=P.PIMPC_FP32, family=family)
     with pytest.raises(P.PimpcError) as ei:
         s.solve(x0=np.full(8, 1e30))
     assert ei.value.code == P.PIMPC_E_NONFINITE
@@ -182,6 +186,7 @@ def test_wide_input_classes_fp32(n, m, N, tv):
     the FP64 oracle; the time-varying case has no lane class that wide and
     runs on the row family's 8+8 class with a short horizon."""
     p = tiny_problem(100 + n + m, n, m, N, tv)
-    s, u0, info, refs = run_both([p], P.PIMPC_FP32)
+    fam = P.PIMPC_FAMILY_ROW if tv else P.PIMPC_FAMILY_LANE
+    s, u0, info, refs = run_both([p], P.PIMPC_FP32, family=fam)
     compare(s, [p], refs, TOL32)
     check_info(info, refs, 1e-4)

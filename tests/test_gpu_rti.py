@@ -34,12 +34,14 @@ def oracle_rti(steps, N, iters):
     return p0, log
 
 
-@pytest.mark.parametrize("precision,tol", [(P.PIMPC_FP64, 1e-10), (P.PIMPC_FP32, TOL32)])
-def test_rti_per_step_parity(precision, tol):
+@pytest.mark.parametrize("precision,tol,family", [(P.PIMPC_FP64, 1e-10, P.PIMPC_FAMILY_AUTO),
+                                                  (P.PIMPC_FP32, TOL32, P.PIMPC_FAMILY_AUTO),
+                                                  (P.PIMPC_FP32, TOL32, P.PIMPC_FAMILY_ROW)])
+def test_rti_per_step_parity(precision, tol, family):
     """20 RTI steps x 100 iterations, N=256: at every step the GPU (fed the
     same linearisations, x(t) and u(t-1)) matches the oracle iterates."""
     p0, log = oracle_rti(steps=20, N=256, iters=100)
-    s = P.Solver([p0], max_iter=100, precision=precision, warm_start=True)
+    s = P.Solver([p0], max_iter=100, precision=precision, warm_start=True, family=family)
     for t, (p, r) in enumerate(log):
         s.linearize(p.A.ravel(), p.B.ravel(), p.e.ravel())
         u0, info = s.solve(x0=p.x0, u_prev=p.u_prev)
