@@ -178,3 +178,31 @@ def test_requested_family_that_cannot_serve_is_unsupported():
     code, msg = _setup_code([small.copy(uset=("l1ball", 1.0))], family=P.PIMPC_FAMILY_ROW,
                             precision=P.PIMPC_FP32)
     assert code == P.PIMPC_E_UNSUPPORTED and "lane family" in msg
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of pimpc_problem, pimpc_options and pimpc_info have
+    the C compiler's field offsets and sizes (a C program built against
+    include/pimpc.h prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"pimpc_problem": P.pimpc_problem, "pimpc_options": P.pimpc_options, "pimpc_info": P.pimpc_info}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "pimpc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for name, cls in structs.items():
+        assert int(got[f"{name} size"]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
