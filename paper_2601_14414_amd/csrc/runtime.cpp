@@ -130,6 +130,9 @@ struct pimpc_ctx_s {
     InstDev* d_inst = nullptr;
     void* d_mats = nullptr;
     double* d_mats64 = nullptr;
+    // host copy of d_mats64, current unless device-side parameters replaced it
+    std::vector<double> h_mats64;
+    bool h_mats64_valid = false;
     void* d_state = nullptr;
     void* d_prev = nullptr;  // restart acceleration: the previous actual iterate (state layout)
     void* d_iters = nullptr;
@@ -968,9 +971,10 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     HIPCHK(ctx, hipMemset(ctx->d_iters, 0, ctx->it_elems * ts));
     HIPCHK(ctx, hipMemset(ctx->d_up, 0, ctx->sum_nu * ts));
 
-    std::vector<double> m64v;
+    std::vector<double>& m64v = ctx->h_mats64;
     build_mats64(ctx, p->A, p->B, p->e, p->Q, p->R, p->Wdu, m64v, false);
     HIPCHK(ctx, hipMemcpy(ctx->d_mats64, m64v.data(), m64v.size() * sizeof(double), hipMemcpyHostToDevice));
+    ctx->h_mats64_valid = true;
     int rc = ctx->fp64
                  ? upload_t_block<double>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax, p->xset_par, p->uset_par)
                  : upload_t_block<float>(ctx, p->qbar, p->xmin, p->xmax, p->umin, p->umax, p->xset_par, p->uset_par);
@@ -1103,8 +1107,15 @@ int32_t pimpc_linearize(pimpc_ctx ctx, const double* A, const double* B, const d
     }
     if (!finite_arr(pA, sA) || !finite_arr(pB, sB) || (pe && !finite_arr(pe, se)))
         return ctx->fail(PIMPC_E_NONFINITE, "stage data contains NaN or Inf");
-    std::vector<double> m64v(ctx->mat64_elems);
-    HIPCHK(ctx, hipMemcpy(m64v.data(), ctx->d_mats64, m64v.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // The weights and bounds of the block stay; only A, B, e are rewritten.
+    // The host copy is current unless pimpc_set_params_dev replaced the
+    // parameters on the device.
+    std::vector<double>& m64v = ctx->h_mats64;
+    if (!ctx->h_mats64_valid) {
+        m64v.resize(ctx->mat64_elems);
+        HIPCHK(ctx, hipMemcpy(m64v.data(), ctx->d_mats64, m64v.size() * sizeof(double), hipMemcpyDeviceToHost));
+        ctx->h_mats64_valid = true;
+    }
     build_mats64(ctx, pA, pB, pe, nullptr, nullptr, nullptr, m64v, true);
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_mats64, m64v.data(), m64v.size() * sizeof(double), hipMemcpyHostToDevice,
                                ctx->stream));
@@ -1184,6 +1195,7 @@ int32_t pimpc_set_params_dev(pimpc_ctx ctx, const void* A, const void* B, const 
         if (I.nx != ctx->inst[0].nx || I.nu != ctx->inst[0].nu)
             return ctx->fail(PIMPC_E_STATE, "set_params_dev needs equal nx and nu across instances");
     const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    ctx->h_mats64_valid = false;  // the device copy changes below
     if (ctx->fp64)
         HIPCHK(ctx, launch_params<double>(ctx->d_inst, ctx->count, (const double*)A, (const double*)B,
                                           (const double*)Qdiag, (const double*)Rdiag, ctx->d_mats64, s));

@@ -40,12 +40,13 @@ class RTIStep:
 
 
 def run_cartpole_rti(steps: int = 20, N: int = 256, iters: int = 100, precision: int = P.PIMPC_FP32,
-                     plant: Optional[Callable] = None, stream: Optional[int] = None) -> List[RTIStep]:
+                     plant: Optional[Callable] = None, stream: Optional[int] = None,
+                     family: int = P.PIMPC_FAMILY_AUTO) -> List[RTIStep]:
     """Swing-up of the cart-pole from the hanging position with RTI."""
     import time
     plant = plant or W.cartpole_rk4
     p = W.cartpole_problem(N=N, K=iters)
-    solver = P.Solver([p], max_iter=iters, precision=precision, warm_start=True, stream=stream)
+    solver = P.Solver([p], max_iter=iters, precision=precision, warm_start=True, stream=stream, family=family)
     x = p.x0.copy()
     u_prev = np.zeros(1)
     xbar_pred = None
