@@ -27,12 +27,11 @@
  *     box sets, plain ADMM), as long as the horizon fits one grid whose
  *     workgroups are all resident at once (up to 4 stages per wave; for the
  *     24 + 12 class N <= 4096 on 256 compute units).
- * With options.family = PIMPC_FAMILY_AUTO, a context of one time-invariant
- * FP32 instance with box sets, plain ADMM and no tape runs on the row family
- * whenever a row class holds it (its iteration is several times shorter than
- * one lane walking all rows of its stage); otherwise, and for every instance
- * of a batch, the lane family serves what it holds and the row family the
- * rest.  A request outside these returns
+ * With options.family = PIMPC_FAMILY_AUTO, a context of one FP32 instance
+ * with box sets, plain ADMM and no tape runs on the row family whenever a row
+ * class holds it (its iteration is several times shorter than one lane
+ * walking all rows of its stage); otherwise, and for every instance of a
+ * batch, the lane family serves what it holds and the row family the rest.  A request outside these returns
  * PIMPC_E_UNSUPPORTED from pimpc_setup.
  *
  * Conventions common to every entry point:

@@ -861,13 +861,10 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
                                  I.nu, I.N);
         } else if (o->family == PIMPC_FAMILY_ROW) {
             lane = false;
-        } else if (count == 1 && !tv && row_ok && I.xset == PIMPC_SET_BOX && I.uset == PIMPC_SET_BOX &&
+        } else if (count == 1 && row_ok && I.xset == PIMPC_SET_BOX && I.uset == PIMPC_SET_BOX &&
                    o->accel != 1 && o->ckpt_every == 0) {
-            // One time-invariant instance alone: a row of the stage per lane
-            // gives a much shorter iteration than one lane walking every row
-            // of its stage.  (With time-varying data the row family rebuilds a
-            // fused block per stage at every re-linearisation, which costs
-            // back what the shorter iterations save over a few hundred.)
+            // One instance alone: a row of the stage per lane gives a much
+            // shorter iteration than one lane walking every row of its stage.
             lane = false;
         }
         if (lane) {

@@ -36,7 +36,7 @@ def oracle_rti(steps, N, iters):
 
 @pytest.mark.parametrize("precision,tol,family", [(P.PIMPC_FP64, 1e-10, P.PIMPC_FAMILY_AUTO),
                                                   (P.PIMPC_FP32, TOL32, P.PIMPC_FAMILY_AUTO),
-                                                  (P.PIMPC_FP32, TOL32, P.PIMPC_FAMILY_ROW)])
+                                                  (P.PIMPC_FP32, TOL32, P.PIMPC_FAMILY_LANE)])
 def test_rti_per_step_parity(precision, tol, family):
     """20 RTI steps x 100 iterations, N=256: at every step the GPU (fed the
     same linearisations, x(t) and u(t-1)) matches the oracle iterates."""
