@@ -42,6 +42,13 @@
  *   - a context owns all its device memory; the caller keeps ownership of
  *     every array it passes (inputs are copied before the call returns);
  *   - a context is bound to one HIP stream and is not thread-safe;
+ *   - a row-family solve needs every workgroup of its grid resident at once.
+ *     One context runs its row-family instances one after another; solves of
+ *     different contexts that hold row-family instances must not overlap in
+ *     time (enqueue them on one stream).  Otherwise each grid may hold part of
+ *     the GPU and wait for the rest: the bounded waits then give up and the
+ *     solve fails (PIMPC_E_HIP, status of the instance non-zero) instead of
+ *     hanging;
  *   - "instance" = one MPC problem; a context holds `count` of them, packed
  *     back to back in the order given (offsets are prefix sums of the sizes).
  */
@@ -188,7 +195,8 @@ typedef struct {
     double c;       /* c^{i+1} of Algorithm 1 step 4                      */
     double r_prim;  /* ||s^{i+1} - s^i||_inf   (primal residual)         */
     double r_dual;  /* rho ||F'G(q^{i+1}-q^i)||_inf   (dual residual)    */
-    int32_t status; /* PIMPC_OK or PIMPC_E_NONFINITE                      */
+    int32_t status; /* PIMPC_OK, PIMPC_E_NONFINITE, or PIMPC_E_HIP when a
+                       row-family wait between workgroups gave up         */
     int32_t pad;
 } pimpc_info;
 

@@ -550,11 +550,15 @@ static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
     std::sort(order.begin(), order.end(), [&](int a, int b) { return ctx->runs[a].cost > ctx->runs[b].cost; });
     std::vector<int64_t> load(ns, 0);
     auto stream_of = [&](int j) { return j == 0 ? s : ctx->aux[j - 1]; };
+    // A row-family kernel needs every workgroup of its grid resident at once
+    // (its halo waits cross workgroups).  Two of them side by side could each
+    // hold part of the GPU and wait for the rest, so they run one after the
+    // other on the first stream; the lane classes, whose workgroups never
+    // wait on each other, balance over the other streams.
     for (size_t rj = 0; rj < ctx->row_insts.size(); ++rj) {
-        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[j] += (int64_t)1 << 40;
+        load[0] += (int64_t)1 << 40;
         HIPCHK(ctx, launch_row(ctx->fp64, ls->d_rargs + rj, ctx->inst[ctx->row_insts[rj]], ctx->d_row_scratch,
-                               stream_of(j)));
+                               stream_of(0)));
     }
     for (int c : order) {
         const ClassRun& r = ctx->runs[c];
@@ -1159,7 +1163,11 @@ int32_t pimpc_solve(pimpc_ctx ctx, const double* x0, const double* u_prev, doubl
             u0_out[j] = ctx->fp64 ? ((double*)bo.data())[j] : (double)((float*)bo.data())[j];
     if (info) memcpy(info, inf.data(), ctx->count * sizeof(InfoDev));
     for (int i = 0; i < ctx->count; ++i)
-        if (inf[i].status != 0) return ctx->fail(PIMPC_E_NONFINITE, "instance %d: iterate became non-finite", i);
+        if (inf[i].status == PIMPC_E_HIP)
+            return ctx->fail(PIMPC_E_HIP, "instance %d: a wait between workgroups gave up (the grid was not "
+                                          "resident at once)", i);
+        else if (inf[i].status != 0)
+            return ctx->fail(PIMPC_E_NONFINITE, "instance %d: iterate became non-finite", i);
     return PIMPC_OK;
 }
 

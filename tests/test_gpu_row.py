@@ -50,3 +50,19 @@ def test_row_eps_stop_and_warm_start():
     s2.solve()
     s2.solve()
     compare(s2, [p], [oracle.solve(p, K=100)], TOL32)
+
+
+def test_several_row_instances_with_lane_instances():
+    """A batch holding two full-size long horizons (the row family, each grid
+    filling the GPU, run one after the other) and lane-family instances on
+    the other streams: every instance against the oracle."""
+    problems = [W.long_horizon_problem(seed=1, N=1024, K=40), W.long_horizon_problem(seed=2, N=900, K=40)]
+    problems += [W.random_batch_instance(seed=2000 + i, K=40) for i in range(6)]
+    # schedule 1: counter-claimed bins on four streams (a batch this small
+    # would otherwise be tuned onto one stream)
+    s = P.Solver(problems, max_iter=40, precision=P.PIMPC_FP32, schedule=1)
+    u0, info = s.solve()
+    refs = [oracle.solve(p, K=40) for p in problems]
+    compare(s, problems, refs, TOL32)
+    check_info(info, refs, 1e-4)
+    s.close()
