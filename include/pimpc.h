@@ -31,8 +31,8 @@
  * with box sets, plain ADMM and no tape runs on the row family whenever a row
  * class holds it (its iteration is several times shorter than one lane
  * walking all rows of its stage); otherwise, and for every instance of a
- * batch, the lane family serves what it holds and the row family the rest.  A request outside these returns
- * PIMPC_E_UNSUPPORTED from pimpc_setup.
+ * batch, the lane family serves what it holds and the row family the rest.
+ * A request outside these returns PIMPC_E_UNSUPPORTED from pimpc_setup.
  *
  * Conventions common to every entry point:
  *   - every call returns an int32 status: PIMPC_OK (0) or a negative error;
