@@ -539,27 +539,26 @@ static void free_set_graphs(pimpc_ctx ctx) {
 static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
     const int ncls = (int)ctx->runs.size();
     if (ctx->schedule == 1 && ncls > 0) HIPCHK(ctx, launch_fill<int32_t>(ctx->d_counters, ncls, 0, s));
-    const int ns = std::min(ctx->nstreams, std::max(1, ncls + (int)ctx->row_insts.size()));
+    // A row-family kernel needs every workgroup of its grid resident at once
+    // (its halo waits cross workgroups).  Beside another row kernel each
+    // could hold part of the GPU and wait for the rest; beside a long lane
+    // batch its resident workgroups could wait longer than their bounded
+    // polls allow.  So the row-family instances run first, one after the
+    // other on the first stream, and the lane classes start after them.
+    for (size_t rj = 0; rj < ctx->row_insts.size(); ++rj)
+        HIPCHK(ctx, launch_row(ctx->fp64, ls->d_rargs + rj, ctx->inst[ctx->row_insts[rj]], ctx->d_row_scratch, s));
+    const int ns = std::min(ctx->nstreams, std::max(1, ncls));
     if (ns > 1) {
         HIPCHK(ctx, hipEventRecord(ctx->ev_fork, s));
         for (int j = 0; j < ns - 1; ++j) HIPCHK(ctx, hipStreamWaitEvent(ctx->aux[j], ctx->ev_fork, 0));
     }
-    // LPT over streams by class cost
+    // the lane classes, whose workgroups never wait on each other: LPT over
+    // the streams by class cost
     std::vector<int> order(ncls);
     for (int c = 0; c < ncls; ++c) order[c] = c;
     std::sort(order.begin(), order.end(), [&](int a, int b) { return ctx->runs[a].cost > ctx->runs[b].cost; });
     std::vector<int64_t> load(ns, 0);
     auto stream_of = [&](int j) { return j == 0 ? s : ctx->aux[j - 1]; };
-    // A row-family kernel needs every workgroup of its grid resident at once
-    // (its halo waits cross workgroups).  Two of them side by side could each
-    // hold part of the GPU and wait for the rest, so they run one after the
-    // other on the first stream; the lane classes, whose workgroups never
-    // wait on each other, balance over the other streams.
-    for (size_t rj = 0; rj < ctx->row_insts.size(); ++rj) {
-        load[0] += (int64_t)1 << 40;
-        HIPCHK(ctx, launch_row(ctx->fp64, ls->d_rargs + rj, ctx->inst[ctx->row_insts[rj]], ctx->d_row_scratch,
-                               stream_of(0)));
-    }
     for (int c : order) {
         const ClassRun& r = ctx->runs[c];
         const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
