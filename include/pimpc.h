@@ -43,12 +43,13 @@
  *     every array it passes (inputs are copied before the call returns);
  *   - a context is bound to one HIP stream and is not thread-safe;
  *   - a row-family solve needs every workgroup of its grid resident at once.
- *     One context runs its row-family instances one after another; solves of
- *     different contexts that hold row-family instances must not overlap in
- *     time (enqueue them on one stream).  Otherwise each grid may hold part of
- *     the GPU and wait for the rest: the bounded waits then give up and the
- *     solve fails (PIMPC_E_HIP, status of the instance non-zero) instead of
- *     hanging;
+ *     A context runs its row-family instances first and one after another;
+ *     solves of different contexts that hold row-family instances must not
+ *     overlap in time (enqueue them on one stream), and other work that keeps
+ *     compute units busy for long delays them.  A wait that cannot complete
+ *     gives up after a bounded number of polls (a fraction of a second) and
+ *     the solve fails (PIMPC_E_HIP, status of the instance non-zero) instead
+ *     of hanging;
  *   - "instance" = one MPC problem; a context holds `count` of them, packed
  *     back to back in the order given (offsets are prefix sums of the sizes).
  */
