@@ -129,3 +129,23 @@ def test_set_params_from_device_tensors(side_stream):
         assert scaled_err(u_dev[3 * i:3 * i + 3], r["u0"]) <= TOL32
     s.close()
     fresh.close()
+
+
+def test_graph_replay_with_row_family_instances(side_stream):
+    """A captured batch holding two long horizons (row family, run first)
+    and lane-family instances on four streams: replays equal the host-path
+    solve of the same context, and every instance matches the oracle."""
+    problems = [W.long_horizon_problem(seed=3, N=1024, K=30), W.long_horizon_problem(seed=4, N=700, K=30)]
+    problems += [W.random_batch_instance(seed=3000 + i, K=30) for i in range(10)]
+    s = P.Solver(problems, max_iter=30, precision=P.PIMPC_FP32, schedule=1, stream=side_stream.cuda_stream)
+    first, _, x0 = _solve_batch(s, problems, side_stream)
+    for rep in range(3):
+        a = torch.randn(256, 256, device="cuda")
+        (a @ a).sum().item()
+        again, _, _ = _solve_batch(s, problems, side_stream, x0=x0)
+        np.testing.assert_array_equal(again, first)
+    u_host, _ = s.solve(x0=np.concatenate([p.x0 for p in problems]).astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(first, u_host, atol=1e-6)
+    refs = [oracle.solve(p, K=30) for p in problems]
+    compare(s, problems, refs, TOL32)
+    s.close()
