@@ -76,6 +76,8 @@ hipError_t lane_dispatch_any(int fp64, int cls, int gs, const LaneArgs* a, int n
     return hipErrorInvalidValue;
 }
 
+size_t pin_align(size_t x) { return (x + 15) / 16 * 16; }
+
 template <typename T>
 T* dmalloc(size_t n, hipError_t* err) {
     T* p = nullptr;
@@ -133,6 +135,8 @@ struct pimpc_ctx_s {
     // host copy of d_mats64, current unless device-side parameters replaced it
     std::vector<double> h_mats64;
     bool h_mats64_valid = false;
+    // pinned staging of pimpc_solve: x0 | u_prev | u0 | info (16-byte aligned parts)
+    char* h_pin = nullptr;
     void* d_state = nullptr;
     void* d_prev = nullptr;  // restart acceleration: the previous actual iterate (state layout)
     void* d_iters = nullptr;
@@ -723,6 +727,7 @@ static void destroy_ctx(pimpc_ctx ctx) {
     rel(ctx->d_ckpt);
     rel(ctx->d_tape);
     rel(ctx->d_grads);
+    if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
     rel(ctx->d_bwd_bins);
     rel(ctx->d_bwd_counters);
     for (int j = 0; j < 3; ++j) {
@@ -962,6 +967,11 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     DALLOC(ctx->d_up, char, ctx->sum_nu * ts);
     DALLOC(ctx->d_u0, char, ctx->sum_nu * ts);
     DALLOC(ctx->d_info, InfoDev, count);
+    {
+        const size_t pin = pin_align(ctx->sum_nx * 8) + 2 * pin_align(ctx->sum_nu * 8) + pin_align(count * sizeof(InfoDev));
+        e = hipHostMalloc((void**)&ctx->h_pin, pin, hipHostMallocDefault);
+        if (e != hipSuccess) return ctx->fail(PIMPC_E_NOMEM, "pinned host staging allocation failed");
+    }
     DALLOC(ctx->d_tasks, FactorTask, ctx->ntasks);
     DALLOC(ctx->d_bad, int32_t, ctx->ntasks);
     HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
@@ -1130,16 +1140,27 @@ int32_t pimpc_solve(pimpc_ctx ctx, const double* x0, const double* u_prev, doubl
     if (!finite_arr(x0, ctx->sum_nx) || (u_prev && !finite_arr(u_prev, ctx->sum_nu)))
         return ctx->fail(PIMPC_E_NONFINITE, "x0 or u_prev contains NaN or Inf");
     const hipStream_t s = ctx->stream;
-    std::vector<char> bx, bu;
-    if (ctx->fp64) {
-        to_t<double>(x0, ctx->sum_nx, bx);
-        if (u_prev) to_t<double>(u_prev, ctx->sum_nu, bu);
-    } else {
-        to_t<float>(x0, ctx->sum_nx, bx);
-        if (u_prev) to_t<float>(u_prev, ctx->sum_nu, bu);
+    // pinned staging (the call ends with a stream synchronisation, so the
+    // next call may reuse it)
+    char* px = ctx->h_pin;
+    char* pu = px + pin_align(ctx->sum_nx * 8);
+    char* po = pu + pin_align(ctx->sum_nu * 8);
+    InfoDev* pinf = (InfoDev*)(po + pin_align(ctx->sum_nu * 8));
+    for (int64_t j = 0; j < ctx->sum_nx; ++j) {
+        if (ctx->fp64)
+            ((double*)px)[j] = x0[j];
+        else
+            ((float*)px)[j] = (float)x0[j];
     }
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_x0, bx.data(), ctx->sum_nx * ctx->tsize, hipMemcpyHostToDevice, s));
-    if (u_prev) HIPCHK(ctx, hipMemcpyAsync(ctx->d_up, bu.data(), ctx->sum_nu * ctx->tsize, hipMemcpyHostToDevice, s));
+    if (u_prev)
+        for (int64_t j = 0; j < ctx->sum_nu; ++j) {
+            if (ctx->fp64)
+                ((double*)pu)[j] = u_prev[j];
+            else
+                ((float*)pu)[j] = (float)u_prev[j];
+        }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_x0, px, ctx->sum_nx * ctx->tsize, hipMemcpyHostToDevice, s));
+    if (u_prev) HIPCHK(ctx, hipMemcpyAsync(ctx->d_up, pu, ctx->sum_nu * ctx->tsize, hipMemcpyHostToDevice, s));
     const int warm = (ctx->opt.warm_start && ctx->has_state) ? 1 : 0;
     int rc = 0;
     LaunchSet* ls = get_set(ctx, ctx->d_x0, u_prev ? ctx->d_up : nullptr, ctx->d_u0, ctx->d_info, warm, 1, s, &rc);
@@ -1151,16 +1172,15 @@ int32_t pimpc_solve(pimpc_ctx ctx, const double* x0, const double* u_prev, doubl
         ctx->tape_x0 = ctx->d_x0;
         ctx->tape_up = u_prev ? ctx->d_up : nullptr;
     }
-    std::vector<char> bo(std::max<int64_t>(ctx->sum_nu, 1) * ctx->tsize);
-    std::vector<InfoDev> inf(ctx->count);
-    HIPCHK(ctx, hipMemcpyAsync(bo.data(), ctx->d_u0, ctx->sum_nu * ctx->tsize, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(inf.data(), ctx->d_info, ctx->count * sizeof(InfoDev), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(po, ctx->d_u0, ctx->sum_nu * ctx->tsize, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(pinf, ctx->d_info, ctx->count * sizeof(InfoDev), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     ctx->has_state = 1;
     if (u0_out)
         for (int64_t j = 0; j < ctx->sum_nu; ++j)
-            u0_out[j] = ctx->fp64 ? ((double*)bo.data())[j] : (double)((float*)bo.data())[j];
-    if (info) memcpy(info, inf.data(), ctx->count * sizeof(InfoDev));
+            u0_out[j] = ctx->fp64 ? ((double*)po)[j] : (double)((float*)po)[j];
+    const InfoDev* inf = pinf;
+    if (info) memcpy(info, inf, ctx->count * sizeof(InfoDev));
     for (int i = 0; i < ctx->count; ++i)
         if (inf[i].status == PIMPC_E_HIP)
             return ctx->fail(PIMPC_E_HIP, "instance %d: a wait between workgroups gave up (the grid was not "
