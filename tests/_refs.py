@@ -13,7 +13,10 @@ None of these call the oracle or share its code.  They restate the *problem*
   * eq_qp_original   equality-constrained QP of eqn. (1) in the original
                      (x, u) coordinates solved through its KKT system;
   * qp_admm          the general-QP ADMM of eqn. (3) on the sparse QP (2),
-                     an independent algorithm with the same optimum.
+                     an independent algorithm with the same optimum;
+  * accel_admm_dense Algorithm 1 with the restart acceleration of steps 6-7,
+                     run on the dense splitting with the two sub-problems
+                     above.
 """
 from __future__ import annotations
 
@@ -231,3 +234,60 @@ def qp_admm(p, rho=1.0, iters=60000, tol=1e-12):
     xs = np.array([y[D["xx"](k)] for k in range(N)])
     return dict(xs=xs, us=us, y=y, w=w, lam=lam, iters=it, E=E, H=H, f=D["f"], Ylo=Ylo, Yhi=Yhi,
                 rho=rho)
+
+
+def accel_admm_dense(p, K, eta=0.999, variant=None):
+    """Algorithm 1 with steps 6-7 (restart acceleration) on the dense
+    splitting of the proof of Theorem 2, written from the algorithm's
+    statement rather than from the stage closed forms:
+
+      p^{i+1} = argmin f(p) + rho/2 ||F p + G qhat - h + shat||^2   (dense solve)
+      q^{i+1} = argmin I_X(z) + rho/2 ||F p^{i+1} + G q - h + shat||^2 (BVLS)
+      s^{i+1} = shat + F p^{i+1} + G q^{i+1} - h
+      c^{i+1} = rho ||s^{i+1} - shat||^2 + rho ||G (q^{i+1} - qhat)||^2
+      if c^{i+1} <= eta c^i:  alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2,
+                              hat = new + (alpha - 1) / alpha' (new - previous)
+      else (restart):         alpha' = 1, hat = new (the current iterate)
+      c^i <- c^{i+1}, with c^0 = 1 and alpha_0 = 1.
+
+    Cold start.  Returns the actual iterates (q, s) after every iteration and
+    the per-iteration c and restart flags.  `variant` deliberately misreads
+    the steps, so that a test can show it would notice such a misreading:
+    "coef_next" takes (alpha' - 1) / alpha' as the coefficient,
+    "restart_prev" resets the hats to the previous iterate on a restart (the
+    reading of the pseudo-code (11)), "cprev_kept" leaves c^i unchanged on a
+    restart."""
+    D = velocity_dense(p)
+    N, nb = p.N, p.nx + p.nu
+    G = D["G"]
+    q = np.zeros(2 * N * nb)
+    s = np.zeros(3 * N * nb)
+    qh, sh = q.copy(), s.copy()
+    alpha, c_prev = 1.0, 1.0
+    qs, ss, cs, restarts = [], [], [], []
+    for _ in range(K):
+        pv = p_subproblem(D, p.rho, qh, sh)
+        qn = q_subproblem(D, p.rho, pv, sh)
+        sn = sh + D["F"] @ pv + G @ qn - D["h"]
+        c = p.rho * float(np.sum((sn - sh) ** 2)) + p.rho * float(np.sum((G @ (qn - qh)) ** 2))
+        if c <= eta * c_prev:
+            a1 = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * alpha * alpha))
+            coef = (a1 - 1.0) / a1 if variant == "coef_next" else (alpha - 1.0) / a1
+            qh = qn + coef * (qn - q)
+            sh = sn + coef * (sn - s)
+            alpha = a1
+            restarts.append(0)
+        else:
+            alpha = 1.0
+            if variant == "restart_prev":
+                qh, sh = q.copy(), s.copy()
+            else:
+                qh, sh = qn.copy(), sn.copy()
+            restarts.append(1)
+        if not (variant == "cprev_kept" and restarts[-1]):
+            c_prev = c
+        q, s = qn, sn
+        qs.append(q.copy())
+        ss.append(s.copy())
+        cs.append(c)
+    return dict(q=qs, s=ss, c=np.array(cs), restart=np.array(restarts), eta=eta)

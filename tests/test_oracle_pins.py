@@ -268,6 +268,53 @@ def test_stop_rule_and_accel_restart():
     np.testing.assert_allclose(r_acc["xs"], r_plain["xs"], atol=1e-3)
 
 
+@pytest.mark.parametrize("seed", [1, 4])
+def test_accel_restart_iterates_equal_dense_algorithm(seed):
+    """Steps 6-7 of Algorithm 1, iterate by iterate: the oracle's accelerated
+    run equals Algorithm 1 carried out on the dense splitting (dense p
+    sub-problem, BVLS q sub-problem, s update and c from F, G, h) for 300
+    iterations on a time-varying affine instance with active bounds: the same
+    restart decisions, the same c^{i+1} and the same iterate after every
+    iteration.  Three plausible misreadings of the steps (momentum
+    coefficient (alpha_{i+1} - 1) / alpha_{i+1}, a restart to the previous
+    iterate as in the pseudo-code (11), c^i kept on a restart) are shown to
+    leave this agreement, so the pin can tell them apart."""
+    p = tiny_tv_problem(seed, n=2, m=1, N=3)
+    K = 300
+    ref = _refs.accel_admm_dense(p, K)
+    run = oracle.solve(p, K=K, accel=True)
+    assert run["iters"] == K
+    flags = run["hist"][:, 3].astype(int)
+    assert flags.sum() >= 3, "the instance must restart several times"
+    assert np.any(flags[:50] == 0), "and extrapolate between restarts"
+    np.testing.assert_array_equal(flags, ref["restart"])
+    # every decision is taken with a margin far above rounding
+    c_prev = np.concatenate([[1.0], ref["c"][:-1]])
+    assert np.min(np.abs(ref["c"] - ref["eta"] * c_prev) / ref["c"]) > 1e-5
+    np.testing.assert_allclose(run["hist"][:, 0], ref["c"], rtol=1e-6, atol=1e-20)
+    for i in range(K):
+        st = oracle.solve(p, K=i + 1, accel=True)["state"]
+        q, s = _refs.state_to_qs(st)
+        np.testing.assert_allclose(q, ref["q"][i], rtol=0, atol=1e-10, err_msg=f"q after {i + 1}")
+        np.testing.assert_allclose(s, ref["s"][i], rtol=0, atol=1e-10, err_msg=f"s after {i + 1}")
+
+
+@pytest.mark.parametrize("variant", ["coef_next", "restart_prev", "cprev_kept"])
+def test_accel_pin_tells_misreadings_apart(variant):
+    """Each misreading of steps 6-7 changes the restart decisions or the
+    iterates of at least one instance of the pin above by far more than its
+    tolerance, so that pin would fail on an oracle built that way."""
+    K = 300
+    gaps = []
+    for seed in (1, 4):
+        p = tiny_tv_problem(seed, n=2, m=1, N=3)
+        ref = _refs.accel_admm_dense(p, K)
+        bad = _refs.accel_admm_dense(p, K, variant=variant)
+        gap = max(np.max(np.abs(bad["q"][i] - ref["q"][i])) for i in range(K))
+        gaps.append(gap > 1e-4 or not np.array_equal(bad["restart"], ref["restart"]))
+    assert any(gaps), variant
+
+
 def test_residuals_at_fixed_iterations_plain_fp64_problem():
     """Reference levels at the fixed 200 iterations of the 4-mass problem: the
     iteration is not converged there (r_prim ~ 1e-2), which is why GPU parity
