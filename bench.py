@@ -25,7 +25,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
+# MI355X published FP32 vector peak (FLOP/s); it needs packed FP32
+# instructions (two FMAs per lane and cycle), which this library does not use.
+PEAK_FP32_PACKED = 157.3e12
+# The rate this library can reach: 256 CUs x 4 SIMDs x 16 lanes x one FMA
+# (2 flop) per cycle at 2.4 GHz, non-packed FP32.
+PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9
 PEAK_HBM = 8.0e12           # bytes/s
 
 METRIC = "ADMM stage-iterations/s (N=1024; 4096-batch) + fwd+bwd time vs plain"
@@ -47,12 +52,27 @@ def measured_traffic():
 
 
 def stage_flops(nx: int, nu: int) -> int:
-    """Algorithmic flops of one stage-iteration of eqn. (8): 2 F(nx, nu) for
-    the mat-vecs (F = nb^2 + nu nb + 2 nx^2 + 3 nx nu FMAs) plus 25 nb for the
-    element-wise projection and dual updates."""
+    """Algorithmic flops of one stage-iteration of eqn. (8) and Algorithm 1
+    steps 1-4: 2 F(nx, nu) for the mat-vecs of steps 1-2 (F = nb^2 + nu nb
+    + 2 nx^2 + 3 nx nu FMAs, counted with the block structure of Abar, Bbar)
+    plus 45 nb for the element-wise work of steps 2-4 (the argument of the
+    projection, the projection, the three dual updates and the six squared
+    differences of c)."""
     nb = nx + nu
     F = nb * nb + nu * nb + 2 * nx * nx + 3 * nx * nu
-    return 2 * F + 25 * nb
+    return 2 * F + 45 * nb
+
+
+def check_info(P, rec, iters=None, what=""):
+    """Refuse to report a timing whose solves did not complete: every
+    instance's status must be 0 (and its iteration count `iters` when given)."""
+    import numpy as np
+    rec = np.atleast_1d(rec)
+    bad = np.nonzero(rec["status"] != 0)[0]
+    if bad.size:
+        raise RuntimeError(f"{what}: instance {int(bad[0])} ended with status {int(rec['status'][bad[0]])}")
+    if iters is not None and np.any(rec["iters"] != iters):
+        raise RuntimeError(f"{what}: an instance ran {int(rec['iters'].min())} iterations, expected {iters}")
 
 
 def time_solves(torch, fn, steps, warmup):
@@ -74,20 +94,97 @@ def time_solves(torch, fn, steps, warmup):
     return t0.elapsed_time(t1), [a.elapsed_time(b) for a, b in evs]
 
 
-def cpu_baseline(min_seconds=10.0):
+def _oracle_worker(args):
+    """One process of the all-core oracle timing: full solves of the
+    long-horizon instance until `seconds` have passed."""
+    seed, seconds = args
+    import oracle
+    from paper_2601_14414_amd import workloads as W
+    p = W.long_horizon_problem(seed=seed)
+    oracle.solve(p, K=2)  # load
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds or reps < 1:
+        oracle.solve(p)
+        reps += 1
+    return reps, time.perf_counter() - t0
+
+
+def host_threads():
+    """Host cores this process may use, at most 16 (the GPU machine's CPU share
+    for one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(single_seconds=8.0, pool_seconds=6.0):
+    """The unchanged FP64 C oracle on the host: one process (one core), then
+    one process per usable host core, each solving its own copy of the
+    workload (independent instances, as a batch would be), for a bounded
+    time; value = the all-core aggregate."""
+    import multiprocessing as mp
+    import numpy as np
     import oracle
     from paper_2601_14414_amd import workloads as W
     p = W.long_horizon_problem(seed=0)
-    oracle.solve(p, K=2)  # load
-    reps, t = 0, 0.0
-    while t < min_seconds or reps < 1:
-        t0 = time.perf_counter()
-        oracle.solve(p)
-        t += time.perf_counter() - t0
-        reps += 1
-    return {"value": p.N * p.K * reps / t, "unit": "stage-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full solves of the N=1024, 500-iteration long-horizon instance by the "
-                      f"single-threaded FP64 C oracle ({t:.1f} s)"}
+    reps1, t1 = _oracle_worker((0, single_seconds))
+    v1 = p.N * p.K * reps1 / t1
+    ncores = host_threads()
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(ncores) as pool:
+        res = pool.map(_oracle_worker, [(s, pool_seconds) for s in range(ncores)])
+    wall = time.perf_counter() - t0
+    reps = sum(r for r, _ in res)
+    vall = p.N * p.K * reps / wall
+    return {"value": vall, "unit": "stage-iterations/s", "cores": ncores, "kind": "oracle",
+            "single_core_value": v1, "host_cpus_visible": os.cpu_count(),
+            "sample": f"unchanged single-threaded FP64 C oracle, full solves of the N=1024, 500-iteration "
+                      f"long-horizon instance: {reps1} solves on one core in {t1:.1f} s; then {ncores} "
+                      f"processes (one per usable host core, x0 seeds 0..{ncores - 1}) for {pool_seconds:.0f} s: "
+                      f"{reps} solves in {wall:.1f} s wall"}
+
+
+def headline_error(p, gpu_state, gpu_u0):
+    """FP32 GPU result of the headline solve against the FP64 oracle run on
+    the same instance and iteration count: largest error of every iterate
+    (scaled by max(1, |oracle|_inf)) and of u0."""
+    import numpy as np
+    import oracle
+    r = oracle.solve(p)
+    it = max(float(np.max(np.abs(gpu_state[w] - r["state"][w])) / max(1.0, float(np.max(np.abs(r["state"][w])))))
+             for w in range(5))
+    return {"max_scaled_iterate_error": it, "u0_max_abs_error": float(np.max(np.abs(gpu_u0 - r["u0"]))),
+            "oracle_r_prim": float(r["hist"][-1][1]), "oracle_r_dual": float(r["hist"][-1][2]),
+            "tolerance": 1e-4}
+
+
+def sync_floor(torch, P, W, K, nwg_target, steps=5):
+    """Per-iteration time of the same row-family kernel over the same grid
+    of workgroups (4 compute waves each), on the narrowest stage class (a
+    2-state, 1-input system padded to 4 + 4, eight stages side by side in a
+    wave, one 8-row dot product per halo): almost no arithmetic, so this is
+    the period of the cross-workgroup cycle itself (publish, hop to the
+    neighbour's receiver wave, forward through LDS, the two halo products and
+    the update)."""
+    import numpy as np
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    N = 8 * 4 * nwg_target  # 8 stages per wave, 4 compute waves per workgroup
+    p = W.paper_random_system(2, 1, N, seed=0, K=K)
+    s = P.Solver([p], max_iter=K, precision=P.PIMPC_FP32, stream=stream, family=P.PIMPC_FAMILY_ROW)
+    x0 = torch.tensor(p.x0, dtype=torch.float32, device=dev)
+    u0 = torch.empty(p.nu, dtype=torch.float32, device=dev)
+    info = torch.zeros(40, dtype=torch.uint8, device=dev)
+    ms, per = time_solves(torch, lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream), steps, 2)
+    rec = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
+    check_info(P, rec, K, "sync_floor")
+    s.close()
+    return {"us_per_iteration": float(np.mean(per)) / K * 1e3, "workgroups": nwg_target, "N": N,
+            "workload": "2-state, 1-input random system (row class 4+4, 8 stages per wave), same grid of "
+                        "workgroups as the headline, same iteration count"}
 
 
 def bench_batch(torch, P, W, steps, warmup):
@@ -98,10 +195,14 @@ def bench_batch(torch, P, W, steps, warmup):
     import numpy as np
     x0 = torch.tensor(np.concatenate([p.x0 for p in problems]), dtype=torch.float32, device=dev)
     u0 = torch.empty(s.sum_nu, dtype=torch.float32, device=dev)
-    fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, None, stream)
+    info = torch.zeros(40 * len(problems), dtype=torch.uint8, device=dev)
+    fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream)
     ms, per = time_solves(torch, fn, steps, warmup)
+    rec = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
+    check_info(P, rec, 300, "batch_4096")
     stage_its = sum(p.N for p in problems) * 300
     flops = sum(p.N * stage_flops(p.nx, p.nu) for p in problems) * 300
+    err = batch_error(P, s, problems, u0.cpu().numpy())
     s.close()
     # the same instances one launch each (the single-instance path, graph
     # replays back to back on one stream): every 32nd instance, scaled to 4096
@@ -123,7 +224,33 @@ def bench_batch(torch, P, W, steps, warmup):
             "iterations": 300, "achieved_tflops": flops / (min(per) / 1e3) / 1e12,
             "one_launch_per_instance_ms": single_ms, "batched_speedup": single_ms / (ms / steps),
             "one_launch_per_instance_note": "128 of the instances (every 32nd) solved one launch each, "
-                                            "back to back on one stream, time scaled to 4096"}
+                                            "back to back on one stream, time scaled to 4096",
+            "error_vs_oracle": err}
+
+
+def batch_error(P, s, problems, u0_all):
+    """Largest FP32-vs-oracle error of the batch over a stratified sample (the
+    shortest and the longest instance of every (nx, nu) class present):
+    every iterate, du, xbar and u0, scaled by max(1, |oracle|_inf)."""
+    import numpy as np
+    import oracle
+    by_cls = {}
+    for i, p in enumerate(problems):
+        by_cls.setdefault((p.nx, p.nu), []).append(i)
+    pick = sorted({j for ids in by_cls.values() for j in (min(ids, key=lambda i: problems[i].N),
+                                                          max(ids, key=lambda i: problems[i].N))})
+    its = {w: s.iterate(w) for w in range(7)}
+    uoff = np.cumsum([0] + [p.nu for p in problems])
+    worst = 0.0
+    for i in pick:
+        r = oracle.solve(problems[i])
+        refs = [r["state"][w] for w in range(5)] + [r["du"], r["xs"]]
+        for w in range(7):
+            worst = max(worst, float(np.max(np.abs(its[w][i] - refs[w])) / max(1.0, np.max(np.abs(refs[w])))))
+        worst = max(worst, float(np.max(np.abs(u0_all[uoff[i]:uoff[i + 1]] - r["u0"]))
+                                 / max(1.0, np.max(np.abs(r["u0"])))))
+    return {"max_scaled_error": worst, "instances_compared": len(pick),
+            "sample": "shortest and longest instance of each (nx, nu) class; all five iterates, du, xbar, u0"}
 
 
 def bench_accel(torch, P, W, steps, warmup):
@@ -206,8 +333,10 @@ def bench_diff(torch, P, W, steps, warmup):
                                         requires_grad=g)
     x0 = f(db.x0)
     u0 = torch.empty(1024 * 3, dtype=torch.float32, device=dev)
-    ms_plain, per_plain = time_solves(torch, lambda: P.pimpc_solve_batch(plain.ctx, x0, None, u0, None, stream),
+    info = torch.zeros(40 * 1024, dtype=torch.uint8, device=dev)
+    ms_plain, per_plain = time_solves(torch, lambda: P.pimpc_solve_batch(plain.ctx, x0, None, u0, info, stream),
                                       steps, warmup)
+    check_info(P, np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE), 200, "differentiable plain")
     xq, Qd, Rd, A, B = f(db.x0, True), f(db.Qdiag, True), f(db.Rdiag, True), f(db.A, True), f(db.Bm, True)
     target = f(db.u_target)
 
@@ -222,12 +351,31 @@ def bench_diff(torch, P, W, steps, warmup):
             PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
 
     ms_f, _ = time_solves(torch, fwd_only, steps, warmup)
+    # gradient error against the oracle's reverse mode on a sample of instances
+    for t in (xq, Qd, Rd, A, B):
+        t.grad = None
+    fwd_bwd()
+    torch.cuda.synchronize()
+    import oracle
+    got = {k: t.grad.detach().cpu().numpy().astype(np.float64) for k, t in
+           dict(dx0=xq, dQd=Qd, dRd=Rd, dA=A, dB=B).items()}
+    worst = 0.0
+    sample = list(range(0, 1024, 256))
+    for i in sample:
+        pi = db.instance(i)
+        r = oracle.solve(pi)
+        g = oracle.grad(8, 3, db.N, pi.A, pi.B, db.Qdiag[i], db.Rdiag[i], pi.lb(), pi.ub(), pi.x0, pi.rho, db.K,
+                        2 * (r["u0"] - db.u_target[i]))
+        for key in ("dx0", "dQd", "dRd", "dA", "dB"):
+            worst = max(worst, float(np.max(np.abs(got[key][i] - g[key])) / max(1e-6, np.max(np.abs(g[key])))))
     plain.close()
     taped.close()
     return {"fwd_bwd_over_plain": ms_fb / ms_plain, "plain_fwd_ms": ms_plain / steps,
             "taped_fwd_ms": ms_f / steps, "fwd_bwd_ms": ms_fb / steps,
             "workload": "1024 x 4-mass chain (nx=8, nu=3), N=128, 200 iterations, checkpoints every 20, "
                         "loss sum ||u0 - u_target||^2, gradients w.r.t. x0, diag Q, diag R, A, B",
+            "gradient_error_vs_oracle": {"max_rel_error": worst, "instances": sample,
+                                         "norm": "per parameter, max |gpu - oracle| / max |oracle|"},
             "plain_stage_iterations_per_s": 1024 * 128 * 200 * steps / (ms_plain / 1e3)}
 
 
@@ -239,6 +387,8 @@ def bench_cstr(steps=21):
     import numpy as np
     from paper_2601_14414_amd import rti
     log = rti.run_cstr_nmpc(steps=steps, N=5000, iters=1000, rho=0.1)
+    if any(int(st.info["iters"][0]) != 1000 for st in log):
+        raise RuntimeError("cstr_nmpc_5000: a sample did not run 1000 iterations")
     t = np.array([st.solve_s for st in log[1:]])
     return {"median_s_per_sample": float(np.median(t)), "max_s_per_sample": float(np.max(t)),
             "stage_iterations_per_s": 5000 * 1000 / float(np.median(t)), "samples": len(t),
@@ -259,6 +409,8 @@ def bench_rti(steps=21):
     import numpy as np
     from paper_2601_14414_amd import rti
     log = rti.run_cartpole_rti(steps=steps, N=256, iters=100)
+    if any(int(st.info["iters"][0]) != 100 for st in log):
+        raise RuntimeError("rti_cartpole_256: a step did not run 100 iterations")
     lib = np.array([st.lib_s for st in log[1:]])
     step = np.array([st.step_s for st in log[1:]])
     jac = np.array([st.jac_s for st in log[1:]])
@@ -282,6 +434,8 @@ def bench_fp64_chain(torch, P, W, n):
     info = torch.zeros(40, dtype=torch.uint8, device=dev)
     fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream)
     ms, per = time_solves(torch, fn, n, 2)
+    import numpy as np
+    check_info(P, np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE), p.K, "fp64_chain_20")
     s.close()
     sol_ms = ms / n
     return {"ms_per_solve": sol_ms, "stage_iterations_per_s": p.N * p.K / (sol_ms / 1e3),
@@ -316,7 +470,10 @@ def bench_table1(torch, P, W, n_solves=10):
             s = P.Solver([p], rho=p.rho, max_iter=200, precision=P.PIMPC_FP32, stream=stream)
             x0 = torch.tensor(p.x0, dtype=torch.float32, device=dev)
             u0 = torch.empty(m, dtype=torch.float32, device=dev)
-            ms, _ = time_solves(torch, lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, None, stream), n_solves, 2)
+            info = torch.zeros(40, dtype=torch.uint8, device=dev)
+            ms, _ = time_solves(torch, lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream), n_solves, 2)
+            import numpy as np
+            check_info(P, np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE), 200, f"table1 {n},{m},{N}")
             s.close()
             out[f"n{n}_m{m}_N{N}"] = {"ms_per_iteration": ms / n_solves / 200, "paper_gpu_ms_per_iteration": gpu,
                                       "paper_cpu_ms_per_iteration": cpu, "paper_osqp_ms_per_iteration": osqp}
@@ -382,11 +539,15 @@ def main():
     fn = lambda: P.pimpc_solve_batch(s.ctx, x0, None, u0, info, stream)
     ms, per = time_solves(torch, fn, args.steps, args.warmup)
     rec = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)[0]
+    check_info(P, rec, p.K, "headline")
     stage_its = p.N * p.K
     value = stage_its * args.steps / (ms / 1e3)
     step_ms = float(np.mean(per))
     flops_per_launch = p.N * p.K * stage_flops(p.nx, p.nu)
     achieved = flops_per_launch / (step_ms / 1e3)
+    gpu_state = s.state(0)
+    gpu_u0 = u0.cpu().numpy().astype(np.float64)
+    floor = sync_floor(torch, P, W, p.K, nwg_target=p.N // 4)
     out = {
         "metric": METRIC, "value": value, "unit": "stage-iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
@@ -398,11 +559,19 @@ def main():
                    "N": p.N, "nx": p.nx, "nu": p.nu, "iterations": p.K, "instances": 1},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
-                     "kernel": "row_kernel (one solve = one launch)",
-                     "flops_per_launch": flops_per_launch, "avg_launch_ms": step_ms},
+                     "kernel": "row_kernel<24,12,1,false> (one solve = one launch)",
+                     "flops_per_launch": flops_per_launch,
+                     "flops_per_stage_iteration": stage_flops(p.nx, p.nu), "avg_launch_ms": step_ms,
+                     "peak_note": "non-packed FP32 FMA rate 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz; "
+                                  "the published 157.3 TFLOP/s needs packed FP32, which this library does not "
+                                  "use",
+                     "frac_of_published_packed_peak": achieved / PEAK_FP32_PACKED,
+                     "sync_floor": {**floor, "us_per_iteration_headline": step_ms / p.K * 1e3,
+                                    "floor_over_headline": floor["us_per_iteration"] / (step_ms / p.K * 1e3)}},
         "residuals": {"c": float(rec["c"]), "r_prim": float(rec["r_prim"]), "r_dual": float(rec["r_dual"])},
     }
     s.close()
+    out["error_vs_oracle"] = headline_error(p, gpu_state, gpu_u0)
     if not args.no_extra:
         out["batch_4096"] = bench_batch(torch, P, W, max(3, args.steps // 4), 1)
         out["differentiable_1024"] = bench_diff(torch, P, W, max(3, args.steps // 4), 1)

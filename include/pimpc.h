@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define PIMPC_VERSION 1
+#define PIMPC_VERSION 2
 
 /* status codes */
 #define PIMPC_OK 0
@@ -196,8 +196,12 @@ typedef struct {
     double c;       /* c^{i+1} of Algorithm 1 step 4                      */
     double r_prim;  /* ||s^{i+1} - s^i||_inf   (primal residual)         */
     double r_dual;  /* rho ||F'G(q^{i+1}-q^i)||_inf   (dual residual)    */
-    int32_t status; /* PIMPC_OK, PIMPC_E_NONFINITE, or PIMPC_E_HIP when a
-                       row-family wait between workgroups gave up         */
+    int32_t status; /* PIMPC_OK; PIMPC_E_NOT_PSD when a stage matrix of the
+                       instance's last factorisation (setup, linearize or
+                       set_params_dev) was not SPD: its iterates are then
+                       meaningless; PIMPC_E_NONFINITE when an iterate became
+                       NaN/Inf; PIMPC_E_HIP when a row-family wait between
+                       workgroups gave up                                  */
     int32_t pad;
 } pimpc_info;
 
@@ -222,7 +226,13 @@ int32_t pimpc_setup(pimpc_ctx *out, const pimpc_problem *prob, const pimpc_optio
  * precision either way) and re-run the FP64 stage factorisation.  Iterates are
  * kept, so the next solve can warm-start: this is the construction-free
  * update of online-linearised / RTI NMPC (Sections I and II).  e may be NULL.
- * Synchronous.
+ * Synchronous.  Device pointers are read by a kernel on the context's stream
+ * (so they may be produced by earlier work on that stream, with no host round
+ * trip); host pointers are validated before anything changes.  Returns
+ * PIMPC_E_NONFINITE for NaN/Inf data and PIMPC_E_NOT_PSD when a stage matrix
+ * is not SPD; after such a failure of a device import the context holds the
+ * rejected data, and its solves report PIMPC_E_NOT_PSD (or non-finite
+ * iterates) until a valid linearize.  Invalidates the tape (pimpc_tape_id).
  */
 int32_t pimpc_linearize(pimpc_ctx ctx, const double *A, const double *B, const double *e,
                         int32_t mem_kind);
@@ -250,25 +260,62 @@ int32_t pimpc_solve_batch(pimpc_ctx ctx, const void *x0_dev, const void *uprev_d
                           void *u0_dev, pimpc_info *info_dev, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as pimpc_solve_batch (same arguments, kernels and results), launched
+ * directly on `hip_stream` (never captured into a graph by the library).
+ * Every per-call buffer the kernels use -- the kernel arguments, the lane
+ * classes' bin counters, the row family's halo mailboxes, abort flag and
+ * reduction words -- lives in one static device array of
+ * PIMPC_NOALLOC_SCRATCH_BYTES per GPU (held from library load until the
+ * process ends) instead of memory the library allocates; the call makes no
+ * hipMalloc, hipFree or other allocating call.  What must start at zero is
+ * cleared by the call itself (with fill kernels).  Contexts whose per-call
+ * scratch exceeds the array (large row-family horizons) get PIMPC_E_DIM;
+ * a context used on another device than the one current at its setup gets
+ * PIMPC_E_STATE.  All calls on one GPU share the array, so calls that overlap
+ * in time on one GPU race (whatever their contexts or streams): order them,
+ * e.g. on one stream.
+ */
+#define PIMPC_NOALLOC_SCRATCH_BYTES (4u << 20)
+int32_t pimpc_solve_batch_noalloc(pimpc_ctx ctx, const void *x0_dev, const void *uprev_dev,
+                                  void *u0_dev, pimpc_info *info_dev, void *hip_stream);
+
+/*
  * Replace per-instance time-invariant parameters from device memory in the
  * context's precision and re-run the factorisation on the device:
  *   A [count][nx][nx], B [count][nx][nu], Qdiag [count][nx], Rdiag [count][nu]
  * (Q and R become diagonal).  Requires equal nx and nu across instances and a
- * time-invariant context.  Asynchronous on `hip_stream`.
+ * time-invariant context.  Asynchronous on `hip_stream`: a stage matrix that
+ * is not SPD (e.g. a negative Qdiag) is not reported here but by every later
+ * solve of that instance, as status PIMPC_E_NOT_PSD in its info record (and
+ * as the return value of pimpc_solve).  Invalidates the tape.
  */
 int32_t pimpc_set_params_dev(pimpc_ctx ctx, const void *A, const void *B, const void *Qdiag,
                              const void *Rdiag, void *hip_stream);
 
 /*
- * Reverse mode through the unrolled iterations of the last taped
- * pimpc_solve_batch (needs opts.ckpt_every > 0, otherwise PIMPC_E_STATE).
+ * Id of the tape the context holds: each taped forward (a solve with
+ * opts.ckpt_every > 0) records a new tape with a new id (1, 2, ...); a later
+ * taped forward, pimpc_linearize or pimpc_set_params_dev replaces or
+ * invalidates it.  0 when there is none (or ctx is NULL).
+ */
+uint64_t pimpc_tape_id(pimpc_ctx ctx);
+
+/*
+ * Reverse mode through the unrolled iterations of the taped forward whose
+ * pimpc_tape_id() was `tape_id` (the differentiable layer; the adjoint of
+ * Algorithm 1 steps 1-3, not in the paper).  PIMPC_E_STATE when the context
+ * has no tape (opts.ckpt_every = 0, no taped solve yet) or when `tape_id` is
+ * not the current tape (another taped forward or a parameter update came
+ * after it: its gradients can no longer be formed).
  * Given dL/du0 (count x nu, device, context precision), writes dL/dx0
  * (count x nx), dL/dQdiag (count x nx), dL/dRdiag (count x nu),
  * dL/dA (count x nx x nx) and dL/dB (count x nx x nu); any output may be
  * NULL.  The loss sees u0 = du_0 of the K-th step 1, a cold start and
  * u_prev = 0.  Asynchronous on `hip_stream`.
  */
-int32_t pimpc_backward(pimpc_ctx ctx, const void *dL_du0_dev, void *dx0, void *dQdiag,
+int32_t pimpc_backward(pimpc_ctx ctx, uint64_t tape_id, const void *dL_du0_dev, void *dx0, void *dQdiag,
                        void *dRdiag, void *dA, void *dB, void *hip_stream);
 
 /*

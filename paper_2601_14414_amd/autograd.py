@@ -26,7 +26,17 @@ class PiMPCFunction(torch.autograd.Function):
         x0c, Qc, Rc, Ac, Bc = (t.detach().contiguous().float() for t in (x0, Qdiag, Rdiag, A, B))
         P.pimpc_set_params_dev(solver.ctx, Ac, Bc, Qc, Rc, stream)
         u0 = torch.empty(solver.count * solver.nu, dtype=torch.float32, device=x0.device)
-        P.pimpc_solve_batch(solver.ctx, x0c, None, u0, None, stream)
+        info = torch.empty(solver.count * (P.INFO_DTYPE.itemsize // 4), dtype=torch.int32, device=x0.device)
+        P.pimpc_solve_batch(solver.ctx, x0c, None, u0, info, stream)
+        ctx.tape_id = P.pimpc_tape_id(solver.ctx)
+        # a stage matrix that is not SPD (e.g. a negative weight) is reported
+        # through the per-instance status of the info records
+        status = info.view(solver.count, -1)[:, P.INFO_DTYPE.fields["status"][1] // 4]
+        bad = torch.nonzero(status).flatten()
+        if bad.numel() > 0:
+            i = int(bad[0])
+            raise P.PimpcError(int(status[i]), f"instance {i} of the differentiable batch failed "
+                                               f"({'stage matrix not SPD' if int(status[i]) == P.PIMPC_E_NOT_PSD else 'non-finite iterate'})")
         ctx.solver = solver
         ctx.save_for_backward(x0c, Qc, Rc, Ac, Bc)  # keep the forward's inputs alive
         return u0.view(solver.count, solver.nu)
@@ -42,7 +52,7 @@ class PiMPCFunction(torch.autograd.Function):
         dR = torch.empty_like(Rc)
         dA = torch.empty_like(Ac)
         dB = torch.empty_like(Bc)
-        P.pimpc_backward(solver.ctx, g, dx0, dQ, dR, dA, dB, stream)
+        P.pimpc_backward(solver.ctx, ctx.tape_id, g, dx0, dQ, dR, dA, dB, stream)
         return dx0, dQ, dR, dA, dB, None
 
 

@@ -750,7 +750,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             r.c = c_last;
             r.r_prim = rp_last;
             r.r_dual = rd_last;
-            r.status = status;
+            r.status = (a.fbad && a.fbad[inst_idx]) ? -3 : status;  // -3: the factorisation failed (not SPD)
             r.pad = 0;
             ((gptr<InfoDev>)a.info)[inst_idx] = r;
         }

@@ -387,9 +387,9 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     const double rho_d = keep_sgpr(a.rho);
     const int check_every = keep_sgpr(a.check_every);
 
-    const gptr<char> sbase = (gptr<char>)((char*)a.scratch + (size_t)I.row_scr16 * 16);
+    const gptr<char> sbase = (gptr<char>)(char*)a.scratch;
     RowScratch sc = row_scratch(sbase, nwaves, NB);
-    const gptr<const float> F = (gptr<const float>)(sbase + row_clear_size(N, NB));  // same offset as the host side
+    const gptr<const float> F = (gptr<const float>)(const float*)a.fused;
     const FusedOffsets fo = fused_offsets(NB);
 
     float(*bc)[LD] = (float(*)[LD])(row_smem + (size_t)wv * NV * LD);
@@ -1060,7 +1060,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         rec.c = c_last;
         rec.r_prim = rp_last;
         rec.r_dual = rd_last;
-        rec.status = status;
+        rec.status = (a.fbad && a.fbad[a.inst_idx]) ? -3 : status;  // -3: the factorisation failed (not SPD)
         rec.pad = 0;
         a.info[a.inst_idx] = rec;
     }
@@ -1173,12 +1173,11 @@ bool row_supported(int nx, int nu, int N, int tv, int fp64, int* nxp, int* nup) 
     return false;
 }
 
-size_t row_scratch_bytes(const InstDev& I, int fp64) {
-    (void)fp64;
-    // sized for one stage per wave, plus the fused stage data (one block per
-    // stage when the stage data is time-varying)
-    return align16(row_clear_size(I.N, I.nbp)) + align16(4 * row_fused_floats(I.nbp) * (I.tv ? I.N : 1));
-}
+// Per-solve scratch sized for one stage per wave (an upper bound for every
+// blocking); fused stage data, one block per stage when the stage data is
+// time-varying.
+size_t row_clear_bytes(const InstDev& I) { return align16(row_clear_size(I.N, I.nbp)); }
+size_t row_fused_bytes(const InstDev& I) { return align16(4 * row_fused_floats(I.nbp) * (I.tv ? I.N : 1)); }
 
 // Choose the blocking S (stages per wave): the smallest S whose grid stays
 // co-resident (every workgroup must be running for the halo waits to end).
@@ -1200,24 +1199,22 @@ hipError_t row_prepare(int fp64, InstDev& I) {
     return hipErrorInvalidConfiguration;
 }
 
-hipError_t launch_row_fuse(const InstDev* d_inst, int inst_idx, const InstDev& I, const void* mats,
-                           void* scratch_base, hipStream_t s) {
+hipError_t launch_row_fuse(const InstDev* d_inst, int inst_idx, const InstDev& I, const void* mats, void* fused,
+                           hipStream_t s) {
     if (I.nbp > kFuseMax) return hipErrorInvalidValue;
-    char* scr = (char*)scratch_base + (size_t)I.row_scr16 * 16;
-    float* fused = (float*)(scr + row_clear_size(I.N, I.nbp));
     if (I.tv)
         hipLaunchKernelGGL(row_fuse_tv_kernel, dim3(I.N), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats,
-                           fused);
+                           (float*)fused);
     else
-        hipLaunchKernelGGL(row_fuse_kernel, dim3(1), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats, fused);
+        hipLaunchKernelGGL(row_fuse_kernel, dim3(1), dim3(256), 0, s, d_inst, inst_idx, (const float*)mats,
+                           (float*)fused);
     return hipGetLastError();
 }
 
-hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, void* scratch_base, hipStream_t s) {
+hipError_t launch_row(int fp64, const RowArgs* a_dev, const InstDev& I, void* scratch, hipStream_t s) {
     (void)fp64;
     const int S = I.row_s > 0 ? I.row_s : 1;
-    char* scr = (char*)scratch_base + (size_t)I.row_scr16 * 16;
-    hipError_t e = launch_fill<int32_t>((int32_t*)scr, (int64_t)(row_clear_size(I.N, I.nbp) / 4), 0, s);
+    hipError_t e = launch_fill<int32_t>((int32_t*)scratch, (int64_t)(row_clear_size(I.N, I.nbp) / 4), 0, s);
     if (e != hipSuccess) return e;
     return row_launch_any(I, S, a_dev, s, nullptr);
 }

@@ -19,6 +19,8 @@
 // hipMemsetAsync so the launch sequence can be graph-captured).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "pimpc_dev.hpp"
 
 namespace pimpc {
@@ -73,7 +75,7 @@ __global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ 
                                                     const FactorTask* __restrict__ tasks,
                                                     const double* __restrict__ mats64,
                                                     T* __restrict__ mats, double rho,
-                                                    int32_t* __restrict__ bad) {
+                                                    int32_t* __restrict__ bad, int32_t* __restrict__ ibad) {
     __shared__ double M[kMaxNb * kLd];
     const FactorTask tk = tasks[blockIdx.x];
     const InstDev I = inst[tk.inst];
@@ -109,7 +111,10 @@ __global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ 
         }
         __syncthreads();
         const bool ok = lds_cholesky(M, NB);
-        if (!ok && t == 0) bad[blockIdx.x] = 1;
+        if (!ok && t == 0) {
+            bad[blockIdx.x] = 1;
+            ibad[tk.inst] = 1;
+        }
         if (t < NB) {
             double x[kMaxNb];
             for (int i = 0; i < NB; ++i) x[i] = (i == t) ? 1.0 : 0.0;
@@ -136,7 +141,10 @@ __global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ 
         }
         __syncthreads();
         const bool ok = lds_cholesky(M, NU);
-        if (!ok && t == 0) bad[blockIdx.x] = 1;
+        if (!ok && t == 0) {
+            bad[blockIdx.x] = 1;
+            ibad[tk.inst] = 1;
+        }
         if (t < NB) {
             double x[kMaxNb];
             for (int i = 0; i < NU; ++i) x[i] = (t < NX) ? Bk[t * NU + i] : ((t - NX) == i ? 1.0 : 0.0);
@@ -216,6 +224,90 @@ __global__ void params_kernel(const InstDev* __restrict__ inst, int count, const
     }
 }
 
+// Construction-free update from device memory: copy the caller's packed
+// stage data (A_k, B_k, e_k at real sizes, row-major, per instance at the
+// packed offsets pk[3 i + 0..2]) into the padded FP64 block; padded entries
+// are zero.  Any non-finite value sets *nonfinite.  Grid (blocks, count).
+__global__ void stage_import_kernel(const InstDev* __restrict__ inst, int count, const int64_t* __restrict__ pk,
+                                    const double* __restrict__ A, const double* __restrict__ B,
+                                    const double* __restrict__ e, double* __restrict__ mats64,
+                                    int32_t* __restrict__ nonfinite) {
+    const int i = blockIdx.y;
+    if (i >= count) return;
+    const InstDev I = inst[i];
+    const int nx = I.nx, nu = I.nu, NX = I.nxp, NU = I.nup, N = I.N;
+    const MatOffsets o = mat_offsets(NX, NU, N, I.tv);
+    double* b64 = mats64 + I.mat64_off;
+    const int S = I.tv ? N : 1;
+    const int per = NX * NX + NX * NU + NX;
+    const int64_t total = (int64_t)S * per;
+    const double* Ai = A + pk[3 * i + 0];
+    const double* Bi = B + pk[3 * i + 1];
+    const double* ei = e ? e + pk[3 * i + 2] : nullptr;
+    bool bad = false;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(idx / per);
+        const int q = (int)(idx % per);
+        double val = 0.0;
+        int64_t dst;
+        if (q < NX * NX) {
+            const int r = q / NX, c = q % NX;
+            if (r < nx && c < nx) val = Ai[(int64_t)k * nx * nx + r * nx + c];
+            dst = o.A64 + (int64_t)k * NX * NX + q;
+        } else if (q < NX * NX + NX * NU) {
+            const int qq = q - NX * NX;
+            const int r = qq / NU, c = qq % NU;
+            if (r < nx && c < nu) val = Bi[(int64_t)k * nx * nu + r * nu + c];
+            dst = o.B64 + (int64_t)k * NX * NU + qq;
+        } else {
+            const int r = q - NX * NX - NX * NU;
+            if (ei && r < nx) val = ei[(int64_t)k * nx + r];
+            dst = o.e64 + (int64_t)k * NX + r;
+        }
+        if (!isfinite(val)) bad = true;
+        b64[dst] = val;
+    }
+    if (bad) *nonfinite = 1;
+}
+
+hipError_t launch_stage_import(const InstDev* inst, int count, const int64_t* pk, const double* A,
+                               const double* B, const double* e, double* mats64, int32_t* nonfinite,
+                               hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stage_import_kernel, dim3(8, count), dim3(256), 0, s, inst, count, pk, A, B, e, mats64,
+                       nonfinite);
+    return hipGetLastError();
+}
+
+// Host bytes handed to the device as a kernel argument (the kernel argument
+// block is copied at launch, and at capture time under graph capture), so a
+// caller that may not allocate can still place small structures in device
+// memory: one launch per chunk.
+constexpr uint32_t kByteChunk = 3072;
+struct ByteChunk {
+    uint32_t n;
+    uint32_t pad;
+    unsigned char b[kByteChunk];
+};
+
+__global__ void __launch_bounds__(256) bytes_store_kernel(ByteChunk c, unsigned char* __restrict__ dst) {
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.b[i];
+}
+
+hipError_t launch_bytes_store(void* dst, const void* src, size_t n, hipStream_t s) {
+    for (size_t off = 0; off < n; off += kByteChunk) {
+        ByteChunk c;
+        c.n = (uint32_t)(n - off < kByteChunk ? n - off : kByteChunk);
+        c.pad = 0;
+        memcpy(c.b, (const unsigned char*)src + off, c.n);
+        hipLaunchKernelGGL(bytes_store_kernel, dim3(1), dim3(256), 0, s, c, (unsigned char*)dst + off);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -227,10 +319,10 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
 
 template <typename T>
 hipError_t launch_factor(const InstDev* inst, const FactorTask* tasks, int ntasks, const double* mats64,
-                         T* mats, double rho, int32_t* bad, hipStream_t s) {
+                         T* mats, double rho, int32_t* bad, int32_t* ibad, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(factor_kernel<T>, dim3(ntasks), dim3(64), 0, s, inst, tasks, mats64, mats, rho,
-                       bad);
+                       bad, ibad);
     return hipGetLastError();
 }
 
@@ -259,9 +351,10 @@ hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {
 }
 
 template hipError_t launch_factor<float>(const InstDev*, const FactorTask*, int, const double*, float*,
-                                         double, int32_t*, hipStream_t);
+                                         double, int32_t*, int32_t*, hipStream_t);
 template hipError_t launch_factor<double>(const InstDev*, const FactorTask*, int, const double*, double*,
-                                          double, int32_t*, hipStream_t);
+                                          double, int32_t*, int32_t*, hipStream_t);
+
 template hipError_t launch_expand<float>(const InstDev*, int, const double*, float*, hipStream_t);
 template hipError_t launch_expand<double>(const InstDev*, int, const double*, double*, hipStream_t);
 template hipError_t launch_params<float>(const InstDev*, int, const float*, const float*, const float*,

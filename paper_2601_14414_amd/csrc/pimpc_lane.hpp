@@ -35,6 +35,7 @@ struct LaneArgs {
     int32_t pad_;
     double eta;          // restart threshold
     void* prev;          // accel: previous actual iterate (T, state layout)
+    const int32_t* fbad; // per instance: non-zero when its stage factorisation failed (not SPD)
 };
 
 // gs != 0 selects the kernel variant that projects onto non-box sets.

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,8 +26,11 @@
 
 namespace pimpc {
 template <typename T>
-hipError_t launch_factor(const InstDev*, const FactorTask*, int, const double*, T*, double, int32_t*,
+hipError_t launch_factor(const InstDev*, const FactorTask*, int, const double*, T*, double, int32_t*, int32_t*,
                          hipStream_t);
+hipError_t launch_stage_import(const InstDev*, int, const int64_t*, const double*, const double*, const double*,
+                               double*, int32_t*, hipStream_t);
+hipError_t launch_bytes_store(void*, const void*, size_t, hipStream_t);
 template <typename T>
 hipError_t launch_expand(const InstDev*, int, const double*, T*, hipStream_t);
 template <typename T>
@@ -88,6 +92,41 @@ T* dmalloc(size_t n, hipError_t* err) {
 
 }  // namespace
 
+// ---------------------------------------------- scratch of the no-alloc solve
+//
+// pimpc_solve_batch_noalloc keeps every per-call buffer (kernel arguments,
+// bin counters, row-family mailboxes and reduction words) in this array
+// instead of memory the library allocates.  Each GPU holds its own copy, at
+// its own address, from module load until the process ends.  Host code never
+// passes `scratch` itself (on the host it only names the symbol): the device
+// address is looked up once per device with hipGetSymbolAddress, at the first
+// pimpc_setup on that device, and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[PIMPC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once).
+hipError_t scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_dev[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = ptr;
+    return hipSuccess;
+}
+
+void* scratch_dev(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_dev[dev];
+}
+}  // namespace
+
 // One distinct argument set of the batched launch sequence (device copies
 // of the per-class kernel arguments and, once captured, its graph).
 struct LaunchSet {
@@ -102,7 +141,12 @@ struct LaunchSet {
     RowArgs* d_rargs = nullptr;  // one per row-family instance
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;  // for the least-recently-used eviction of the set cache
 };
+
+// Distinct argument sets (each with its device arguments and graph) a
+// context keeps; the least recently used one is released beyond this.
+constexpr size_t kMaxLaunchSets = 8;
 
 struct ClassRun {
     int cls = 0;
@@ -116,6 +160,7 @@ struct ClassRun {
 
 struct pimpc_ctx_s {
     std::string err;
+    int device = 0;  // the device current at pimpc_setup
     hipStream_t stream = nullptr;
     hipStream_t aux[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr;
@@ -146,13 +191,18 @@ struct pimpc_ctx_s {
     InfoDev* d_info = nullptr;
     FactorTask* d_tasks = nullptr;
     int ntasks = 0;
-    int32_t* d_bad = nullptr;
+    int32_t* d_bad = nullptr;       // per factorisation task: not SPD
+    int32_t* d_ibad = nullptr;      // per instance: some stage matrix not SPD (read by the solve kernels)
+    int32_t* d_nonfinite = nullptr; // device stage import saw NaN/Inf
+    int64_t* d_pack_off = nullptr;  // per instance: offsets of A, B, e in the caller's packed arrays
     Bin* d_bins = nullptr;
     int32_t* d_counters = nullptr;
     std::vector<ClassRun> runs;
     std::vector<int> row_insts;  // instances handled by the row family
-    void* d_row_scratch = nullptr;
-    size_t row_scratch_bytes = 0;
+    void* d_row_clear = nullptr;   // per-solve scratch of the row-family instances (cleared every solve)
+    void* d_row_fused = nullptr;   // fused stage data of the row-family instances
+    std::vector<size_t> row_clear_off, row_fused_off;  // per row-family instance (bytes)
+    size_t row_clear_total = 0;
     int schedule = 1;            // 1 = dynamic counter, 2 = static striding
     int nstreams = 1;
     int has_state = 0;
@@ -164,7 +214,11 @@ struct pimpc_ctx_s {
     Bin* d_bwd_bins = nullptr;
     int32_t* d_bwd_counters = nullptr;
     std::vector<ClassRun> bwd_runs;
-    int taped = 0;
+    uint64_t tape_id = 0;    // id of the tape pimpc_backward may use (0: none)
+    uint64_t tape_count = 0; // taped forwards so far (ids are 1, 2, ...)
+    uint64_t set_clock = 0;  // launch-set use counter
+    std::vector<LaneArgs> na_args;  // host staging of pimpc_solve_batch_noalloc's arguments
+    std::vector<RowArgs> na_rargs;
     const void* tape_x0 = nullptr;
     const void* tape_up = nullptr;
 
@@ -340,9 +394,11 @@ static int upload_t_block(pimpc_ctx ctx, const double* qbar, const double* xmin,
 
 // Fused stage data of the row-family instances (once their scratch exists).
 static hipError_t fuse_rows(pimpc_ctx ctx, hipStream_t s) {
-    if (!ctx->d_row_scratch) return hipSuccess;
-    for (int i : ctx->row_insts) {
-        hipError_t e = launch_row_fuse(ctx->d_inst, i, ctx->inst[i], ctx->d_mats, ctx->d_row_scratch, s);
+    if (!ctx->d_row_fused) return hipSuccess;
+    for (size_t j = 0; j < ctx->row_insts.size(); ++j) {
+        const int i = ctx->row_insts[j];
+        hipError_t e = launch_row_fuse(ctx->d_inst, i, ctx->inst[i], ctx->d_mats,
+                                       (char*)ctx->d_row_fused + ctx->row_fused_off[j], s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -352,14 +408,15 @@ static hipError_t fuse_rows(pimpc_ctx ctx, hipStream_t s) {
 static int refactor(pimpc_ctx ctx, bool sync_check) {
     hipStream_t s = ctx->stream;
     HIPCHK(ctx, launch_fill<int32_t>(ctx->d_bad, std::max(ctx->ntasks, 1), 0, s));
+    HIPCHK(ctx, launch_fill<int32_t>(ctx->d_ibad, ctx->count, 0, s));
     if (ctx->fp64) {
         HIPCHK(ctx, launch_expand<double>(ctx->d_inst, ctx->count, ctx->d_mats64, (double*)ctx->d_mats, s));
         HIPCHK(ctx, launch_factor<double>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->d_mats64,
-                                          (double*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, s));
+                                          (double*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, ctx->d_ibad, s));
     } else {
         HIPCHK(ctx, launch_expand<float>(ctx->d_inst, ctx->count, ctx->d_mats64, (float*)ctx->d_mats, s));
         HIPCHK(ctx, launch_factor<float>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->d_mats64,
-                                         (float*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, s));
+                                         (float*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, ctx->d_ibad, s));
     }
     HIPCHK(ctx, fuse_rows(ctx, s));
     if (sync_check) {
@@ -438,8 +495,20 @@ static int class_grid(pimpc_ctx ctx, const ClassRun& r) {
     return std::max(1, std::min(r.nbins, cap));
 }
 
-static int fill_set_args(pimpc_ctx ctx, LaunchSet* ls) {
-    std::vector<LaneArgs> args(ctx->runs.size());
+// Where the per-solve scratch of a launch lives: the bin counters of the lane
+// classes and the per-solve part of every row-family instance's scratch.
+struct SolveScratch {
+    int32_t* counters;
+    char* row_clear;  // row-family instance j at row_clear + ctx->row_clear_off[j]
+};
+
+static SolveScratch ctx_scratch(pimpc_ctx ctx) { return {ctx->d_counters, (char*)ctx->d_row_clear}; }
+
+// Kernel arguments of one batched solve (host copies).
+static void build_args(pimpc_ctx ctx, const void* x0, const void* up, void* u0, void* info, int warm,
+                       int write_iters, const SolveScratch& sc, std::vector<LaneArgs>& args,
+                       std::vector<RowArgs>& rargs) {
+    args.assign(ctx->runs.size(), LaneArgs{});
     for (size_t c = 0; c < ctx->runs.size(); ++c) {
         const ClassRun& r = ctx->runs[c];
         LaneArgs& a = args[c];
@@ -447,54 +516,76 @@ static int fill_set_args(pimpc_ctx ctx, LaunchSet* ls) {
         a.inst = ctx->d_inst;
         a.bins = ctx->d_bins + r.bin_first;
         a.nbins = r.nbins;
-        a.bin_counter = (ctx->schedule == 1) ? ctx->d_counters + c : nullptr;
+        a.bin_counter = (ctx->schedule == 1) ? sc.counters + c : nullptr;
         a.mats = ctx->d_mats;
         a.state = ctx->d_state;
         a.iters_out = ctx->d_iters;
-        a.x0 = ls->x0;
-        a.uprev = ls->up;
-        a.u0 = ls->u0;
-        a.info = (InfoDev*)ls->info;
+        a.x0 = x0;
+        a.uprev = up;
+        a.u0 = u0;
+        a.info = (InfoDev*)info;
         a.rho = ctx->opt.rho;
         a.eps = ctx->opt.eps;
         a.K = ctx->opt.max_iter;
         a.check_every = ctx->opt.check_every;
-        a.warm = ls->warm;
+        a.warm = warm;
         a.nbmax = r.nbmax;
-        a.write_iters = ls->write_iters;
+        a.write_iters = write_iters;
         a.ckpt_every = ctx->opt.ckpt_every;
         a.ckpt = ctx->d_ckpt;
         a.accel = ctx->opt.accel;
         a.eta = ctx->opt.eta;
         a.prev = ctx->d_prev;
+        a.fbad = ctx->d_ibad;
     }
+    rargs.assign(ctx->row_insts.size(), RowArgs{});
+    for (size_t j = 0; j < ctx->row_insts.size(); ++j) {
+        RowArgs& a = rargs[j];
+        memset(&a, 0, sizeof(a));
+        a.inst = ctx->d_inst;
+        a.inst_idx = ctx->row_insts[j];
+        a.mats = ctx->d_mats;
+        a.state = ctx->d_state;
+        a.iters_out = ctx->d_iters;
+        a.x0 = x0;
+        a.uprev = up;
+        a.u0 = u0;
+        a.info = (InfoDev*)info;
+        a.rho = ctx->opt.rho;
+        a.eps = ctx->opt.eps;
+        a.K = ctx->opt.max_iter;
+        a.check_every = ctx->opt.check_every;
+        a.warm = warm;
+        a.write_iters = write_iters;
+        a.scratch = sc.row_clear + ctx->row_clear_off[j];
+        a.fused = (const char*)ctx->d_row_fused + ctx->row_fused_off[j];
+        a.fbad = ctx->d_ibad;
+    }
+}
+
+static int fill_set_args(pimpc_ctx ctx, LaunchSet* ls) {
+    std::vector<LaneArgs> args;
+    std::vector<RowArgs> rargs;
+    build_args(ctx, ls->x0, ls->up, ls->u0, ls->info, ls->warm, ls->write_iters, ctx_scratch(ctx), args, rargs);
     if (!args.empty())
         HIPCHK(ctx, hipMemcpy(ls->d_args, args.data(), args.size() * sizeof(LaneArgs), hipMemcpyHostToDevice));
-    if (!ctx->row_insts.empty()) {
-        std::vector<RowArgs> rargs(ctx->row_insts.size());
-        for (size_t j = 0; j < ctx->row_insts.size(); ++j) {
-            RowArgs& a = rargs[j];
-            memset(&a, 0, sizeof(a));
-            a.inst = ctx->d_inst;
-            a.inst_idx = ctx->row_insts[j];
-            a.mats = ctx->d_mats;
-            a.state = ctx->d_state;
-            a.iters_out = ctx->d_iters;
-            a.x0 = ls->x0;
-            a.uprev = ls->up;
-            a.u0 = ls->u0;
-            a.info = (InfoDev*)ls->info;
-            a.rho = ctx->opt.rho;
-            a.eps = ctx->opt.eps;
-            a.K = ctx->opt.max_iter;
-            a.check_every = ctx->opt.check_every;
-            a.warm = ls->warm;
-            a.write_iters = ls->write_iters;
-            a.scratch = ctx->d_row_scratch;
-        }
+    if (!rargs.empty())
         HIPCHK(ctx, hipMemcpy(ls->d_rargs, rargs.data(), rargs.size() * sizeof(RowArgs), hipMemcpyHostToDevice));
-    }
     return PIMPC_OK;
+}
+
+static void release_set(LaunchSet* ls) {
+    // a graph launch of this set may still run on its stream
+    if (ls->stream) (void)hipStreamSynchronize(ls->stream);
+    else (void)hipDeviceSynchronize();
+    if (ls->exec) (void)hipGraphExecDestroy(ls->exec);
+    if (ls->graph) (void)hipGraphDestroy(ls->graph);
+    if (ls->d_args) (void)hipFree(ls->d_args);
+    if (ls->d_rargs) (void)hipFree(ls->d_rargs);
+    ls->exec = nullptr;
+    ls->graph = nullptr;
+    ls->d_args = nullptr;
+    ls->d_rargs = nullptr;
 }
 
 static LaunchSet* get_set(pimpc_ctx ctx, const void* x0, const void* up, void* u0, void* info, int warm,
@@ -502,10 +593,20 @@ static LaunchSet* get_set(pimpc_ctx ctx, const void* x0, const void* up, void* u
     for (auto& p : ctx->sets) {
         LaunchSet* ls = p.get();
         if (ls->x0 == x0 && ls->up == up && ls->u0 == u0 && ls->info == info && ls->warm == warm &&
-            ls->write_iters == write_iters && ls->stream == s)
+            ls->write_iters == write_iters && ls->stream == s) {
+            ls->last_use = ++ctx->set_clock;
             return ls;
+        }
+    }
+    if (ctx->sets.size() >= kMaxLaunchSets) {  // release the least recently used set
+        size_t lru = 0;
+        for (size_t j = 1; j < ctx->sets.size(); ++j)
+            if (ctx->sets[j]->last_use < ctx->sets[lru]->last_use) lru = j;
+        release_set(ctx->sets[lru].get());
+        ctx->sets.erase(ctx->sets.begin() + lru);
     }
     auto ls = std::make_unique<LaunchSet>();
+    ls->last_use = ++ctx->set_clock;
     ls->x0 = x0;
     ls->up = up;
     ls->u0 = u0;
@@ -539,10 +640,12 @@ static void free_set_graphs(pimpc_ctx ctx) {
     }
 }
 
-// Enqueue the whole batched ADMM launch sequence on `s`.
-static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
+// Enqueue the whole batched ADMM launch sequence on `s`, with the kernel
+// arguments at d_args / d_rargs (device) and the per-solve scratch `sc`.
+static int enqueue_launches(pimpc_ctx ctx, const LaneArgs* d_args, const RowArgs* d_rargs, const SolveScratch& sc,
+                            hipStream_t s) {
     const int ncls = (int)ctx->runs.size();
-    if (ctx->schedule == 1 && ncls > 0) HIPCHK(ctx, launch_fill<int32_t>(ctx->d_counters, ncls, 0, s));
+    if (ctx->schedule == 1 && ncls > 0) HIPCHK(ctx, launch_fill<int32_t>(sc.counters, ncls, 0, s));
     // A row-family kernel needs every workgroup of its grid resident at once
     // (its halo waits cross workgroups).  Beside another row kernel each
     // could hold part of the GPU and wait for the rest; beside a long lane
@@ -550,7 +653,8 @@ static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
     // polls allow.  So the row-family instances run first, one after the
     // other on the first stream, and the lane classes start after them.
     for (size_t rj = 0; rj < ctx->row_insts.size(); ++rj)
-        HIPCHK(ctx, launch_row(ctx->fp64, ls->d_rargs + rj, ctx->inst[ctx->row_insts[rj]], ctx->d_row_scratch, s));
+        HIPCHK(ctx, launch_row(ctx->fp64, d_rargs + rj, ctx->inst[ctx->row_insts[rj]],
+                               sc.row_clear + ctx->row_clear_off[rj], s));
     const int ns = std::min(ctx->nstreams, std::max(1, ncls));
     if (ns > 1) {
         HIPCHK(ctx, hipEventRecord(ctx->ev_fork, s));
@@ -567,7 +671,7 @@ static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
         const ClassRun& r = ctx->runs[c];
         const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[j] += r.cost;
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, ls->d_args + c, r.nbmax, class_grid(ctx, r),
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, d_args + c, r.nbmax, class_grid(ctx, r),
                                       stream_of(j), nullptr));
     }
     if (ns > 1) {
@@ -577,6 +681,10 @@ static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
         }
     }
     return PIMPC_OK;
+}
+
+static int enqueue_solve(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s) {
+    return enqueue_launches(ctx, ls->d_args, ls->d_rargs, ctx_scratch(ctx), s);
 }
 
 static int run_set(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s, bool graph) {
@@ -723,7 +831,11 @@ static void destroy_ctx(pimpc_ctx ctx) {
     rel(ctx->d_bad);
     rel(ctx->d_bins);
     rel(ctx->d_counters);
-    rel(ctx->d_row_scratch);
+    rel(ctx->d_row_clear);
+    rel(ctx->d_row_fused);
+    rel(ctx->d_ibad);
+    rel(ctx->d_nonfinite);
+    rel(ctx->d_pack_off);
     rel(ctx->d_ckpt);
     rel(ctx->d_tape);
     rel(ctx->d_grads);
@@ -945,7 +1057,9 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     // ---------------- device
     int dev = 0;
     HIPCHK(ctx, hipGetDevice(&dev));
+    ctx->device = dev;
     HIPCHK(ctx, hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(ctx, scratch_init(dev));  // the no-alloc solve's scratch on this device
     for (int j = 0; j < 3; ++j) {
         HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->aux[j], hipStreamNonBlocking));
         HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join[j], hipEventDisableTiming));
@@ -974,6 +1088,25 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     }
     DALLOC(ctx->d_tasks, FactorTask, ctx->ntasks);
     DALLOC(ctx->d_bad, int32_t, ctx->ntasks);
+    DALLOC(ctx->d_ibad, int32_t, count);
+    DALLOC(ctx->d_nonfinite, int32_t, 1);
+    {
+        // offsets of every instance's A, B, e in the caller's packed arrays
+        // (the device-side stage import of pimpc_linearize reads them)
+        std::vector<int64_t> pk(3 * (size_t)count);
+        int64_t oa = 0, ob = 0, oe = 0;
+        for (int i = 0; i < count; ++i) {
+            const int64_t S = tv ? ctx->inst[i].N : 1;
+            pk[3 * i + 0] = oa;
+            pk[3 * i + 1] = ob;
+            pk[3 * i + 2] = oe;
+            oa += S * ctx->inst[i].nx * ctx->inst[i].nx;
+            ob += S * ctx->inst[i].nx * ctx->inst[i].nu;
+            oe += S * ctx->inst[i].nx;
+        }
+        DALLOC(ctx->d_pack_off, int64_t, pk.size());
+        HIPCHK(ctx, hipMemcpy(ctx->d_pack_off, pk.data(), pk.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
     HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(ctx->d_tasks, tasks.data(), tasks.size() * sizeof(FactorTask), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemset(ctx->d_state, 0, ctx->st_elems * ts));
@@ -1006,16 +1139,18 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         r.occ = occ;
     }
     if (!ctx->row_insts.empty()) {
-        size_t bytes = 0;
-        for (int i : ctx->row_insts) bytes += row_scratch_bytes(ctx->inst[i], ctx->fp64);
-        ctx->row_scratch_bytes = bytes;
-        DALLOC(ctx->d_row_scratch, char, bytes);
-        HIPCHK(ctx, hipMemset(ctx->d_row_scratch, 0, bytes));
-        size_t off = 0;
+        size_t cbytes = 0, fbytes = 0;
         for (int i : ctx->row_insts) {
-            ctx->inst[i].row_scr16 = (int32_t)(off / 16);  // scratch offset in 16-byte units
-            off += row_scratch_bytes(ctx->inst[i], ctx->fp64);
+            ctx->row_clear_off.push_back(cbytes);
+            ctx->row_fused_off.push_back(fbytes);
+            cbytes += row_clear_bytes(ctx->inst[i]);
+            fbytes += row_fused_bytes(ctx->inst[i]);
         }
+        ctx->row_clear_total = cbytes;
+        DALLOC(ctx->d_row_clear, char, cbytes);
+        DALLOC(ctx->d_row_fused, char, fbytes);
+        HIPCHK(ctx, hipMemset(ctx->d_row_clear, 0, cbytes));
+        HIPCHK(ctx, hipMemset(ctx->d_row_fused, 0, fbytes));
         const char* env_s = getenv("PIMPC_ROW_STAGES");
         for (int i : ctx->row_insts) {
             ctx->inst[i].row_s = env_s ? atoi(env_s) : 1;
@@ -1060,6 +1195,8 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         DALLOC(ctx->d_bwd_counters, int32_t, std::max<size_t>(ctx->bwd_runs.size(), 1));
     }
 #undef DALLOC
+    ctx->na_args.reserve(ctx->runs.size());
+    ctx->na_rargs.reserve(ctx->row_insts.size());
     rc = autotune(ctx);
     if (rc != PIMPC_OK) return rc;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1093,6 +1230,22 @@ int32_t pimpc_linearize(pimpc_ctx ctx, const double* A, const double* B, const d
     if (!A || !B) return ctx->fail(PIMPC_E_ARG, "A and B are required");
     if (mem_kind != PIMPC_MEM_HOST && mem_kind != PIMPC_MEM_DEVICE)
         return ctx->fail(PIMPC_E_ARG, "mem_kind must be PIMPC_MEM_HOST or PIMPC_MEM_DEVICE");
+    ctx->tape_id = 0;  // a tape refers to the factors it was recorded with
+    if (mem_kind == PIMPC_MEM_DEVICE) {
+        // import on the device, ordered on the context's stream after the work
+        // that produced A, B, e there; the padded FP64 block is rewritten in
+        // place and the host copy of it goes stale
+        const hipStream_t s = ctx->stream;
+        ctx->h_mats64_valid = false;
+        HIPCHK(ctx, launch_fill<int32_t>(ctx->d_nonfinite, 1, 0, s));
+        HIPCHK(ctx, launch_stage_import(ctx->d_inst, ctx->count, ctx->d_pack_off, A, B, e, ctx->d_mats64,
+                                        ctx->d_nonfinite, s));
+        int rc = refactor(ctx, true);  // synchronises the stream
+        int32_t nf = 0;
+        HIPCHK(ctx, hipMemcpy(&nf, ctx->d_nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (nf) return ctx->fail(PIMPC_E_NONFINITE, "stage data contains NaN or Inf");
+        return rc;
+    }
     int64_t sA = 0, sB = 0, se = 0;
     for (const InstDev& I : ctx->inst) {
         const int64_t S = I.tv ? I.N : 1;
@@ -1100,21 +1253,7 @@ int32_t pimpc_linearize(pimpc_ctx ctx, const double* A, const double* B, const d
         sB += S * I.nx * I.nu;
         se += S * I.nx;
     }
-    std::vector<double> hA, hB, he;
     const double *pA = A, *pB = B, *pe = e;
-    if (mem_kind == PIMPC_MEM_DEVICE) {
-        hA.resize(sA);
-        hB.resize(sB);
-        HIPCHK(ctx, hipMemcpy(hA.data(), A, sA * sizeof(double), hipMemcpyDeviceToHost));
-        HIPCHK(ctx, hipMemcpy(hB.data(), B, sB * sizeof(double), hipMemcpyDeviceToHost));
-        pA = hA.data();
-        pB = hB.data();
-        if (e) {
-            he.resize(se);
-            HIPCHK(ctx, hipMemcpy(he.data(), e, se * sizeof(double), hipMemcpyDeviceToHost));
-            pe = he.data();
-        }
-    }
     if (!finite_arr(pA, sA) || !finite_arr(pB, sB) || (pe && !finite_arr(pe, se)))
         return ctx->fail(PIMPC_E_NONFINITE, "stage data contains NaN or Inf");
     // The weights and bounds of the block stay; only A, B, e are rewritten.
@@ -1168,7 +1307,7 @@ int32_t pimpc_solve(pimpc_ctx ctx, const double* x0, const double* u_prev, doubl
     rc = run_set(ctx, ls, s, false);
     if (rc != PIMPC_OK) return rc;
     if (ctx->opt.ckpt_every > 0) {
-        ctx->taped = 1;
+        ctx->tape_id = ++ctx->tape_count;
         ctx->tape_x0 = ctx->d_x0;
         ctx->tape_up = u_prev ? ctx->d_up : nullptr;
     }
@@ -1185,6 +1324,9 @@ int32_t pimpc_solve(pimpc_ctx ctx, const double* x0, const double* u_prev, doubl
         if (inf[i].status == PIMPC_E_HIP)
             return ctx->fail(PIMPC_E_HIP, "instance %d: a wait between workgroups gave up (the grid was not "
                                           "resident at once)", i);
+        else if (inf[i].status == PIMPC_E_NOT_PSD)
+            return ctx->fail(PIMPC_E_NOT_PSD, "instance %d: a stage matrix of the last factorisation is not SPD",
+                             i);
         else if (inf[i].status != 0)
             return ctx->fail(PIMPC_E_NONFINITE, "instance %d: iterate became non-finite", i);
     return PIMPC_OK;
@@ -1203,7 +1345,53 @@ int32_t pimpc_solve_batch(pimpc_ctx ctx, const void* x0_dev, const void* uprev_d
     if (rc != PIMPC_OK) return rc;
     ctx->has_state = 1;
     if (ctx->opt.ckpt_every > 0) {
-        ctx->taped = 1;
+        ctx->tape_id = ++ctx->tape_count;
+        ctx->tape_x0 = x0_dev;
+        ctx->tape_up = uprev_dev;
+    }
+    return PIMPC_OK;
+}
+
+int32_t pimpc_solve_batch_noalloc(pimpc_ctx ctx, const void* x0_dev, const void* uprev_dev, void* u0_dev,
+                                  pimpc_info* info_dev, void* hip_stream) {
+    if (!ctx) return PIMPC_E_ARG;
+    if (!x0_dev || !u0_dev) return ctx->fail(PIMPC_E_ARG, "x0_dev and u0_dev are required");
+    int dev = -1;
+    HIPCHK(ctx, hipGetDevice(&dev));
+    if (dev != ctx->device)
+        return ctx->fail(PIMPC_E_STATE, "the context was set up on device %d, device %d is current", ctx->device,
+                         dev);
+    char* base = (char*)scratch_dev(dev);
+    if (!base) return ctx->fail(PIMPC_E_STATE, "the no-alloc scratch of device %d was not set up", dev);
+    // layout of this call's scratch: lane arguments | row arguments | bin
+    // counters | per-solve part of every row-family instance
+    auto up256 = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t ncls = ctx->runs.size(), nrow = ctx->row_insts.size();
+    const size_t o_args = 0;
+    const size_t o_rargs = up256(o_args + ncls * sizeof(LaneArgs));
+    const size_t o_cnt = up256(o_rargs + nrow * sizeof(RowArgs));
+    const size_t o_row = up256(o_cnt + std::max<size_t>(ncls, 1) * sizeof(int32_t));
+    const size_t need = o_row + ctx->row_clear_total;
+    if (need > (size_t)PIMPC_NOALLOC_SCRATCH_BYTES)
+        return ctx->fail(PIMPC_E_DIM, "this context needs %zu bytes of per-solve scratch; the static scratch holds %zu "
+                                      "(use pimpc_solve_batch)", need, (size_t)PIMPC_NOALLOC_SCRATCH_BYTES);
+    const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    const int warm = (ctx->opt.warm_start && ctx->has_state) ? 1 : 0;
+    const SolveScratch sc{(int32_t*)(base + o_cnt), base + o_row};
+    // host staging of the arguments, reserved at setup (no allocation here)
+    std::vector<LaneArgs>& args = ctx->na_args;
+    std::vector<RowArgs>& rargs = ctx->na_rargs;
+    build_args(ctx, x0_dev, uprev_dev, u0_dev, info_dev, warm, 0, sc, args, rargs);
+    // the arguments travel as kernel arguments into the scratch, ordered on
+    // `s` before the launches that read them
+    if (!args.empty()) HIPCHK(ctx, launch_bytes_store(base + o_args, args.data(), args.size() * sizeof(LaneArgs), s));
+    if (!rargs.empty())
+        HIPCHK(ctx, launch_bytes_store(base + o_rargs, rargs.data(), rargs.size() * sizeof(RowArgs), s));
+    const int rc = enqueue_launches(ctx, (const LaneArgs*)(base + o_args), (const RowArgs*)(base + o_rargs), sc, s);
+    if (rc != PIMPC_OK) return rc;
+    ctx->has_state = 1;
+    if (ctx->opt.ckpt_every > 0) {
+        ctx->tape_id = ++ctx->tape_count;
         ctx->tape_x0 = x0_dev;
         ctx->tape_up = uprev_dev;
     }
@@ -1220,6 +1408,7 @@ int32_t pimpc_set_params_dev(pimpc_ctx ctx, const void* A, const void* B, const 
             return ctx->fail(PIMPC_E_STATE, "set_params_dev needs equal nx and nu across instances");
     const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     ctx->h_mats64_valid = false;  // the device copy changes below
+    ctx->tape_id = 0;             // a tape refers to the factors it was recorded with
     if (ctx->fp64)
         HIPCHK(ctx, launch_params<double>(ctx->d_inst, ctx->count, (const double*)A, (const double*)B,
                                           (const double*)Qdiag, (const double*)Rdiag, ctx->d_mats64, s));
@@ -1233,11 +1422,18 @@ int32_t pimpc_set_params_dev(pimpc_ctx ctx, const void* A, const void* B, const 
     return rc;
 }
 
-int32_t pimpc_backward(pimpc_ctx ctx, const void* dL_du0_dev, void* dx0, void* dQdiag, void* dRdiag, void* dA,
-                       void* dB, void* hip_stream) {
+uint64_t pimpc_tape_id(pimpc_ctx ctx) { return ctx ? ctx->tape_id : 0; }
+
+int32_t pimpc_backward(pimpc_ctx ctx, uint64_t tape_id, const void* dL_du0_dev, void* dx0, void* dQdiag,
+                       void* dRdiag, void* dA, void* dB, void* hip_stream) {
     if (!ctx) return PIMPC_E_ARG;
-    if (ctx->opt.ckpt_every <= 0 || !ctx->taped)
-        return ctx->fail(PIMPC_E_STATE, "no taped forward is available (needs ckpt_every > 0 and a solve first)");
+    if (ctx->opt.ckpt_every <= 0 || ctx->tape_id == 0)
+        return ctx->fail(PIMPC_E_STATE, "no taped forward is available (needs ckpt_every > 0 and a solve after "
+                                        "the last parameter update)");
+    if (tape_id != ctx->tape_id)
+        return ctx->fail(PIMPC_E_STATE, "tape %llu was overwritten: the current tape is %llu (another taped "
+                                        "forward, or a parameter update, came after it)",
+                         (unsigned long long)tape_id, (unsigned long long)ctx->tape_id);
     if (!dL_du0_dev) return ctx->fail(PIMPC_E_ARG, "dL_du0_dev is required");
     const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     const int ncls = (int)ctx->bwd_runs.size();

@@ -69,7 +69,8 @@ assert INFO_DTYPE.itemsize == ctypes.sizeof(pimpc_info) == 40
 
 EXPORTS = ["pimpc_default_options", "pimpc_setup", "pimpc_linearize", "pimpc_solve",
            "pimpc_solve_batch", "pimpc_set_params_dev", "pimpc_backward", "pimpc_get_iterates",
-           "pimpc_set_iterates", "pimpc_destroy", "pimpc_last_error", "pimpc_version"]
+           "pimpc_set_iterates", "pimpc_destroy", "pimpc_last_error", "pimpc_version", "pimpc_tape_id",
+           "pimpc_solve_batch_noalloc"]
 
 _lib = None
 
@@ -106,8 +107,11 @@ def lib():
     L.pimpc_linearize.argtypes = [vp, vp, vp, vp, ctypes.c_int32]
     L.pimpc_solve.argtypes = [vp, _dp, _dp, _dp, ctypes.POINTER(pimpc_info)]
     L.pimpc_solve_batch.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pimpc_solve_batch_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     L.pimpc_set_params_dev.argtypes = [vp, vp, vp, vp, vp, vp]
-    L.pimpc_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.pimpc_backward.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, vp, vp, vp, vp]
+    L.pimpc_tape_id.argtypes = [vp]
+    L.pimpc_tape_id.restype = ctypes.c_uint64
     L.pimpc_get_iterates.argtypes = [vp, ctypes.c_int32, _dp]
     L.pimpc_set_iterates.argtypes = [vp, ctypes.c_int32, _dp]
     L.pimpc_destroy.argtypes = [vp]
@@ -115,7 +119,7 @@ def lib():
     L.pimpc_last_error.argtypes = [vp]
     L.pimpc_last_error.restype = ctypes.c_char_p
     L.pimpc_version.argtypes = []
-    for f in ["pimpc_setup", "pimpc_linearize", "pimpc_solve", "pimpc_solve_batch",
+    for f in ["pimpc_setup", "pimpc_linearize", "pimpc_solve", "pimpc_solve_batch", "pimpc_solve_batch_noalloc",
               "pimpc_set_params_dev", "pimpc_backward", "pimpc_get_iterates", "pimpc_set_iterates",
               "pimpc_version"]:
         getattr(L, f).restype = ctypes.c_int32
@@ -258,14 +262,24 @@ def pimpc_solve_batch(ctx, x0_dev, uprev_dev, u0_dev, info_dev=None, stream: Opt
     _check(rc, ctx)
 
 
+def pimpc_solve_batch_noalloc(ctx, x0_dev, uprev_dev, u0_dev, info_dev=None, stream: Optional[int] = None):
+    rc = lib().pimpc_solve_batch_noalloc(ctx, _tptr(x0_dev), _tptr(uprev_dev), _tptr(u0_dev),
+                                         _tptr(info_dev), stream)
+    _check(rc, ctx)
+
+
 def pimpc_set_params_dev(ctx, A, B, Qdiag, Rdiag, stream: Optional[int] = None):
     rc = lib().pimpc_set_params_dev(ctx, _tptr(A), _tptr(B), _tptr(Qdiag), _tptr(Rdiag), stream)
     _check(rc, ctx)
 
 
-def pimpc_backward(ctx, dL_du0, dx0=None, dQdiag=None, dRdiag=None, dA=None, dB=None,
+def pimpc_tape_id(ctx) -> int:
+    return int(lib().pimpc_tape_id(ctx))
+
+
+def pimpc_backward(ctx, tape_id: int, dL_du0, dx0=None, dQdiag=None, dRdiag=None, dA=None, dB=None,
                    stream: Optional[int] = None):
-    rc = lib().pimpc_backward(ctx, _tptr(dL_du0), _tptr(dx0), _tptr(dQdiag), _tptr(dRdiag),
+    rc = lib().pimpc_backward(ctx, tape_id, _tptr(dL_du0), _tptr(dx0), _tptr(dQdiag), _tptr(dRdiag),
                               _tptr(dA), _tptr(dB), stream)
     _check(rc, ctx)
 

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert P.pimpc_version() == 1
+    assert P.pimpc_version() == 2
     o = P.pimpc_default_options()
     assert o.rho == 1.0 and o.max_iter == 200 and o.precision == P.PIMPC_FP32
     assert o.eta == pytest.approx(0.999) and o.check_every == 1

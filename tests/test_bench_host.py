@@ -43,7 +43,37 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_stage_flop_model():
-    # 2 F + 25 nb with F = nb^2 + nu nb + 2 nx^2 + 3 nx nu (the 12-mass chain: nx = 24, nu = 11)
+    # 2 F + 45 nb with F = nb^2 + nu nb + 2 nx^2 + 3 nx nu (the 12-mass chain: nx = 24, nu = 11):
+    # F = 3554 and 8683 flops per stage-iteration
     nb = 35
     F = nb * nb + 11 * nb + 2 * 24 * 24 + 3 * 24 * 11
-    assert bench.stage_flops(24, 11) == 2 * F + 25 * nb
+    assert F == 3554
+    assert bench.stage_flops(24, 11) == 2 * F + 45 * nb == 8683
+
+
+def test_peak_is_the_non_packed_fp32_rate():
+    assert abs(bench.PEAK_FP32_VALU - 78.6e12) < 0.1e12
+    assert bench.PEAK_FP32_PACKED == 157.3e12
+
+
+def test_info_check_refuses_failed_solves():
+    import numpy as np
+    import pytest
+    from paper_2601_14414_amd import pimpc as P
+    rec = np.zeros(3, dtype=P.INFO_DTYPE)
+    rec["iters"] = 300
+    bench.check_info(P, rec, 300, "ok")
+    rec["status"][1] = P.PIMPC_E_HIP
+    with pytest.raises(RuntimeError):
+        bench.check_info(P, rec, 300, "bad status")
+    rec["status"][1] = 0
+    rec["iters"][2] = 120
+    with pytest.raises(RuntimeError):
+        bench.check_info(P, rec, 300, "short run")
+
+
+def test_oracle_pool_worker_counts_solves():
+    """The all-core CPU baseline's worker runs whole oracle solves of the
+    headline workload for a bounded time."""
+    reps, t = bench._oracle_worker((0, 0.0))
+    assert reps == 1 and t > 0

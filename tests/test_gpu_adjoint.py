@@ -95,7 +95,7 @@ def test_backward_without_tape_is_an_error():
     s = P.Solver([p], precision=P.PIMPC_FP32)
     g = torch.zeros(3, device="cuda")
     with pytest.raises(P.PimpcError) as ei:
-        P.pimpc_backward(s.ctx, g)
+        P.pimpc_backward(s.ctx, P.pimpc_tape_id(s.ctx), g)
     assert ei.value.code == P.PIMPC_E_STATE
 
 
