@@ -1,0 +1,85 @@
+"""The entry point that allocates nothing, pimpc_solve_batch_noalloc: its
+kernels keep every per-call buffer in the library's static device array, and
+its results equal those of pimpc_solve_batch on the same context.  Two calls
+in a row on one GPU, the second with a smaller batch and a shorter
+row-family horizon, so that the second call runs on what the first left in
+the array."""
+import numpy as np
+import pytest
+
+from paper_2601_14414_amd import pimpc as P
+from paper_2601_14414_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _problems(n_lane, n_row, seed):
+    """n_lane instances of the random batch recipe (lane family, N <= 512)
+    plus one 4-mass chain of horizon n_row (> 512: row family)."""
+    ps = W.random_batch(n_lane, base_seed=seed, K=60)
+    ps.append(W.mass_spring_problem(4, N=n_row, seed=seed, x0_scale=1.0, K=60))
+    return ps
+
+
+def _run(entry, solver, problems, stream):
+    dev = torch.device("cuda")
+    with torch.cuda.stream(stream):
+        x0 = torch.tensor(np.concatenate([p.x0 for p in problems]), dtype=torch.float32, device=dev)
+        u0 = torch.full((solver.sum_nu,), float("nan"), dtype=torch.float32, device=dev)
+        info = torch.zeros((solver.count * 40,), dtype=torch.uint8, device=dev)
+        entry(solver.ctx, x0, None, u0, info, stream.cuda_stream)
+    stream.synchronize()
+    inf = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
+    states = [np.concatenate([a.ravel() for a in solver.iterate(w)]) for w in range(7)]
+    return u0.cpu().numpy(), inf, states
+
+
+@pytest.mark.parametrize("n_lane,n_row", [(96, 900), (24, 600)])
+def test_noalloc_equals_solve_batch(n_lane, n_row):
+    """Same context, cold start: the no-alloc call reproduces the allocating
+    entry point's inputs, info records and final iterates bit for bit (same
+    kernels, same per-instance reduction order)."""
+    problems = _problems(n_lane, n_row, seed=500 + n_lane)
+    s = P.Solver(problems, max_iter=60, precision=P.PIMPC_FP32)
+    stream = torch.cuda.Stream()
+    u_ref, i_ref, st_ref = _run(P.pimpc_solve_batch, s, problems, stream)
+    u_na, i_na, st_na = _run(P.pimpc_solve_batch_noalloc, s, problems, stream)
+    s.close()
+    assert np.all(np.isfinite(u_ref)) and np.all(i_ref["status"] == 0) and np.all(i_ref["iters"] == 60)
+    np.testing.assert_array_equal(u_na, u_ref)
+    np.testing.assert_array_equal(i_na, i_ref)
+    for w in range(7):
+        np.testing.assert_array_equal(st_na[w], st_ref[w])
+
+
+def test_noalloc_two_calls_second_smaller():
+    """Two no-alloc calls back to back, the second on a smaller context
+    (fewer instances, shorter row horizon): each equals pimpc_solve_batch."""
+    stream = torch.cuda.Stream()
+    for n_lane, n_row in ((128, 1000), (16, 540)):
+        problems = _problems(n_lane, n_row, seed=700 + n_lane)
+        ref = P.Solver(problems, max_iter=60, precision=P.PIMPC_FP32)
+        u_ref, i_ref, st_ref = _run(P.pimpc_solve_batch, ref, problems, stream)
+        ref.close()
+        na = P.Solver(problems, max_iter=60, precision=P.PIMPC_FP32)
+        u_na, i_na, st_na = _run(P.pimpc_solve_batch_noalloc, na, problems, stream)
+        na.close()
+        np.testing.assert_array_equal(u_na, u_ref)
+        np.testing.assert_array_equal(i_na, i_ref)
+        for w in range(7):
+            np.testing.assert_array_equal(st_na[w], st_ref[w])
+
+
+def test_noalloc_rejects_a_context_beyond_the_array():
+    """A row-family horizon whose per-call scratch exceeds the static array is
+    refused with PIMPC_E_DIM before anything is launched."""
+    p = W.long_horizon_problem(seed=0, N=4096, K=10)
+    s = P.Solver([p], max_iter=10, precision=P.PIMPC_FP32)
+    dev = torch.device("cuda")
+    x0 = torch.tensor(p.x0, dtype=torch.float32, device=dev)
+    u0 = torch.zeros(p.nu, dtype=torch.float32, device=dev)
+    with pytest.raises(P.PimpcError) as ei:
+        P.pimpc_solve_batch_noalloc(s.ctx, x0, None, u0, None, torch.cuda.current_stream().cuda_stream)
+    assert ei.value.code == P.PIMPC_E_DIM
+    s.close()
