@@ -202,7 +202,14 @@ def bench_batch(torch, P, W, steps, warmup):
     check_info(P, rec, 300, "batch_4096")
     stage_its = sum(p.N for p in problems) * 300
     flops = sum(p.N * stage_flops(p.nx, p.nu) for p in problems) * 300
-    err = batch_error(P, s, problems, u0.cpu().numpy())
+    # the device-pointer path does not write the step-1 outputs (du, xbar);
+    # one host-path solve of the same context (same kernels, same inputs)
+    # does, and must give the same u0 bit for bit
+    u0_dev = u0.cpu().numpy().astype(np.float64)
+    u0_host, _ = s.solve(x0=x0.cpu().numpy().astype(np.float64))
+    if not np.array_equal(u0_host, u0_dev):
+        raise RuntimeError("batch_4096: host-path and device-path solves differ")
+    err = batch_error(P, s, problems, u0_dev)
     s.close()
     # the same instances one launch each (the single-instance path, graph
     # replays back to back on one stream): every 32nd instance, scaled to 4096

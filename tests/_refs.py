@@ -291,3 +291,152 @@ def accel_admm_dense(p, K, eta=0.999, variant=None):
         ss.append(s.copy())
         cs.append(c)
     return dict(q=qs, s=ss, c=np.array(cs), restart=np.array(restarts), eta=eta)
+
+
+def sparse_qp(p):
+    """QP (2) of problem (1) as scipy.sparse matrices, in the same original
+    coordinates y = col(u_0, x_1, ..., u_{N-1}, x_N) as `original_qp`, for
+    horizons where dense matrices do not fit.  The linear term qbar of the
+    velocity-form cost (-qbar' xbar_{k+1}, xbar_{k+1} = col(x_{k+1}, u_k)) and
+    an input-rate weight Wdu are included."""
+    import scipy.sparse as sp
+    n, m, N = p.nx, p.nu, p.N
+    nb = n + m
+    A, B, e = p.stage_A(), p.stage_B(), p.stage_e()
+    ny = N * nb
+    Hr, Hc, Hv = [], [], []
+
+    def blk(r0, c0, M):
+        M = np.asarray(M, np.float64)
+        rr, cc = np.nonzero(M)
+        Hr.extend(rr + r0)
+        Hc.extend(cc + c0)
+        Hv.extend(M[rr, cc])
+
+    f = np.zeros(ny)
+    Wd = getattr(p, "Wdu", None)
+    qb = None if p.qbar is None else np.asarray(p.qbar, np.float64)
+    for k in range(N):
+        u0, x0 = k * nb, k * nb + m
+        blk(u0, u0, p.R)
+        blk(x0, x0, p.Q)
+        if qb is not None:
+            f[x0:x0 + n] -= qb[:n]
+            f[u0:u0 + m] -= qb[n:]
+        if Wd is not None:
+            blk(u0, u0, Wd)
+            if k >= 1:
+                blk(u0 - nb, u0 - nb, Wd)
+                blk(u0, u0 - nb, -np.asarray(Wd))
+                blk(u0 - nb, u0, -np.asarray(Wd))
+            else:
+                f[u0:u0 + m] -= np.asarray(Wd) @ np.asarray(p.u_prev, np.float64)
+    H = sp.csc_matrix((Hv, (Hr, Hc)), shape=(ny, ny))
+    Ar, Ac, Av = [], [], []
+    beq = np.zeros(N * n)
+    for k in range(N):
+        r0, u0, x0 = k * n, k * nb, k * nb + m
+        for i in range(n):
+            Ar.append(r0 + i); Ac.append(x0 + i); Av.append(1.0)
+            for j in range(m):
+                if B[k][i, j] != 0.0:
+                    Ar.append(r0 + i); Ac.append(u0 + j); Av.append(-B[k][i, j])
+            if k >= 1:
+                for j in range(n):
+                    if A[k][i, j] != 0.0:
+                        Ar.append(r0 + i); Ac.append(x0 - nb + j); Av.append(-A[k][i, j])
+        beq[r0:r0 + n] = e[k] + (A[0] @ p.x0 if k == 0 else 0.0)
+    Aeq = sp.csc_matrix((Av, (Ar, Ac)), shape=(N * n, ny))
+    lo = np.tile(np.concatenate([p.umin, p.xmin]).astype(np.float64), N)
+    hi = np.tile(np.concatenate([p.umax, p.xmax]).astype(np.float64), N)
+    return dict(H=H, f=f, Aeq=Aeq, beq=beq, lo=lo, hi=hi, nb=nb)
+
+
+def ipm_qp(p, tol=1e-12, max_iter=80):
+    """Optimum of QP (2) by a primal-dual interior-point method (Mehrotra's
+    predictor-corrector, textbook form; infeasible start, slacks for every
+    finite bound), each Newton system solved by a sparse LU of the
+    quasi-definite KKT matrix.  An algorithm unrelated to ADMM, for a KKT
+    point of long horizons.  Returns dict(xs (N,n), us (N,m), y, kkt = the
+    largest scaled residual, iters, ok)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    D = sparse_qp(p)
+    H, f, Aeq, beq, lo, hi = D["H"], D["f"], D["Aeq"], D["beq"], D["lo"], D["hi"]
+    ny, ne = H.shape[0], Aeq.shape[0]
+    il = np.flatnonzero(np.isfinite(lo))
+    iu = np.flatnonzero(np.isfinite(hi))
+    y = np.zeros(ny)
+    both = np.isfinite(lo) & np.isfinite(hi)
+    y[both] = 0.5 * (lo[both] + hi[both])
+    sl = np.maximum(y[il] - lo[il], 1.0)
+    su = np.maximum(hi[iu] - y[iu], 1.0)
+    zl = np.ones(il.size)
+    zu = np.ones(iu.size)
+    nu_ = np.zeros(ne)
+    AT = Aeq.T.tocsc()
+    nbound = il.size + iu.size
+    ok = False
+    it = 0
+    kkt = np.inf
+    scale = 1.0 + max(np.max(np.abs(f)), np.max(np.abs(beq)))
+    for it in range(1, max_iter + 1):
+        rd = H @ y + f - AT @ nu_
+        rd[il] -= zl
+        rd[iu] += zu
+        re = Aeq @ y - beq
+        rl = y[il] - lo[il] - sl
+        ru = hi[iu] - y[iu] - su
+        mu = (sl @ zl + su @ zu) / max(nbound, 1)
+        kkt = max(np.max(np.abs(rd)), np.max(np.abs(re)), np.max(np.abs(rl), initial=0.0),
+                  np.max(np.abs(ru), initial=0.0), mu) / scale
+        if kkt <= tol:
+            ok = True
+            break
+        sig = np.zeros(ny)
+        np.add.at(sig, il, zl / sl)
+        np.add.at(sig, iu, zu / su)
+        Kmat = sp.bmat([[H + sp.diags(sig), AT], [Aeq, None]], format="csc")
+        lu = spla.splu(Kmat)
+
+        def step(cl, cu):
+            # complementarity targets sl zl -> cl, su zu -> cu
+            r1 = -rd.copy()
+            r1[il] += (cl - zl * rl) / sl - zl + zl * 0.0
+            r1[iu] -= (cu - zu * ru) / su - zu
+            # r1 built from: -rd + Pl[(cl)/sl - zl - (zl/sl) rl] - Pu[(cu)/su - zu - (zu/su) ru]
+            sol = lu.solve(np.concatenate([r1, -re]))
+            dy = sol[:ny]
+            dsl = dy[il] + rl
+            dsu = -dy[iu] + ru
+            dzl = (cl - sl * zl - zl * dsl) / sl
+            dzu = (cu - su * zu - zu * dsu) / su
+            dnu = -sol[ny:]
+            return dy, dsl, dsu, dzl, dzu, dnu
+
+        def maxstep(x, dx):
+            neg = dx < 0
+            return min(1.0, float(np.min(-x[neg] / dx[neg]))) if np.any(neg) else 1.0
+
+        # predictor (affine scaling)
+        dy, dsl, dsu, dzl, dzu, dnu = step(np.zeros(il.size), np.zeros(iu.size))
+        ap = min(maxstep(sl, dsl), maxstep(su, dsu))
+        ad = min(maxstep(zl, dzl), maxstep(zu, dzu))
+        mu_aff = ((sl + ap * dsl) @ (zl + ad * dzl) + (su + ap * dsu) @ (zu + ad * dzu)) / max(nbound, 1)
+        sigma = (mu_aff / mu) ** 3 if mu > 0 else 0.0
+        # corrector with Mehrotra's second-order term
+        cl = sigma * mu - dsl * dzl
+        cu = sigma * mu - dsu * dzu
+        dy, dsl, dsu, dzl, dzu, dnu = step(cl, cu)
+        ap = 0.99 * min(maxstep(sl, dsl), maxstep(su, dsu))
+        ad = 0.99 * min(maxstep(zl, dzl), maxstep(zu, dzu))
+        ap, ad = min(ap, 1.0), min(ad, 1.0)
+        y += ap * dy
+        sl += ap * dsl
+        su += ap * dsu
+        zl += ad * dzl
+        zu += ad * dzu
+        nu_ += ad * dnu
+    nb, m = D["nb"], p.nu
+    Y = y.reshape(p.N, nb)
+    return dict(xs=Y[:, m:].copy(), us=Y[:, :m].copy(), y=y, kkt=kkt, iters=it, ok=ok)

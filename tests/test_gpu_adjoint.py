@@ -4,8 +4,9 @@ central finite differences in test_oracle_pins.py).
 
 Tolerance: FP32 forward and adjoint over K iterations vs FP64; gradients are
 compared relative to the largest oracle gradient entry of the same parameter,
-at 2e-3 (the adjoint map is the transpose of a nonexpansive one, so rounding
-accumulates at most about linearly in K)."""
+at 1e-3 (the adjoint map is the transpose of a nonexpansive one, so rounding
+accumulates at most about linearly in K; the largest error measured on the
+differentiable batch is about 4e-5)."""
 import numpy as np
 import pytest
 
@@ -16,7 +17,7 @@ from paper_2601_14414_amd import workloads as W
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-TOLG = 2e-3
+TOLG = 1e-3
 
 
 def rel(a, b):
@@ -70,14 +71,19 @@ def test_adjoint_matches_oracle_small(ckpt):
 
 def test_adjoint_differentiable_batch_sampled():
     """The differentiable batch: 1024 chains (nx=8, nu=3, N=128), 200
-    iterations, checkpoints every 20; 6 sampled instances vs the oracle."""
+    iterations, checkpoints every 20; 32 instances (every 32nd, the last
+    one included) vs the oracle's reverse mode."""
     db = W.diff_batch(count=1024, seed=7, N=128, K=200)
     g = run_gpu(db, 1024, 20, db.u_target)
-    for i in (0, 1, 511, 1000, 1022, 1023):
+    worst = {}
+    for i in list(range(0, 1024, 33)) + [1023]:
         r, go = oracle_grad(db, i, db.u_target)
         assert rel(g["u0"][i], r["u0"]) <= 1e-4
         for key in ("dx0", "dQd", "dRd", "dA", "dB"):
-            assert rel(g[key][i], go[key]) <= TOLG, (i, key, rel(g[key][i], go[key]))
+            e = rel(g[key][i], go[key])
+            worst[key] = max(worst.get(key, 0.0), e)
+            assert e <= TOLG, (i, key, e)
+    print("largest relative gradient errors:", {k: f"{v:.2e}" for k, v in worst.items()})
 
 
 def test_checkpoint_spacing_does_not_change_gradients():

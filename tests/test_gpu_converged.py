@@ -1,10 +1,14 @@
 """Converged mode (the accuracy target "primal and dual residual <= 1e-4 in
 FP32"): the FP32 iteration (FP64 factorisation) runs with the eps stop of
 Algorithm 1 step 5 until c <= 1e-8; its reported residuals must then be
-<= 1e-4, and its input trajectory (the u part of xbar) within 1e-3 of the
-FP64 oracle's solution at c <= 1e-22 (a KKT point to ~1e-12, see
-test_oracle_pins.py).  Lane family: three 4-mass chains in one batch; row
-family: a packed narrow long horizon."""
+<= 1e-4, and its input trajectory (the u part of xbar) close to the optimum
+of the QP: within 1e-3 of the FP64 oracle's solution at c <= 1e-22 (a KKT
+point to ~1e-12, see test_oracle_pins.py) for the small cases, and of the
+interior-point optimum of QP (2) (`_refs.ipm_qp`, pinned against the oracle
+and the QP-ADMM on the CPU) for the batch and the long horizon.
+Lane family: three 4-mass chains in one batch, and the shortest and longest
+instance of every (nx, nu) class of the uneven batch; row family: a packed
+narrow long horizon."""
 import numpy as np
 import pytest
 
@@ -12,6 +16,8 @@ import oracle
 from paper_2601_14414_amd import pimpc as P
 from paper_2601_14414_amd import workloads as W
 
+import _refs
+from test_gpu_batch import stratified_sample
 from test_gpu_lane import tiny_problem
 
 pytestmark = pytest.mark.gpu
@@ -43,4 +49,29 @@ def test_fp32_reaches_target_row_family():
     s = P.Solver([p], rho=p.rho, max_iter=40000, eps=1e-8, check_every=10, precision=P.PIMPC_FP32)
     _, info = s.solve()
     _check([p], s, info)
+    s.close()
+
+
+def test_fp32_reaches_target_uneven_batch_classes():
+    """The shortest and the longest instance of each of the 16 (nx, nu)
+    classes of the uneven batch, solved together in one batched launch to
+    c <= 1e-8: residuals <= 1e-4 and input trajectories within 1e-3 of the
+    interior-point optimum of each instance."""
+    all_p = W.random_batch(4096, base_seed=1000, K=300)
+    pick, _ = stratified_sample(all_p, extra=0)
+    problems = [all_p[i] for i in pick]
+    assert len(problems) == 32
+    s = P.Solver(problems, rho=1.0, max_iter=100000, eps=1e-8, check_every=10, precision=P.PIMPC_FP32)
+    _, info = s.solve()
+    xbar = s.iterate(P.IT_XBAR)
+    worst = 0.0
+    for i, p in enumerate(problems):
+        assert info["status"][i] == 0 and info["c"][i] <= 1e-8, (i, info["c"][i])
+        assert info["r_prim"][i] <= 1e-4 and info["r_dual"][i] <= 1e-4, (i, info["r_prim"][i], info["r_dual"][i])
+        ref = _refs.ipm_qp(p)
+        assert ref["ok"], i
+        e = float(np.max(np.abs(xbar[i][:, p.nx:] - ref["us"]))) / max(1.0, float(np.max(np.abs(ref["us"]))))
+        worst = max(worst, e)
+        assert e <= 1e-3, (pick[i], e)
+    print(f"largest input-trajectory error against the optimum: {worst:.2e}")
     s.close()

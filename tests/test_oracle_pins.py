@@ -228,6 +228,28 @@ def test_constrained_fixed_point_matches_qp_admm(case, seed):
     np.testing.assert_allclose(r["xs"][:, p.nx:], ref["us"], rtol=0, atol=1e-10)
 
 
+@pytest.mark.parametrize("case,seed", [("u", 0), ("x", 1), ("uw", 0), ("tv", 2)])
+def test_interior_point_reference_equals_qp_admm_and_oracle(case, seed):
+    """The interior-point reference (`_refs.ipm_qp`, Mehrotra predictor-
+    corrector on the sparse QP (2)), used for the converged-mode checks of
+    long horizons, reaches the same optimum as the general-QP ADMM and as the
+    converged oracle, with active bounds, the input-rate weight, and
+    time-varying affine data with a linear cost term."""
+    if case == "tv":
+        p = tiny_tv_problem(seed, bounded=True)
+    else:
+        p = {"u": _u_bound_case, "x": _x_bound_case, "uw": _u_bound_rate_case}[case](seed)
+    ip = _refs.ipm_qp(p)
+    assert ip["ok"] and ip["kkt"] <= 1e-12
+    r = oracle.solve(p, K=200000, eps=1e-26)
+    assert r["hist"][-1][0] <= 1e-26
+    np.testing.assert_allclose(ip["xs"], r["xs"][:, :p.nx], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(ip["us"], r["xs"][:, p.nx:], rtol=0, atol=1e-9)
+    if case != "tv":
+        ref = _refs.qp_admm(p, rho=1.0, iters=100000, tol=1e-13)
+        np.testing.assert_allclose(ip["us"], ref["us"], rtol=0, atol=1e-9)
+
+
 def test_optimum_invariant_to_rho_and_uprev():
     """The minimiser of (1) depends on neither the ADMM penalty rho nor on
     u(t-1) (no input-rate weight): every run converges to the same U."""
