@@ -56,26 +56,26 @@ namespace {
 constexpr int kSpinLimit = 1 << 22;  // polls before a wait gives up (seconds at worst)
 constexpr int kMboxVecs = 3;         // per buffer: w (to the left), d (to the right), dd (to the left)
 
-// Scratch of one row-family instance (16-byte aligned pieces).  The first
-// part is cleared before every solve: abort flag, reduction tags, per-wave
-// partials, decision word, global mailboxes [nwaves][2 buf][3 vec][NBP]
-// (64-bit words).  The second part holds the fused stage data, written at
-// factorisation time.
+// Scratch of one row-family instance (16-byte aligned pieces), cleared
+// before every solve: abort flag; per-wave residual words [3][nwaves] (c,
+// r_prim, r_dual of the wave, each tag << 32 | float bits); global halo
+// mailboxes [nwaves][2 buf][3 vec][NBP] (64-bit words); the reducer waves'
+// per-workgroup partials of c [nwg], then the decision word.  The fused
+// stage data sit elsewhere (written at factorisation time).
 // Device pointers carry the global address space, so that every access is a
 // global (not flat) instruction and never waits on the LDS counter.
 struct RowScratch {
     gptr<int32_t> abort;
-    gptr<uint64_t> red_tag;   // [nwaves]
-    gptr<double> red_val;     // [nwaves][3]
-    gptr<uint64_t> decision;  // [1]
-    gptr<uint64_t> mbox;      // [nwaves][2][kMboxVecs][NBP]
+    gptr<uint64_t> red;      // [3][nwaves]
+    gptr<uint64_t> mbox;     // [nwaves][2][kMboxVecs][NBP]
+    gptr<uint64_t> wg_part;  // [nwg] partials, [nwg] decision word (room for 2 nwaves words)
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) / 16 * 16; }
 
 __host__ __device__ inline size_t row_clear_size(int nwaves, int nbp) {
-    return align16(16) + align16(8ull * nwaves) + align16(24ull * nwaves) + align16(16) +
-           align16(8ull * nwaves * 2 * kMboxVecs * nbp);
+    return align16(16) + align16(24ull * nwaves) + align16(8ull * nwaves * 2 * kMboxVecs * nbp) +
+           align16(16ull * nwaves);
 }
 
 // Fused block (floats): BJ | HAt | AH | AHAt  [NB][NB] row-major, then
@@ -102,14 +102,11 @@ __device__ inline RowScratch row_scratch(gptr<char> base, int nwaves, int nbp) {
     RowScratch s;
     s.abort = (gptr<int32_t>)p;
     p += align16(16);
-    s.red_tag = (gptr<uint64_t>)p;
-    p += align16(8ull * nwaves);
-    s.red_val = (gptr<double>)p;
+    s.red = (gptr<uint64_t>)p;
     p += align16(24ull * nwaves);
-    s.decision = (gptr<uint64_t>)p;
-    p += align16(16);
     s.mbox = (gptr<uint64_t>)p;
-    (void)nbp;
+    p += align16(8ull * nwaves * 2 * kMboxVecs * nbp);
+    s.wg_part = (gptr<uint64_t>)p;
     return s;
 }
 
@@ -157,7 +154,119 @@ __device__ inline T wmax(T v) {
     return v;
 }
 
+// Gathers the words base[c * stride + i], i < n, of NC components c, each
+// (tag << 32 | float bits), once they all carry `tag`: lane l takes i = l,
+// l + 64, ..., and every word it still waits for is in flight at once in
+// each poll, so the wait costs about one memory round trip after the last
+// word is stored.  v[c][q] = value of word i = 64 q + lane.  Returns false
+// (and raises the abort flag) when the wait gives up.
+template <int NC, int PER>
+__device__ inline bool gather_tagged(gptr<uint64_t> base, size_t stride, int n, uint32_t tag, float (&v)[NC][PER],
+                                     gptr<int32_t> abort) {
+    const int lane = threadIdx.x & 63;
+    uint64_t need = 0, have = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            v[c][q] = 0.f;
+            if (q * 64 + lane < n) need |= 1ull << (c * PER + q);
+        }
+    bool fail = false;
+    int spins = 0;
+    for (;;) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const uint64_t bit = 1ull << (c * PER + q);
+                if ((need & bit) && !(have & bit)) {
+                    const uint64_t w = gload(base + c * stride + q * 64 + lane);
+                    if (unpack_tag(w) == tag) {
+                        v[c][q] = unpack_val(w);
+                        have |= bit;
+                    }
+                }
+            }
+        if (have == need) break;
+        if (++spins > kSpinLimit ||
+            ((spins & 31) == 0 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            fail = true;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return !wave_any(fail);
+}
+
 constexpr int kFuseMax = 48;  // largest padded stage size of the row family
+
+// Sums and maxima over the lanes of one stage group: G groups of NB lanes
+// per wave (NB a power of two when G > 1, so xor shuffles stay inside the
+// group; with G = 1 the group is the wave, lanes past the stage holding 0).
+template <int G, int NB>
+__device__ inline float gsum(float v) {
+    if constexpr (G == 1) {
+        return wsum(v);
+    } else {
+#pragma unroll
+        for (int off = NB / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        return v;
+    }
+}
+template <int G, int NB>
+__device__ inline float gmax(float v) {
+    if constexpr (G == 1) {
+        return wmax(v);
+    } else {
+#pragma unroll
+        for (int off = NB / 2; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+        return v;
+    }
+}
+
+// Projection onto one non-box factor (x_k or u_k) of Xbar = X x U, one
+// entry per lane (the sets the proof of Theorem 1 lists; formulas of Parikh
+// and Boyd, Ch. 6).  `in`: the lane holds entry j of the factor (j < n);
+// a_j: its normal entry (halfspace, hyperplane), pn: b or the l1 radius;
+// `first`: lane of the factor's entry 0 in this lane's group.  Every lane of
+// the wave calls this (the reductions span the group), with the same kind.
+template <int G, int NB>
+__device__ inline float project_row_factor(float y, bool in, int j, int n, int kind, float a_j, float pn,
+                                           int first) {
+    if (kind == 1 || kind == 2) {  // halfspace a'w <= b, hyperplane a'w = b
+        const float t = gsum<G, NB>(in ? a_j * y : 0.f) - pn;
+        const float aa = gsum<G, NB>(in ? a_j * a_j : 0.f);
+        if (in && (kind == 2 || t > 0.f)) y -= (t / aa) * a_j;
+    } else if (kind == 3) {  // second-order cone ||w_1..w_{n-1}|| <= w_n
+        const float q = gsum<G, NB>((in && j < n - 1) ? y * y : 0.f);
+        const float t = gsum<G, NB>((in && j == n - 1) ? y : 0.f);
+        const float nq = sqrtf(q);
+        if (in && !(nq <= t)) {
+            const float al = (nq + t) * 0.5f;
+            y = (nq <= -t) ? 0.f : (j < n - 1 ? y * (al / nq) : al);
+        }
+    } else if (kind == 4) {  // l1 ball ||w||_1 <= r: soft threshold at level theta
+        const float m = in ? fabsf(y) : 0.f;
+        const float l1 = gsum<G, NB>(m);
+        // theta = max_j (sum_{|w_i| >= |w_j|} |w_i| - r) / #{i : |w_i| >= |w_j|}
+        float sj = 0.f, cj = 0.f;
+        for (int i = 0; i < n; ++i) {
+            const float mi = __shfl(m, first + i, 64);
+            if (mi >= m) {
+                sj += mi;
+                cj += 1.f;
+            }
+        }
+        const float theta = gmax<G, NB>(in ? (sj - pn) / cj : -INFINITY);
+        if (in && l1 > pn) {
+            const float a = m - theta;
+            y = a > 0.f ? (y > 0.f ? a : -a) : 0.f;
+        }
+    }
+    return y;
+}
 
 }  // namespace
 
@@ -330,6 +439,12 @@ __global__ void __launch_bounds__(256) row_fuse_tv_kernel(const InstDev* __restr
 constexpr int kRowWaves = 4;
 constexpr int kRecvWaves = 2;
 constexpr int kRowThreads = 64 * (kRowWaves + kRecvWaves);
+// With restart acceleration (Algorithm 1 steps 6-7) a seventh, reducer wave
+// sums c^{i+1} over the workgroup's compute waves (LDS), publishes the
+// workgroup's partial, gathers every workgroup's partial in a fixed order
+// (so all workgroups reach the same sum and the same decision), applies
+// steps 5-7 and hands the decision to the compute waves through LDS.
+constexpr int kRowThreadsRed = kRowThreads + 64;
 
 // Stage groups per wave: narrow stages (NB <= 16) share a wave side by side.
 __host__ __device__ constexpr int row_groups(int nb) { return nb <= 16 ? 64 / nb : 1; }
@@ -347,9 +462,9 @@ __host__ __device__ constexpr size_t row_lds_bytes(int NX, int NU, int S, bool T
 
 extern __shared__ __align__(16) float row_smem[];
 
-template <int NX, int NU, int S, bool TV>
-__global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restrict__ ap, int nwaves,
-                                                             int nwg) {
+template <int NX, int NU, int S, bool TV, bool RED, bool SETS>
+__global__ void __launch_bounds__(RED ? kRowThreadsRed : kRowThreads)
+    row_kernel(const RowArgs* __restrict__ ap, int nwaves, int nwg) {
     constexpr int NB = NX + NU;
     constexpr int NB4 = NB / 4;
     constexpr int NX4 = NX / 4;
@@ -359,6 +474,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     static_assert(NB <= 64, "row kernel needs nx + nu <= 64");
     static_assert(G == 1 || S == 1, "packed narrow stages take one stage per group");
     static_assert(!TV || S == 1, "time-varying stage data: one stage per wave or group");
+    static_assert(!SETS || S == 1, "non-box sets: one stage per wave or group");
     constexpr int LG = TV ? G : 1;     // groups with their own lane-private rows
     constexpr int NL4 = 3 * NB4 + NX4 + (TV ? NX4 : 0);  // float4 rows per lane
     static_assert(NB % 4 == 0 && NX % 4 == 0, "padded sizes must be multiples of 4");
@@ -409,10 +525,141 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     __shared__ __align__(16) float lmv[kRowWaves][2][2][NB];
     __shared__ __align__(16) float linv[2][2][NB];
     __shared__ int lstop;               // set by the compute waves when they leave the loop
+    // restart acceleration: each compute wave's partial of c^{i+1} (value, then
+    // its tag), and the reducer's decision (c, extrapolation coefficient,
+    // restart count, then the tag word: tag << 32 | stop | nonfinite << 1)
+    __shared__ double lcp[kRowWaves];
+    __shared__ uint32_t lcpt[kRowWaves];
+    __shared__ double ldec_c;
+    __shared__ float ldec_coef;
+    __shared__ int ldec_rs;
+    __shared__ uint64_t ldec_tag;
     for (int i = threadIdx.x; i < kRowWaves * 2 * kMboxVecs * NB; i += blockDim.x) (&lmbox[0][0][0][0])[i] = 0;
     for (int i = threadIdx.x; i < 2 * 2 * NB; i += blockDim.x) (&lin[0][0][0])[i] = 0;
-    if (threadIdx.x == 0) lstop = 0;
+    if (threadIdx.x < kRowWaves) lcpt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        lstop = 0;
+        ldec_tag = 0;
+    }
     __syncthreads();  // no workgroup barrier below this point
+
+    if constexpr (RED) {
+        if (wv == kRowWaves + kRecvWaves) {
+            // ---- reducer wave: for every iteration, c^{i+1} (tag i + 2) of the
+            // whole horizon, then steps 5-7 of Algorithm 1 (reading R11: the
+            // eps stop is tested first; c_prev starts at 1 and takes c^{i+1}
+            // after every decision; a restart sets alpha = 1 and hats = the
+            // current iterate)
+            const int first = lwg * kRowWaves;
+            const int nin = min(kRowWaves, nwaves - first);  // compute waves of this workgroup
+            const double eta = keep_sgpr(a.eta);
+            const bool accel = keep_sgpr(a.accel) != 0;
+            double alpha = 1.0, cprev = 1.0;
+            int restarts = 0;
+            int ck = check_every;
+            for (int it = 0; it < K; ++it) {
+                // c of this step is reduced every step with acceleration, else
+                // every check_every-th step (for the eps stop)
+                if (!accel) {
+                    if (--ck != 0) continue;
+                    ck = check_every;
+                }
+                const uint32_t tag = (uint32_t)it + 2;
+                bool fail = false;
+                // this workgroup's partial: its compute waves' partials in wave order
+                double part = 0.0;
+                for (int w = 0; w < nin && !fail; ++w) {
+                    int spins = 0;
+                    while (__hip_atomic_load(&lcpt[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != tag) {
+                        if ((++spins & 31) == 0) {
+                            if (__hip_atomic_load(&lstop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0 ||
+                                __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                fail = true;
+                                break;
+                            }
+                            if (spins > kSpinLimit) {
+                                __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                fail = true;
+                                break;
+                            }
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the value read stays after the tag
+                    if (!fail) part += lcp[w];
+                }
+                if (fail) return;
+                // publish this workgroup's partial; the reducer of workgroup 0
+                // gathers them all and publishes the decision in one word that
+                // the other reducers poll (two hops, but one reader of the
+                // partials and one word for the rest: an all-to-all gather has
+                // every reducer hammer the same few cache lines).  One slot is
+                // enough: a workgroup's next partial needs this decision, which
+                // needs every partial of this step to have been read.
+                if (lane == 0) gstore(sc.wg_part + lwg, pack((float)part, tag));
+                const gptr<uint64_t> dword = sc.wg_part + nwg;  // tag << 32 | payload
+                constexpr uint32_t kStopWord = 0xFFFFFFFFu, kNonfiniteWord = 0xFFFFFFFEu;
+                bool stop = false, nonfinite = false;
+                float coef = 0.f;
+                double c = 0.0;
+                if (lwg == 0) {
+                    // workgroup order (lane l takes l, l + 64, ...), then a fixed
+                    // shuffle tree: deterministic
+                    float val[1][16];
+                    if (!gather_tagged<1, 16>(sc.wg_part, 0, nwg, tag, val, sc.abort)) return;
+                    double cs = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) cs += (double)val[0][q];
+                    cs = wsum(cs);
+                    c = rho_d * cs;
+                    nonfinite = !(c < INFINITY);
+                    stop = nonfinite || (eps > 0.0 && c <= eps);
+                    if (!stop && accel) {
+                        if (c <= eta * cprev) {
+                            const double a1 = 0.5 + 0.5 * sqrt(1.0 + 4.0 * alpha * alpha);
+                            coef = (float)((alpha - 1.0) / a1);
+                            alpha = a1;
+                        } else {
+                            alpha = 1.0;
+                            ++restarts;
+                        }
+                        cprev = c;
+                    }
+                    const uint32_t payload = nonfinite ? kNonfiniteWord : (stop ? kStopWord : __float_as_uint(coef));
+                    if (lane == 0) gstore(dword, ((uint64_t)tag << 32) | payload);
+                } else {
+                    uint64_t d = 0;
+                    int spins = 0;
+                    for (;;) {
+                        d = gload(dword);
+                        if ((uint32_t)(d >> 32) == tag) break;
+                        if (++spins > kSpinLimit ||
+                            ((spins & 31) == 0 &&
+                             __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                            __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            return;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    const uint32_t payload = (uint32_t)d;
+                    nonfinite = payload == kNonfiniteWord;
+                    stop = nonfinite || payload == kStopWord;
+                    coef = stop ? 0.f : __uint_as_float(payload);
+                }
+                if (lane == 0) {
+                    ldec_c = c;  // (workgroup 0 only: the info record's c)
+                    ldec_coef = coef;
+                    ldec_rs = restarts;
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // payload before tag (in-order LDS)
+                    __hip_atomic_store(&ldec_tag,
+                                       ((uint64_t)tag << 32) | (stop ? 1u : 0u) | (nonfinite ? 2u : 0u),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                if (stop) return;
+            }
+            return;
+        }
+    }
 
     if (wv >= kRowWaves) {
         // ---- receiver wave: side 0 forwards w of the first stage of the right
@@ -512,6 +759,12 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     const float lb_r = rowl ? M[o.lb + r] : 0.f;
     const float ub_r = rowl ? M[o.ub + r] : 0.f;
     const float hbd_r = (rowl && !TV) ? M[o.Hb + r * NB + r] : 0.f;
+    // non-box factors: kinds, the lane's entry of the normal and b or r
+    const int xkind = SETS ? I.xset : 0, ukind = SETS ? I.uset : 0;
+    const bool in_x = SETS && rowl && r < I.nx;
+    const bool in_u = SETS && rowl && r >= NX && r - NX < I.nu;
+    const float ax_r = in_x ? M[o.sx + r] : 0.f, bx = SETS ? M[o.sx + NX] : 0.f;
+    const float au_r = in_u ? M[o.su + (r - NX)] : 0.f, bu = SETS ? M[o.su + NU] : 0.f;
     const float Hq_r = rowl ? Fk[fo.Hq + r] : 0.f;
     const float Hbq_r = rowl ? Fk[fo.Hbq + r] : 0.f;
     const float cq_r = rowl ? Fk[fo.cq + r] : 0.f;
@@ -552,6 +805,26 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
         la[s] = ld ? st[(size_t)(4 * NB + r) * N + k] : 0.f;
         pv[s] = 0.f;
         xs[s] = 0.f;
+    }
+    // Restart acceleration: the previous iterate, and the step-1 products of
+    // it.  Step 1 is affine in the hats, and the hats are an affine
+    // combination of the current and the previous iterate,
+    //   hat = cur + coef (cur - prev),
+    // so the products of the hats are the same combination of the products of
+    // the two iterates.  The mat-vecs therefore run on the current iterate
+    // while the restart decision (which needs c of the whole horizon) is in
+    // flight, and the combination is formed once the decision is known.
+    constexpr int SA = RED ? S : 1;
+    float pvv[SA], pzz[SA], pth[SA], pbe[SA], pla[SA];  // previous iterate
+    float lbb[SA], lxl[SA], lcl[SA];                    // products of the previous iterate
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+        pvv[s] = v[s];
+        pzz[s] = z[s];
+        pth[s] = th[s];
+        pbe[s] = be[s];
+        pla[s] = la[s];
+        lbb[s] = lxl[s] = lcl[s] = 0.f;
     }
 
     const bool has_left = ns > 0 && k0 > 0;
@@ -604,19 +877,137 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     int iters = 0;
     double c_last = 0.0, rp_last = 0.0, rd_last = 0.0;
     int status = 0;
-    bool stop = false;
 
-    int ck = check_every;  // iterations left until the next residual check
+    // per-lane residual terms of the last step (kept for the final pass with
+    // restart acceleration)
+    float cpart = 0.f, rpart = 0.f;
+    float ddv[S], dzv[S], dvv[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) ddv[s] = dzv[s] = dvv[s] = 0.f;
+    // Residuals of the step that produced the iterate with tag `tout`:
+    // c^{i+1}, r_prim and r_dual of the whole horizon, reduced on wave 0.
+    // Each wave has already sent dd of its first stage to the left.
+    auto residuals = [&](const uint32_t tout) {
+        // dual residual (Section IV-B): du block Bbar_k' dv_k and xbar block
+        // dz_{k+1} + Abar_{k+1}' (dz_{k+2} - dv_{k+1}); with the top rows of
+        // Abar' as column r of [A B]: (Abar' x)_r = [r >= NX] x_r + sum_i [A B]_{i r} x_i.
+        float ddR = 0.f;
+        if (has_right && rowl) {
+            uint64_t* lp = &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][tout & 1][2][r];
+            const gptr<uint64_t> gp = mbox_g(gw + 1 < nwaves ? gw + 1 : gw, tout & 1, 2);
+            int spins = 0;
+            for (;;) {
+                uint64_t wd;
+                if (right_in_wg)
+                    wd = lload(lp);
+                else
+                    wd = gload(gp);
+                if (unpack_tag(wd) == tout) {
+                    ddR = unpack_val(wd);
+                    break;
+                }
+                if ((++spins & 31) == 0) {
+                    if (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                        spins > kSpinLimit) {
+                        __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        failed = true;
+                        break;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        float rdpart = 0.f;
+        // dd of the next stage when it sits in the next group of lanes
+        const float ddg = (G > 1) ? __shfl(ddv[0], lane + NB < 64 ? lane + NB : lane, 64) : 0.f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s < nsl) {
+                const int t = tb + s;
+                float ddn = (t + 1 < ns) ? (G > 1 ? ddg : 0.f) : ddR;
+#pragma unroll
+                for (int u = 1; u < S; ++u)
+                    if (u == s + 1 && t + 1 < ns) ddn = ddv[u];
+                const bool hasnext = kl + s + 1 < N;
+                if (rowl) {
+                    bc[3 * tb + 0][r] = dvv[s];
+                    bc[3 * tb + 1][r] = ddn;
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (rowl) {
+                    float bt = (r >= NX) ? dvv[s] : 0.f;
+                    float tg = (r >= NX) ? ddn : 0.f;
+#pragma unroll
+                    for (int q = 0; q < NX4; ++q) {
+                        const float4 c4 = LACOL(q);  // Abar_{k+1} (the next stage's)
+                        float4 b4 = c4;                // Bbar_k (this stage's)
+                        if constexpr (TV) b4 = LBCOL(q);
+                        const float4 x4 = *(const float4*)&bc[3 * tb + 0][4 * q];
+                        const float4 y4 = *(const float4*)&bc[3 * tb + 1][4 * q];
+                        bt += b4.x * x4.x + b4.y * x4.y + b4.z * x4.z + b4.w * x4.w;
+                        tg += c4.x * y4.x + c4.y * y4.y + c4.z * y4.z + c4.w * y4.w;
+                    }
+                    if (r >= NX) rdpart = fmax(rdpart, fabsf(bt));
+                    rdpart = fmax(rdpart, fabsf(dzv[s] + (hasnext ? tg : 0.f)));
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (!rowl) cpart = rpart = rdpart = 0.f;
+        const double csum = wsum((double)cpart);
+        const double rpm = wmax((double)rpart);
+        const double rdm = wmax((double)rdpart);
+        if (lane == 0) {
+            gstore(sc.red + gw, pack((float)csum, tout));
+            gstore(sc.red + nwaves + gw, pack((float)rpm, tout));
+            gstore(sc.red + 2 * nwaves + gw, pack((float)rdm, tout));
+        }
+        if (gw == 0) {
+            // deterministic reduction: lane l takes waves l, l + 64, ... in
+            // order, then a fixed shuffle tree combines the lanes
+            float val[3][16];
+            const bool ok = gather_tagged<3, 16>(sc.red, (size_t)nwaves, nwaves, tout, val, sc.abort);
+            double cs = 0.0, rp = 0.0, rd = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                cs += (double)val[0][q];
+                rp = fmax(rp, (double)val[1][q]);
+                rd = fmax(rd, (double)val[2][q]);
+            }
+            cs = wsum(cs);
+            rp = wmax(rp);
+            rd = wmax(rd);
+            if (lane == 0) {
+                c_last = rho_d * cs;
+                rp_last = rp;
+                rd_last = rho_d * rd;
+                if (!(c_last < INFINITY)) status = -4;
+                if (!ok) status = -5;
+            }
+        }
+    };
+
+    int ck = check_every;  // steps left until c next goes to the reducer (eps stop)
+    const bool accel = RED && keep_sgpr(a.accel) != 0;
+    bool pub_prev = false;  // the previous step's c went to the reducer: its decision is due
 #pragma unroll 1
-    for (int it = 0; it < K && !stop; ++it) {
+    for (int it = 0; it < K; ++it) {
         const uint32_t tin = (uint32_t)it + 1;   // tag of the iterate this step reads
         const uint32_t tout = (uint32_t)it + 2;  // tag of the iterate it produces
         // residuals every check_every-th iteration when stopping on eps, and
         // after the last one
-        bool check = it == K - 1;
-        if (eps > 0.0 && --ck == 0) {
-            check = true;
-            ck = check_every;
+        // the plain kernel (fixed K) forms the residuals after the last step;
+        // with a reducer wave, c goes to it after every step (acceleration) or
+        // every check_every-th step (eps stop), and r_prim, r_dual are formed
+        // once, after the loop
+        const bool check = !RED && it == K - 1;
+        bool pub = false;
+        if constexpr (RED) {
+            pub = accel;
+            if (!accel && --ck == 0) {
+                pub = true;
+                ck = check_every;
+            }
         }
 
         // ---- halo mailboxes of the iterate entering this step (LDS only): w of
@@ -641,8 +1032,9 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 if (s < nsl) {
-                    pv[s] = v[s] - be[s];
-                    bc[3 * (tb + s) + 0][r] = pv[s];
+                    const float p_ = v[s] - be[s];
+                    if constexpr (!RED) pv[s] = p_;  // with acceleration: from the hats, below
+                    bc[3 * (tb + s) + 0][r] = p_;
                     bc[3 * (tb + s) + 1][r] = dvec(s);
                     bc[3 * (tb + s) + 2][r] = wvec(s);
                 }
@@ -825,23 +1217,84 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             if (has_left && tb == 0) cl[0] += rho * ((y0 + y1) + (y2 + y3));
         }
 
+        if constexpr (RED) {
+            // ---- steps 6-7: the decision taken on c^{i} of the previous
+            // step (none before the first step, where the hats are the
+            // initial iterate)
+            float coef = 0.f;
+            if (pub_prev) {
+                const uint64_t want = (uint64_t)(it + 1);
+                uint64_t d = 0;
+                int spins = 0;
+                for (;;) {
+                    d = __hip_atomic_load(&ldec_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if ((d >> 32) == want) break;
+                    if ((++spins & 31) == 0) {
+                        if (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                            spins > kSpinLimit) {
+                            __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            failed = true;
+                            break;
+                        }
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the payload read stays after the tag
+                if (failed) {
+                    status = -5;
+                    break;
+                }
+                if (d & 2u) status = -4;  // c^{i} is not finite
+                if (d & 1u) break;        // step 5: c^{i} <= eps (the iterate stays the current one)
+                coef = accel ? ldec_coef : 0.f;
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const float b_ = bb[s], x_ = xl[s], c_ = cl[s];
+                bb[s] = b_ + coef * (b_ - lbb[s]);
+                xl[s] = x_ + coef * (x_ - lxl[s]);
+                cl[s] = c_ + coef * (c_ - lcl[s]);
+                lbb[s] = b_;
+                lxl[s] = x_;
+                lcl[s] = c_;
+                auto hat = [&](float& cur, float& prv) {
+                    const float h = cur + coef * (cur - prv);
+                    prv = cur;
+                    cur = h;
+                };
+                hat(v[s], pvv[s]);
+                hat(z[s], pzz[s]);
+                hat(th[s], pth[s]);
+                hat(be[s], pbe[s]);
+                hat(la[s], pla[s]);
+                pv[s] = v[s] - be[s];  // du of this step is J (vhat - betahat)
+            }
+        }
+
         // ---- steps 2-3 (Theorem 1 closed form, box projection, dual update)
         // (lanes without a row hold zeros throughout: their bounds are [0, 0])
-        float cpart = 0.f, rpart = 0.f;
-        float ddv[S], dzv[S], dvv[S];
+        cpart = 0.f;
+        rpart = 0.f;
+        float yset = 0.f;  // non-box factors: Theorem 1's point projected factor by factor
+        if constexpr (SETS) {
+            yset = (2.f * (xl[0] + th[0]) + bb[0] + cl[0]) * third;
+            yset = project_row_factor<G, NB>(yset, in_x, r, I.nx, xkind, ax_r, bx, grp * NB);
+            yset = project_row_factor<G, NB>(yset, in_u, r - NX, I.nu, ukind, au_r, bu, grp * NB + NX);
+        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             ddv[s] = dzv[s] = dvv[s] = 0.f;
             if (s < nsl) {
                 const float bi = bb[s], ci = cl[s], xi = xl[s];
                 const float gam = bi - ci;
-                const float y = (2.f * (xi + th[s]) + bi + ci) * third;
+                // (a non-box factor stores +-inf bounds, so the clamp only zeroes padding)
+                const float y = SETS ? yset : (2.f * (xi + th[s]) + bi + ci) * third;
                 const float zn = y < lb_r ? lb_r : (y > ub_r ? ub_r : y);
                 const float vn = (zn + gam) * 0.5f;
                 const float thn = th[s] + xi - zn;
                 const float ben = bi - vn;
                 const float lan = zn - vn - ci;
-                if (check) {
+                if (check || RED) {
                     const float dv = vn - v[s], dz = zn - z[s];
                     const float dth = thn - th[s], dbe = ben - be[s], dla = lan - la[s];
                     const float dd = dz - dv;
@@ -860,159 +1313,60 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
             }
         }
         publish(tout);
-        if (check && has_left && rowl && tb == 0) put(left_in_wg, tout & 1, 2, pack(ddv[0], tout));
         ++iters;
-
-        if (check) {
-            // dual residual (Section IV-B): du block Bbar_k' dv_k and xbar block
-            // dz_{k+1} + Abar_{k+1}' (dz_{k+2} - dv_{k+1}); with the top rows of
-            // Abar' as column r of [A B]: (Abar' x)_r = [r >= NX] x_r + sum_i [A B]_{i r} x_i.
-            float ddR = 0.f;
-            if (has_right && rowl) {
-                uint64_t* lp = &lmbox[wv + 1 < kRowWaves ? wv + 1 : wv][tout & 1][2][r];
-                const gptr<uint64_t> gp = mbox_g(gw + 1 < nwaves ? gw + 1 : gw, tout & 1, 2);
-                int spins = 0;
-                for (;;) {
-                    uint64_t wd;
-                    if (right_in_wg)
-                        wd = lload(lp);
-                    else
-                        wd = gload(gp);
-                    if (unpack_tag(wd) == tout) {
-                        ddR = unpack_val(wd);
-                        break;
-                    }
-                    if ((++spins & 31) == 0) {
-                        if (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                            spins > kSpinLimit) {
-                            __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            failed = true;
-                            break;
-                        }
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            float rdpart = 0.f;
-            // dd of the next stage when it sits in the next group of lanes
-            const float ddg = (G > 1) ? __shfl(ddv[0], lane + NB < 64 ? lane + NB : lane, 64) : 0.f;
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if (s < nsl) {
-                    const int t = tb + s;
-                    float ddn = (t + 1 < ns) ? (G > 1 ? ddg : 0.f) : ddR;
-#pragma unroll
-                    for (int u = 1; u < S; ++u)
-                        if (u == s + 1 && t + 1 < ns) ddn = ddv[u];
-                    const bool hasnext = kl + s + 1 < N;
-                    if (rowl) {
-                        bc[3 * tb + 0][r] = dvv[s];
-                        bc[3 * tb + 1][r] = ddn;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    if (rowl) {
-                        float bt = (r >= NX) ? dvv[s] : 0.f;
-                        float tg = (r >= NX) ? ddn : 0.f;
-#pragma unroll
-                        for (int q = 0; q < NX4; ++q) {
-                            const float4 c4 = LACOL(q);  // Abar_{k+1} (the next stage's)
-                            float4 b4 = c4;                // Bbar_k (this stage's)
-                            if constexpr (TV) b4 = LBCOL(q);
-                            const float4 x4 = *(const float4*)&bc[3 * tb + 0][4 * q];
-                            const float4 y4 = *(const float4*)&bc[3 * tb + 1][4 * q];
-                            bt += b4.x * x4.x + b4.y * x4.y + b4.z * x4.z + b4.w * x4.w;
-                            tg += c4.x * y4.x + c4.y * y4.y + c4.z * y4.z + c4.w * y4.w;
-                        }
-                        if (r >= NX) rdpart = fmax(rdpart, fabsf(bt));
-                        rdpart = fmax(rdpart, fabsf(dzv[s] + (hasnext ? tg : 0.f)));
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                }
-            }
-            if (!rowl) cpart = rpart = rdpart = 0.f;
-            const double csum = wsum((double)cpart);
-            const double rpm = wmax((double)rpart);
-            const double rdm = wmax((double)rdpart);
+        if constexpr (RED) pub_prev = pub;
+        if (RED && pub) {
+            // this wave's partial of c^{i+1}, for the reducer wave
+            const double csum = wsum((double)(rowl ? cpart : 0.f));
             if (lane == 0) {
-                sc.red_val[gw * 3 + 0] = csum;
-                sc.red_val[gw * 3 + 1] = rpm;
-                sc.red_val[gw * 3 + 2] = rdm;
-                __hip_atomic_store(&sc.red_tag[gw], (uint64_t)tout, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (gw == 0) {
-                // deterministic reduction: lane l accumulates waves l, l+64, ...
-                // in order, then a fixed shuffle tree combines the lanes
-                double cs = 0.0, rp = 0.0, rd = 0.0;
-                bool lfail = false;
-                for (int w0 = 0; w0 < nwaves; w0 += 64) {
-                    const int w = w0 + lane;
-                    if (w < nwaves && !lfail) {
-                        int spins = 0;
-                        while (__hip_atomic_load(&sc.red_tag[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-                               (uint64_t)tout) {
-                            if (++spins > kSpinLimit ||
-                                __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                                __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                lfail = true;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                        }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    if (w < nwaves && !lfail) {
-                        cs += sc.red_val[w * 3 + 0];
-                        rp = fmax(rp, sc.red_val[w * 3 + 1]);
-                        rd = fmax(rd, sc.red_val[w * 3 + 2]);
-                    }
-                }
-                cs = wsum(cs);
-                rp = wmax(rp);
-                rd = wmax(rd);
-                const bool anyfail = wave_any(lfail);
-                if (lane == 0) {
-                    c_last = rho_d * cs;
-                    rp_last = rp;
-                    rd_last = rho_d * rd;
-                    int dec = 0;
-                    if (!(c_last < INFINITY)) {
-                        status = -4;
-                        dec = 1;
-                    }
-                    if (eps > 0.0 && c_last <= eps) dec = 1;
-                    if (anyfail) {
-                        status = -5;
-                        dec = 1;
-                    }
-                    __hip_atomic_store(sc.decision, ((uint64_t)tout << 32) | (uint64_t)dec, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            if (eps > 0.0) {  // everyone learns the decision (stop or continue)
-                uint64_t d = 0;
-                if (lane == 0) {
-                    int spins = 0;
-                    for (;;) {
-                        d = __hip_atomic_load(sc.decision, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                        if ((uint32_t)(d >> 32) == tout) break;
-                        if (++spins > kSpinLimit ||
-                            __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            d = 1;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-                d = __shfl(d, 0, 64);
-                if ((uint32_t)d & 1u) stop = true;
+                lcp[wv] = csum;
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);  // value before tag (in-order LDS)
+                __hip_atomic_store(&lcpt[wv], tout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
+
     }
 
     // leaving before K iterations (stop decision or failure): no compute wave
     // of this workgroup consumes another halo, so the receivers may end too
     if (iters < K && lane == 0) __hip_atomic_store(&lstop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+    // ---- residuals of the last step (after the loop, so that the gather's
+    // registers do not weigh on the loop); with a reducer wave, c^{i+1} and
+    // the restart count are the reducer's when the last step's c went to it
+    int restarts_out = 0;
+    if (!failed && iters > 0) {
+        const uint32_t tf = (uint32_t)iters + 1;
+        if (has_left && rowl && tb == 0) put(left_in_wg, tf & 1, 2, pack(ddv[0], tf));
+        residuals(tf);
+    }
+    if constexpr (RED) {
+        if (!failed && iters > 0) {
+            const uint32_t tf = (uint32_t)iters + 1;
+            if (gw == 0 && pub_prev) {  // the last step's c went to the reducer
+                uint64_t d = 0;
+                int spins = 0;
+                for (;;) {
+                    d = __hip_atomic_load(&ldec_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if ((uint32_t)(d >> 32) == tf) break;
+                    if ((++spins & 31) == 0 &&
+                        (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                         spins > kSpinLimit)) {
+                        __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        status = -5;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the payload reads stay after the tag
+                if (status != -5) {
+                    c_last = ldec_c;
+                    restarts_out = ldec_rs;
+                    if (d & 2u) status = -4;
+                }
+            }
+        }
+    }
 
     // ---- outputs: final iterate; du_k = J_k (v_k - beta_k) and xbar_{k+1}
     // of the last step 1
@@ -1056,7 +1410,7 @@ __global__ void __launch_bounds__(kRowThreads) row_kernel(const RowArgs* __restr
     if (gw == 0 && lane == 0 && a.info) {
         InfoDev rec;
         rec.iters = iters;
-        rec.restarts = 0;
+        rec.restarts = restarts_out;
         rec.c = c_last;
         rec.r_prim = rp_last;
         rec.r_dual = rd_last;
@@ -1087,54 +1441,69 @@ struct RowCfg {
 // the 2-state, 1-input reactor at N = 5000).
 constexpr RowCfg kRowCfgs[] = {{4, 4}, {8, 8}, {24, 12}, {32, 16}};
 
-template <int NX, int NU, int S, bool TV>
+template <int NX, int NU, int S, bool TV, bool RED, bool SETS>
 hipError_t row_launch_t(const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
     const size_t lds = row_lds_bytes(NX, NU, S, TV);
+    constexpr int threads = RED ? kRowThreadsRed : kRowThreads;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)row_kernel<NX, NU, S, TV>,
+        hipError_t e = hipFuncSetAttribute((const void*)row_kernel<NX, NU, S, TV, RED, SETS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, row_kernel<NX, NU, S, TV>, kRowThreads, lds);
-    hipLaunchKernelGGL((row_kernel<NX, NU, S, TV>), dim3(nwg), dim3(kRowThreads), lds, s, a_dev, nwaves, nwg);
+    if (occ)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, row_kernel<NX, NU, S, TV, RED, SETS>, threads, lds);
+    hipLaunchKernelGGL((row_kernel<NX, NU, S, TV, RED, SETS>), dim3(nwg), dim3(threads), lds, s, a_dev, nwaves,
+                       nwg);
     return hipGetLastError();
 }
 
-template <int NX, int NU>
+template <int NX, int NU, bool RED, bool SETS>
 hipError_t row_launch_s(int S, bool tv, const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s, int* occ) {
     if (tv) {  // time-varying stage data: one stage per wave or group
         if (S != 1) return hipErrorInvalidValue;
-        return row_launch_t<NX, NU, 1, true>(a_dev, nwaves, nwg, s, occ);
+        return row_launch_t<NX, NU, 1, true, RED, SETS>(a_dev, nwaves, nwg, s, occ);
     }
-    if constexpr (row_groups(NX + NU) > 1) {  // packed narrow stages: one stage per group
+    // packed narrow stages, non-box sets: one stage per wave or group
+    if constexpr (SETS || row_groups(NX + NU) > 1) {
         if (S != 1) return hipErrorInvalidValue;
-        return row_launch_t<NX, NU, 1, false>(a_dev, nwaves, nwg, s, occ);
+        return row_launch_t<NX, NU, 1, false, RED, SETS>(a_dev, nwaves, nwg, s, occ);
     } else {
         switch (S) {
             case 1:
-                return row_launch_t<NX, NU, 1, false>(a_dev, nwaves, nwg, s, occ);
+                return row_launch_t<NX, NU, 1, false, RED, false>(a_dev, nwaves, nwg, s, occ);
             case 2:
-                return row_launch_t<NX, NU, 2, false>(a_dev, nwaves, nwg, s, occ);
+                return row_launch_t<NX, NU, 2, false, RED, false>(a_dev, nwaves, nwg, s, occ);
             case 4:
-                return row_launch_t<NX, NU, 4, false>(a_dev, nwaves, nwg, s, occ);
+                return row_launch_t<NX, NU, 4, false, RED, false>(a_dev, nwaves, nwg, s, occ);
             default:
                 return hipErrorInvalidValue;
         }
     }
 }
 
+template <bool RED, bool SETS>
+hipError_t row_launch_cls(const InstDev& I, int S, const RowArgs* a_dev, int nwaves, int nwg, hipStream_t s,
+                          int* occ) {
+    const bool tv = I.tv != 0;
+    if (I.nxp == 4 && I.nup == 4) return row_launch_s<4, 4, RED, SETS>(S, tv, a_dev, nwaves, nwg, s, occ);
+    if (I.nxp == 8 && I.nup == 8) return row_launch_s<8, 8, RED, SETS>(S, tv, a_dev, nwaves, nwg, s, occ);
+    if (I.nxp == 24 && I.nup == 12) return row_launch_s<24, 12, RED, SETS>(S, tv, a_dev, nwaves, nwg, s, occ);
+    if (I.nxp == 32 && I.nup == 16) return row_launch_s<32, 16, RED, SETS>(S, tv, a_dev, nwaves, nwg, s, occ);
+    return hipErrorInvalidValue;
+}
+
 hipError_t row_launch_any(const InstDev& I, int S, const RowArgs* a_dev, hipStream_t s, int* occ) {
     const int per = S * row_groups(I.nbp);  // stages per wave
     const int nwaves = (I.N + per - 1) / per;
     const int nwg = (nwaves + kRowWaves - 1) / kRowWaves;
-    const bool tv = I.tv != 0;
-    if (I.nxp == 4 && I.nup == 4) return row_launch_s<4, 4>(S, tv, a_dev, nwaves, nwg, s, occ);
-    if (I.nxp == 8 && I.nup == 8) return row_launch_s<8, 8>(S, tv, a_dev, nwaves, nwg, s, occ);
-    if (I.nxp == 24 && I.nup == 12) return row_launch_s<24, 12>(S, tv, a_dev, nwaves, nwg, s, occ);
-    if (I.nxp == 32 && I.nup == 16) return row_launch_s<32, 16>(S, tv, a_dev, nwaves, nwg, s, occ);
-    return hipErrorInvalidValue;
+    const bool sets = I.xset != 0 || I.uset != 0;
+    if (I.row_acc)
+        return sets ? row_launch_cls<true, true>(I, S, a_dev, nwaves, nwg, s, occ)
+                    : row_launch_cls<true, false>(I, S, a_dev, nwaves, nwg, s, occ);
+    return sets ? row_launch_cls<false, true>(I, S, a_dev, nwaves, nwg, s, occ)
+                : row_launch_cls<false, false>(I, S, a_dev, nwaves, nwg, s, occ);
 }
 
 int num_cus() {
@@ -1154,7 +1523,8 @@ int num_cus() {
 // (lmbox, lin, lmv, linv, lstop as declared in the kernel).
 constexpr size_t row_total_lds(int NX, int NU, bool tv) {
     const size_t NB = (size_t)(NX + NU);
-    return row_lds_bytes(NX, NU, 1, tv) + 8 * NB * (kRowWaves * 2 * kMboxVecs + 4) + 4 * NB * (kRowWaves * 4 + 4) + 16;
+    return row_lds_bytes(NX, NU, 1, tv) + 8 * NB * (kRowWaves * 2 * kMboxVecs + 4) + 4 * NB * (kRowWaves * 4 + 4) + 16 +
+           12 * kRowWaves + 32;
 }
 constexpr size_t kRowLdsLimit = 160 * 1024;  // per workgroup on gfx950
 
@@ -1185,13 +1555,16 @@ hipError_t row_prepare(int fp64, InstDev& I) {
     (void)fp64;
     const int want = I.row_s > 0 ? I.row_s : 1;
     for (int S : {want, 1, 2, 4}) {
-        if (S > 1 && (row_groups(I.nbp) > 1 || I.tv)) break;  // packed narrow stages, time-varying data: S = 1
+        // packed narrow stages, time-varying data, non-box sets: S = 1
+        if (S > 1 && (row_groups(I.nbp) > 1 || I.tv || I.xset != 0 || I.uset != 0)) break;
         int occ = 0;
         hipError_t e = row_launch_any(I, S, nullptr, nullptr, &occ);
         if (e != hipSuccess) return e;
         const int per = S * row_groups(I.nbp);
         const int nwg = ((I.N + per - 1) / per + kRowWaves - 1) / kRowWaves;
-        if (occ > 0 && nwg <= occ * num_cus()) {
+        // (the reducer wave of the accelerated kernel gathers at most 1024
+        // workgroup partials)
+        if (occ > 0 && nwg <= occ * num_cus() && (!I.row_acc || nwg <= 1024)) {
             I.row_s = S;
             return hipSuccess;
         }

@@ -22,7 +22,7 @@ struct InstDev {
     int32_t cls;               // lane-family class index (-1 if row family)
     int32_t tv;                // time-varying stage data
     int32_t hb_diag;           // H_{N-1} is diagonal (time-invariant only)
-    int32_t spare;             // unused (keeps the 8-byte alignment of the offsets below)
+    int32_t row_acc;           // row family: kernel with a reducer wave (eps stop, restart acceleration)
     int32_t row_s;             // row family: stages per wave (block size S)
     int32_t xset, uset;        // constraint-set kinds of the x and u factors (PIMPC_SET_*)
     int64_t mat_off;           // T matrix block (see layout below)

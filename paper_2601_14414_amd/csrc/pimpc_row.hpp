@@ -26,6 +26,9 @@ struct RowArgs {
     int32_t check_every;
     int32_t warm;
     int32_t write_iters;
+    double eta;           // restart threshold of Algorithm 1 step 6
+    int32_t accel;        // restart acceleration (Algorithm 1 steps 6-7) on
+    int32_t pad2;
 };
 
 // True if the row family handles an instance of this shape; sets the padded sizes.
