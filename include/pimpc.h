@@ -24,14 +24,15 @@
  *     pimpc_backward for FP32 time-invariant instances with N <= 256;
  *   - row family, one row of a stage per lane, one block of stages per wave
  *     (FP32, nx <= 32, nu <= 16; time-varying data up to nx <= 24, nu <= 12;
- *     box sets, plain ADMM), as long as the horizon fits one grid whose
- *     workgroups are all resident at once (up to 4 stages per wave; for the
- *     24 + 12 class N <= 4096 on 256 compute units).
+ *     restart acceleration; non-box sets at one stage per wave or group; no
+ *     tape), as long as the horizon fits one grid whose workgroups are all
+ *     resident at once (up to 4 stages per wave; for the 24 + 12 class
+ *     N <= 4096 on 256 compute units, N <= 1024 with non-box sets).
  * With options.family = PIMPC_FAMILY_AUTO, a context of one FP32 instance
- * with box sets, plain ADMM and no tape runs on the row family whenever a row
- * class holds it (its iteration is several times shorter than one lane
- * walking all rows of its stage); otherwise, and for every instance of a
- * batch, the lane family serves what it holds and the row family the rest.
+ * with box sets and no tape runs on the row family whenever a row class
+ * holds it (its iteration is several times shorter than one lane walking all
+ * rows of its stage); otherwise, and for every instance of a batch, the lane
+ * family serves what it holds and the row family the rest.
  * A request outside these returns PIMPC_E_UNSUPPORTED from pimpc_setup.
  *
  * Conventions common to every entry point:
@@ -109,9 +110,10 @@ extern "C" {
 typedef struct pimpc_ctx_s *pimpc_ctx;
 
 /*
- * Problem data, eqn. (1) with C = I, W_y = Q, W_u = R (Section II), the
- * velocity-form linear term qbar of Theorem 2 and the input-rate weight
- * W_du of the experiments (Section V).
+ * Problem data, eqn. (1) (Section II) with W_u = R: the state weight Q
+ * (C = I, W_y = Q) or the output form below, the velocity-form linear term
+ * qbar of Theorem 2 and the input-rate weight W_du of the experiments
+ * (Section V).
  *   count          number of instances (>= 1)
  *   nx, nu, N      per-instance state/input sizes and horizon (count entries each)
  *   time_varying   0: one (A, B, e) per instance; 1: N stage copies per instance
@@ -125,11 +127,29 @@ typedef struct pimpc_ctx_s *pimpc_ctx;
  *                  du cache: J_k = (Wdu / rho + Bbar_k' Bbar_k)^-1 Bbar_k'.
  *   xset, uset     per-instance PIMPC_SET_* kind of the X and U factors, NULL =
  *                  all boxes.  For a non-box factor the matching xmin/xmax (or
- *                  umin/umax) entries are ignored.  Non-box sets run on the
- *                  lane family (N <= 512) without a tape; other requests
- *                  return PIMPC_E_UNSUPPORTED.
+ *                  umin/umax) entries are ignored.  Non-box sets run without
+ *                  a tape (the taped forward returns PIMPC_E_UNSUPPORTED).
  *   xset_par       (nx + 1) values per instance: (a, b) or (., r); may be NULL
  *   uset_par       (nu + 1) values per instance, likewise
+ * Output form of eqn. (1), all optional (ny == NULL: C = I with W_y = Q and
+ * r_y = 0; ru == NULL: r_u = 0).  The tracking cost
+ * 1/2 ||C x_{k+1} - r_y||^2_Wy + 1/2 ||u_k - r_u||^2_R is folded into the
+ * velocity-form weights at setup (constant terms dropped):
+ *   Q <- Q + C' Wy C,  qbar_x <- qbar_x + C' Wy r_y,  qbar_u <- qbar_u + R r_u.
+ *   ny             outputs per instance (count entries, each >= 0 and <= 32)
+ *   C              ny*nx output matrix per instance (y = C x), row-major
+ *   Wy             ny*ny symmetric PSD output weight per instance
+ *   ry             ny output reference per instance, NULL = 0
+ *   ymin, ymax     ny output bounds per instance, NULL = none; +-INFINITY
+ *                  allowed.  A finite bound on output i needs row i of C to
+ *                  select one state (one nonzero c_ij): it then tightens the
+ *                  box of x_j to [ymin_i, ymax_i] / c_ij, so X stays a box
+ *                  (the output constraints of the experiments of Section V
+ *                  are of this kind).  A finite bound on a row that mixes
+ *                  states returns PIMPC_E_UNSUPPORTED; an empty intersection
+ *                  PIMPC_E_ARG.  The x factor must then be a box.
+ *   ru             nu input reference per instance (W_u = R), NULL = 0
+ * With the output form Q may be NULL (= 0).
  */
 typedef struct {
     int32_t count;
@@ -152,6 +172,13 @@ typedef struct {
     const int32_t *uset;
     const double *xset_par;
     const double *uset_par;
+    const int32_t *ny;
+    const double *C;
+    const double *Wy;
+    const double *ry;
+    const double *ymin;
+    const double *ymax;
+    const double *ru;
 } pimpc_problem;
 
 /*
@@ -165,7 +192,11 @@ typedef struct {
  *   eta          restart threshold (Algorithm 1 uses 0.999)
  *   warm_start   1 = start from the previous solve's iterate (unshifted)
  *   ckpt_every   > 0 records a tape for pimpc_backward every that many iterations
- *   schedule     batch schedule: 0 = autotune, > 0 = fixed candidate index
+ *   schedule     batch schedule: 0 = autotune (measured at setup), k = 1..8 a
+ *                fixed candidate: bin claiming by atomic counter (1, 2, 5, 6,
+ *                7), static striding (3) or one workgroup per bin (4, 8), on
+ *                4, 1, 4, 4, 4, 3, 2, 4 streams, class launches whole (1-4)
+ *                or split in two (5-8)
  *   family       kernel family: PIMPC_FAMILY_AUTO (choose as described at the
  *                top of this file), PIMPC_FAMILY_LANE or PIMPC_FAMILY_ROW
  *                (PIMPC_E_UNSUPPORTED when that family cannot serve an

@@ -96,9 +96,52 @@ def project(spec, w, lo=None, hi=None):
     return w
 
 
+def effective(p):
+    """Problem `p` with the output form of eqn. (1) written into the velocity-
+    form weights: cost 1/2||C x - ry||^2_Wy + 1/2||u - ru||^2_R, expanded with
+    its constant dropped, adds C'Wy C to Q, C'Wy ry to the x part and R ru to
+    the u part of the linear term qbar (the cost is -qbar' xbar); an output
+    bound on a row of C with one nonzero c_ij bounds x_j by [ymin, ymax]/c_ij.
+    Problems without the output form are returned unchanged."""
+    C = getattr(p, "C", None)
+    ru = getattr(p, "ru", None)
+    if C is None and ru is None:
+        return p
+    Q = np.array(p.Q, np.float64)
+    qbar = np.zeros(p.nx + p.nu) if p.qbar is None else np.array(p.qbar, np.float64)
+    xmin = np.array(p.xmin, np.float64)
+    xmax = np.array(p.xmax, np.float64)
+    if C is not None:
+        C = np.asarray(C, np.float64)
+        Wy = np.asarray(p.Wy, np.float64)
+        Q = Q + C.T @ Wy @ C
+        if getattr(p, "ry", None) is not None:
+            qbar[:p.nx] += C.T @ (Wy @ np.asarray(p.ry, np.float64))
+        ny = C.shape[0]
+        lo = np.full(ny, -np.inf) if getattr(p, "ymin", None) is None else np.asarray(p.ymin, np.float64)
+        hi = np.full(ny, np.inf) if getattr(p, "ymax", None) is None else np.asarray(p.ymax, np.float64)
+        for i in range(ny):
+            if lo[i] == -np.inf and hi[i] == np.inf:
+                continue
+            nz = np.flatnonzero(C[i])
+            if nz.size != 1:
+                raise OracleError("a bounded output must select one state")
+            j = int(nz[0])
+            a, b = lo[i] / C[i, j], hi[i] / C[i, j]
+            if C[i, j] < 0:
+                a, b = b, a
+            xmin[j] = max(xmin[j], a)
+            xmax[j] = min(xmax[j], b)
+    if ru is not None:
+        qbar[p.nx:] += np.asarray(p.R, np.float64) @ np.asarray(ru, np.float64)
+    return p.copy(Q=Q, qbar=qbar, xmin=xmin, xmax=xmax, C=None, Wy=None, ry=None, ymin=None,
+                  ymax=None, ru=None)
+
+
 def factor(p):
     """Stage caches (H_k, J_k) of Algorithm 1 for problem `p` (FP64)."""
     lib = _load()
+    p = effective(p)
     nb = p.nx + p.nu
     H = np.zeros((p.N, nb, nb))
     J = np.zeros((p.N, p.nu, nb))
@@ -122,6 +165,7 @@ def solve(p, K: Optional[int] = None, eps: float = 0.0, accel: bool = False, eta
     hist=(iters,4) [c, r_prim, r_dual, restart], iters, u0 = u_prev + du_0).
     """
     lib = _load()
+    p = effective(p)
     K = p.K if K is None else K
     nb = p.nx + p.nu
     st = zero_state(p) if state is None else _c(state).copy()

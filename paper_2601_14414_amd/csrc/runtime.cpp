@@ -198,6 +198,7 @@ struct pimpc_ctx_s {
     Bin* d_bins = nullptr;
     int32_t* d_counters = nullptr;
     std::vector<ClassRun> runs;
+    std::vector<int> bin_waves;  // waves of each bin (host copy of the schedule, for the autotuner)
     std::vector<int> row_insts;  // instances handled by the row family
     void* d_row_clear = nullptr;   // per-solve scratch of the row-family instances (cleared every solve)
     void* d_row_fused = nullptr;   // fused stage data of the row-family instances
@@ -560,6 +561,8 @@ static void build_args(pimpc_ctx ctx, const void* x0, const void* up, void* u0, 
         a.scratch = sc.row_clear + ctx->row_clear_off[j];
         a.fused = (const char*)ctx->d_row_fused + ctx->row_fused_off[j];
         a.fbad = ctx->d_ibad;
+        a.eta = ctx->opt.eta;
+        a.accel = ctx->opt.accel;
     }
 }
 
@@ -707,37 +710,91 @@ static int run_set(pimpc_ctx ctx, LaunchSet* ls, hipStream_t s, bool graph) {
     return PIMPC_OK;
 }
 
-// Pick the schedule (counter-claimed vs static striding vs one workgroup per
-// bin, and 1 or 4 streams) by timing each candidate once on the real batch.
+// Each class launch split in two, at the bin where the waves of its
+// (largest-first) bins reach half of the class's: twice as many, smaller
+// launches for the streams to balance.  Costs split in proportion.
+static std::vector<ClassRun> split_runs(pimpc_ctx ctx, const std::vector<ClassRun>& base) {
+    std::vector<ClassRun> out;
+    for (const ClassRun& r : base) {
+        if (r.nbins < 2) {
+            out.push_back(r);
+            continue;
+        }
+        int64_t total = 0;
+        for (int b = 0; b < r.nbins; ++b) total += ctx->bin_waves[r.bin_first + b];
+        int64_t acc = 0;
+        int cut = 1;
+        for (int b = 0; b < r.nbins - 1; ++b) {
+            acc += ctx->bin_waves[r.bin_first + b];
+            cut = b + 1;
+            if (2 * acc >= total) break;
+        }
+        int64_t w0 = 0;
+        for (int b = 0; b < cut; ++b) w0 += ctx->bin_waves[r.bin_first + b];
+        ClassRun a = r, c = r;
+        a.nbins = cut;
+        c.bin_first = r.bin_first + cut;
+        c.nbins = r.nbins - cut;
+        a.cost = std::max<int64_t>(1, r.cost * w0 / std::max<int64_t>(total, 1));
+        c.cost = std::max<int64_t>(1, r.cost - a.cost);
+        out.push_back(a);
+        out.push_back(c);
+    }
+    return out;
+}
+
+// Time one enqueued solve (or one class alone) on the context's stream.
+static int time_launch(pimpc_ctx ctx, LaunchSet* ls, int only_class, hipEvent_t t0, hipEvent_t t1, float* ms) {
+    HIPCHK(ctx, hipEventRecord(t0, ctx->stream));
+    if (only_class < 0) {
+        const int rc = enqueue_solve(ctx, ls, ctx->stream);
+        if (rc != PIMPC_OK) return rc;
+    } else {
+        const ClassRun& r = ctx->runs[only_class];
+        if (ctx->schedule == 1) HIPCHK(ctx, launch_fill<int32_t>(ctx->d_counters + only_class, 1, 0, ctx->stream));
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, ls->d_args + only_class, r.nbmax, class_grid(ctx, r),
+                                      ctx->stream, nullptr));
+    }
+    HIPCHK(ctx, hipEventRecord(t1, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(t1));
+    HIPCHK(ctx, hipEventElapsedTime(ms, t0, t1));
+    return PIMPC_OK;
+}
+
+// The batch schedule, picked by measurement on the real batch at setup:
+//   1. each class launch is timed alone, and its measured time replaces the
+//      FMA-count estimate as its cost in the longest-processing-time
+//      assignment of class launches to streams (the classes' throughputs
+//      differ: narrow stages use the lanes less well);
+//   2. candidates -- bin claiming (atomic counter, static striding, one
+//      workgroup per bin), 1 to 4 streams, and class launches whole or split
+//      in two -- are each timed once on the full batch; the fastest is kept.
 static int autotune(pimpc_ctx ctx) {
     struct Cand {
-        int schedule, nstreams;
+        int schedule, nstreams, split;
     };
-    const Cand cands[] = {{1, 4}, {1, 1}, {2, 4}, {3, 4}};
+    const Cand cands[] = {{1, 4, 0}, {1, 1, 0}, {2, 4, 0}, {3, 4, 0}, {1, 4, 1}, {1, 3, 1}, {1, 2, 1}, {3, 4, 1}};
+    const int ncand = (int)(sizeof(cands) / sizeof(cands[0]));
+    const std::vector<ClassRun> base = ctx->runs;
     if (ctx->opt.schedule > 0) {
-        const Cand& c = cands[(ctx->opt.schedule - 1) % 4];
+        const Cand& c = cands[(ctx->opt.schedule - 1) % ncand];
         ctx->schedule = c.schedule;
         ctx->nstreams = c.nstreams;
+        if (c.split) ctx->runs = split_runs(ctx, base);
         return PIMPC_OK;
     }
     int64_t total_waves = 0;
     for (const InstDev& I : ctx->inst) total_waves += (I.N + 63) / 64;
-    if (ctx->count == 1 || total_waves <= 64) {  // nothing to balance
+    if (ctx->count == 1 || total_waves <= 64 || base.empty()) {  // nothing to balance
         ctx->schedule = 2;
         ctx->nstreams = 1;
         return PIMPC_OK;
     }
-    // scratch outputs so that timing runs do not disturb caller-visible state
     hipError_t e = hipSuccess;
     hipEvent_t t0, t1;
     HIPCHK(ctx, hipEventCreate(&t0));
     HIPCHK(ctx, hipEventCreate(&t1));
-    float best = 1e30f;
-    Cand bestc = cands[0];
-    for (const Cand& c : cands) {
-        ctx->schedule = c.schedule;
-        ctx->nstreams = c.nstreams;
-        LaunchSet ls;
+    auto make_set = [&](LaunchSet& ls) -> int {
         ls.x0 = ctx->d_x0;
         ls.up = ctx->d_up;
         ls.u0 = ctx->d_u0;
@@ -745,19 +802,43 @@ static int autotune(pimpc_ctx ctx) {
         ls.d_args = dmalloc<LaneArgs>(std::max<size_t>(ctx->runs.size(), 1), &e);
         ls.d_rargs = dmalloc<RowArgs>(std::max<size_t>(ctx->row_insts.size(), 1), &e);
         if (e != hipSuccess) return ctx->fail(PIMPC_E_NOMEM, "hipMalloc failed in autotune");
-        int rc = fill_set_args(ctx, &ls);
-        if (rc == PIMPC_OK) rc = enqueue_solve(ctx, &ls, ctx->stream);  // warm-up
-        if (rc == PIMPC_OK) {
-            HIPCHK(ctx, hipEventRecord(t0, ctx->stream));
-            rc = enqueue_solve(ctx, &ls, ctx->stream);
-            HIPCHK(ctx, hipEventRecord(t1, ctx->stream));
-            HIPCHK(ctx, hipEventSynchronize(t1));
-        }
+        return fill_set_args(ctx, &ls);
+    };
+    auto free_set = [&](LaunchSet& ls) {
         (void)hipFree(ls.d_args);
         (void)hipFree(ls.d_rargs);
-        if (rc != PIMPC_OK) return rc;
+    };
+    // 1. measured class costs (after one warm-up solve)
+    {
+        ctx->schedule = 1;
+        ctx->nstreams = 4;
+        LaunchSet ls;
+        int rc = make_set(ls);
         float ms = 0.f;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, t0, t1));
+        if (rc == PIMPC_OK) rc = time_launch(ctx, &ls, -1, t0, t1, &ms);
+        for (size_t c = 0; c < ctx->runs.size() && rc == PIMPC_OK; ++c) {
+            rc = time_launch(ctx, &ls, (int)c, t0, t1, &ms);
+            ctx->runs[c].cost = std::max<int64_t>(1, (int64_t)(ms * 1e6f));  // ns
+        }
+        free_set(ls);
+        if (rc != PIMPC_OK) return rc;
+    }
+    const std::vector<ClassRun> measured = ctx->runs;
+    const std::vector<ClassRun> halves = split_runs(ctx, measured);
+    // 2. candidates on the full batch
+    float best = 1e30f;
+    Cand bestc = cands[0];
+    for (const Cand& c : cands) {
+        ctx->schedule = c.schedule;
+        ctx->nstreams = c.nstreams;
+        ctx->runs = c.split ? halves : measured;
+        LaunchSet ls;
+        int rc = make_set(ls);
+        float ms = 0.f;
+        if (rc == PIMPC_OK) rc = time_launch(ctx, &ls, -1, t0, t1, &ms);  // warm-up
+        if (rc == PIMPC_OK) rc = time_launch(ctx, &ls, -1, t0, t1, &ms);
+        free_set(ls);
+        if (rc != PIMPC_OK) return rc;
         if (ms < best) {
             best = ms;
             bestc = c;
@@ -767,6 +848,7 @@ static int autotune(pimpc_ctx ctx) {
     (void)hipEventDestroy(t1);
     ctx->schedule = bestc.schedule;
     ctx->nstreams = bestc.nstreams;
+    ctx->runs = bestc.split ? halves : measured;
     return PIMPC_OK;
 }
 
@@ -982,7 +1064,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         } else if (o->family == PIMPC_FAMILY_ROW) {
             lane = false;
         } else if (count == 1 && row_ok && I.xset == PIMPC_SET_BOX && I.uset == PIMPC_SET_BOX &&
-                   o->accel != 1 && o->ckpt_every == 0) {
+                   o->ckpt_every == 0) {
             // One instance alone: a row of the stage per lane gives a much
             // shorter iteration than one lane walking every row of its stage.
             lane = false;
@@ -1000,15 +1082,9 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             I.cls = -1;
             I.nxp = rnx;
             I.nup = rnu;
-            if (I.xset != PIMPC_SET_BOX || I.uset != PIMPC_SET_BOX)
-                return ctx->fail(PIMPC_E_UNSUPPORTED,
-                                 "instance %d (nx=%d, nu=%d, N=%d): non-box constraint sets need the lane family "
-                                 "(N <= 512)", i, I.nx, I.nu, I.N);
-            if (o->accel == 1)
-                return ctx->fail(PIMPC_E_UNSUPPORTED,
-                                 "instance %d (nx=%d, nu=%d, N=%d): restart acceleration needs the lane family "
-                                 "(a per-iteration residual reduction across the row family's workgroups is "
-                                 "not built)", i, I.nx, I.nu, I.N);
+            // the kernel variant with a reducer wave serves the eps stop and
+            // restart acceleration
+            I.row_acc = (o->accel == 1 || o->eps > 0.0) ? 1 : 0;
             ctx->row_insts.push_back(i);
         }
         I.nbp = I.nxp + I.nup;
@@ -1132,7 +1208,13 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         DALLOC(ctx->d_bins, Bin, bins.size());
         HIPCHK(ctx, hipMemcpy(ctx->d_bins, bins.data(), bins.size() * sizeof(Bin), hipMemcpyHostToDevice));
     }
-    DALLOC(ctx->d_counters, int32_t, std::max<size_t>(ctx->runs.size(), 1));
+    for (const Bin& b : bins) {
+        int w = 0;
+        for (int j = 0; j < b.n; ++j) w += b.e[j].nwaves;
+        ctx->bin_waves.push_back(w);
+    }
+    // (the autotuner may split every class launch in two)
+    DALLOC(ctx->d_counters, int32_t, std::max<size_t>(2 * ctx->runs.size(), 1));
     for (ClassRun& r : ctx->runs) {
         int occ = 1;
         HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, nullptr, r.nbmax, 0, ctx->stream, &occ));
@@ -1195,11 +1277,137 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         DALLOC(ctx->d_bwd_counters, int32_t, std::max<size_t>(ctx->bwd_runs.size(), 1));
     }
 #undef DALLOC
-    ctx->na_args.reserve(ctx->runs.size());
-    ctx->na_rargs.reserve(ctx->row_insts.size());
     rc = autotune(ctx);
     if (rc != PIMPC_OK) return rc;
+    ctx->na_args.reserve(ctx->runs.size());
+    ctx->na_rargs.reserve(ctx->row_insts.size());
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return PIMPC_OK;
+}
+
+// Output form of eqn. (1): the cost 1/2 ||C x_{k+1} - r_y||^2_Wy +
+// 1/2 ||u_k - r_u||^2_R expands (constant terms dropped) to
+// 1/2 x'(C' Wy C) x - (C' Wy r_y)' x + 1/2 u'R u - (R r_u)' u, which is the
+// velocity-form cost with Q + C' Wy C and qbar + (C' Wy r_y, R r_u).  A bound
+// on an output that selects one state (y_i = c_ij x_j) is a bound on x_j.
+// Writes the folded problem to *q (pointing into f); the caller's arrays
+// are not touched.
+struct Folded {
+    std::vector<double> Q, qbar, xmin, xmax;
+};
+
+static int fold_outputs(pimpc_ctx ctx, const pimpc_problem* p, pimpc_problem* q, Folded& f) {
+    *q = *p;
+    if (!p || (!p->ny && !p->ru)) return PIMPC_OK;
+    if (p->count < 1 || !p->nx || !p->nu || !p->R || !p->xmin || !p->xmax)
+        return ctx->fail(PIMPC_E_ARG, "a required problem array is NULL");
+    if (!p->Q && !p->ny) return ctx->fail(PIMPC_E_ARG, "Q is required without the output form");
+    const int count = p->count;
+    int64_t snx = 0, snu = 0, sQ = 0, sR = 0, sny = 0, sC = 0, sW = 0;
+    for (int i = 0; i < count; ++i) {
+        const int nx = p->nx[i], nu = p->nu[i], ny = p->ny ? p->ny[i] : 0;
+        if (nx < 1 || nu < 1 || nx > 48 || nu > 16)
+            return ctx->fail(PIMPC_E_DIM, "instance %d: nx <= 48, nu <= 16 supported", i);
+        if (ny < 0 || ny > 32) return ctx->fail(PIMPC_E_DIM, "instance %d: ny must be in [0, 32]", i);
+        snx += nx;
+        snu += nu;
+        sQ += (int64_t)nx * nx;
+        sR += (int64_t)nu * nu;
+        sny += ny;
+        sC += (int64_t)ny * nx;
+        sW += (int64_t)ny * ny;
+    }
+    if (p->ny && (!p->C || !p->Wy)) return ctx->fail(PIMPC_E_ARG, "the output form needs C and Wy");
+    if ((p->C && !finite_arr(p->C, sC)) || (p->Wy && !finite_arr(p->Wy, sW)) ||
+        (p->ry && !finite_arr(p->ry, sny)) || !finite_arr(p->R, sR) || (p->ru && !finite_arr(p->ru, snu)) ||
+        (p->Q && !finite_arr(p->Q, sQ)) || (p->qbar && !finite_arr(p->qbar, snx + snu)))
+        return ctx->fail(PIMPC_E_NONFINITE, "problem data contains NaN or Inf");
+    f.Q.assign(sQ, 0.0);
+    if (p->Q) std::copy(p->Q, p->Q + sQ, f.Q.begin());
+    f.qbar.assign(snx + snu, 0.0);
+    if (p->qbar) std::copy(p->qbar, p->qbar + snx + snu, f.qbar.begin());
+    f.xmin.assign(p->xmin, p->xmin + snx);
+    f.xmax.assign(p->xmax, p->xmax + snx);
+    int64_t oq = 0, orr = 0, ox = 0, ou = 0, oy = 0, oc = 0, ow = 0, ob = 0;
+    for (int i = 0; i < count; ++i) {
+        const int nx = p->nx[i], nu = p->nu[i], ny = p->ny ? p->ny[i] : 0;
+        if (ny > 0) {
+            const double* C = p->C + oc;
+            const double* Wy = p->Wy + ow;
+            bool sym = true;
+            if (!sym_psd(Wy, ny, &sym))
+                return ctx->fail(PIMPC_E_NOT_PSD, "instance %d: Wy is not %s", i, sym ? "PSD" : "symmetric");
+            std::vector<double> WC((size_t)ny * nx, 0.0);  // Wy C
+            for (int a = 0; a < ny; ++a)
+                for (int j = 0; j < nx; ++j)
+                    for (int b = 0; b < ny; ++b) WC[(size_t)a * nx + j] += Wy[a * ny + b] * C[(size_t)b * nx + j];
+            for (int r = 0; r < nx; ++r)
+                for (int c = 0; c < nx; ++c) {
+                    double acc = 0.0;
+                    for (int a = 0; a < ny; ++a) acc += C[(size_t)a * nx + r] * WC[(size_t)a * nx + c];
+                    f.Q[oq + (int64_t)r * nx + c] += acc;
+                }
+            if (p->ry)
+                for (int r = 0; r < nx; ++r) {
+                    double acc = 0.0;
+                    for (int a = 0; a < ny; ++a) acc += WC[(size_t)a * nx + r] * p->ry[oy + a];
+                    f.qbar[ob + r] += acc;  // C' Wy r_y (Wy symmetric)
+                }
+            if (p->ymin || p->ymax) {
+                const int xk = p->xset ? p->xset[i] : PIMPC_SET_BOX;
+                for (int a = 0; a < ny; ++a) {
+                    const double lo = p->ymin ? p->ymin[oy + a] : -INFINITY;
+                    const double hi = p->ymax ? p->ymax[oy + a] : INFINITY;
+                    if (std::isnan(lo) || std::isnan(hi) || lo > hi)
+                        return ctx->fail(PIMPC_E_ARG, "instance %d: output bound %d needs ymin <= ymax (no NaN)", i, a);
+                    if (lo == -INFINITY && hi == INFINITY) continue;
+                    int nz = 0, jsel = -1;
+                    for (int j = 0; j < nx; ++j)
+                        if (C[(size_t)a * nx + j] != 0.0) {
+                            ++nz;
+                            jsel = j;
+                        }
+                    if (nz != 1)
+                        return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                         "instance %d: a bound on output %d, which mixes %d states (a bounded "
+                                         "output must select one state)", i, a, nz);
+                    if (xk != PIMPC_SET_BOX)
+                        return ctx->fail(PIMPC_E_UNSUPPORTED,
+                                         "instance %d: output bounds need a box x factor", i);
+                    const double cj = C[(size_t)a * nx + jsel];
+                    double xl = lo / cj, xh = hi / cj;
+                    if (cj < 0.0) std::swap(xl, xh);
+                    double& mn = f.xmin[ox + jsel];
+                    double& mx = f.xmax[ox + jsel];
+                    mn = std::max(mn, xl);
+                    mx = std::min(mx, xh);
+                    if (!(mn <= mx))
+                        return ctx->fail(PIMPC_E_ARG, "instance %d: output bound %d leaves an empty box on x_%d", i,
+                                         a, jsel);
+                }
+            }
+        }
+        if (p->ru)
+            for (int r = 0; r < nu; ++r) {
+                double acc = 0.0;
+                for (int c = 0; c < nu; ++c) acc += p->R[orr + (int64_t)r * nu + c] * p->ru[ou + c];
+                f.qbar[ob + nx + r] += acc;
+            }
+        oq += (int64_t)nx * nx;
+        orr += (int64_t)nu * nu;
+        ox += nx;
+        ou += nu;
+        oy += ny;
+        oc += (int64_t)ny * nx;
+        ow += (int64_t)ny * ny;
+        ob += nx + nu;
+    }
+    q->Q = f.Q.data();
+    q->qbar = f.qbar.data();
+    q->xmin = f.xmin.data();
+    q->xmax = f.xmax.data();
+    q->ny = nullptr;
+    q->C = q->Wy = q->ry = q->ymin = q->ymax = q->ru = nullptr;
     return PIMPC_OK;
 }
 
@@ -1215,7 +1423,10 @@ int32_t pimpc_setup(pimpc_ctx* out, const pimpc_problem* prob, const pimpc_optio
         return PIMPC_E_NOMEM;
     }
     ctx->stream = (hipStream_t)hip_stream;
-    const int rc = setup_impl(ctx, prob, opts);
+    pimpc_problem folded;
+    Folded fstore;
+    int rc = prob ? fold_outputs(ctx, prob, &folded, fstore) : PIMPC_OK;
+    if (rc == PIMPC_OK) rc = setup_impl(ctx, prob ? &folded : nullptr, opts);
     if (rc != PIMPC_OK) {
         g_setup_err = ctx->err;
         destroy_ctx(ctx);

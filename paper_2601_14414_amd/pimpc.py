@@ -46,7 +46,8 @@ class pimpc_problem(ctypes.Structure):
                 ("time_varying", ctypes.c_int32), ("A", _dp), ("B", _dp), ("e", _dp),
                 ("Q", _dp), ("R", _dp), ("qbar", _dp), ("xmin", _dp), ("xmax", _dp),
                 ("umin", _dp), ("umax", _dp), ("Wdu", _dp), ("xset", _ip), ("uset", _ip),
-                ("xset_par", _dp), ("uset_par", _dp)]
+                ("xset_par", _dp), ("uset_par", _dp), ("ny", _ip), ("C", _dp), ("Wy", _dp),
+                ("ry", _dp), ("ymin", _dp), ("ymax", _dp), ("ru", _dp)]
 
 
 class pimpc_options(ctypes.Structure):
@@ -219,15 +220,32 @@ def pimpc_setup(problems: Sequence, opts: pimpc_options, stream: Optional[int] =
                                     else np.asarray(p.Wdu)).ravel() for p in problems]))
     xk, xpar = _set_arrays([getattr(p, "xset", None) for p in problems], [p.nx for p in problems])
     uk, upar = _set_arrays([getattr(p, "uset", None) for p in problems], [p.nu for p in problems])
+    # output form of eqn. (1): y = C x with weight Wy, reference ry, bounds
+    ny = C = Wy = ry = ymin = ymax = ru = None
+    if any(getattr(p, "C", None) is not None for p in problems):
+        nys = [0 if getattr(p, "C", None) is None else int(np.asarray(p.C).shape[0]) for p in problems]
+        ny = np.array(nys, np.int32)
+        part = lambda p, name, n, fill: (np.full(n, fill) if getattr(p, name, None) is None
+                                         else np.asarray(getattr(p, name), np.float64).ravel())
+        C = _f64(np.concatenate([part(p, "C", n * p.nx, 0.0) for p, n in zip(problems, nys)]))
+        Wy = _f64(np.concatenate([part(p, "Wy", n * n, 0.0) for p, n in zip(problems, nys)]))
+        ry = _f64(np.concatenate([part(p, "ry", n, 0.0) for p, n in zip(problems, nys)]))
+        ymin = _f64(np.concatenate([part(p, "ymin", n, -np.inf) for p, n in zip(problems, nys)]))
+        ymax = _f64(np.concatenate([part(p, "ymax", n, np.inf) for p, n in zip(problems, nys)]))
+    if any(getattr(p, "ru", None) is not None for p in problems):
+        ru = _f64(np.concatenate([np.zeros(p.nu) if getattr(p, "ru", None) is None else np.asarray(p.ru)
+                                  for p in problems]))
     keep.update(nx=nx, nu=nu, N=N, A=A, B=B, e=e, Q=Q, R=R, qbar=qbar, xmin=xmin, xmax=xmax,
-                umin=umin, umax=umax, Wdu=Wdu, xk=xk, xpar=xpar, uk=uk, upar=upar)
+                umin=umin, umax=umax, Wdu=Wdu, xk=xk, xpar=xpar, uk=uk, upar=upar, ny=ny, C=C, Wy=Wy,
+                ry=ry, ymin=ymin, ymax=ymax, ru=ru)
     prob = pimpc_problem(count=len(problems), nx=nx.ctypes.data_as(_ip), nu=nu.ctypes.data_as(_ip),
                          N=N.ctypes.data_as(_ip), time_varying=tv, A=_p(A), B=_p(B), e=_p(e),
                          Q=_p(Q), R=_p(R), qbar=_p(qbar), xmin=_p(xmin), xmax=_p(xmax),
                          umin=_p(umin), umax=_p(umax), Wdu=_p(Wdu),
                          xset=None if xk is None else xk.ctypes.data_as(_ip),
                          uset=None if uk is None else uk.ctypes.data_as(_ip), xset_par=_p(xpar),
-                         uset_par=_p(upar))
+                         uset_par=_p(upar), ny=None if ny is None else ny.ctypes.data_as(_ip),
+                         C=_p(C), Wy=_p(Wy), ry=_p(ry), ymin=_p(ymin), ymax=_p(ymax), ru=_p(ru))
     ctx = ctypes.c_void_p()
     rc = lib().pimpc_setup(ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opts), stream)
     _check(rc, None)

@@ -38,6 +38,10 @@ class Problem:
     ("halfspace", a, b) = {a'w <= b}, ("hyperplane", a, b) = {a'w = b},
     ("soc",) = {||w[:-1]||_2 <= w[-1]}, ("l1ball", r) = {||w||_1 <= r}.
     Bounds are per-component boxes; +-inf allowed.  x0 = x(t), u_prev = u(t-1).
+    Output form of eqn. (1), optional: C (ny, nx) with y = C x, Wy (ny, ny),
+    ry (ny,), output bounds ymin / ymax (ny,), input reference ru (nu,) with
+    W_u = R; the cost then has 1/2 ||C x - ry||^2_Wy + 1/2 ||u - ru||^2_R on
+    top of 1/2 x'Q x (Q may be zero).
     """
 
     nx: int
@@ -60,6 +64,12 @@ class Problem:
     Wdu: Optional[np.ndarray] = None
     xset: Optional[tuple] = None
     uset: Optional[tuple] = None
+    C: Optional[np.ndarray] = None
+    Wy: Optional[np.ndarray] = None
+    ry: Optional[np.ndarray] = None
+    ymin: Optional[np.ndarray] = None
+    ymax: Optional[np.ndarray] = None
+    ru: Optional[np.ndarray] = None
 
     @property
     def nb(self) -> int:
@@ -387,6 +397,24 @@ def afti16(dt: float = 0.05):
                    [-17.251, -1.5766],
                    [0.0, 0.0]])
     return zoh(Ac, Bc, dt)
+
+
+def afti16_problem(N: int = 5, K: int = 500, rho: float = 10.0, pitch_ref: float = 10.0,
+                   x0: Optional[np.ndarray] = None) -> Problem:
+    """AFTI-16 tracking problem of Section V-A in the output form of eqn. (1):
+    y = C x with C selecting the angle of attack (y_1) and the pitch angle
+    (y_2), W_y = diag(100, 100), W_u = 0, W_du = diag(0.1, 0.1), |u_i| <= 25,
+    -0.5 <= y_1 <= 0.5, -100 <= y_2 <= 100, reference y_2 -> pitch_ref.
+    Not printed, so chosen here: the reference value, the initial state (0)
+    and rho."""
+    A, B = afti16()
+    C = np.array([[0.0, 1.0, 0.0, 0.0], [0.0, 0.0, 0.0, 1.0]])
+    return Problem(nx=4, nu=2, N=N, A=A, B=B, Q=np.zeros((4, 4)), R=np.zeros((2, 2)),
+                   xmin=np.full(4, -np.inf), xmax=np.full(4, np.inf), umin=np.full(2, -25.0),
+                   umax=np.full(2, 25.0), x0=np.zeros(4) if x0 is None else np.asarray(x0, np.float64),
+                   u_prev=np.zeros(2), rho=rho, K=K, Wdu=np.diag([0.1, 0.1]), C=C,
+                   Wy=np.diag([100.0, 100.0]), ry=np.array([0.0, pitch_ref]),
+                   ymin=np.array([-0.5, -100.0]), ymax=np.array([0.5, 100.0]))
 
 
 # ---------------------------------------------------------------------------

@@ -297,8 +297,10 @@ def sparse_qp(p):
     """QP (2) of problem (1) as scipy.sparse matrices, in the same original
     coordinates y = col(u_0, x_1, ..., u_{N-1}, x_N) as `original_qp`, for
     horizons where dense matrices do not fit.  The linear term qbar of the
-    velocity-form cost (-qbar' xbar_{k+1}, xbar_{k+1} = col(x_{k+1}, u_k)) and
-    an input-rate weight Wdu are included."""
+    velocity-form cost (-qbar' xbar_{k+1}, xbar_{k+1} = col(x_{k+1}, u_k)), an
+    input-rate weight Wdu, and the output form of eqn. (1) (outputs w_k =
+    C x_{k+1} as extra variables with their weight, reference and bounds; an
+    input reference) are included."""
     import scipy.sparse as sp
     n, m, N = p.nx, p.nu, p.N
     nb = n + m
@@ -331,9 +333,25 @@ def sparse_qp(p):
                 blk(u0 - nb, u0, -np.asarray(Wd))
             else:
                 f[u0:u0 + m] -= np.asarray(Wd) @ np.asarray(p.u_prev, np.float64)
-    H = sp.csc_matrix((Hv, (Hr, Hc)), shape=(ny, ny))
+    # output form of eqn. (1): extra variables w_k = C x_{k+1} (after the
+    # N (n + m) block) carry 1/2 ||w - ry||^2_Wy and the output bounds; the
+    # input reference adds 1/2 ||u - ru||^2_R - 1/2 u'R u = -(R ru)'u (+ const)
+    C = getattr(p, "C", None)
+    nyo = 0 if C is None else int(np.asarray(C).shape[0])
+    nw = N * nyo
+    if nyo:
+        Wy = np.asarray(p.Wy, np.float64)
+        ry = np.zeros(nyo) if getattr(p, "ry", None) is None else np.asarray(p.ry, np.float64)
+        for k in range(N):
+            blk(ny + k * nyo, ny + k * nyo, Wy)
+        f = np.concatenate([f, np.tile(-Wy @ ry, N)])
+    if getattr(p, "ru", None) is not None:
+        fu = -np.asarray(p.R, np.float64) @ np.asarray(p.ru, np.float64)
+        for k in range(N):
+            f[k * nb:k * nb + m] += fu
+    H = sp.csc_matrix((Hv, (Hr, Hc)), shape=(ny + nw, ny + nw))
     Ar, Ac, Av = [], [], []
-    beq = np.zeros(N * n)
+    beq = np.zeros(N * n + nw)
     for k in range(N):
         r0, u0, x0 = k * n, k * nb, k * nb + m
         for i in range(n):
@@ -346,9 +364,23 @@ def sparse_qp(p):
                     if A[k][i, j] != 0.0:
                         Ar.append(r0 + i); Ac.append(x0 - nb + j); Av.append(-A[k][i, j])
         beq[r0:r0 + n] = e[k] + (A[0] @ p.x0 if k == 0 else 0.0)
-    Aeq = sp.csc_matrix((Av, (Ar, Ac)), shape=(N * n, ny))
+    if nyo:
+        Cm = np.asarray(C, np.float64)
+        for k in range(N):
+            for a in range(nyo):
+                row = N * n + k * nyo + a
+                Ar.append(row); Ac.append(ny + k * nyo + a); Av.append(1.0)
+                for j in range(n):
+                    if Cm[a, j] != 0.0:
+                        Ar.append(row); Ac.append(k * nb + m + j); Av.append(-Cm[a, j])
+    Aeq = sp.csc_matrix((Av, (Ar, Ac)), shape=(N * n + nw, ny + nw))
     lo = np.tile(np.concatenate([p.umin, p.xmin]).astype(np.float64), N)
     hi = np.tile(np.concatenate([p.umax, p.xmax]).astype(np.float64), N)
+    if nyo:
+        ylo = np.full(nyo, -np.inf) if getattr(p, "ymin", None) is None else np.asarray(p.ymin, np.float64)
+        yhi = np.full(nyo, np.inf) if getattr(p, "ymax", None) is None else np.asarray(p.ymax, np.float64)
+        lo = np.concatenate([lo, np.tile(ylo, N)])
+        hi = np.concatenate([hi, np.tile(yhi, N)])
     return dict(H=H, f=f, Aeq=Aeq, beq=beq, lo=lo, hi=hi, nb=nb)
 
 
@@ -438,5 +470,5 @@ def ipm_qp(p, tol=1e-12, max_iter=80):
         zu += ad * dzu
         nu_ += ad * dnu
     nb, m = D["nb"], p.nu
-    Y = y.reshape(p.N, nb)
+    Y = y[:p.N * nb].reshape(p.N, nb)
     return dict(xs=Y[:, m:].copy(), us=Y[:, :m].copy(), y=y, kkt=kkt, iters=it, ok=ok)

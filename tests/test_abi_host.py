@@ -94,10 +94,7 @@ def test_bad_constraint_sets_rejected():
     # a cone needs two entries
     one = W.cartpole_problem(N=16, K=5).copy(uset=("soc",))
     assert _setup_code([one])[0] == P.PIMPC_E_DIM
-    # non-box sets: lane family only, and no tape
-    lh = W.long_horizon_problem(0, N=600, K=10).copy(uset=("l1ball", 1.0))
-    code, msg = _setup_code([lh])
-    assert code == P.PIMPC_E_UNSUPPORTED and "lane family" in msg
+    # non-box sets: no tape
     code, msg = _setup_code([p.copy(uset=("soc",))], ckpt_every=20)
     assert code == P.PIMPC_E_UNSUPPORTED and "box" in msg
 
@@ -116,11 +113,7 @@ def test_bad_rate_weight_rejected():
 
 
 def test_unsupported_requests_are_reported():
-    # restart acceleration runs on the lane family only (a long wide horizon
-    # goes to the row family), and the taped forward differentiates plain ADMM
-    lh = W.long_horizon_problem(0, N=256, K=10)
-    code, msg = _setup_code([lh], accel=1)
-    assert code == P.PIMPC_E_UNSUPPORTED and "restart" in msg
+    # the taped forward differentiates plain ADMM
     code, msg = _setup_code([W.plain_fp64_problem(0)], accel=1, ckpt_every=20)
     assert code == P.PIMPC_E_UNSUPPORTED and "accel" in msg
 
@@ -175,9 +168,6 @@ def test_requested_family_that_cannot_serve_is_unsupported():
     small = W.plain_fp64_problem(0)
     code, _ = _setup_code([small], family=P.PIMPC_FAMILY_ROW, precision=P.PIMPC_FP64)  # row: FP32 only
     assert code == P.PIMPC_E_UNSUPPORTED
-    code, msg = _setup_code([small.copy(uset=("l1ball", 1.0))], family=P.PIMPC_FAMILY_ROW,
-                            precision=P.PIMPC_FP32)
-    assert code == P.PIMPC_E_UNSUPPORTED and "lane family" in msg
 
 
 def test_binding_structs_match_the_header_layout(tmp_path):
@@ -206,3 +196,24 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert int(got[f"{name} size"]) == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
+
+
+def test_output_form_validation():
+    """The output form of eqn. (1) is folded on the host: a bounded output
+    that mixes states is unsupported, bounds that empty a state box and a
+    non-PSD output weight are rejected, all before any HIP call."""
+    p = W.afti16_problem(N=5)
+    mixed = p.copy(C=np.array([[0.0, 1.0, 0.0, 0.5], [0.0, 0.0, 0.0, 1.0]]))
+    code, msg = _setup_code([mixed])
+    assert code == P.PIMPC_E_UNSUPPORTED and "mixes" in msg
+    empty = p.copy(xmin=np.array([-np.inf, 0.6, -np.inf, -np.inf]))  # y_1 <= 0.5 and x_2 >= 0.6
+    code, msg = _setup_code([empty])
+    assert code == P.PIMPC_E_ARG and "empty" in msg
+    bad = p.copy(Wy=np.diag([100.0, -1.0]))
+    code, msg = _setup_code([bad])
+    assert code == P.PIMPC_E_NOT_PSD and "Wy" in msg
+    nanr = p.copy(ry=np.array([0.0, np.nan]))
+    assert _setup_code([nanr])[0] == P.PIMPC_E_NONFINITE
+    soc = p.copy(xset=("soc",))
+    code, msg = _setup_code([soc])
+    assert code == P.PIMPC_E_UNSUPPORTED and "box" in msg

@@ -396,3 +396,39 @@ def test_oracle_adjoint_matches_finite_differences(seed, masses, rho, rate):
     fd = _loss_and_grad_fd(nx, nu, N, A, B, Qd, Rd, lb, ub, x0, rho, K, ut, Wdu=Wdu)
     for name, key in [("A", "dA"), ("B", "dB"), ("Qd", "dQd"), ("Rd", "dRd"), ("x0", "dx0")]:
         np.testing.assert_allclose(g[key], fd[name], rtol=1e-5, atol=1e-7, err_msg=name)
+
+
+def _mixed_output_problem(seed):
+    """Outputs that mix states (general C, no bounds on them), an output and
+    an input reference, a small state weight, active input bounds."""
+    rng = np.random.default_rng(seed)
+    A, B = W.mass_spring(2)
+    C = rng.standard_normal((3, 4))
+    Wy = np.diag(rng.uniform(0.5, 2.0, 3))
+    return W.Problem(nx=4, nu=1, N=8, A=A, B=B, Q=0.05 * np.eye(4), R=0.1 * np.eye(1),
+                     xmin=np.full(4, -3.0), xmax=np.full(4, 3.0), umin=np.full(1, -0.3), umax=np.full(1, 0.3),
+                     x0=rng.uniform(-1, 1, 4), u_prev=np.zeros(1), rho=1.0, K=0, C=C, Wy=Wy,
+                     ry=rng.uniform(-0.5, 0.5, 3), ru=np.array([0.1]))
+
+
+@pytest.mark.parametrize("case", ["afti_N5", "afti_N30", "mixed0", "mixed1"])
+def test_output_form_fixed_point_equals_interior_point(case):
+    """Eqn. (1) with an output matrix C, output weight, references and output
+    bounds: the oracle (which folds them into Q, qbar and the state box) at
+    its fixed point equals the interior-point optimum of the QP written with
+    the outputs as variables of their own (w_k = C x_{k+1}, bounds on w)."""
+    if case.startswith("afti"):
+        N = int(case[6:])
+        p = W.afti16_problem(N=N, rho=10.0 if N == 5 else 100.0)
+    else:
+        p = _mixed_output_problem(int(case[-1]))
+    ip = _refs.ipm_qp(p)
+    assert ip["ok"] and ip["kkt"] <= 1e-12
+    r = oracle.solve(p, K=300000, eps=1e-22)
+    assert r["hist"][-1][0] <= 1e-22
+    np.testing.assert_allclose(r["xs"][:, p.nx:], ip["us"], rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r["xs"][:, :p.nx], ip["xs"], rtol=0, atol=1e-7)
+    if case.startswith("afti"):
+        # the angle-of-attack bound y_1 <= 0.5 and the input bounds are active
+        assert np.any(np.isclose(ip["xs"][:, 1], 0.5, atol=1e-8))
+        assert np.any(np.isclose(np.abs(ip["us"]), 25.0, atol=1e-8))
