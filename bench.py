@@ -321,6 +321,34 @@ def bench_accel(torch, P, W, steps, warmup):
     res["iteration_ratio"] = res["accel"]["mean_iters"] / res["plain"]["mean_iters"]
     res["workload"] = "1024 4-mass chains (nx=8, nu=3), N=128, FP32, to c <= 1e-5, check every 10, max 20000"
     out["chains_1024"] = res
+    # single long horizons on the row family (a global reduction of c after
+    # every accelerated step): the 12-mass chain and the reactor
+    for key, prob, eps_r, kmax, rho in (
+            ("long_horizon_1024", W.long_horizon_problem(seed=0), 1e-4, 200000, 1.0),
+            ("cstr_5000", W.cstr_problem(N=5000, K=1000, rho=0.1), 1e-6, 200000, 0.1)):
+        res = {}
+        x0r = torch.tensor(prob.x0, dtype=torch.float32, device=dev)
+        upr = torch.tensor(prob.u_prev, dtype=torch.float32, device=dev)
+        for name, accel in (("plain", False), ("accel", True)):
+            s = P.Solver([prob], rho=rho, max_iter=kmax, eps=eps_r, check_every=10 if not accel else 1,
+                         precision=P.PIMPC_FP32, accel=accel, stream=stream)
+            u0 = torch.empty(prob.nu, dtype=torch.float32, device=dev)
+            info = torch.zeros(40, dtype=torch.uint8, device=dev)
+            fn = lambda: P.pimpc_solve_batch(s.ctx, x0r, upr, u0, info, stream)
+            ms, per = time_solves(torch, fn, 2, 1)
+            rec = np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE)
+            check_info(P, rec, None, f"restart_accel {key} {name}")
+            it = int(rec["iters"][0])
+            res[name] = {"ms_per_solve": ms / 2, "iters": it, "c": float(rec["c"][0]),
+                         "us_per_iteration": ms / 2 / it * 1e3}
+            if accel:
+                res[name]["restarts"] = int(rec["restarts"][0])
+            s.close()
+        res["speedup"] = res["plain"]["ms_per_solve"] / res["accel"]["ms_per_solve"]
+        res["iteration_ratio"] = res["accel"]["iters"] / res["plain"]["iters"]
+        res["workload"] = (f"one instance on the row family, FP32, to c <= {eps_r:g} (plain: checked every 10 "
+                           f"iterations; accelerated: every iteration, as steps 6-7 need), max {kmax}")
+        out[key] = res
     return out
 
 
