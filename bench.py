@@ -594,7 +594,7 @@ def main():
                    "N": p.N, "nx": p.nx, "nu": p.nu, "iterations": p.K, "instances": 1},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
-                     "kernel": "row_kernel<24,12,1,false> (one solve = one launch)",
+                     "kernel": "row_kernel<24,12,1,false,false,false> (one solve = one launch)",
                      "flops_per_launch": flops_per_launch,
                      "flops_per_stage_iteration": stage_flops(p.nx, p.nu), "avg_launch_ms": step_ms,
                      "peak_note": "non-packed FP32 FMA rate 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz; "
