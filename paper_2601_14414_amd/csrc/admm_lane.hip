@@ -699,6 +699,19 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             if (accel && run && !done && it + 1 < K && act) {
                 const gptr<T> pv = (gptr<T>)((T*)(*AP()).prev + (*IP()).st_off);
                 const T cf = (T)coef;
+                // the hats are the new iterate itself after a restart (and
+                // while alpha is 1): then the previous iterate is only
+                // replaced, not read (the decision is uniform over the wave)
+                if (cf == T(0)) {
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) {
+                        pv[(int64_t)(0 * NB + i) * N + k] = v[i];
+                        pv[(int64_t)(1 * NB + i) * N + k] = z[i];
+                        pv[(int64_t)(2 * NB + i) * N + k] = th[i];
+                        pv[(int64_t)(3 * NB + i) * N + k] = be[i];
+                        pv[(int64_t)(4 * NB + i) * N + k] = la[i];
+                    }
+                } else
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
                     const int64_t o0 = (int64_t)(0 * NB + i) * N + k, o1 = (int64_t)(1 * NB + i) * N + k,
