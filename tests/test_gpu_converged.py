@@ -75,3 +75,26 @@ def test_fp32_reaches_target_uneven_batch_classes():
         assert e <= 1e-3, (pick[i], e)
     print(f"largest input-trajectory error against the optimum: {worst:.2e}")
     s.close()
+
+
+def test_fp32_reaches_target_long_horizon():
+    """The full long-horizon workload (24 + 11 chain, N = 1024) in converged
+    mode: FP32 to c <= 1e-8 (about 2.5e5 iterations) meets the residual
+    target r_prim, r_dual <= 1e-4.  The iteration approaches the optimum
+    slowly on this instance: the FP64 oracle itself, at the same c (2.6e5
+    iterations), is still 5.8e-3 from the interior-point optimum in the
+    input trajectory, and FP32 is measured at 9.9e-3; the gate is 2e-2 (of
+    the 0.5 input bound: 4 %)."""
+    p = W.long_horizon_problem(seed=0)
+    s = P.Solver([p], max_iter=1000000, eps=1e-8, check_every=10, precision=P.PIMPC_FP32)
+    _, info = s.solve()
+    assert info["status"][0] == 0 and info["c"][0] <= 1e-8
+    assert info["r_prim"][0] <= 1e-4 and info["r_dual"][0] <= 1e-4
+    ip = _refs.ipm_qp(p)
+    assert ip["ok"]
+    u = s.iterate(P.IT_XBAR)[0][:, p.nx:]
+    err = float(np.max(np.abs(u - ip["us"])))
+    print(f"long horizon: {info['iters'][0]} iterations, r_prim {info['r_prim'][0]:.1e}, "
+          f"r_dual {info['r_dual'][0]:.1e}, input error against the optimum {err:.2e}")
+    assert err <= 2e-2
+    s.close()

@@ -42,13 +42,15 @@ def oracle_loop(steps, N, iters):
 def test_cstr_per_sample_parity(N, iters, steps):
     log = oracle_loop(steps, N, iters)
     s = P.Solver([log[0][0]], rho=RHO, max_iter=iters, precision=P.PIMPC_FP32, warm_start=True)
+    worst = 0.0
     try:
         for t, (p, r) in enumerate(log):
             s.linearize(p.A.ravel(), p.B.ravel(), p.e.ravel())
             u0, info = s.solve(x0=p.x0, u_prev=p.u_prev)
             assert scaled_err(u0, r["u0"]) <= TOL32, t
-            compare(s, [p], [r], TOL32)
+            worst = max(worst, compare(s, [p], [r], TOL32))
             assert info["status"][0] == 0
+        print(f"largest scaled iterate error over {steps} samples (N = {N}): {worst:.2e}")
     finally:
         s.close()
 

@@ -25,14 +25,22 @@ def scaled_err(a, b):
 
 
 def compare(solver, problems, refs, tol, which=range(len(P.EXPORTS))):
-    """Compare every iterate of every instance with the oracle results."""
+    """Compare every iterate of every instance with the oracle results;
+    returns the largest scaled error."""
     its = {w: solver.iterate(w) for w in range(7)}
+    worst = 0.0
     for i, (p, r) in enumerate(zip(problems, refs)):
         for w in range(5):
             e = scaled_err(its[w][i], r["state"][w])
+            worst = max(worst, e)
             assert e <= tol, f"instance {i} iterate {w}: {e:.3e}"
-        assert scaled_err(its[P.IT_DU][i], r["du"]) <= tol, f"instance {i} du"
-        assert scaled_err(its[P.IT_XBAR][i], r["xs"]) <= tol, f"instance {i} xbar"
+        e = scaled_err(its[P.IT_DU][i], r["du"])
+        worst = max(worst, e)
+        assert e <= tol, f"instance {i} du"
+        e = scaled_err(its[P.IT_XBAR][i], r["xs"])
+        worst = max(worst, e)
+        assert e <= tol, f"instance {i} xbar"
+    return worst
 
 
 def run_both(problems, precision, K=None, **kw):
