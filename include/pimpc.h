@@ -192,11 +192,14 @@ typedef struct {
  *   eta          restart threshold (Algorithm 1 uses 0.999)
  *   warm_start   1 = start from the previous solve's iterate (unshifted)
  *   ckpt_every   > 0 records a tape for pimpc_backward every that many iterations
- *   schedule     batch schedule: 0 = autotune (measured at setup), k = 1..8 a
- *                fixed candidate: bin claiming by atomic counter (1, 2, 5, 6,
- *                7), static striding (3) or one workgroup per bin (4, 8), on
- *                4, 1, 4, 4, 4, 3, 2, 4 streams, class launches whole (1-4)
- *                or split in two (5-8)
+ *   schedule     batch schedule: 0 = autotune (measured at setup), k = 1..14
+ *                a fixed candidate: bin claiming by atomic counter (1, 2, 5,
+ *                6, 7, 9, 11, 12, 14), static striding (3, 13) or one
+ *                workgroup per bin (4, 8, 10), on 4 streams (2: 1 stream,
+ *                6: 3, 7: 2), class launches whole or split in two (5-8),
+ *                grids of all resident workgroups or half (11, 13, 14) or a
+ *                quarter (12) of them; when fixed, launches are assigned to
+ *                streams by FMA count
  *   family       kernel family: PIMPC_FAMILY_AUTO (choose as described at the
  *                top of this file), PIMPC_FAMILY_LANE or PIMPC_FAMILY_ROW
  *                (PIMPC_E_UNSUPPORTED when that family cannot serve an

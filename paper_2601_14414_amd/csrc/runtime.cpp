@@ -206,6 +206,7 @@ struct pimpc_ctx_s {
     size_t row_clear_total = 0;
     int schedule = 1;            // 1 = dynamic counter, 2 = static striding
     int nstreams = 1;
+    int grid_div = 1;            // resident workgroups of a class launch: (occupancy x CUs) / grid_div
     int has_state = 0;
     std::vector<std::unique_ptr<LaunchSet>> sets;
     // differentiable path (ckpt_every > 0)
@@ -492,7 +493,7 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassR
 // Grid size of a class launch under the current schedule.
 static int class_grid(pimpc_ctx ctx, const ClassRun& r) {
     if (ctx->schedule == 3) return r.nbins;  // one workgroup per bin, hardware dispatch order
-    const int cap = std::max(1, r.occ * ctx->num_cus);
+    const int cap = std::max(1, r.occ * ctx->num_cus / std::max(1, ctx->grid_div));
     return std::max(1, std::min(r.nbins, cap));
 }
 
@@ -762,24 +763,30 @@ static int time_launch(pimpc_ctx ctx, LaunchSet* ls, int only_class, hipEvent_t 
 }
 
 // The batch schedule, picked by measurement on the real batch at setup:
-//   1. each class launch is timed alone, and its measured time replaces the
-//      FMA-count estimate as its cost in the longest-processing-time
-//      assignment of class launches to streams (the classes' throughputs
-//      differ: narrow stages use the lanes less well);
+//   1. each class launch is timed alone; its measured time is the
+//      alternative to the FMA-count estimate as its cost in the
+//      longest-processing-time assignment of class launches to streams (the
+//      classes' throughputs differ: narrow stages use the lanes less well);
 //   2. candidates -- bin claiming (atomic counter, static striding, one
-//      workgroup per bin), 1 to 4 streams, and class launches whole or split
-//      in two -- are each timed once on the full batch; the fastest is kept.
+//      workgroup per bin), 1 to 4 streams, class launches whole or split in
+//      two, FMA-count or measured costs, grids of all resident workgroups or
+//      of a half or a quarter of them -- are each timed once on the full
+//      batch; the fastest is kept.
 static int autotune(pimpc_ctx ctx) {
     struct Cand {
-        int schedule, nstreams, split;
+        int schedule, nstreams, split, measured, grid_div;
     };
-    const Cand cands[] = {{1, 4, 0}, {1, 1, 0}, {2, 4, 0}, {3, 4, 0}, {1, 4, 1}, {1, 3, 1}, {1, 2, 1}, {3, 4, 1}};
+    const Cand cands[] = {{1, 4, 0, 0, 1}, {1, 1, 0, 0, 1}, {2, 4, 0, 0, 1}, {3, 4, 0, 0, 1},
+                          {1, 4, 1, 1, 1}, {1, 3, 1, 1, 1}, {1, 2, 1, 1, 1}, {3, 4, 1, 1, 1},
+                          {1, 4, 0, 1, 1}, {3, 4, 0, 1, 1}, {1, 4, 0, 0, 2}, {1, 4, 0, 0, 4},
+                          {2, 4, 0, 0, 2}, {1, 4, 0, 1, 2}};
     const int ncand = (int)(sizeof(cands) / sizeof(cands[0]));
     const std::vector<ClassRun> base = ctx->runs;
-    if (ctx->opt.schedule > 0) {
+    if (ctx->opt.schedule > 0) {  // a fixed candidate; split launches take their costs from the FMA model
         const Cand& c = cands[(ctx->opt.schedule - 1) % ncand];
         ctx->schedule = c.schedule;
         ctx->nstreams = c.nstreams;
+        ctx->grid_div = c.grid_div;
         if (c.split) ctx->runs = split_runs(ctx, base);
         return PIMPC_OK;
     }
@@ -812,6 +819,7 @@ static int autotune(pimpc_ctx ctx) {
     {
         ctx->schedule = 1;
         ctx->nstreams = 4;
+        ctx->grid_div = 1;
         LaunchSet ls;
         int rc = make_set(ls);
         float ms = 0.f;
@@ -825,13 +833,18 @@ static int autotune(pimpc_ctx ctx) {
     }
     const std::vector<ClassRun> measured = ctx->runs;
     const std::vector<ClassRun> halves = split_runs(ctx, measured);
+    const std::vector<ClassRun> base_halves = split_runs(ctx, base);
+    auto runs_of = [&](const Cand& c) -> const std::vector<ClassRun>& {
+        return c.split ? (c.measured ? halves : base_halves) : (c.measured ? measured : base);
+    };
     // 2. candidates on the full batch
     float best = 1e30f;
     Cand bestc = cands[0];
     for (const Cand& c : cands) {
         ctx->schedule = c.schedule;
         ctx->nstreams = c.nstreams;
-        ctx->runs = c.split ? halves : measured;
+        ctx->grid_div = c.grid_div;
+        ctx->runs = runs_of(c);
         LaunchSet ls;
         int rc = make_set(ls);
         float ms = 0.f;
@@ -848,7 +861,8 @@ static int autotune(pimpc_ctx ctx) {
     (void)hipEventDestroy(t1);
     ctx->schedule = bestc.schedule;
     ctx->nstreams = bestc.nstreams;
-    ctx->runs = bestc.split ? halves : measured;
+    ctx->grid_div = bestc.grid_div;
+    ctx->runs = runs_of(bestc);
     return PIMPC_OK;
 }
 
