@@ -140,18 +140,6 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             la[i] = act ? p[(int64_t)(4 * NB + i) * N + k] : 0.f;
         }
     };
-    auto store_state = [&](float* base) {
-        if (!act) return;
-        const gptr<float> p = (gptr<float>)base;
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            p[(int64_t)(0 * NB + i) * N + k] = v[i];
-            p[(int64_t)(1 * NB + i) * N + k] = z[i];
-            p[(int64_t)(2 * NB + i) * N + k] = th[i];
-            p[(int64_t)(3 * NB + i) * N + k] = be[i];
-            p[(int64_t)(4 * NB + i) * N + k] = la[i];
-        }
-    };
 
     // Step 1 of the iteration from the current iterate: du, h, xbar (two barriers).
     float du[NU], h[NB], xs[NB], d[NB];
@@ -286,12 +274,100 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 }
             });
     };
+    // du = J d and xbar_{k+1} = H h of a recorded step (d, h from the tape),
+    // xbar_{k+1} then published in LDS for stage k + 1 (one barrier before the
+    // write: every lane has read the previous halo words there).
+    auto step1_from_rec = [&]() {
+        MATS()
+        using RowJ = SRow<float, NB>;
+        stream_rows<RowJ, NU, true>(
+            [&](int r) {
+                RowJ x;
+                sload_into<float, NB>(x.x, Jm + r * NB);
+                return x;
+            },
+            [&](int r, const RowJ& x) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) s += x.x[j] * d[j];
+                du[r] = s;
+            });
+        using RowH = SRow<float, NB>;
+        stream_rows<RowH, NB, true>(
+            [&](int r) {
+                RowH x;
+                sload_into<float, NB>(x.x, Hm + r * NB);
+                return x;
+            },
+            [&](int r, const RowH& x) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
+                xs[r] = s;
+            });
+        if (is_last) {
+            if (hb_diag) {
+#pragma unroll
+                for (int r = 0; r < NB; ++r) xs[r] = Hbm[r * NB + r] * h[r];
+            } else {
+                stream_rows<RowH, NB, true>(
+                    [&](int r) {
+                        RowH x;
+                        sload_into<float, NB>(x.x, Hbm + r * NB);
+                        return x;
+                    },
+                    [&](int r, const RowH& x) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
+                        xs[r] = s;
+                    });
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) xx[i * kBBD + tid] = xs[i];
+        __syncthreads();
+    };
     auto get_xp = [&](float (&xp)[NB]) {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const float xv = xx[i * kBBD + tid - 1];
             xp[i] = (k == 0) ? xb0[i] : (act ? xv : 0.f);
         }
+    };
+
+    // Segment tape: per stage and step, what the transposes need from the
+    // forward step -- d = v - beta (the input of du = J d), w = z - v - ebar
+    // + lambda (top rows: the input of g = Abar' w), h (the input of xbar =
+    // H h) and the box mask of the projection -- rather than the whole
+    // iterate: 2 NB + NX + 1 words instead of 5 NB, and the reverse step
+    // recomputes only du = J d and xbar = H h instead of steps 1-3.
+    constexpr int R = tape_rec_floats(NB, NX);
+    float w[NX];
+    uint32_t mask = 0u;
+    auto store_rec = [&](float* base) {
+        if (!act) return;
+        const gptr<float> p = (gptr<float>)base;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            p[(int64_t)i * N + k] = d[i];
+            p[(int64_t)(NB + i) * N + k] = h[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) p[(int64_t)(2 * NB + i) * N + k] = w[i];
+        p[(int64_t)(2 * NB + NX) * N + k] = __uint_as_float(mask);
+    };
+    auto load_rec = [&](const float* base) {
+        const gptr<float> p = (gptr<float>)base;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            d[i] = act ? p[(int64_t)i * N + k] : 0.f;
+            h[i] = act ? p[(int64_t)(NB + i) * N + k] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) w[i] = act ? p[(int64_t)(2 * NB + i) * N + k] : 0.f;
+        mask = act ? __float_as_uint(p[(int64_t)(2 * NB + NX) * N + k]) : 0u;
     };
 
     const int K = a.K;
@@ -303,22 +379,24 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
         const int i0 = seg * CK;
         const int i1 = min(i0 + CK, K);
         load_state(have ? a.ckpt + I.ck_off + (int64_t)seg * 5 * NB * N : a.ckpt);
-        // forward over the segment, keeping the iterate entering each step
+        // forward over the segment from its checkpoint, recording each step
 #pragma unroll 1
         for (int i = i0; i < i1; ++i) {
-            store_state(tape + (int64_t)(i - i0) * 5 * NB * N);
-            if (i + 1 < i1) {
-                step1();
-                float xp[NB];
-                uint32_t mask;
-                get_xp(xp);
-                step23(xp, true, mask);
+            step1();
+            {
+                MATS()
+#pragma unroll
+                for (int r = 0; r < NX; ++r) w[r] = z[r] - v[r] - em[r] + la[r];
             }
+            float xp[NB];
+            get_xp(xp);
+            step23(xp, i + 1 < i1, mask);
+            store_rec(tape + (int64_t)(i - i0) * R * N);
         }
         // reverse sweep
 #pragma unroll 1
         for (int i = i1 - 1; i >= i0; --i) {
-            load_state(tape + (int64_t)(i - i0) * 5 * NB * N);
+            load_rec(tape + (int64_t)(i - i0) * R * N);
             if (i == K - 1) {
                 // seed: u0 = u_prev + J (v_0 - beta_0) of the last step 1
                 MATS()
@@ -330,7 +408,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                     for (int r = 0; r < NU; ++r) ub[r] = r < nu_real ? a.dLdu0[I.u_off + r] : 0.f;
 #pragma unroll
                     for (int j = 0; j < NB; ++j) {
-                        dd[j] = v[j] - be[j];
+                        dd[j] = d[j];
                         float t = 0.f;
 #pragma unroll
                         for (int r = 0; r < NU; ++r) t += Jm[r * NB + j] * ub[r];
@@ -341,12 +419,11 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 stage_accum(CJ, ub, dd, stg, lane);
                 continue;
             }
-            // ---- recompute the step's intermediates
-            step1();
+            // ---- the step's du = J d and xbar_{k+1} = H h (H_{N-1} for the last
+            // stage); xbar_k from stage k - 1 through LDS
+            step1_from_rec();
             float xp[NB];
-            uint32_t mask;
             get_xp(xp);
-            step23(xp, false, mask);
             MATS()
             // ---- transpose of steps 2-3 (sv.. hold the adjoint of the new iterate)
             float nth[NB], xsb[NB], bb[NB], cb[NB];
@@ -502,7 +579,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 float v1[16], v2[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
-                    v1[q] = (q < NX && act) ? (z[q] - v[q] - em[q] + la[q]) : 0.f;
+                    v1[q] = (q < NX && act) ? w[q] : 0.f;
                     v2[q] = (q < NB) ? gr[q] : 0.f;
                 }
                 stage_accum(CA, v1, v2, stg, lane);

@@ -6,6 +6,11 @@
 
 namespace pimpc {
 
+// Words per stage and step of the backward's segment tape: d = v - beta (nb),
+// h (nb), the top rows of w = z - v - ebar + lambda (nx) and the box mask of
+// the projection (one word).
+__host__ __device__ constexpr int tape_rec_floats(int nb, int nx) { return 2 * nb + nx + 1; }
+
 struct BwdArgs {
     const InstDev* inst;
     const Bin* bins;

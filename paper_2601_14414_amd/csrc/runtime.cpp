@@ -1277,7 +1277,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             I.ck_off = ck;
             ck += (int64_t)nck * 5 * I.nbp * I.N;
             I.tape_off = tp;
-            tp += (int64_t)o->ckpt_every * 5 * I.nbp * I.N;
+            tp += (int64_t)o->ckpt_every * tape_rec_floats(I.nbp, I.nxp) * I.N;
             I.gr_off = (int64_t)i * kGradStride;
         }
         DALLOC(ctx->d_ckpt, float, ck);
