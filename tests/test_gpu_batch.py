@@ -9,7 +9,7 @@ import oracle
 from paper_2601_14414_amd import pimpc as P
 from paper_2601_14414_amd import workloads as W
 
-from test_gpu_lane import TOL32, compare, scaled_err
+from test_gpu_lane import TOL32, compare, scaled_err, tiny_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -165,4 +165,30 @@ def test_graph_replay_with_row_family_instances(side_stream):
     np.testing.assert_allclose(first, u_host, atol=1e-6)
     refs = [oracle.solve(p, K=30) for p in problems]
     compare(s, problems, refs, TOL32)
+    s.close()
+
+
+@pytest.mark.parametrize("accel", [False, True])
+def test_graph_replay_row_family_reducer_kernel(side_stream, accel):
+    """Graph replays of a batch whose row-family instance runs the reducer
+    kernel (eps stop, or restart acceleration) beside lane-family instances:
+    every replay equals the first and the host-path solve."""
+    problems = [tiny_problem(11, 3, 2, 700, 0)]  # row family; meets eps within 45 iterations
+    problems += [W.random_batch_instance(seed=3100 + i, K=300) for i in range(6)]
+    s = P.Solver(problems, max_iter=300, eps=1e-3, check_every=5, precision=P.PIMPC_FP32, accel=accel,
+                 schedule=1, stream=side_stream.cuda_stream)
+    first, info, x0 = _solve_batch(s, problems, side_stream)
+    assert np.all(info["status"] == 0) and info["iters"][0] < 300
+    for rep in range(3):
+        a = torch.randn(256, 256, device="cuda")
+        (a @ a).sum().item()
+        again, info2, _ = _solve_batch(s, problems, side_stream, x0=x0)
+        np.testing.assert_array_equal(again, first)
+        np.testing.assert_array_equal(info2["iters"], info["iters"])
+    # the device calls pass no u_prev: the host path gets zeros too (the
+    # problems' own u_prev enter the initial augmented state)
+    u_host, info_h = s.solve(x0=np.concatenate([p.x0 for p in problems]).astype(np.float32).astype(np.float64),
+                             u_prev=np.zeros(s.sum_nu))
+    np.testing.assert_array_equal(u_host, first)
+    np.testing.assert_array_equal(info_h["iters"], info["iters"])
     s.close()

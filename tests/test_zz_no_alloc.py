@@ -10,6 +10,8 @@ import pytest
 from paper_2601_14414_amd import pimpc as P
 from paper_2601_14414_amd import workloads as W
 
+from test_gpu_lane import tiny_problem
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -83,3 +85,25 @@ def test_noalloc_rejects_a_context_beyond_the_array():
         P.pimpc_solve_batch_noalloc(s.ctx, x0, None, u0, None, torch.cuda.current_stream().cuda_stream)
     assert ei.value.code == P.PIMPC_E_DIM
     s.close()
+
+
+def test_noalloc_with_eps_stop_and_acceleration():
+    """The row family's reducer-wave kernel (eps stop, restart acceleration)
+    keeps its per-workgroup partials and decision word in the same scratch:
+    the no-alloc call equals the allocating one, twice in a row."""
+    stream = torch.cuda.Stream()
+    for accel, N in ((False, 800), (True, 600)):
+        # the row instance (3 states, 2 inputs) meets eps within 60 iterations
+        problems = W.random_batch(8, base_seed=900 + N, K=400) + [tiny_problem(11, 3, 2, N, 0)]
+        kw = dict(max_iter=400, eps=1e-4, check_every=5, precision=P.PIMPC_FP32, accel=accel)
+        ref = P.Solver(problems, **kw)
+        u_ref, i_ref, st_ref = _run(P.pimpc_solve_batch, ref, problems, stream)
+        ref.close()
+        na = P.Solver(problems, **kw)
+        u_na, i_na, st_na = _run(P.pimpc_solve_batch_noalloc, na, problems, stream)
+        na.close()
+        assert np.all(i_ref["status"] == 0) and i_ref["iters"][-1] < 400
+        np.testing.assert_array_equal(u_na, u_ref)
+        np.testing.assert_array_equal(i_na, i_ref)
+        for w in range(5):
+            np.testing.assert_array_equal(st_na[w], st_ref[w])
