@@ -50,27 +50,53 @@ extern __shared__ __align__(16) unsigned char bwd_smem[];
 // without it the 16-float rows put the even lanes of a 128-bit write on the
 // same banks (a 4-way conflict); with it every write and read is
 // conflict-free for 32 and for 64 banks.
+//
+// A wave's staging tile holds four such [64][16] areas, so that one round
+// stages two products and runs their two MFMA chains interleaved (one write
+// pass, one read pass, two independent accumulators).
+constexpr int kStgArea = 64 * 16;           // floats per staged vector
+constexpr int kStgFloats = 4 * kStgArea + 32;  // four areas + the last stage's two vectors
 __device__ inline int stage_rot(int s) { return ((s >> 1) + (s >> 3)) & 3; }
+
+__device__ inline void stage_write(float* area, const float (&v)[16], int lane) {
+    float4* d = (float4*)(area + lane * 16);
+    const int wr = stage_rot(lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[(q + wr) & 3] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+
+// offset, within an area, of element lane % 16 of stage 4 t + lane / 16
+__device__ inline int stage_off(int t, int lane) {
+    const int i = lane & 15, st = 4 * t + (lane >> 4);
+    return st * 16 + 4 * (((i >> 2) + stage_rot(st)) & 3) + (i & 3);
+}
 
 __device__ inline void stage_accum(floatx4& C, const float (&v1)[16], const float (&v2)[16], float* stg,
                                    int lane) {
-    float4* s1 = (float4*)(stg + lane * 16);
-    float4* s2 = (float4*)(stg + 1024 + lane * 16);
-    const int wr = stage_rot(lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        s1[(q + wr) & 3] = make_float4(v1[4 * q], v1[4 * q + 1], v1[4 * q + 2], v1[4 * q + 3]);
-        s2[(q + wr) & 3] = make_float4(v2[4 * q], v2[4 * q + 1], v2[4 * q + 2], v2[4 * q + 3]);
-    }
+    stage_write(stg, v1, lane);
+    stage_write(stg + kStgArea, v2, lane);
     __builtin_amdgcn_wave_barrier();
-    const int i = lane & 15, kk = lane >> 4;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-        const int st = 4 * t + kk;  // the stage whose element i this lane supplies
-        const int off = st * 16 + 4 * (((i >> 2) + stage_rot(st)) & 3) + (i & 3);
-        const float av = stg[off];
-        const float bv = stg[1024 + off];
-        C = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, C, 0, 0, 0);
+        const int off = stage_off(t, lane);
+        C = __builtin_amdgcn_mfma_f32_16x16x4f32(stg[off], stg[kStgArea + off], C, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Two products in one round: C1 += A1 B1^T and C2 += A2 B2^T.
+__device__ inline void stage_accum2(floatx4& C1, const float (&a1)[16], const float (&b1)[16], floatx4& C2,
+                                    const float (&a2)[16], const float (&b2)[16], float* stg, int lane) {
+    stage_write(stg, a1, lane);
+    stage_write(stg + kStgArea, b1, lane);
+    stage_write(stg + 2 * kStgArea, a2, lane);
+    stage_write(stg + 3 * kStgArea, b2, lane);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int off = stage_off(t, lane);
+        C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(stg[off], stg[kStgArea + off], C1, 0, 0, 0);
+        C2 = __builtin_amdgcn_mfma_f32_16x16x4f32(stg[2 * kStgArea + off], stg[3 * kStgArea + off], C2, 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -96,7 +122,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     const cptr<float> M0 = (cptr<float>)uniform_ptr(have ? a.mats + I.mat_off : a.mats);
     float* xg = (float*)bwd_smem;
     float* xx = xg + 16 * kBBD;
-    float* stg = xx + 16 * kBBD + wave * 2048;  // this wave's staging tile
+    float* stg = xx + 16 * kBBD + wave * kStgFloats;  // this wave's staging tile
 
     const cptr<float> x0p = (cptr<float>)uniform_ptr(a.x0 + (have ? I.x_off : 0));
     const cptr<float> upp = (cptr<float>)uniform_ptr(a.uprev ? a.uprev + (have ? I.u_off : 0) : nullptr);
@@ -106,6 +132,10 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     for (int i = 0; i < NB; ++i)
         xb0[i] = i < NX ? (i < nx_real ? x0p[i] : 0.f) : ((upp && i - NX < nu_real) ? upp[i - NX] : 0.f);
     const bool is_last = act && k == N - 1;
+    const bool last_wave = have && (N - 1) / 64 == wave - gw0;  // the wave that holds stage N - 1
+    // J_bar and the top rows of B_bar share one 16 x 16 tile when they fit:
+    // rows dub (NU) then bb (NX), columns d (NB) then du (NU)
+    constexpr bool kMergeBJ = NB + NU <= 16;
     const bool hb_diag = have && I.hb_diag;
 
 #define MATS()                           \
@@ -481,20 +511,30 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             });
 #pragma unroll
             for (int i = 0; i < NB; ++i) xg[i * kBBD + tid] = xpb[i];
-            {  // Abar += cb xbar_k' (top rows), Bbar += bb du' (top rows)
-                float v1[16], v2[16];
+            {  // Abar += cb xbar_k' (top rows); Bbar += bb du' (top rows) and
+               // J_bar += dub d' (du = J (v - beta)).  Stages without a stage
+               // hold zero adjoints (cb, bb, dub), so their rows add nothing.
+                float a1[16], b1[16], a2[16], b2[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
-                    v1[q] = (q < NX) ? cb[q] : 0.f;
-                    v2[q] = (q < NB && act) ? xp[q] : 0.f;
+                    a1[q] = (q < NX) ? cb[q] : 0.f;
+                    b1[q] = (q < NB) ? xp[q] : 0.f;
                 }
-                stage_accum(CA, v1, v2, stg, lane);
+                if constexpr (kMergeBJ) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    v1[q] = (q < NX) ? bb[q] : 0.f;
-                    v2[q] = (q < NU && act) ? du[q] : 0.f;
+                    for (int q = 0; q < 16; ++q) {
+                        a2[q] = (q < NU) ? dub[q] : ((q < NB) ? bb[q - NU] : 0.f);
+                        b2[q] = (q < NB) ? d[q] : ((q < NB + NU) ? du[q - NB] : 0.f);
+                    }
+                    stage_accum2(CA, a1, b1, CJ, a2, b2, stg, lane);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        a2[q] = (q < NX) ? bb[q] : 0.f;
+                        b2[q] = (q < NU) ? du[q] : 0.f;
+                    }
+                    stage_accum2(CA, a1, b1, CB, a2, b2, stg, lane);
                 }
-                stage_accum(CB, v1, v2, stg, lane);
             }
             __syncthreads();
             // ---- transpose of step 1
@@ -539,17 +579,20 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                         });
                 }
             }
-            {  // H_a += xsb h' (k < N-1), H_{N-1} += xsb h' (k = N-1)
-                float v1[16], v2[16];
+            if (last_wave) {  // H_{N-1} += xsb h' of stage N - 1, in the MFMA tile layout
+                float* lw = stg + 4 * kStgArea;
+                if (is_last) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    v1[q] = (q < NB && act && !is_last) ? xsb[q] : 0.f;
-                    v2[q] = (q < NB && act) ? h[q] : 0.f;
+                    for (int q = 0; q < 16; ++q) {
+                        lw[q] = (q < NB) ? xsb[q] : 0.f;
+                        lw[16 + q] = (q < NB) ? h[q] : 0.f;
+                    }
                 }
-                stage_accum(CHa, v1, v2, stg, lane);
+                __builtin_amdgcn_wave_barrier();
+                const float hv = lw[16 + (lane & 15)];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) v1[q] = (q < NB && is_last) ? xsb[q] : 0.f;
-                stage_accum(CHb, v1, v2, stg, lane);
+                for (int q = 0; q < 4; ++q) CHb[q] += lw[4 * (lane >> 4) + q] * hv;
+                __builtin_amdgcn_wave_barrier();
             }
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
@@ -575,14 +618,16 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 for (int cc = 0; cc < NB; ++cc) s += x.x[cc] * gr[cc];
                 wb[r] = s;
             });
-            {  // Abar += w_k g_bar' (top rows)
-                float v1[16], v2[16];
+            {  // H_a += xsb h' (k < N-1); Abar += w_k g_bar' (top rows)
+                float a1[16], b1[16], a2[16], b2[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
-                    v1[q] = (q < NX && act) ? w[q] : 0.f;
-                    v2[q] = (q < NB) ? gr[q] : 0.f;
+                    a1[q] = (q < NB && !is_last) ? xsb[q] : 0.f;
+                    b1[q] = (q < NB) ? h[q] : 0.f;
+                    a2[q] = (q < NX) ? w[q] : 0.f;
+                    b2[q] = (q < NB) ? gr[q] : 0.f;
                 }
-                stage_accum(CA, v1, v2, stg, lane);
+                stage_accum2(CHa, a1, b1, CA, a2, b2, stg, lane);
             }
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
@@ -590,13 +635,12 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 nv[i] -= wb[i];
                 nla[i] += wb[i];
             }
-            // du = J (v - beta)
-            {
+            if constexpr (!kMergeBJ) {  // J_bar += dub d' (du = J (v - beta))
                 float v1[16], v2[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
-                    v1[q] = (q < NU && act) ? dub[q] : 0.f;
-                    v2[q] = (q < NB && act) ? d[q] : 0.f;
+                    v1[q] = (q < NU) ? dub[q] : 0.f;
+                    v2[q] = (q < NB) ? d[q] : 0.f;
                 }
                 stage_accum(CJ, v1, v2, stg, lane);
             }
@@ -634,7 +678,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
 
     // ---- reduce the per-wave tiles over the instance's waves, write raw adjoints
     __syncthreads();
-    float* red = xx + 16 * kBBD + wave * 2048;  // reuse this wave's staging tile
+    float* red = xx + 16 * kBBD + wave * kStgFloats;  // reuse this wave's staging tile
     const floatx4 tiles[5] = {CHa, CHb, CJ, CA, CB};
 #pragma unroll
     for (int b5 = 0; b5 < 5; ++b5)
@@ -645,8 +689,21 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
         const int nw = (N + 63) >> 6;
         float* out = a.grads + I.gr_off;
         for (int e = lane; e < 5 * 256; e += 64) {
+            // with the merged tile (slot 2): J_bar is its rows < NU, columns
+            // < NB; the top rows of B_bar are rows NU.., columns NB..
+            int src = e;
+            bool zero = false;
+            if constexpr (kMergeBJ) {
+                const int tile = e >> 8, row = (e >> 4) & 15, col = e & 15;
+                if (tile == 2) zero = !(row < NU && col < NB);
+                if (tile == 4) {
+                    src = 2 * 256 + (NU + row) * 16 + NB + col;
+                    zero = !(row < NX && col < NU);
+                }
+            }
             float s = 0.f;
-            for (int w = gw0; w < gw0 + nw; ++w) s += (xx + 16 * kBBD)[w * 2048 + e];
+            if (!zero)
+                for (int w = gw0; w < gw0 + nw; ++w) s += (xx + 16 * kBBD)[w * kStgFloats + src];
             out[e] = s;
         }
         if (k == 0)
@@ -848,7 +905,9 @@ __global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ i
 
 // ---------------------------------------------------------------- host side
 
-inline size_t bwd_lds_bytes() { return (size_t)2 * 16 * kBBD * sizeof(float) + (size_t)kBwdWaves * 2048 * sizeof(float); }
+inline size_t bwd_lds_bytes() {
+    return (size_t)2 * 16 * kBBD * sizeof(float) + (size_t)kBwdWaves * kStgFloats * sizeof(float);
+}
 
 template <int NX, int NU>
 hipError_t launch_bwd_cls(const BwdArgs& a, int grid, hipStream_t s) {
