@@ -51,11 +51,13 @@ extern __shared__ __align__(16) unsigned char bwd_smem[];
 // same banks (a 4-way conflict); with it every write and read is
 // conflict-free for 32 and for 64 banks.
 //
-// A wave's staging tile holds four such [64][16] areas, so that one round
-// stages two products and runs their two MFMA chains interleaved (one write
-// pass, one read pass, two independent accumulators).
-constexpr int kStgArea = 64 * 16;           // floats per staged vector
-constexpr int kStgFloats = 4 * kStgArea + 32;  // four areas + the last stage's two vectors
+// A wave's staging tile holds six such [64][16] areas: each product's two
+// vectors are written to their areas as soon as they are final (so they do
+// not stay live in registers through the rest of the step), and one round
+// then runs two products' MFMA chains interleaved.  After the areas: the
+// last stage's xsb and h (32 floats) and the x0 adjoint (16 floats).
+constexpr int kStgArea = 64 * 16;                 // floats per staged vector
+constexpr int kStgFloats = 6 * kStgArea + 48;     // six areas + 48 floats
 __device__ inline int stage_rot(int s) { return ((s >> 1) + (s >> 3)) & 3; }
 
 __device__ inline void stage_write(float* area, const float (&v)[16], int lane) {
@@ -65,41 +67,172 @@ __device__ inline void stage_write(float* area, const float (&v)[16], int lane) 
     for (int q = 0; q < 4; ++q) d[(q + wr) & 3] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
 }
 
-// offset, within an area, of element lane % 16 of stage 4 t + lane / 16
-__device__ inline int stage_off(int t, int lane) {
-    const int i = lane & 15, st = 4 * t + (lane >> 4);
-    return st * 16 + 4 * (((i >> 2) + stage_rot(st)) & 3) + (i & 3);
+// offset, within an area, of element i = lane % 16 of stage st = 4 t + kk,
+// kk = lane / 16: st * 16 + 4 ((i / 4 + stage_rot(st)) mod 4) + i mod 4.
+// With st / 2 = 2 t + kk / 2 and st / 8 = t / 2, stage_rot(st) is
+// kk / 2 + (2 t + t / 2) mod 4, so the offset is 64 t plus one of four
+// per-lane bases (four VGPRs for all sixteen t; 64 t goes into the
+// instruction's offset field).
+__device__ inline int stage_base(int r, int lane) {
+    const int i = lane & 15, kk = lane >> 4;
+    return kk * 16 + 4 * (((i >> 2) + (kk >> 1) + r) & 3) + (i & 3);
+}
+__device__ inline int stage_off(int t, int lane) { return 64 * t + stage_base((2 * t + (t >> 1)) & 3, lane); }
+
+// C += A B^T from two staged areas
+__device__ inline void stage_mfma(floatx4& C, const float* A, const float* B, int lane) {
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int off = stage_off(t, lane);
+        C = __builtin_amdgcn_mfma_f32_16x16x4f32(A[off], B[off], C, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// C1 += A1 B1^T and C2 += A2 B2^T, the two chains interleaved
+__device__ inline void stage_mfma2(floatx4& C1, const float* A1, const float* B1, floatx4& C2, const float* A2,
+                                   const float* B2, int lane) {
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int off = stage_off(t, lane);
+        C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A1[off], B1[off], C1, 0, 0, 0);
+        C2 = __builtin_amdgcn_mfma_f32_16x16x4f32(A2[off], B2[off], C2, 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
 }
 
 __device__ inline void stage_accum(floatx4& C, const float (&v1)[16], const float (&v2)[16], float* stg,
                                    int lane) {
     stage_write(stg, v1, lane);
     stage_write(stg + kStgArea, v2, lane);
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int off = stage_off(t, lane);
-        C = __builtin_amdgcn_mfma_f32_16x16x4f32(stg[off], stg[kStgArea + off], C, 0, 0, 0);
-    }
-    __builtin_amdgcn_wave_barrier();
+    stage_mfma(C, stg, stg + kStgArea, lane);
 }
 
-// Two products in one round: C1 += A1 B1^T and C2 += A2 B2^T.
-__device__ inline void stage_accum2(floatx4& C1, const float (&a1)[16], const float (&b1)[16], floatx4& C2,
-                                    const float (&a2)[16], const float (&b2)[16], float* stg, int lane) {
-    stage_write(stg, a1, lane);
-    stage_write(stg + kStgArea, b1, lane);
-    stage_write(stg + 2 * kStgArea, a2, lane);
-    stage_write(stg + 3 * kStgArea, b2, lane);
-    __builtin_amdgcn_wave_barrier();
+// The stage matrices of a wave's instance, copied once per bin into the
+// wave's own LDS image, rows padded to a multiple of four floats:
+// J [NU][NBP], H and H_{N-1} [NB][NBP], the top rows [A_r B_r] [NX][NBP],
+// then ebar, qbar, lb, ub (NBP each).  Rows are read as float4 broadcasts
+// (every lane the same address): LDS returns in order, so several rows can
+// be in flight behind partial waits.
+constexpr int kMatFloats = 832;  // the widest class: 4 x 16 + 2 x 16 x 16 + 12 x 16 + 4 x 16
+
+template <int NX, int NU>
+struct MatImg {
+    static constexpr int NB = NX + NU;
+    static constexpr int NBP = (NB + 3) & ~3;
+    static constexpr int J = 0;
+    static constexpr int H = J + NU * NBP;
+    static constexpr int Hb = H + NB * NBP;
+    static constexpr int AB = Hb + NB * NBP;
+    static constexpr int E = AB + NX * NBP;
+    static constexpr int Q = E + NBP;
+    static constexpr int LB = Q + NBP;
+    static constexpr int UB = LB + NBP;
+    static constexpr int TOT = UB + NBP;
+    static_assert(TOT <= kMatFloats, "the matrix image exceeds its LDS slot");
+};
+
+// one padded row from LDS (16-byte aligned)
+template <int NBP>
+__device__ __forceinline__ void lds_row(float (&x)[NBP], const float* p) {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int off = stage_off(t, lane);
-        C1 = __builtin_amdgcn_mfma_f32_16x16x4f32(stg[off], stg[kStgArea + off], C1, 0, 0, 0);
-        C2 = __builtin_amdgcn_mfma_f32_16x16x4f32(stg[2 * kStgArea + off], stg[3 * kStgArea + off], C2, 0, 0, 0);
+    for (int q = 0; q < NBP / 4; ++q) {
+        const float4 t = ((const float4*)p)[q];
+        x[4 * q] = t.x;
+        x[4 * q + 1] = t.y;
+        x[4 * q + 2] = t.z;
+        x[4 * q + 3] = t.w;
     }
-    __builtin_amdgcn_wave_barrier();
 }
+
+// Rows 0..R-1 of a padded LDS matrix, body(r, row): row r + D is requested
+// before body(r) runs, and a scheduling fence after each row keeps the
+// compiler from hoisting further rows (each row in flight holds NBP VGPRs).
+template <int R, int NBP, int D = 2, typename B>
+__device__ __forceinline__ void lds_rows(const float* base, B&& body) {
+    float buf[D + 1][NBP];
+#pragma unroll
+    for (int r = 0; r < D && r < R; ++r) lds_row(buf[r], base + r * NBP);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r + D < R) lds_row(buf[(r + D) % (D + 1)], base + (r + D) * NBP);
+        body(r, buf[r % (D + 1)]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Where a step reads its stage matrices: the LDS image (LR, stages up to
+// twelve floats wide), or the global copy streamed through SGPRs one row
+// ahead (wider stages: their per-lane vectors leave no VGPRs for rows).
+// body(r, x) gets row r in x[0..NB).
+template <int NX, int NU, bool LR>
+struct MatView {
+    static constexpr int NB = NX + NU;
+    static constexpr int NBP = (NB + 3) & ~3;
+    using MI = MatImg<NX, NU>;
+    using Row = SRow<float, NBP>;
+    const float* L;  // the LDS image
+    cptr<float> G;   // the global matrices
+    MatOffsets o;
+    __device__ float e(int i) const { if constexpr (LR) return L[MI::E + i]; else return G[o.e + i]; }
+    __device__ float qb(int i) const { if constexpr (LR) return L[MI::Q + i]; else return G[o.qbar + i]; }
+    __device__ float lb(int i) const { if constexpr (LR) return L[MI::LB + i]; else return G[o.lb + i]; }
+    __device__ float ub(int i) const { if constexpr (LR) return L[MI::UB + i]; else return G[o.ub + i]; }
+    __device__ float j(int r, int c) const {
+        if constexpr (LR) return L[MI::J + r * NBP + c]; else return G[o.J + r * NB + c];
+    }
+    template <typename B>
+    __device__ __forceinline__ void rowsJ(B&& body) const {
+        if constexpr (LR) {
+            lds_rows<NU, NBP>(L + MI::J, body);
+        } else {
+            stream_rows<Row, NU, true>(
+                [&](int r) {
+                    Row x;
+                    sload_into<float, NB>(x.x, G + o.J + r * NB);
+                    return x;
+                },
+                [&](int r, const Row& x) { body(r, x.x); });
+        }
+    }
+    // the top rows [A_r B_r]
+    template <typename B>
+    __device__ __forceinline__ void rowsAB(B&& body) const {
+        if constexpr (LR) {
+            lds_rows<NX, NBP>(L + MI::AB, body);
+        } else {
+            stream_rows<Row, NX, true>(
+                [&](int r) {
+                    Row x;
+                    sload_into<float, NX>(x.x, G + o.A + r * NX);
+                    sload_into<float, NU>(x.x + NX, G + o.B + r * NU);
+                    return x;
+                },
+                [&](int r, const Row& x) { body(r, x.x); });
+        }
+    }
+    // H, or H_{N-1} where `last` (body assigns, so the second pass overwrites)
+    template <typename B>
+    __device__ __forceinline__ void rowsH(bool last, B&& body) const {
+        if constexpr (LR) {
+            lds_rows<NB, NBP>(L + (last ? MI::Hb : MI::H), body);
+        } else {
+            auto pass = [&](int64_t off) {
+                stream_rows<Row, NB, true>(
+                    [&](int r) {
+                        Row x;
+                        sload_into<float, NB>(x.x, G + off + r * NB);
+                        return x;
+                    },
+                    [&](int r, const Row& x) { body(r, x.x); });
+            };
+            pass(o.H);
+            if (last) pass(o.Hb);
+        }
+    }
+};
 
 template <int NX, int NU>
 __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool have, int gw0,
@@ -120,17 +253,55 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     const float third = 1.0f / 3.0f;
     const MatOffsets o = mat_offsets(NX, NU, have ? N : 1, 0);
     const cptr<float> M0 = (cptr<float>)uniform_ptr(have ? a.mats + I.mat_off : a.mats);
+    // LDS: three halo buffers [16][kBBD] (stage to stage: xg towards k - 1,
+    // xx and xq towards k + 1), then one staging tile per wave
     float* xg = (float*)bwd_smem;
     float* xx = xg + 16 * kBBD;
-    float* stg = xx + 16 * kBBD + wave * kStgFloats;  // this wave's staging tile
+    float* xq = xx + 16 * kBBD;
+    float* stg0 = xq + 16 * kBBD;
+    float* stg = stg0 + wave * kStgFloats;  // this wave's staging tile
+    using MI = MatImg<NX, NU>;
+    constexpr int NBP = MI::NBP;
+    constexpr bool kLdsRows = NBP <= 12;
+    float* mw = stg0 + kBwdWaves * kStgFloats + wave * kMatFloats;  // this wave's matrix image
+    if constexpr (kLdsRows) {
+        const float* Mg = a.mats + (have ? I.mat_off : 0);
+        for (int e = lane; e < MI::TOT; e += 64) {
+            float val = 0.f;
+            if (have) {
+                if (e < MI::AB) {  // J, H, H_{N-1}: rows of NB
+                    const int blk = e < MI::H ? 0 : (e < MI::Hb ? 1 : 2);
+                    const int base = blk == 0 ? MI::J : (blk == 1 ? MI::H : MI::Hb);
+                    const int r = (e - base) / NBP, c = (e - base) % NBP;
+                    const int64_t src = blk == 0 ? o.J : (blk == 1 ? o.H : o.Hb);
+                    if (c < NB) val = Mg[src + r * NB + c];
+                } else if (e < MI::E) {  // [A_r B_r]
+                    const int r = (e - MI::AB) / NBP, c = (e - MI::AB) % NBP;
+                    if (c < NX)
+                        val = Mg[o.A + r * NX + c];
+                    else if (c < NB)
+                        val = Mg[o.B + r * NU + (c - NX)];
+                } else {
+                    const int blk = (e - MI::E) / NBP, c = (e - MI::E) % NBP;
+                    if (blk == 0) {
+                        if (c < NX) val = Mg[o.e + c];
+                    } else if (c < NB) {
+                        val = Mg[(blk == 1 ? o.qbar : (blk == 2 ? o.lb : o.ub)) + c];
+                    }
+                }
+            }
+            mw[e] = val;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 
     const cptr<float> x0p = (cptr<float>)uniform_ptr(a.x0 + (have ? I.x_off : 0));
     const cptr<float> upp = (cptr<float>)uniform_ptr(a.uprev ? a.uprev + (have ? I.u_off : 0) : nullptr);
     const int nx_real = have ? I.nx : 0, nu_real = have ? I.nu : 0;
-    float xb0[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        xb0[i] = i < NX ? (i < nx_real ? x0p[i] : 0.f) : ((upp && i - NX < nu_real) ? upp[i - NX] : 0.f);
+    // xbar_0 = (x0, u_prev), read where stage 0 needs it
+    auto xb0 = [&](int i) -> float {
+        return i < NX ? (i < nx_real ? x0p[i] : 0.f) : ((upp && i - NX < nu_real) ? upp[i - NX] : 0.f);
+    };
     const bool is_last = act && k == N - 1;
     const bool last_wave = have && (N - 1) / 64 == wave - gw0;  // the wave that holds stage N - 1
     // J_bar and the top rows of B_bar share one 16 x 16 tile when they fit:
@@ -138,25 +309,22 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     constexpr bool kMergeBJ = NB + NU <= 16;
     const bool hb_diag = have && I.hb_diag;
 
-#define MATS()                           \
-    cptr<float> Mi = M0;                 \
-    asm volatile("" : "+s"(Mi));         \
-    const cptr<float> Jm = Mi + o.J;     \
-    const cptr<float> Hm = Mi + o.H;     \
-    const cptr<float> Hbm = Mi + o.Hb;   \
-    const cptr<float> Am = Mi + o.A;     \
-    const cptr<float> Bm = Mi + o.B;     \
-    const cptr<float> em = Mi + o.e;     \
-    const cptr<float> qb = Mi + o.qbar;  \
-    const cptr<float> lbm = Mi + o.lb;   \
-    const cptr<float> ubm = Mi + o.ub;   \
-    (void)Jm; (void)Hm; (void)Hbm; (void)Am; (void)Bm; (void)em; (void)qb; (void)lbm; (void)ubm;
+// the stage matrices behind opaque offsets: their reads stay in the step
+// that makes them (not hoisted out of the iteration loops into registers)
+#define MATS()                                  \
+    int mo_ = 0;                                \
+    asm volatile("" : "+s"(mo_));               \
+    cptr<float> mg_ = M0;                       \
+    asm volatile("" : "+s"(mg_));               \
+    const MatView<NX, NU, kLdsRows> mv{mw + mo_, mg_, o};
 
     float v[NB], z[NB], th[NB], be[NB], la[NB];
     float sv[NB], sz[NB], sth[NB], sbe[NB], sla[NB];  // adjoint of the iterate entering the step
-    float x0b[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) sv[i] = sz[i] = sth[i] = sbe[i] = sla[i] = x0b[i] = 0.f;
+    for (int i = 0; i < NB; ++i) sv[i] = sz[i] = sth[i] = sbe[i] = sla[i] = 0.f;
+    float* lw = stg + 6 * kStgArea;  // [0, 32): the last stage's xsb and h; [32, 48): the x0 adjoint
+    if (lane < 16) lw[32 + lane] = 0.f;
+    __builtin_amdgcn_wave_barrier();
     floatx4 CHa = {0, 0, 0, 0}, CHb = {0, 0, 0, 0}, CJ = {0, 0, 0, 0}, CA = {0, 0, 0, 0}, CB = {0, 0, 0, 0};
 
     auto load_state = [&](const float* base) {
@@ -180,33 +348,18 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
         float g[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) g[c] = (c < NX) ? 0.f : (z[c] - v[c] + la[c]);
-        // one stream of rows: J (du = J d), then [A_r B_r e_r] (g = Abar' w)
-        using RowJA = SRow<float, NB + 1>;
-        stream_rows<RowJA, NU + NX, true>(
-            [&](int r) {
-                RowJA x;
-                if (r < NU) {
-                    sload_into<float, NB>(x.x, Jm + r * NB);
-                } else {
-                    sload_into<float, NX>(x.x, Am + (r - NU) * NX);
-                    sload_into<float, NU>(x.x + NX, Bm + (r - NU) * NU);
-                    sload_into<float, 1>(x.x + NB, em + (r - NU));
-                }
-                return x;
-            },
-            [&](int r, const RowJA& x) {
-                if (r < NU) {
-                    float s = 0.f;
+        // du = J d, and g = Abar' w from the top rows [A_r B_r]
+        mv.rowsJ([&](int r, const float (&x)[NBP]) {
+            float s = 0.f;
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) s += x.x[j] * d[j];
-                    du[r] = s;
-                } else {
-                    const int rr = r - NU;
-                    const float w = z[rr] - v[rr] - x.x[NB] + la[rr];
+            for (int j = 0; j < NB; ++j) s += x[j] * d[j];
+            du[r] = s;
+        });
+        mv.rowsAB([&](int rr, const float (&x)[NBP]) {
+            const float w = z[rr] - v[rr] - mv.e(rr) + la[rr];
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) g[c] += x.x[c] * w;
-                }
-            });
+            for (int c = 0; c < NB; ++c) g[c] += x[c] * w;
+        });
 #pragma unroll
         for (int c = 0; c < NB; ++c) xg[c * kBBD + tid] = g[c];
         __syncthreads();
@@ -214,40 +367,15 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const float gv = xg[i * kBBD + tid + 1];
-            h[i] = qb[i] + rho * (z[i] - th[i] + (hasnext ? gv : 0.f));
+            h[i] = mv.qb(i) + rho * (z[i] - th[i] + (hasnext ? gv : 0.f));
         }
-        using RowH = SRow<float, NB>;
-        stream_rows<RowH, NB, true>(
-            [&](int r) {
-                RowH x;
-                sload_into<float, NB>(x.x, Hm + r * NB);
-                return x;
-            },
-            [&](int r, const RowH& x) {
-                float s = 0.f;
+        // xbar_{k+1} = H h (H_{N-1} for the last stage)
+        mv.rowsH(is_last, [&](int r, const float (&x)[NBP]) {
+            float s = 0.f;
 #pragma unroll
-                for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
-                xs[r] = s;
-            });
-        if (is_last) {
-            if (hb_diag) {
-#pragma unroll
-                for (int r = 0; r < NB; ++r) xs[r] = Hbm[r * NB + r] * h[r];
-            } else {
-                stream_rows<RowH, NB, true>(
-                    [&](int r) {
-                        RowH x;
-                        sload_into<float, NB>(x.x, Hbm + r * NB);
-                        return x;
-                    },
-                    [&](int r, const RowH& x) {
-                        float s = 0.f;
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
-                        xs[r] = s;
-                    });
-            }
-        }
+            for (int j = 0; j < NB; ++j) s += x[j] * h[j];
+            xs[r] = s;
+        });
 #pragma unroll
         for (int i = 0; i < NB; ++i) xx[i * kBBD + tid] = xs[i];
         __syncthreads();
@@ -258,112 +386,44 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     auto step23 = [&](const float (&xp)[NB], bool advance, uint32_t& mask) {
         MATS()
         mask = 0u;
-        using Row = SRow<float, NB + 3>;
-        stream_rows<Row, NB, true>(
-            [&](int i) {
-                Row x;
-                if (i < NX) {
-                    sload_into<float, NX>(x.x, Am + i * NX);
-                    sload_into<float, NU>(x.x + NX, Bm + i * NU);
-                    sload_into<float, 1>(x.x + NB, em + i);
+        // rows i < NX use [A_i B_i]; the input rows i >= NX have none
+        auto tail = [&](int i, float bi, float ci) {
+            const float lo = mv.lb(i), hi = mv.ub(i);
+            const float y = (2.f * (xs[i] + th[i]) + bi + ci) * third;
+            if (y > lo && y < hi) mask |= 1u << i;
+            if (advance) {
+                const float gam = bi - ci;
+                const float zn = y < lo ? lo : (y > hi ? hi : y);
+                const float vn = (zn + gam) * 0.5f;
+                const float thn = th[i] + xs[i] - zn;
+                if (act) {
+                    v[i] = vn;
+                    th[i] = thn;
+                    be[i] = bi - vn;
+                    la[i] = zn - vn - ci;
+                    z[i] = zn;
                 }
-                sload_into<float, 1>(x.x + NB + 1, lbm + i);
-                sload_into<float, 1>(x.x + NB + 2, ubm + i);
-                return x;
-            },
-            [&](int i, const Row& x) {
-                float bi, ci;
-                if (i < NX) {
-                    bi = be[i];
-#pragma unroll
-                    for (int j = 0; j < NU; ++j) bi += x.x[NX + j] * du[j];
-                    ci = x.x[NB] - la[i];
-#pragma unroll
-                    for (int j = 0; j < NX; ++j) ci += x.x[j] * xp[j];
-#pragma unroll
-                    for (int j = 0; j < NU; ++j) ci += x.x[NX + j] * xp[NX + j];
-                } else {
-                    bi = du[i - NX] + be[i];
-                    ci = xp[i] - la[i];
-                }
-                const float lo = x.x[NB + 1], hi = x.x[NB + 2];
-                const float y = (2.f * (xs[i] + th[i]) + bi + ci) * third;
-                if (y > lo && y < hi) mask |= 1u << i;
-                if (advance) {
-                    const float gam = bi - ci;
-                    const float zn = y < lo ? lo : (y > hi ? hi : y);
-                    const float vn = (zn + gam) * 0.5f;
-                    const float thn = th[i] + xs[i] - zn;
-                    if (act) {
-                        v[i] = vn;
-                        th[i] = thn;
-                        be[i] = bi - vn;
-                        la[i] = zn - vn - ci;
-                        z[i] = zn;
-                    }
-                }
-            });
-    };
-    // du = J d and xbar_{k+1} = H h of a recorded step (d, h from the tape),
-    // xbar_{k+1} then published in LDS for stage k + 1 (one barrier before the
-    // write: every lane has read the previous halo words there).
-    auto step1_from_rec = [&]() {
-        MATS()
-        using RowJ = SRow<float, NB>;
-        stream_rows<RowJ, NU, true>(
-            [&](int r) {
-                RowJ x;
-                sload_into<float, NB>(x.x, Jm + r * NB);
-                return x;
-            },
-            [&](int r, const RowJ& x) {
-                float s = 0.f;
-#pragma unroll
-                for (int j = 0; j < NB; ++j) s += x.x[j] * d[j];
-                du[r] = s;
-            });
-        using RowH = SRow<float, NB>;
-        stream_rows<RowH, NB, true>(
-            [&](int r) {
-                RowH x;
-                sload_into<float, NB>(x.x, Hm + r * NB);
-                return x;
-            },
-            [&](int r, const RowH& x) {
-                float s = 0.f;
-#pragma unroll
-                for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
-                xs[r] = s;
-            });
-        if (is_last) {
-            if (hb_diag) {
-#pragma unroll
-                for (int r = 0; r < NB; ++r) xs[r] = Hbm[r * NB + r] * h[r];
-            } else {
-                stream_rows<RowH, NB, true>(
-                    [&](int r) {
-                        RowH x;
-                        sload_into<float, NB>(x.x, Hbm + r * NB);
-                        return x;
-                    },
-                    [&](int r, const RowH& x) {
-                        float s = 0.f;
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) s += x.x[j] * h[j];
-                        xs[r] = s;
-                    });
             }
-        }
-        __syncthreads();
+        };
+        mv.rowsAB([&](int i, const float (&x)[NBP]) {
+            float bi = be[i];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) xx[i * kBBD + tid] = xs[i];
-        __syncthreads();
+            for (int j = 0; j < NU; ++j) bi += x[NX + j] * du[j];
+            float ci = mv.e(i) - la[i];
+#pragma unroll
+            for (int j = 0; j < NX; ++j) ci += x[j] * xp[j];
+#pragma unroll
+            for (int j = 0; j < NU; ++j) ci += x[NX + j] * xp[NX + j];
+            tail(i, bi, ci);
+        });
+#pragma unroll
+        for (int i = NX; i < NB; ++i) tail(i, du[i - NX] + be[i], xp[i] - la[i]);
     };
     auto get_xp = [&](float (&xp)[NB]) {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const float xv = xx[i * kBBD + tid - 1];
-            xp[i] = (k == 0) ? xb0[i] : (act ? xv : 0.f);
+            xp[i] = (k == 0) ? xb0(i) : (act ? xv : 0.f);
         }
     };
 
@@ -388,6 +448,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
         for (int i = 0; i < NX; ++i) p[(int64_t)(2 * NB + i) * N + k] = w[i];
         p[(int64_t)(2 * NB + NX) * N + k] = __uint_as_float(mask);
     };
+    // (the reverse step reads w from the record where it uses it)
     auto load_rec = [&](const float* base) {
         const gptr<float> p = (gptr<float>)base;
 #pragma unroll
@@ -395,8 +456,6 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             d[i] = act ? p[(int64_t)i * N + k] : 0.f;
             h[i] = act ? p[(int64_t)(NB + i) * N + k] : 0.f;
         }
-#pragma unroll
-        for (int i = 0; i < NX; ++i) w[i] = act ? p[(int64_t)(2 * NB + i) * N + k] : 0.f;
         mask = act ? __float_as_uint(p[(int64_t)(2 * NB + NX) * N + k]) : 0u;
     };
 
@@ -416,7 +475,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             {
                 MATS()
 #pragma unroll
-                for (int r = 0; r < NX; ++r) w[r] = z[r] - v[r] - em[r] + la[r];
+                for (int r = 0; r < NX; ++r) w[r] = z[r] - v[r] - mv.e(r) + la[r];
             }
             float xp[NB];
             get_xp(xp);
@@ -426,6 +485,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
         // reverse sweep
 #pragma unroll 1
         for (int i = i1 - 1; i >= i0; --i) {
+            const gptr<float> rec = (gptr<float>)(tape + (int64_t)(i - i0) * R * N);
             load_rec(tape + (int64_t)(i - i0) * R * N);
             if (i == K - 1) {
                 // seed: u0 = u_prev + J (v_0 - beta_0) of the last step 1
@@ -441,7 +501,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                         dd[j] = d[j];
                         float t = 0.f;
 #pragma unroll
-                        for (int r = 0; r < NU; ++r) t += Jm[r * NB + j] * ub[r];
+                        for (int r = 0; r < NU; ++r) t += mv.j(r, j) * ub[r];
                         sv[j] += t;
                         sbe[j] -= t;
                     }
@@ -449,12 +509,25 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 stage_accum(CJ, ub, dd, stg, lane);
                 continue;
             }
-            // ---- the step's du = J d and xbar_{k+1} = H h (H_{N-1} for the last
-            // stage); xbar_k from stage k - 1 through LDS
-            step1_from_rec();
-            float xp[NB];
-            get_xp(xp);
             MATS()
+            // staging areas of the parameter products: 0 cb | w, 1 xbar_k | gr,
+            // 2 [dub; bb] (bb alone when J_bar has its own tile), 3 [d; du] (du),
+            // 4 xsb (zero at stage N - 1), 5 h; stages without a stage hold
+            // zero adjoints (cb, bb, dub, xsb) and zero tape words, so their
+            // rows add nothing
+            float* ar0 = stg;
+            float* ar1 = stg + kStgArea;
+            float* ar2 = stg + 2 * kStgArea;
+            float* ar3 = stg + 3 * kStgArea;
+            float* ar4 = stg + 4 * kStgArea;
+            float* ar5 = stg + 5 * kStgArea;
+            auto put = [&](float* area, auto&& f) {
+                float t[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) t[q] = f(q);
+                stage_write(area, t, lane);
+            };
+            put(ar5, [&](int q) { return q < NB ? h[q] : 0.f; });
             // ---- transpose of steps 2-3 (sv.. hold the adjoint of the new iterate)
             float nth[NB], xsb[NB], bb[NB], cb[NB];
 #pragma unroll
@@ -480,6 +553,8 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 bb[i] = act ? bbi : 0.f;
                 cb[i] = act ? cbi : 0.f;
             }
+            put(ar0, [&](int q) { return q < NX ? cb[q] : 0.f; });
+            if constexpr (!kMergeBJ) put(ar2, [&](int q) { return q < NX ? bb[q] : 0.f; });
             // adjoint of the step's input iterate, first contributions
             float nv[NB], nz[NB], nbe[NB], nla[NB];
 #pragma unroll
@@ -490,52 +565,54 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 nla[i] = -cb[i];
             }
             // xbar_k adjoint = Abar' cb (to stage k-1, or to xbar_0 at k = 0)
-            // and du adjoint = Bbar' bb, from one stream of rows [A_r B_r]
-            float xpb[NB], dub[NU];
+            // and du adjoint = Bbar' bb, from the top rows [A_r B_r]
+            float dub[NU];
+            {
+                float xpb[NB];
 #pragma unroll
-            for (int cc = 0; cc < NB; ++cc) xpb[cc] = (cc < NX) ? 0.f : cb[cc];
+                for (int cc = 0; cc < NB; ++cc) xpb[cc] = (cc < NX) ? 0.f : cb[cc];
 #pragma unroll
-            for (int cc = 0; cc < NU; ++cc) dub[cc] = bb[NX + cc];
-            using RowAB = SRow<float, NB>;
-            auto load_ab = [&](int r) {
-                RowAB x;
-                sload_into<float, NX>(x.x, Am + r * NX);
-                sload_into<float, NU>(x.x + NX, Bm + r * NU);
-                return x;
-            };
-            stream_rows<RowAB, NX, true>(load_ab, [&](int r, const RowAB& x) {
+                for (int cc = 0; cc < NU; ++cc) dub[cc] = bb[NX + cc];
+                mv.rowsAB([&](int r, const float (&x)[NBP]) {
 #pragma unroll
-                for (int cc = 0; cc < NB; ++cc) xpb[cc] += x.x[cc] * cb[r];
+                    for (int cc = 0; cc < NB; ++cc) xpb[cc] += x[cc] * cb[r];
 #pragma unroll
-                for (int cc = 0; cc < NU; ++cc) dub[cc] += x.x[NX + cc] * bb[r];
-            });
+                    for (int cc = 0; cc < NU; ++cc) dub[cc] += x[NX + cc] * bb[r];
+                });
 #pragma unroll
-            for (int i = 0; i < NB; ++i) xg[i * kBBD + tid] = xpb[i];
-            {  // Abar += cb xbar_k' (top rows); Bbar += bb du' (top rows) and
-               // J_bar += dub d' (du = J (v - beta)).  Stages without a stage
-               // hold zero adjoints (cb, bb, dub), so their rows add nothing.
-                float a1[16], b1[16], a2[16], b2[16];
+                for (int i = 0; i < NB; ++i) xg[i * kBBD + tid] = xpb[i];
+                if (act && k == 0) {  // the x0 adjoint (lane of stage 0 only)
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    a1[q] = (q < NX) ? cb[q] : 0.f;
-                    b1[q] = (q < NB) ? xp[q] : 0.f;
-                }
-                if constexpr (kMergeBJ) {
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        a2[q] = (q < NU) ? dub[q] : ((q < NB) ? bb[q - NU] : 0.f);
-                        b2[q] = (q < NB) ? d[q] : ((q < NB + NU) ? du[q - NB] : 0.f);
-                    }
-                    stage_accum2(CA, a1, b1, CJ, a2, b2, stg, lane);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        a2[q] = (q < NX) ? bb[q] : 0.f;
-                        b2[q] = (q < NU) ? du[q] : 0.f;
-                    }
-                    stage_accum2(CA, a1, b1, CB, a2, b2, stg, lane);
+                    for (int i = 0; i < NB; ++i) lw[32 + i] += xpb[i];
                 }
             }
+            if constexpr (kMergeBJ)
+                put(ar2, [&](int q) { return q < NU ? dub[q] : ((q < NB) ? bb[q - NU] : 0.f); });
+            // the step's du = J d (recomputed from the recorded d) and the
+            // transpose J' dub, from the J rows
+            {
+                float jt[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) jt[j] = 0.f;
+                mv.rowsJ([&](int r, const float (&x)[NBP]) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        s += x[j] * d[j];
+                        jt[j] += x[j] * dub[r];
+                    }
+                    du[r] = s;
+                });
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    nv[j] += jt[j];
+                    nbe[j] -= jt[j];
+                }
+            }
+            if constexpr (kMergeBJ)
+                put(ar3, [&](int q) { return q < NB ? d[q] : ((q < NB + NU) ? du[q - NB] : 0.f); });
+            else
+                put(ar3, [&](int q) { return q < NU ? du[q] : 0.f; });
             __syncthreads();
             // ---- transpose of step 1
             const bool hasnext = act && (k + 1 < N);
@@ -543,44 +620,22 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             for (int i = 0; i < NB; ++i) {
                 const float t = xg[i * kBBD + tid + 1];
                 xsb[i] += hasnext ? t : 0.f;
-                if (act && k == 0) x0b[i] += xpb[i];
             }
-            // h adjoint = H' xsb (H symmetric)
+            put(ar4, [&](int q) { return (q < NB && !is_last) ? xsb[q] : 0.f; });
+            // the step's xbar_{k+1} = H h (for stage k + 1) and the h adjoint
+            // H' xsb (H symmetric), from the H rows (H_{N-1} at the last stage)
             float hb[NB];
-            using RowH = SRow<float, NB>;
-            stream_rows<RowH, NB, true>(
-                [&](int r) {
-                    RowH x;
-                    sload_into<float, NB>(x.x, Hm + r * NB);
-                    return x;
-                },
-                [&](int r, const RowH& x) {
-                    float s = 0.f;
+            mv.rowsH(is_last, [&](int r, const float (&x)[NBP]) {
+                float s = 0.f, t = 0.f;
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) s += x.x[j] * xsb[j];
-                    hb[r] = s;
-                });
-            if (is_last) {  // H_{N-1}' xsb (H_{N-1} is symmetric; diagonal for diagonal Q, R)
-                if (hb_diag) {
-#pragma unroll
-                    for (int r = 0; r < NB; ++r) hb[r] = Hbm[r * NB + r] * xsb[r];
-                } else {
-                    stream_rows<RowH, NB, true>(
-                        [&](int r) {
-                            RowH x;
-                            sload_into<float, NB>(x.x, Hbm + r * NB);
-                            return x;
-                        },
-                        [&](int r, const RowH& x) {
-                            float s = 0.f;
-#pragma unroll
-                            for (int j = 0; j < NB; ++j) s += x.x[j] * xsb[j];
-                            hb[r] = s;
-                        });
+                for (int j = 0; j < NB; ++j) {
+                    s += x[j] * h[j];
+                    t += x[j] * xsb[j];
                 }
-            }
+                xs[r] = s;
+                hb[r] = t;
+            });
             if (last_wave) {  // H_{N-1} += xsb h' of stage N - 1, in the MFMA tile layout
-                float* lw = stg + 4 * kStgArea;
                 if (is_last) {
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
@@ -599,71 +654,49 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
                 const float rh = act ? rho * hb[i] : 0.f;
                 nz[i] += rh;
                 nth[i] -= rh;
-                xx[i * kBBD + tid] = rh;  // adjoint of g_{k+1}, read by stage k+1
+                xx[i * kBBD + tid] = rh;     // adjoint of g_{k+1}, read by stage k+1
+                xq[i * kBBD + tid] = xs[i];  // xbar_{k+1}, read by stage k+1
             }
             __syncthreads();
-            // g_k = Abar' w_k with w_k = z - v - ebar + lambda: adjoint from stage k-1
+            // g_k = Abar' w_k with w_k = z - v - ebar + lambda: adjoint from
+            // stage k-1; xbar_k of the step from stage k-1 (xbar_0 at k = 0)
+            put(ar1, [&](int q) {
+                if (q >= NB) return 0.f;
+                const float xv = xq[q * kBBD + tid - 1];
+                return (k == 0) ? xb0(q) : (act ? xv : 0.f);
+            });
+            // round 1: Abar += cb xbar_k' (top rows); J_bar += dub d' and
+            // Bbar += bb du' (top rows) in one tile, or Bbar alone
+            stage_mfma2(CA, ar0, ar1, kMergeBJ ? CJ : CB, ar2, ar3, lane);
             float gr[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 const float t = xx[i * kBBD + tid - 1];
                 gr[i] = (act && k >= 1) ? t : 0.f;
             }
+            put(ar0, [&](int q) { return (q < NX && act) ? rec[(int64_t)(2 * NB + q) * N + k] : 0.f; });  // w
+            put(ar1, [&](int q) { return q < NB ? gr[q] : 0.f; });
+            // round 2: H_a += xsb h' (k < N-1); Abar += w_k g_bar' (top rows)
+            stage_mfma2(CHa, ar4, ar5, CA, ar0, ar1, lane);
+            if constexpr (!kMergeBJ) {  // J_bar += dub d'
+                put(ar2, [&](int q) { return q < NU ? dub[q] : 0.f; });
+                put(ar3, [&](int q) { return (q < NB && act) ? rec[(int64_t)q * N + k] : 0.f; });  // d, from the tape
+                stage_mfma(CJ, ar2, ar3, lane);
+            }
             float wb[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) wb[i] = (i < NX) ? 0.f : gr[i];
-            stream_rows<RowAB, NX, true>(load_ab, [&](int r, const RowAB& x) {
+            mv.rowsAB([&](int r, const float (&x)[NBP]) {
                 float s = 0.f;
 #pragma unroll
-                for (int cc = 0; cc < NB; ++cc) s += x.x[cc] * gr[cc];
+                for (int cc = 0; cc < NB; ++cc) s += x[cc] * gr[cc];
                 wb[r] = s;
             });
-            {  // H_a += xsb h' (k < N-1); Abar += w_k g_bar' (top rows)
-                float a1[16], b1[16], a2[16], b2[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    a1[q] = (q < NB && !is_last) ? xsb[q] : 0.f;
-                    b1[q] = (q < NB) ? h[q] : 0.f;
-                    a2[q] = (q < NX) ? w[q] : 0.f;
-                    b2[q] = (q < NB) ? gr[q] : 0.f;
-                }
-                stage_accum2(CHa, a1, b1, CA, a2, b2, stg, lane);
-            }
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 nz[i] += wb[i];
                 nv[i] -= wb[i];
                 nla[i] += wb[i];
-            }
-            if constexpr (!kMergeBJ) {  // J_bar += dub d' (du = J (v - beta))
-                float v1[16], v2[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    v1[q] = (q < NU) ? dub[q] : 0.f;
-                    v2[q] = (q < NB) ? d[q] : 0.f;
-                }
-                stage_accum(CJ, v1, v2, stg, lane);
-            }
-            {  // J' dub, one stream of J rows
-                float jt[NB];
-#pragma unroll
-                for (int j = 0; j < NB; ++j) jt[j] = 0.f;
-                using RowJ = SRow<float, NB>;
-                stream_rows<RowJ, NU, true>(
-                    [&](int r) {
-                        RowJ x;
-                        sload_into<float, NB>(x.x, Jm + r * NB);
-                        return x;
-                    },
-                    [&](int r, const RowJ& x) {
-#pragma unroll
-                        for (int j = 0; j < NB; ++j) jt[j] += x.x[j] * dub[r];
-                    });
-#pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    nv[j] += jt[j];
-                    nbe[j] -= jt[j];
-                }
             }
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
@@ -678,7 +711,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
 
     // ---- reduce the per-wave tiles over the instance's waves, write raw adjoints
     __syncthreads();
-    float* red = xx + 16 * kBBD + wave * kStgFloats;  // reuse this wave's staging tile
+    float* red = stg;  // reuse this wave's staging tile
     const floatx4 tiles[5] = {CHa, CHb, CJ, CA, CB};
 #pragma unroll
     for (int b5 = 0; b5 < 5; ++b5)
@@ -703,11 +736,11 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             }
             float s = 0.f;
             if (!zero)
-                for (int w = gw0; w < gw0 + nw; ++w) s += (xx + 16 * kBBD)[w * kStgFloats + src];
+                for (int w = gw0; w < gw0 + nw; ++w) s += stg0[w * kStgFloats + src];
             out[e] = s;
         }
         if (k == 0)
-            for (int i = 0; i < 16; ++i) out[5 * 256 + i] = i < NB ? x0b[i] : 0.f;
+            for (int i = 0; i < 16; ++i) out[5 * 256 + i] = i < NB ? lw[32 + i] : 0.f;
     }
     __syncthreads();
     (void)leader_mask;
@@ -906,7 +939,7 @@ __global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ i
 // ---------------------------------------------------------------- host side
 
 inline size_t bwd_lds_bytes() {
-    return (size_t)2 * 16 * kBBD * sizeof(float) + (size_t)kBwdWaves * kStgFloats * sizeof(float);
+    return (size_t)3 * 16 * kBBD * sizeof(float) + (size_t)kBwdWaves * (kStgFloats + kMatFloats) * sizeof(float);
 }
 
 template <int NX, int NU>
