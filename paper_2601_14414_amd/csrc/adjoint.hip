@@ -111,57 +111,8 @@ __device__ inline void stage_accum(floatx4& C, const float (&v1)[16], const floa
 }
 
 // The stage matrices of a wave's instance, copied once per bin into the
-// wave's own LDS image, rows padded to a multiple of four floats:
-// J [NU][NBP], H and H_{N-1} [NB][NBP], the top rows [A_r B_r] [NX][NBP],
-// then ebar, qbar, lb, ub (NBP each).  Rows are read as float4 broadcasts
-// (every lane the same address): LDS returns in order, so several rows can
-// be in flight behind partial waits.
+// wave's own LDS image (MatImg): every class's image fits this slot.
 constexpr int kMatFloats = 832;  // the widest class: 4 x 16 + 2 x 16 x 16 + 12 x 16 + 4 x 16
-
-template <int NX, int NU>
-struct MatImg {
-    static constexpr int NB = NX + NU;
-    static constexpr int NBP = (NB + 3) & ~3;
-    static constexpr int J = 0;
-    static constexpr int H = J + NU * NBP;
-    static constexpr int Hb = H + NB * NBP;
-    static constexpr int AB = Hb + NB * NBP;
-    static constexpr int E = AB + NX * NBP;
-    static constexpr int Q = E + NBP;
-    static constexpr int LB = Q + NBP;
-    static constexpr int UB = LB + NBP;
-    static constexpr int TOT = UB + NBP;
-    static_assert(TOT <= kMatFloats, "the matrix image exceeds its LDS slot");
-};
-
-// one padded row from LDS (16-byte aligned)
-template <int NBP>
-__device__ __forceinline__ void lds_row(float (&x)[NBP], const float* p) {
-#pragma unroll
-    for (int q = 0; q < NBP / 4; ++q) {
-        const float4 t = ((const float4*)p)[q];
-        x[4 * q] = t.x;
-        x[4 * q + 1] = t.y;
-        x[4 * q + 2] = t.z;
-        x[4 * q + 3] = t.w;
-    }
-}
-
-// Rows 0..R-1 of a padded LDS matrix, body(r, row): row r + D is requested
-// before body(r) runs, and a scheduling fence after each row keeps the
-// compiler from hoisting further rows (each row in flight holds NBP VGPRs).
-template <int R, int NBP, int D = 2, typename B>
-__device__ __forceinline__ void lds_rows(const float* base, B&& body) {
-    float buf[D + 1][NBP];
-#pragma unroll
-    for (int r = 0; r < D && r < R; ++r) lds_row(buf[r], base + r * NBP);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (r + D < R) lds_row(buf[(r + D) % (D + 1)], base + (r + D) * NBP);
-        body(r, buf[r % (D + 1)]);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
 
 // Where a step reads its stage matrices: the LDS image (LR, stages up to
 // twelve floats wide), or the global copy streamed through SGPRs one row
@@ -186,7 +137,7 @@ struct MatView {
     template <typename B>
     __device__ __forceinline__ void rowsJ(B&& body) const {
         if constexpr (LR) {
-            lds_rows<NU, NBP>(L + MI::J, body);
+            lds_rows<float, NU, NBP>(L + MI::J, body);
         } else {
             stream_rows<Row, NU, true>(
                 [&](int r) {
@@ -201,7 +152,7 @@ struct MatView {
     template <typename B>
     __device__ __forceinline__ void rowsAB(B&& body) const {
         if constexpr (LR) {
-            lds_rows<NX, NBP>(L + MI::AB, body);
+            lds_rows<float, NX, NBP>(L + MI::AB, body);
         } else {
             stream_rows<Row, NX, true>(
                 [&](int r) {
@@ -217,7 +168,7 @@ struct MatView {
     template <typename B>
     __device__ __forceinline__ void rowsH(bool last, B&& body) const {
         if constexpr (LR) {
-            lds_rows<NB, NBP>(L + (last ? MI::Hb : MI::H), body);
+            lds_rows<float, NB, NBP>(L + (last ? MI::Hb : MI::H), body);
         } else {
             auto pass = [&](int64_t off) {
                 stream_rows<Row, NB, true>(
@@ -264,34 +215,9 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     constexpr int NBP = MI::NBP;
     constexpr bool kLdsRows = NBP <= 12;
     float* mw = stg0 + kBwdWaves * kStgFloats + wave * kMatFloats;  // this wave's matrix image
+    static_assert(MI::TOT <= kMatFloats, "the matrix image exceeds its LDS slot");
     if constexpr (kLdsRows) {
-        const float* Mg = a.mats + (have ? I.mat_off : 0);
-        for (int e = lane; e < MI::TOT; e += 64) {
-            float val = 0.f;
-            if (have) {
-                if (e < MI::AB) {  // J, H, H_{N-1}: rows of NB
-                    const int blk = e < MI::H ? 0 : (e < MI::Hb ? 1 : 2);
-                    const int base = blk == 0 ? MI::J : (blk == 1 ? MI::H : MI::Hb);
-                    const int r = (e - base) / NBP, c = (e - base) % NBP;
-                    const int64_t src = blk == 0 ? o.J : (blk == 1 ? o.H : o.Hb);
-                    if (c < NB) val = Mg[src + r * NB + c];
-                } else if (e < MI::E) {  // [A_r B_r]
-                    const int r = (e - MI::AB) / NBP, c = (e - MI::AB) % NBP;
-                    if (c < NX)
-                        val = Mg[o.A + r * NX + c];
-                    else if (c < NB)
-                        val = Mg[o.B + r * NU + (c - NX)];
-                } else {
-                    const int blk = (e - MI::E) / NBP, c = (e - MI::E) % NBP;
-                    if (blk == 0) {
-                        if (c < NX) val = Mg[o.e + c];
-                    } else if (c < NB) {
-                        val = Mg[(blk == 1 ? o.qbar : (blk == 2 ? o.lb : o.ub)) + c];
-                    }
-                }
-            }
-            mw[e] = val;
-        }
+        fill_mat_img<float, NX, NU>(mw, a.mats + (have ? I.mat_off : 0), o, have, lane);
         __builtin_amdgcn_wave_barrier();
     }
 

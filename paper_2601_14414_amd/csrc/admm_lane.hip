@@ -150,11 +150,21 @@ __device__ __forceinline__ double shr1(double x) {
 
 // Run (or, with have = false, only shadow the barrier sequence of) one
 // instance on the waves [gw0, gw0 + gnw) of the workgroup.
+// Time-invariant FP32 box classes up to twelve entries wide read their stage
+// matrices from a per-wave LDS image instead of the SGPR row stream (see
+// MatImg): several rows in flight behind in-order waits.  Wider classes, and
+// FP64 (twice the registers per entry), keep the SGPR stream: their per-lane
+// vectors leave no VGPRs for rows.
+template <typename T, int NX, int NU, bool TV, bool GS>
+constexpr bool lane_lds_rows() { return !TV && !GS && sizeof(T) == 4 && MatImg<NX, NU>::NBP <= 12; }
+template <int NX, int NU>
+constexpr int lane_img_stride() { return (MatImg<NX, NU>::TOT + 3) & ~3; }
+
 template <typename T, int NX, int NU, bool TV, bool GS>
 __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bool have, int gw0,
                                          unsigned leader_mask, T (*bnd_g)[NX + NU], T (*bnd_x)[NX + NU],
                                          T (*dzl)[kBinThreads], T (*ddl)[kBinThreads], double* red,
-                                         int* gdone) {
+                                         int* gdone, T* limg) {
     inst_idx = __builtin_amdgcn_readfirstlane(inst_idx);
     gw0 = __builtin_amdgcn_readfirstlane(gw0);
     have = __builtin_amdgcn_readfirstlane((int)have) != 0;
@@ -204,6 +214,15 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     const cptr<T> lbm = (Mp) + o.lb;               \
     const cptr<T> ubm = (Mp) + o.ub;               \
     (void)Jm; (void)Hm; (void)Hbm; (void)Am; (void)Bm; (void)em; (void)qb; (void)lbm; (void)ubm;
+
+    using MI = MatImg<NX, NU>;
+    constexpr int NBP = MI::NBP;
+    constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS>();
+    T* img = limg + (kLR ? wave * lane_img_stride<NX, NU>() : 0);  // this wave's matrix image
+    if constexpr (kLR) {
+        fill_mat_img<T, NX, NU>(img, (const T*)(*ap).mats + (have ? (*ip).mat_off : 0), o, have, lane);
+        __builtin_amdgcn_wave_barrier();
+    }
 
     // per-lane stage data (time-varying only)
     T Jr[TV ? NU * NB : 1], Hr[TV ? NB * NB : 1], Ar[TV ? NX * NX : 1], Br[TV ? NX * NU : 1],
@@ -299,6 +318,11 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
         }
         const cptr<T> Mi = MB();
         PIMPC_MAT_PTRS(Mi)
+        // the image behind an opaque offset: its reads stay in this iteration
+        int mo_ = 0;
+        asm volatile("" : "+s"(mo_));
+        const T* L = img + mo_;
+        (void)L;
 
         // ---- step 1a: du_k = J_k (v_k - beta_k); g_k = Abar_k' (z_{k+1} - v_k - ebar_k + lambda_k)
         T g[NB], xs[NB];
@@ -321,6 +345,18 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 #pragma unroll
                     for (int c = 0; c < NU; ++c) g[NX + c] += Br[r * NU + c] * w;
                 }
+            } else if constexpr (kLR) {
+                lds_rows<T, NU, NBP>(L + MI::J, [&](int r, const T (&x)[NBP]) {
+                    T s = T(0);
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s += x[j] * (v[j] - be[j]);
+                    du[r] = s;
+                });
+                lds_rows<T, NX, NBP>(L + MI::AB, [&](int i, const T (&x)[NBP]) {
+                    const T w = z[i] - v[i] - L[MI::E + i] + la[i];
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) g[c] += x[c] * w;
+                });
             } else {
                 // one stream: rows of J (du), then rows [A_r B_r e_r] (g)
                 using Row = SRow<T, NB + 1>;
@@ -366,7 +402,20 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
         // ---- step 1b: h_k = qbar + rho (z_{k+1} - theta_k + g_{k+1}); xbar_{k+1} = H_k h_k
         if (run) {
             T h[NB];
-            if constexpr (!TV) {
+            if constexpr (kLR) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const T gn = from_next_wave ? bnd_g[wave + 1 < kBinWaves ? wave + 1 : wave][i] : g[i];
+                    h[i] = L[MI::Q + i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
+                }
+                // H_{N-1} for the last stage
+                lds_rows<T, NB, NBP>(L + (is_last ? MI::Hb : MI::H), [&](int r, const T (&x)[NBP]) {
+                    T s = T(0);
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s += x[j] * h[j];
+                    xs[r] = s;
+                });
+            } else if constexpr (!TV) {
                 T q[NB];
                 sload_into<T, NB>(q, qb);
                 swait();
@@ -529,6 +578,17 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     comp(
                         i, [&](int j) { return Ar[(i < NX ? i : 0) * NX + j]; },
                         [&](int j) { return Br[(i < NX ? i : 0) * NU + j]; }, i < NX ? er[i] : T(0), lbq[i], ubq[i]);
+            } else if constexpr (kLR) {
+                lds_rows<T, NX, NBP>(L + MI::AB, [&](int i, const T (&x)[NBP]) {
+                    comp(
+                        i, [&](int j) { return x[j]; }, [&](int j) { return x[NX + j]; }, L[MI::E + i],
+                        L[MI::LB + i], L[MI::UB + i]);
+                });
+#pragma unroll
+                for (int i = NX; i < NB; ++i)
+                    comp(
+                        i, [&](int) { return T(0); }, [&](int) { return T(0); }, T(0), L[MI::LB + i],
+                        L[MI::UB + i]);
             } else {
                 // one stream over the components: [A_i B_i e_i lb_i ub_i] (i < NX), [lb_i ub_i]
                 using Row = SRow<T, NB + 3>;
@@ -597,6 +657,12 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 #pragma unroll
                             for (int c = 0; c < NU; ++c) tg[NX + c] += Br[r * NU + c] * dd;
                         }
+                    } else if constexpr (kLR) {
+                        lds_rows<T, NX, NBP>(L + MI::AB, [&](int r, const T (&x)[NBP]) {
+                            const T dd = ddl[r][tid];
+#pragma unroll
+                            for (int c = 0; c < NB; ++c) tg[c] += x[c] * dd;
+                        });
                     } else {
                         PIMPC_MAT_PTRS(MB())
                         using Row = SRow<T, NB>;
@@ -790,6 +856,8 @@ __global__ void __launch_bounds__(kBinThreads)
     __shared__ T ddl[NX + NU][kBinThreads];  // check iterations: dz - dv of every lane
     __shared__ double red[kBinWaves * 4];   // per-wave residual partials
     __shared__ int gdone[kBinWaves];        // per-instance stop flags (indexed by first wave)
+    constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS>();
+    __shared__ __align__(16) T limg[kLR ? kBinWaves * lane_img_stride<NX, NU>() : 1];  // matrix images
     __shared__ int s_bin;
     const int wave = threadIdx.x >> 6;
     for (int j = 0;; ++j) {
@@ -815,9 +883,10 @@ __global__ void __launch_bounds__(kBinThreads)
         __syncthreads();
         if (my >= 0)
             lane_run<T, NX, NU, TV, GS>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g, bnd_x,
-                                        dzl, ddl, red, gdone);
+                                        dzl, ddl, red, gdone, limg);
         else
-            lane_run<T, NX, NU, TV, GS>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone);
+            lane_run<T, NX, NU, TV, GS>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone,
+                                        limg);
         __syncthreads();
     }
 }

@@ -82,4 +82,99 @@ __device__ __forceinline__ void stream_rows(L&& load, B&& body) {
 }
 
 
+// ---- stage matrices of one time-invariant instance held in LDS
+// Rows padded to a multiple of four entries (16-byte aligned rows for FP32,
+// two 16-byte pieces per four FP64 entries): J [NU][NBP], H and H_{N-1}
+// [NB][NBP], the top rows [A_r B_r] [NX][NBP], then ebar, qbar, lb, ub (NBP
+// each).  Rows are read with every lane at the same address (broadcast), and
+// LDS answers in order, so rows can be requested ahead behind partial waits
+// (a scalar-load stream must wait for all its loads at once).
+template <int NX, int NU>
+struct MatImg {
+    static constexpr int NB = NX + NU;
+    static constexpr int NBP = (NB + 3) & ~3;
+    static constexpr int J = 0;
+    static constexpr int H = J + NU * NBP;
+    static constexpr int Hb = H + NB * NBP;
+    static constexpr int AB = Hb + NB * NBP;
+    static constexpr int E = AB + NX * NBP;
+    static constexpr int Q = E + NBP;
+    static constexpr int LB = Q + NBP;
+    static constexpr int UB = LB + NBP;
+    static constexpr int TOT = UB + NBP;
+};
+
+// One wave copies the matrices at Mg (offsets o of the time-invariant layout)
+// into its image; zeros where the wave has no instance and in the padding.
+template <typename T, int NX, int NU, typename O>
+__device__ __forceinline__ void fill_mat_img(T* img, const T* Mg, const O o, bool have, int lane) {
+    using MI = MatImg<NX, NU>;
+    constexpr int NB = MI::NB, NBP = MI::NBP;
+    for (int e = lane; e < MI::TOT; e += 64) {
+        T val = T(0);
+        if (have) {
+            if (e < MI::AB) {  // J, H, H_{N-1}: rows of NB
+                const int blk = e < MI::H ? 0 : (e < MI::Hb ? 1 : 2);
+                const int base = blk == 0 ? MI::J : (blk == 1 ? MI::H : MI::Hb);
+                const int r = (e - base) / NBP, c = (e - base) % NBP;
+                const int64_t src = blk == 0 ? o.J : (blk == 1 ? o.H : o.Hb);
+                if (c < NB) val = Mg[src + r * NB + c];
+            } else if (e < MI::E) {  // [A_r B_r]
+                const int r = (e - MI::AB) / NBP, c = (e - MI::AB) % NBP;
+                if (c < NX)
+                    val = Mg[o.A + r * NX + c];
+                else if (c < NB)
+                    val = Mg[o.B + r * NU + (c - NX)];
+            } else {
+                const int blk = (e - MI::E) / NBP, c = (e - MI::E) % NBP;
+                if (blk == 0) {
+                    if (c < NX) val = Mg[o.e + c];
+                } else if (c < NB) {
+                    val = Mg[(blk == 1 ? o.qbar : (blk == 2 ? o.lb : o.ub)) + c];
+                }
+            }
+        }
+        img[e] = val;
+    }
+}
+
+// one padded row from LDS (16-byte pieces)
+template <typename T, int NBP>
+__device__ __forceinline__ void lds_row(T (&x)[NBP], const T* p) {
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int q = 0; q < NBP / 4; ++q) {
+            const float4 t = ((const float4*)p)[q];
+            x[4 * q] = t.x;
+            x[4 * q + 1] = t.y;
+            x[4 * q + 2] = t.z;
+            x[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NBP / 2; ++q) {
+            const double2 t = ((const double2*)p)[q];
+            x[2 * q] = t.x;
+            x[2 * q + 1] = t.y;
+        }
+    }
+}
+
+// Rows 0..R-1 of a padded LDS matrix, body(r, row): row r + D is requested
+// before body(r) runs, and a scheduling fence after each row keeps the
+// compiler from hoisting further rows (each row in flight holds NBP entries
+// of VGPRs).
+template <typename T, int R, int NBP, int D = 2, typename B>
+__device__ __forceinline__ void lds_rows(const T* base, B&& body) {
+    T buf[D + 1][NBP];
+#pragma unroll
+    for (int r = 0; r < D && r < R; ++r) lds_row(buf[r], base + r * NBP);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r + D < R) lds_row(buf[(r + D) % (D + 1)], base + (r + D) * NBP);
+        body(r, buf[r % (D + 1)]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 }  // namespace pimpc
