@@ -152,19 +152,21 @@ __device__ __forceinline__ double shr1(double x) {
 // instance on the waves [gw0, gw0 + gnw) of the workgroup.
 // Time-invariant FP32 box classes up to twelve entries wide read their stage
 // matrices from a per-wave LDS image instead of the SGPR row stream (see
-// MatImg): several rows in flight behind in-order waits.  Wider classes, and
-// FP64 (twice the registers per entry), keep the SGPR stream: their per-lane
-// vectors leave no VGPRs for rows.
-template <typename T, int NX, int NU, bool TV, bool GS>
-constexpr bool lane_lds_rows() { return !TV && !GS && sizeof(T) == 4 && MatImg<NX, NU>::NBP <= 12; }
+// MatImg): several rows in flight behind in-order waits.  Wider classes keep
+// the SGPR stream (their per-lane vectors leave no VGPRs for rows), and so
+// does FP64 (measured: the single FP64 chain gains nothing from LDS rows).
+template <typename T, int NX, int NU, bool TV, bool GS, int BW>
+constexpr bool lane_lds_rows() {
+    return !TV && !GS && sizeof(T) == 4 && MatImg<NX, NU>::NBP <= 12;
+}
 template <int NX, int NU>
 constexpr int lane_img_stride() { return (MatImg<NX, NU>::TOT + 3) & ~3; }
 
-template <typename T, int NX, int NU, bool TV, bool GS>
+template <typename T, int NX, int NU, bool TV, bool GS, int BW>
 __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bool have, int gw0,
                                          unsigned leader_mask, T (*bnd_g)[NX + NU], T (*bnd_x)[NX + NU],
-                                         T (*dzl)[kBinThreads], T (*ddl)[kBinThreads], double* red,
-                                         int* gdone, T* limg) {
+                                         T (*dzl)[64 * BW], T (*ddl)[64 * BW], double* red, int* gdone,
+                                         T* limg) {
     inst_idx = __builtin_amdgcn_readfirstlane(inst_idx);
     gw0 = __builtin_amdgcn_readfirstlane(gw0);
     have = __builtin_amdgcn_readfirstlane((int)have) != 0;
@@ -217,7 +219,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 
     using MI = MatImg<NX, NU>;
     constexpr int NBP = MI::NBP;
-    constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS>();
+    constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS, BW>();
     T* img = limg + (kLR ? wave * lane_img_stride<NX, NU>() : 0);  // this wave's matrix image
     if constexpr (kLR) {
         fill_mat_img<T, NX, NU>(img, (const T*)(*ap).mats + (have ? (*ip).mat_off : 0), o, have, lane);
@@ -405,7 +407,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             if constexpr (kLR) {
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
-                    const T gn = from_next_wave ? bnd_g[wave + 1 < kBinWaves ? wave + 1 : wave][i] : g[i];
+                    const T gn = from_next_wave ? bnd_g[wave + 1 < BW ? wave + 1 : wave][i] : g[i];
                     h[i] = L[MI::Q + i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
                 }
                 // H_{N-1} for the last stage
@@ -421,7 +423,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                 swait();
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
-                    const T gn = from_next_wave ? bnd_g[wave + 1 < kBinWaves ? wave + 1 : wave][i] : g[i];
+                    const T gn = from_next_wave ? bnd_g[wave + 1 < BW ? wave + 1 : wave][i] : g[i];
                     h[i] = q[i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
                 }
                 using Row = SRow<T, NB>;
@@ -467,7 +469,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             } else {
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
-                    const T gn = from_next_wave ? bnd_g[wave + 1 < kBinWaves ? wave + 1 : wave][i] : g[i];
+                    const T gn = from_next_wave ? bnd_g[wave + 1 < BW ? wave + 1 : wave][i] : g[i];
                     h[i] = qb[i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
                 }
 #pragma unroll
@@ -690,7 +692,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                 if (check) {
 #pragma unroll
                     for (int i = 0; i < NB; ++i) tg[i] = shl1(tg[i]);  // every lane active (see step 2)
-                    const int wnext = wave + 1 < kBinWaves ? wave + 1 : wave;
+                    const int wnext = wave + 1 < BW ? wave + 1 : wave;
 #pragma unroll
                     for (int i = 0; i < NB; ++i) {
                         const T tn = from_next_wave ? bnd_g[wnext][i] : tg[i];
@@ -840,24 +842,29 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 
 // One persistent kernel per class (each gets the whole register file; the
 // classes of a batch run as concurrent branches of one graph).  Workgroups
-// claim bins of this class from a counter, largest first.
-// Narrow stages fit two 512-thread workgroups per CU (<= 128 VGPRs a lane);
-// wider ones take the whole register file with one.
-constexpr int lane_waves_per_eu(int nb, int tsize) { return (tsize == 4 && nb <= 7) ? 4 : 2; }
+// claim bins of BW waves of this class from a counter, largest first.
+// Narrow FP32 stages fit two 512-thread workgroups per CU (<= 128 VGPRs a
+// lane); wider ones take the whole register file with one.  FP64 classes
+// whose horizons all fit four waves run 256-thread workgroups, one wave per
+// SIMD with up to 512 registers (their doubled vectors spill past 256).
+constexpr int lane_waves_per_eu(int nb, int tsize, int bw) {
+    return bw == 4 ? 1 : ((tsize == 4 && nb <= 7) ? 4 : 2);
+}
 
-template <typename T, int NX, int NU, bool TV, bool GS>
-__global__ void __launch_bounds__(kBinThreads)
-    __attribute__((amdgpu_waves_per_eu(lane_waves_per_eu(NX + NU, sizeof(T)))))
+template <typename T, int NX, int NU, bool TV, bool GS, int BW>
+__global__ void __launch_bounds__(64 * BW)
+    __attribute__((amdgpu_waves_per_eu(lane_waves_per_eu(NX + NU, sizeof(T), BW))))
     lane_kernel(const LaneArgs* __restrict__ ap) {
+    static_assert(BW == 4 || BW == kBinWaves, "bins of four or eight waves");
     const LaneArgs& a = *ap;
-    __shared__ T bnd_g[kBinWaves][NX + NU];  // g (and the dual-residual term) crossing a wave boundary
-    __shared__ T bnd_x[kBinWaves][NX + NU];  // xbar crossing a wave boundary
-    __shared__ T dzl[NX + NU][kBinThreads];  // check iterations: dz of every lane
-    __shared__ T ddl[NX + NU][kBinThreads];  // check iterations: dz - dv of every lane
-    __shared__ double red[kBinWaves * 4];   // per-wave residual partials
-    __shared__ int gdone[kBinWaves];        // per-instance stop flags (indexed by first wave)
-    constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS>();
-    __shared__ __align__(16) T limg[kLR ? kBinWaves * lane_img_stride<NX, NU>() : 1];  // matrix images
+    __shared__ T bnd_g[BW][NX + NU];   // g (and the dual-residual term) crossing a wave boundary
+    __shared__ T bnd_x[BW][NX + NU];   // xbar crossing a wave boundary
+    __shared__ T dzl[NX + NU][64 * BW];  // check iterations: dz of every lane
+    __shared__ T ddl[NX + NU][64 * BW];  // check iterations: dz - dv of every lane
+    __shared__ double red[BW * 4];       // per-wave residual partials
+    __shared__ int gdone[BW];            // per-instance stop flags (indexed by first wave)
+    constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS, BW>();
+    __shared__ __align__(16) T limg[kLR ? BW * lane_img_stride<NX, NU>() : 1];  // matrix images
     __shared__ int s_bin;
     const int wave = threadIdx.x >> 6;
     for (int j = 0;; ++j) {
@@ -879,62 +886,66 @@ __global__ void __launch_bounds__(kBinThreads)
             if (wave >= bin.e[e].wave0 && wave < bin.e[e].wave0 + bin.e[e].nwaves) my = e;
         }
         my = __builtin_amdgcn_readfirstlane(my);
-        if (threadIdx.x < kBinWaves) gdone[threadIdx.x] = 1;
+        if (threadIdx.x < BW) gdone[threadIdx.x] = 1;
         __syncthreads();
         if (my >= 0)
-            lane_run<T, NX, NU, TV, GS>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g, bnd_x,
-                                        dzl, ddl, red, gdone, limg);
+            lane_run<T, NX, NU, TV, GS, BW>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g,
+                                            bnd_x, dzl, ddl, red, gdone, limg);
         else
-            lane_run<T, NX, NU, TV, GS>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone,
-                                        limg);
+            lane_run<T, NX, NU, TV, GS, BW>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone,
+                                            limg);
         __syncthreads();
     }
 }
 
-template <typename T, int NX, int NU, bool TV>
+template <typename T, int NX, int NU, bool TV, int BW>
 hipError_t launch_lane_cls(const LaneArgs* a_dev, int grid, hipStream_t s, bool gs) {
     if (gs)
-        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, true>), dim3(grid), dim3(kBinThreads), 0, s, a_dev);
+        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, true, BW>), dim3(grid), dim3(64 * BW), 0, s, a_dev);
     else
-        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, false>), dim3(grid), dim3(kBinThreads), 0, s, a_dev);
+        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, false, BW>), dim3(grid), dim3(64 * BW), 0, s, a_dev);
     return hipGetLastError();
 }
 
-template <typename T, int NX, int NU, bool TV>
+template <typename T, int NX, int NU, bool TV, int BW>
 int lane_occupancy(bool gs) {
     int nb = 0;
     const hipError_t e =
-        gs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, true>, kBinThreads, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, false>, kBinThreads, 0);
+        gs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, true, BW>, 64 * BW, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, false, BW>, 64 * BW, 0);
     if (e != hipSuccess) return -1;
     return nb > 0 ? nb : 1;
 }
 
 // Class dispatch, split into parts compiled separately (PIMPC_LANE_PART of
 // PIMPC_LANE_NPARTS) so the per-class kernels build in parallel.
+// bw: waves per bin of the class's run (4 only for FP64 classes whose
+// horizons all fit four waves).
 template <int P>
-hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s,
+hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int bw, int grid, hipStream_t s,
                          int* occ, bool* handled) {
-    (void)nbmax;
     *handled = false;
-#define PIMPC_CASE(id, nx, nu, tv)                                                           \
-    if constexpr ((id) % PIMPC_LANE_NPARTS == P) {                                          \
-        if (cls == (id)) {                                                                  \
-            *handled = true;                                                                \
-            if (occ) {                                                                      \
-                if (!fp64)                                                                  \
-                    *occ = lane_occupancy<float, nx, nu, tv>(gs != 0);                      \
-                else if constexpr (lane_fp64_class(nx + nu))                                \
-                    *occ = lane_occupancy<double, nx, nu, tv>(gs != 0);                     \
-                else                                                                        \
-                    *occ = -1;                                                              \
-                return *occ > 0 ? hipSuccess : hipErrorInvalidValue;                        \
-            }                                                                               \
-            if (!fp64) return launch_lane_cls<float, nx, nu, tv>(a_dev, grid, s, gs != 0);  \
-            if constexpr (lane_fp64_class(nx + nu))                                         \
-                return launch_lane_cls<double, nx, nu, tv>(a_dev, grid, s, gs != 0);        \
-            return hipErrorInvalidValue;                                                    \
-        }                                                                                   \
+#define PIMPC_CASE(id, nx, nu, tv)                                                                \
+    if constexpr ((id) % PIMPC_LANE_NPARTS == P) {                                               \
+        if (cls == (id)) {                                                                       \
+            *handled = true;                                                                     \
+            if (occ) {                                                                           \
+                if (!fp64)                                                                       \
+                    *occ = lane_occupancy<float, nx, nu, tv, kBinWaves>(gs != 0);                \
+                else if constexpr (lane_fp64_class(nx + nu))                                     \
+                    *occ = bw == 4 ? lane_occupancy<double, nx, nu, tv, 4>(gs != 0)              \
+                                   : lane_occupancy<double, nx, nu, tv, kBinWaves>(gs != 0);     \
+                else                                                                             \
+                    *occ = -1;                                                                   \
+                return *occ > 0 ? hipSuccess : hipErrorInvalidValue;                             \
+            }                                                                                    \
+            if (!fp64) return launch_lane_cls<float, nx, nu, tv, kBinWaves>(a_dev, grid, s, gs != 0); \
+            if constexpr (lane_fp64_class(nx + nu)) {                                            \
+                if (bw == 4) return launch_lane_cls<double, nx, nu, tv, 4>(a_dev, grid, s, gs != 0); \
+                return launch_lane_cls<double, nx, nu, tv, kBinWaves>(a_dev, grid, s, gs != 0);  \
+            }                                                                                    \
+            return hipErrorInvalidValue;                                                         \
+        }                                                                                        \
     }
 #define PIMPC_CASE_TI(id, nx, nu) PIMPC_CASE(id, nx, nu, false)
 #define PIMPC_CASE_TV(id, nx, nu) PIMPC_CASE(id, nx, nu, true)

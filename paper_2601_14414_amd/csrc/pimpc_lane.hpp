@@ -40,7 +40,7 @@ struct LaneArgs {
 
 // gs != 0 selects the kernel variant that projects onto non-box sets.
 template <int P>
-hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int nbmax, int grid, hipStream_t s,
+hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int bw, int grid, hipStream_t s,
                          int* occ, bool* handled);
 
 // Whether a class of padded stage size nb fits the lane kernel in this

@@ -63,12 +63,12 @@ inline int64_t stage_fma(int nx, int nu) {
     return nb * nb + nu * nb + 2LL * nx * nx + 3LL * nx * nu;
 }
 
-hipError_t lane_dispatch_any(int fp64, int cls, int gs, const LaneArgs* a, int nbmax, int grid, hipStream_t s,
+hipError_t lane_dispatch_any(int fp64, int cls, int gs, const LaneArgs* a, int bw, int grid, hipStream_t s,
                              int* occ) {
     bool handled = false;
     hipError_t e;
 #define PIMPC_TRY(P)                                                            \
-    e = lane_dispatch<P>(fp64, cls, gs, a, nbmax, grid, s, occ, &handled);     \
+    e = lane_dispatch<P>(fp64, cls, gs, a, bw, grid, s, occ, &handled);        \
     if (handled) return e;
     PIMPC_TRY(0)
     PIMPC_TRY(1)
@@ -151,6 +151,7 @@ constexpr size_t kMaxLaunchSets = 8;
 struct ClassRun {
     int cls = 0;
     int nbmax = 0;
+    int bw = kBinWaves;  // waves per bin (the launch's workgroup size / 64)
     int bin_first = 0;
     int nbins = 0;
     int occ = 1;
@@ -433,7 +434,11 @@ static int refactor(pimpc_ctx ctx, bool sync_check) {
 
 // ------------------------------------------------------------ batch schedule
 
-static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassRun>& runs, int cap_waves) {
+// Bins of at most cap_waves waves; with fp64_narrow, FP64 classes whose
+// horizons all fit four waves get bins of four (256-thread workgroups, one
+// wave per SIMD with the whole register file).
+static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassRun>& runs, int cap_waves,
+                       bool fp64_narrow) {
     bins.clear();
     runs.clear();
     for (const ClassDesc& cd : kClassTable) {
@@ -445,6 +450,7 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassR
             if (ctx->inst[a].N != ctx->inst[b].N) return ctx->inst[a].N > ctx->inst[b].N;
             return a < b;
         });
+        const int cap = (fp64_narrow && ctx->inst[members[0]].N <= 4 * 64) ? 4 : cap_waves;
         // first-fit decreasing on waves
         std::vector<Bin> cb;
         std::vector<int> used;
@@ -452,7 +458,7 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassR
             const int w = (ctx->inst[i].N + 63) / 64;
             int tgt = -1;
             for (size_t b = 0; b < cb.size(); ++b)
-                if (used[b] + w <= cap_waves && cb[b].n < cap_waves) {
+                if (used[b] + w <= cap && cb[b].n < cap) {
                     tgt = (int)b;
                     break;
                 }
@@ -478,6 +484,7 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassR
         for (int i : members)
             if (ctx->inst[i].xset != 0 || ctx->inst[i].uset != 0) run.gs = 1;
         run.nbmax = cd.nx + cd.nu;
+        run.bw = cap;
         run.bin_first = (int)bins.size();
         run.nbins = (int)cb.size();
         int64_t waves = 0;
@@ -675,7 +682,7 @@ static int enqueue_launches(pimpc_ctx ctx, const LaneArgs* d_args, const RowArgs
         const ClassRun& r = ctx->runs[c];
         const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[j] += r.cost;
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, d_args + c, r.nbmax, class_grid(ctx, r),
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, d_args + c, r.bw, class_grid(ctx, r),
                                       stream_of(j), nullptr));
     }
     if (ns > 1) {
@@ -753,7 +760,7 @@ static int time_launch(pimpc_ctx ctx, LaunchSet* ls, int only_class, hipEvent_t 
     } else {
         const ClassRun& r = ctx->runs[only_class];
         if (ctx->schedule == 1) HIPCHK(ctx, launch_fill<int32_t>(ctx->d_counters + only_class, 1, 0, ctx->stream));
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, ls->d_args + only_class, r.nbmax, class_grid(ctx, r),
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, ls->d_args + only_class, r.bw, class_grid(ctx, r),
                                       ctx->stream, nullptr));
     }
     HIPCHK(ctx, hipEventRecord(t1, ctx->stream));
@@ -1217,7 +1224,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
 
     // ---------------- schedule
     std::vector<Bin> bins;
-    build_bins(ctx, bins, ctx->runs, kBinWaves);
+    build_bins(ctx, bins, ctx->runs, kBinWaves, ctx->fp64 != 0);
     if (!bins.empty()) {
         DALLOC(ctx->d_bins, Bin, bins.size());
         HIPCHK(ctx, hipMemcpy(ctx->d_bins, bins.data(), bins.size() * sizeof(Bin), hipMemcpyHostToDevice));
@@ -1231,7 +1238,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     DALLOC(ctx->d_counters, int32_t, std::max<size_t>(2 * ctx->runs.size(), 1));
     for (ClassRun& r : ctx->runs) {
         int occ = 1;
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, nullptr, r.nbmax, 0, ctx->stream, &occ));
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, nullptr, r.bw, 0, ctx->stream, &occ));
         r.occ = occ;
     }
     if (!ctx->row_insts.empty()) {
@@ -1285,7 +1292,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         DALLOC(ctx->d_grads, float, (int64_t)count * kGradStride);
         HIPCHK(ctx, hipMemcpy(ctx->d_inst, ctx->inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice));
         std::vector<Bin> bb;
-        build_bins(ctx, bb, ctx->bwd_runs, 4);
+        build_bins(ctx, bb, ctx->bwd_runs, 4, false);
         DALLOC(ctx->d_bwd_bins, Bin, bb.size());
         HIPCHK(ctx, hipMemcpy(ctx->d_bwd_bins, bb.data(), bb.size() * sizeof(Bin), hipMemcpyHostToDevice));
         DALLOC(ctx->d_bwd_counters, int32_t, std::max<size_t>(ctx->bwd_runs.size(), 1));
