@@ -9,18 +9,20 @@
 // Backward kernel (one lane per stage, same bins as the forward):
 //   * the taped forward stored the iterate entering every ckpt_every-th
 //     iteration; the backward re-runs each segment from its checkpoint into a
-//     per-instance tape, then walks it in reverse;
-//   * per reverse step it recomputes the step's intermediates (du, g, h,
-//     xbar and the box mask of the projection), applies the exact transpose
-//     of steps 2-3, then of step 1; the halo directions are reversed (the
-//     adjoint of xbar_k goes to stage k-1, the adjoint of g_{k+1} to stage
-//     k+1); the uniform matrix rows stream through SGPRs one row ahead of
-//     their use, as in the forward kernel;
+//     per-instance tape (per stage and step: d = v - beta, h, the top rows of
+//     w and the box mask), then walks it in reverse;
+//   * per reverse step it applies the exact transpose of steps 2-3, then of
+//     step 1, recomputing du = J d and xbar = H h from the record in the same
+//     passes over J and H that the transposes make; the halo directions are
+//     reversed (the adjoint of xbar_k goes to stage k-1, the adjoint of
+//     g_{k+1} to stage k+1);
+//   * the stage matrices come from a per-wave LDS image (stages up to 12
+//     wide) or stream through SGPRs one row ahead (wider stages);
 //   * parameter adjoints are sums over stages and iterations of outer
-//     products (e.g. Hbar += xbar_bar h^T).  Each wave stages the two vectors
-//     of its 64 stages in LDS and contracts over the stages with FP32 MFMA
-//     (16x16x4), accumulating in AGPR-resident 16x16 tiles: the one dense
-//     contraction on this path.
+//     products (e.g. Hbar += xbar_bar h^T).  Each wave stages the vectors of
+//     its 64 stages in LDS and contracts over the stages with FP32 MFMA
+//     (16x16x4), two products per round, accumulating in 16x16 tiles: the
+//     one dense contraction on this path.
 // Chain kernel (FP64, one workgroup per instance): maps the adjoints of
 // H_a, H_{N-1}, J and the Abar/Bbar blocks to dA, dB, diag Q, diag R through
 // M_bar = -H Hbar H and the derivative of J = (Bbar'Bbar)^-1 Bbar'.
@@ -233,7 +235,6 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     // J_bar and the top rows of B_bar share one 16 x 16 tile when they fit:
     // rows dub (NU) then bb (NX), columns d (NB) then du (NU)
     constexpr bool kMergeBJ = NB + NU <= 16;
-    const bool hb_diag = have && I.hb_diag;
 
 // the stage matrices behind opaque offsets: their reads stay in the step
 // that makes them (not hoisted out of the iteration loops into registers)

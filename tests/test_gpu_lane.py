@@ -114,13 +114,24 @@ def test_padding_time_varying_affine_fp64(n, m, tv):
     check_info(info, refs, 1e-10)
 
 
-@pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 127, 200, 511, 512])
+@pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 127, 200, 256, 257, 511, 512])
 def test_wave_and_bin_boundaries_fp64(N):
-    """Horizons at and around wave (64) and workgroup (512) boundaries."""
+    """Horizons at and around wave (64) and workgroup (512) boundaries; FP64
+    classes whose horizons all fit four waves (N <= 256) run 256-thread
+    workgroups, longer ones 512-thread workgroups."""
     p = tiny_problem(N, 4, 2, N, 0, dense_q=False)
     s, u0, info, refs = run_both([p], P.PIMPC_FP64, K=40)
     compare(s, [p], refs, TOL64)
     check_info(info, refs, 1e-10)
+
+def test_fp64_class_mixing_short_and_long_horizons():
+    """One FP64 class holding horizons on both sides of four waves: the whole
+    class runs eight-wave bins; every instance matches the oracle."""
+    problems = [tiny_problem(40 + i, 4, 2, N, 0, dense_q=False) for i, N in enumerate((30, 200, 300, 90))]
+    s, u0, info, refs = run_both(problems, P.PIMPC_FP64, K=40)
+    compare(s, problems, refs, TOL64)
+    check_info(info, refs, 1e-10)
+
 
 
 def test_eps_stop_matches_oracle_fp64():
