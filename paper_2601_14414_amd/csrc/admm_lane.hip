@@ -6,12 +6,16 @@
 //   * one lane owns one horizon stage k and keeps its five iterate vectors
 //     (v_k, z_{k+1}, theta_k, beta_k, lambda_k) in VGPRs for all iterations;
 //   * an instance occupies ceil(N/64) consecutive waves of a 512-thread
-//     workgroup; several instances share a workgroup ("bin");
+//     workgroup (256 threads for FP64 classes whose horizons all fit four
+//     waves); several instances share a workgroup ("bin");
 //   * time-invariant stage data (J, H, A, B, e, bounds) is uniform across the
-//     wave and is streamed row by row through SGPRs with scalar loads, one row
-//     ahead of its use (each row's load overlaps the previous row's FMAs), so
-//     every mat-vec FMA takes its matrix operand from an SGPR; time-varying
-//     stage data is loaded once into VGPRs per lane;
+//     wave.  FP32 classes up to 12 wide copy it once per bin into a per-wave
+//     LDS image and read each row as float4 broadcasts, two rows ahead of its
+//     use; wider classes and FP64 stream it row by row through SGPRs with
+//     scalar loads, one row ahead of its use (each row's load overlaps the
+//     previous row's FMAs), so that every mat-vec FMA takes its matrix
+//     operand from an SGPR; time-varying stage data is loaded once into VGPRs
+//     per lane;
 //   * the two one-stage halos of an iteration (g_{k+1} for step 1 and
 //     xbar_k for step 2) move between neighbouring lanes with DPP wavefront
 //     shifts; only the value crossing a wave boundary goes through a small
