@@ -107,3 +107,28 @@ def test_noalloc_with_eps_stop_and_acceleration():
         np.testing.assert_array_equal(i_na, i_ref)
         for w in range(5):
             np.testing.assert_array_equal(st_na[w], st_ref[w])
+
+
+def test_noalloc_fp64_four_wave_bins():
+    """FP64 classes whose horizons all fit four waves run 256-thread
+    workgroups: the no-alloc call launches them the same way, twice in a
+    row (the second context smaller), equal to pimpc_solve_batch."""
+    stream = torch.cuda.Stream()
+    dev = torch.device("cuda")
+    for n, seed in ((24, 40), (6, 41)):
+        problems = [tiny_problem(seed + i, 4, 2, 30 + (37 * i) % 220, 0) for i in range(n)]  # N <= 249
+        outs = []
+        for entry in (P.pimpc_solve_batch, P.pimpc_solve_batch_noalloc):
+            s = P.Solver(problems, max_iter=50, precision=P.PIMPC_FP64)
+            with torch.cuda.stream(stream):
+                x0 = torch.tensor(np.concatenate([p.x0 for p in problems]), dtype=torch.float64, device=dev)
+                u0 = torch.full((s.sum_nu,), float("nan"), dtype=torch.float64, device=dev)
+                info = torch.zeros((s.count * 40,), dtype=torch.uint8, device=dev)
+                entry(s.ctx, x0, None, u0, info, stream.cuda_stream)
+            stream.synchronize()
+            outs.append((u0.cpu().numpy(), info.cpu().numpy(),
+                         np.concatenate([a.ravel() for a in s.iterate(P.IT_Z)])))
+            s.close()
+        assert np.all(np.isfinite(outs[0][0]))
+        for a, b in zip(outs[0], outs[1]):
+            np.testing.assert_array_equal(a, b)
