@@ -154,14 +154,18 @@ __device__ __forceinline__ double shr1(double x) {
 
 // Run (or, with have = false, only shadow the barrier sequence of) one
 // instance on the waves [gw0, gw0 + gnw) of the workgroup.
-// Time-invariant FP32 box classes up to twelve entries wide read their stage
+// Time-invariant FP32 box classes up to 18 entries wide read their stage
 // matrices from a per-wave LDS image instead of the SGPR row stream (see
-// MatImg): several rows in flight behind in-order waits.  Wider classes keep
-// the SGPR stream (their per-lane vectors leave no VGPRs for rows), and so
-// does FP64 (measured: the single FP64 chain gains nothing from LDS rows).
+// MatImg): several rows in flight behind in-order waits.  Measured per class
+// (batches of 512-1024 instances, 300 iterations): (12,1..4) 17-20 % and
+// (16,1..2) 21-23 % faster, though the rows in flight cost the widest of them
+// a few dozen spilled VGPRs; (16,3) and (16,4) spill 180-230 and run 5-31 %
+// slower, so classes from 19 wide keep the SGPR stream, and so does (8,8)
+// (LDS rows would spill 161 VGPRs there against 24).  FP64 keeps it too
+// (measured: the single FP64 chain gains nothing from LDS rows).
 template <typename T, int NX, int NU, bool TV, bool GS, int BW>
 constexpr bool lane_lds_rows() {
-    return !TV && !GS && sizeof(T) == 4 && MatImg<NX, NU>::NBP <= 12;
+    return !TV && !GS && sizeof(T) == 4 && NX + NU <= 18 && NU <= 4;
 }
 template <int NX, int NU>
 constexpr int lane_img_stride() { return (MatImg<NX, NU>::TOT + 3) & ~3; }
