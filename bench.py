@@ -355,7 +355,9 @@ def bench_accel(torch, P, W, steps, warmup):
 def bench_diff(torch, P, W, steps, warmup):
     """Differentiable batch: 1024 chains (nx=8, nu=3, N=128), 200 iterations,
     checkpoints every 20.  Returns the time of (taped forward + backward) over
-    the time of the plain forward on the same batch."""
+    the time of the plain forward on the same batch; the same for the tape
+    the forward records in full (ckpt_every = 1: no checkpoints, no re-run in
+    the backward, 3.25 GB of records)."""
     import numpy as np
     from paper_2601_14414_amd.autograd import PiMPCFunction
     db = W.diff_batch(count=1024, seed=7, N=128, K=200)
@@ -363,7 +365,6 @@ def bench_diff(torch, P, W, steps, warmup):
     stream = torch.cuda.current_stream().cuda_stream
     problems = [db.instance(i) for i in range(1024)]
     plain = P.Solver(problems, max_iter=200, precision=P.PIMPC_FP32, stream=stream)
-    taped = P.Solver(problems, max_iter=200, precision=P.PIMPC_FP32, ckpt_every=20, stream=stream)
     f = lambda a, g=False: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev,
                                         requires_grad=g)
     x0 = f(db.x0)
@@ -372,45 +373,58 @@ def bench_diff(torch, P, W, steps, warmup):
     ms_plain, per_plain = time_solves(torch, lambda: P.pimpc_solve_batch(plain.ctx, x0, None, u0, info, stream),
                                       steps, warmup)
     check_info(P, np.frombuffer(info.cpu().numpy().tobytes(), dtype=P.INFO_DTYPE), 200, "differentiable plain")
+    plain.close()
     xq, Qd, Rd, A, B = f(db.x0, True), f(db.Qdiag, True), f(db.Rdiag, True), f(db.A, True), f(db.Bm, True)
     target = f(db.u_target)
-
-    def fwd_bwd():
-        u = PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
-        ((u - target) ** 2).sum().backward()
-
-    ms_fb, per_fb = time_solves(torch, fwd_bwd, steps, warmup)
-
-    def fwd_only():
-        with torch.no_grad():
-            PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
-
-    ms_f, _ = time_solves(torch, fwd_only, steps, warmup)
-    # gradient error against the oracle's reverse mode on a sample of instances
-    for t in (xq, Qd, Rd, A, B):
-        t.grad = None
-    fwd_bwd()
-    torch.cuda.synchronize()
+    # the oracle's reverse mode on a sample of instances
     import oracle
-    got = {k: t.grad.detach().cpu().numpy().astype(np.float64) for k, t in
-           dict(dx0=xq, dQd=Qd, dRd=Rd, dA=A, dB=B).items()}
-    worst = 0.0
     sample = list(range(0, 1024, 256))
+    ref = {}
     for i in sample:
         pi = db.instance(i)
         r = oracle.solve(pi)
-        g = oracle.grad(8, 3, db.N, pi.A, pi.B, db.Qdiag[i], db.Rdiag[i], pi.lb(), pi.ub(), pi.x0, pi.rho, db.K,
-                        2 * (r["u0"] - db.u_target[i]))
-        for key in ("dx0", "dQd", "dRd", "dA", "dB"):
-            worst = max(worst, float(np.max(np.abs(got[key][i] - g[key])) / max(1e-6, np.max(np.abs(g[key])))))
-    plain.close()
-    taped.close()
+        ref[i] = oracle.grad(8, 3, db.N, pi.A, pi.B, db.Qdiag[i], db.Rdiag[i], pi.lb(), pi.ub(), pi.x0, pi.rho,
+                             db.K, 2 * (r["u0"] - db.u_target[i]))
+
+    def run(ckpt):
+        taped = P.Solver(problems, max_iter=200, precision=P.PIMPC_FP32, ckpt_every=ckpt, stream=stream)
+
+        def fwd_bwd():
+            u = PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
+            ((u - target) ** 2).sum().backward()
+
+        def fwd_only():
+            with torch.no_grad():
+                PiMPCFunction.apply(xq, Qd, Rd, A, B, taped)
+
+        ms_fb, _ = time_solves(torch, fwd_bwd, steps, warmup)
+        ms_f, _ = time_solves(torch, fwd_only, steps, warmup)
+        for t in (xq, Qd, Rd, A, B):
+            t.grad = None
+        fwd_bwd()
+        torch.cuda.synchronize()
+        got = {k: t.grad.detach().cpu().numpy().astype(np.float64) for k, t in
+               dict(dx0=xq, dQd=Qd, dRd=Rd, dA=A, dB=B).items()}
+        taped.close()
+        worst = 0.0
+        for i in sample:
+            for key in ("dx0", "dQd", "dRd", "dA", "dB"):
+                g = ref[i][key]
+                worst = max(worst, float(np.max(np.abs(got[key][i] - g)) / max(1e-6, np.max(np.abs(g)))))
+        return ms_fb, ms_f, worst
+
+    ms_fb, ms_f, worst = run(20)
+    ms_fb1, ms_f1, worst1 = run(1)
     return {"fwd_bwd_over_plain": ms_fb / ms_plain, "plain_fwd_ms": ms_plain / steps,
             "taped_fwd_ms": ms_f / steps, "fwd_bwd_ms": ms_fb / steps,
             "workload": "1024 x 4-mass chain (nx=8, nu=3), N=128, 200 iterations, checkpoints every 20, "
                         "loss sum ||u0 - u_target||^2, gradients w.r.t. x0, diag Q, diag R, A, B",
             "gradient_error_vs_oracle": {"max_rel_error": worst, "instances": sample,
                                          "norm": "per parameter, max |gpu - oracle| / max |oracle|"},
+            "full_tape": {"fwd_bwd_over_plain": ms_fb1 / ms_plain, "taped_fwd_ms": ms_f1 / steps,
+                          "fwd_bwd_ms": ms_fb1 / steps, "max_rel_gradient_error": worst1,
+                          "tape": "ckpt_every = 1: the forward records all 200 steps (31 floats a stage "
+                                  "and step, 3.25 GB), the backward re-runs nothing"},
             "plain_stage_iterations_per_s": 1024 * 128 * 200 * steps / (ms_plain / 1e3)}
 
 

@@ -191,7 +191,15 @@ typedef struct {
  *   accel        0 = plain ADMM; 1 = restart acceleration (steps 6-7)
  *   eta          restart threshold (Algorithm 1 uses 0.999)
  *   warm_start   1 = start from the previous solve's iterate (unshifted)
- *   ckpt_every   > 0 records a tape for pimpc_backward every that many iterations
+ *   ckpt_every   > 0: the forward records a tape for pimpc_backward (FP32,
+ *                time-invariant, box sets, plain ADMM, eps <= 0).  k >= 2:
+ *                the iterate entering every k-th iteration (5 nb floats a
+ *                stage), and the backward re-runs each k-step segment from it
+ *                into a k-step record buffer; 1: the forward itself writes
+ *                the backward's record of every iteration (2 nb + nx + 1
+ *                floats a stage and iteration, max_iter of them: 24.8 KB a
+ *                stage for nx = 8, nu = 3 and 200 iterations) and the
+ *                backward re-runs nothing
  *   schedule     batch schedule: 0 = autotune (measured at setup), k = 1..14
  *                a fixed candidate: bin claiming by atomic counter (1, 2, 5,
  *                6, 7, 9, 11, 12, 14), static striding (3, 13) or one

@@ -10,7 +10,9 @@
 //   * the taped forward stored the iterate entering every ckpt_every-th
 //     iteration; the backward re-runs each segment from its checkpoint into a
 //     per-instance tape (per stage and step: d = v - beta, h, the top rows of
-//     w and the box mask), then walks it in reverse;
+//     w and the box mask), then walks it in reverse.  With ckpt_every = 1 the
+//     forward wrote that record for every step itself, and the backward only
+//     walks it;
 //   * per reverse step it applies the exact transpose of steps 2-3, then of
 //     step 1, recomputing du = J d and xbar = H h from the record in the same
 //     passes over J and H that the transposes make; the halo directions are
@@ -386,18 +388,21 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
         mask = act ? __float_as_uint(p[(int64_t)(2 * NB + NX) * N + k]) : 0u;
     };
 
+    // With a full tape the forward recorded all K steps: one segment, no
+    // replay.  Otherwise each segment is re-run from its checkpoint first.
     const int K = a.K;
-    const int CK = a.ckpt_every;
+    const bool full = a.full_tape != 0;
+    const int CK = full ? K : a.ckpt_every;
     const int nck = (K + CK - 1) / CK;
     float* tape = have ? a.tape + I.tape_off : a.tape;
 #pragma unroll 1
     for (int seg = nck - 1; seg >= 0; --seg) {
         const int i0 = seg * CK;
         const int i1 = min(i0 + CK, K);
-        load_state(have ? a.ckpt + I.ck_off + (int64_t)seg * 5 * NB * N : a.ckpt);
+        if (!full) load_state(have ? a.ckpt + I.ck_off + (int64_t)seg * 5 * NB * N : a.ckpt);
         // forward over the segment from its checkpoint, recording each step
 #pragma unroll 1
-        for (int i = i0; i < i1; ++i) {
+        for (int i = i0; i < (full ? i0 : i1); ++i) {
             step1();
             {
                 MATS()

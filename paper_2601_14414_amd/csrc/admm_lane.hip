@@ -35,6 +35,7 @@
 
 #include "pimpc_dev.hpp"
 #include "pimpc_lane.hpp"
+#include "pimpc_adjoint.hpp"
 #include "lane_common.hpp"
 
 namespace pimpc {
@@ -170,7 +171,7 @@ constexpr bool lane_lds_rows() {
 template <int NX, int NU>
 constexpr int lane_img_stride() { return (MatImg<NX, NU>::TOT + 3) & ~3; }
 
-template <typename T, int NX, int NU, bool TV, bool GS, int BW>
+template <typename T, int NX, int NU, bool TV, bool GS, int BW, bool REC>
 __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bool have, int gw0,
                                          unsigned leader_mask, T (*bnd_g)[NX + NU], T (*bnd_x)[NX + NU],
                                          T (*dzl)[64 * BW], T (*ddl)[64 * BW], double* red, int* gdone,
@@ -308,6 +309,17 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     const bool use_eps = (*ap).eps > 0.0;
     const int check_every = (*ap).check_every;
     const int ckpt_every = (*ap).ckpt_every;
+    // REC: a taped forward that records every step (FP32, time-invariant
+    // boxes): the reverse sweep's record of the step -- d = v - beta, h, the
+    // top rows of w = z - v - ebar + lambda and the box mask of the
+    // projection -- so that the backward replays nothing.  A variant of its
+    // own: the stores, even skipped, would change the plain kernel's register
+    // allocation.
+    static_assert(!REC || (sizeof(T) == 4 && !TV && !GS), "recorded steps: FP32, time-invariant, boxes");
+    constexpr int kRec = tape_rec_floats(NB, NX);
+    auto RECP = [&](int it) {
+        return (gptr<T>)((T*)(*AP()).tape + (*IP()).tape_off + (int64_t)it * kRec * N);
+    };
 #pragma unroll 1
     for (int it = 0; it < K; ++it) {
         const bool check = (use_eps && ((it + 1) % check_every) == 0) || (it == K - 1);
@@ -333,6 +345,18 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
         asm volatile("" : "+s"(mo_));
         const T* L = img + mo_;
         (void)L;
+        if constexpr (REC) {
+            if (act) {
+                const gptr<T> tr = RECP(it);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) tr[(int64_t)i * N + k] = v[i] - be[i];
+#pragma unroll
+                for (int i = 0; i < NX; ++i) {
+                    const T ei = kLR ? L[MI::E + i] : (T)em[i];
+                    tr[(int64_t)(2 * NB + i) * N + k] = z[i] - v[i] - ei + la[i];
+                }
+            }
+        }
 
         // ---- step 1a: du_k = J_k (v_k - beta_k); g_k = Abar_k' (z_{k+1} - v_k - ebar_k + lambda_k)
         T g[NB], xs[NB];
@@ -488,6 +512,13 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     xs[r] = s;
                 }
             }
+            if constexpr (REC) {
+                if (act) {
+                    const gptr<T> tr = RECP(it);
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) tr[(int64_t)(NB + i) * N + k] = h[i];
+                }
+            }
             // xbar moves one lane up (stage k -> k + 1); lane 63 hands its
             // xbar to the next wave through LDS
             if (lane == 63) {
@@ -553,6 +584,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             };
             // general sets: y, b, c of every component, projected after the stream
             T gy[GS ? NB : 1], gbv[GS ? NB : 1], gcv[GS ? NB : 1];
+            uint32_t rmask = 0u;  // REC: bit i set where lb_i < y_i < ub_i
             // component i: b_i = (Bbar du)_i + beta_i;  c_i = (Abar xbar_k)_i + ebar_i - lambda_i
             // (rows are passed as accessors, never as addresses, so that they stay in registers)
             auto comp = [&](int i, auto&& arow, auto&& brow, T ei, T lo, T hi) {
@@ -571,6 +603,9 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     ci = xp[i] - la[i];
                 }
                 const T y = (T(2) * (xs[i] + th[i]) + bi + ci) * third;
+                if constexpr (REC) {
+                    if (y > lo && y < hi) rmask |= 1u << i;
+                }
                 if constexpr (GS) {
                     gy[i] = y;
                     gbv[i] = bi;
@@ -619,6 +654,9 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                             i, [&](int j) { return x.x[j]; }, [&](int j) { return x.x[NX + j]; },
                             i < NX ? x.x[NB] : T(0), x.x[NB + 1], x.x[NB + 2]);
                     });
+            }
+            if constexpr (REC) {
+                if (act) RECP(it)[(int64_t)(2 * NB + NX) * N + k] = __uint_as_float(rmask);
             }
             if constexpr (GS) {
                 // z = Proj_{X x U}(y): the non-box factor (if any) first, then the
@@ -859,7 +897,7 @@ constexpr int lane_waves_per_eu(int nb, int tsize, int bw) {
     return bw == 4 ? 1 : ((tsize == 4 && nb <= 7) ? 4 : 2);
 }
 
-template <typename T, int NX, int NU, bool TV, bool GS, int BW>
+template <typename T, int NX, int NU, bool TV, bool GS, int BW, bool REC>
 __global__ void __launch_bounds__(64 * BW)
     __attribute__((amdgpu_waves_per_eu(lane_waves_per_eu(NX + NU, sizeof(T), BW))))
     lane_kernel(const LaneArgs* __restrict__ ap) {
@@ -897,30 +935,52 @@ __global__ void __launch_bounds__(64 * BW)
         if (threadIdx.x < BW) gdone[threadIdx.x] = 1;
         __syncthreads();
         if (my >= 0)
-            lane_run<T, NX, NU, TV, GS, BW>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g,
+            lane_run<T, NX, NU, TV, GS, BW, REC>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g,
                                             bnd_x, dzl, ddl, red, gdone, limg);
         else
-            lane_run<T, NX, NU, TV, GS, BW>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone,
+            lane_run<T, NX, NU, TV, GS, BW, REC>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone,
                                             limg);
         __syncthreads();
     }
 }
 
+// whether the class has the variant that records every step
+template <typename T, int NX, int NU, bool TV>
+constexpr bool lane_has_rec() { return sizeof(T) == 4 && !TV && lane_rec_class(NX + NU); }
+
 template <typename T, int NX, int NU, bool TV, int BW>
-hipError_t launch_lane_cls(const LaneArgs* a_dev, int grid, hipStream_t s, bool gs) {
+hipError_t launch_lane_cls(const LaneArgs* a_dev, int grid, hipStream_t s, bool gs, bool rec) {
+    if (rec) {
+        if constexpr (lane_has_rec<T, NX, NU, TV>()) {
+            if (gs) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, false, BW, true>), dim3(grid), dim3(64 * BW), 0, s,
+                               a_dev);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (gs)
-        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, true, BW>), dim3(grid), dim3(64 * BW), 0, s, a_dev);
+        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, true, BW, false>), dim3(grid), dim3(64 * BW), 0, s, a_dev);
     else
-        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, false, BW>), dim3(grid), dim3(64 * BW), 0, s, a_dev);
+        hipLaunchKernelGGL((lane_kernel<T, NX, NU, TV, false, BW, false>), dim3(grid), dim3(64 * BW), 0, s, a_dev);
     return hipGetLastError();
 }
 
 template <typename T, int NX, int NU, bool TV, int BW>
-int lane_occupancy(bool gs) {
+int lane_occupancy(bool gs, bool rec) {
     int nb = 0;
-    const hipError_t e =
-        gs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, true, BW>, 64 * BW, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, false, BW>, 64 * BW, 0);
+    hipError_t e = hipErrorInvalidValue;
+    if (rec) {
+        if constexpr (lane_has_rec<T, NX, NU, TV>())
+            if (!gs)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, false, BW, true>,
+                                                                 64 * BW, 0);
+    } else {
+        e = gs ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, true, BW, false>,
+                                                              64 * BW, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lane_kernel<T, NX, NU, TV, false, BW, false>,
+                                                              64 * BW, 0);
+    }
     if (e != hipSuccess) return -1;
     return nb > 0 ? nb : 1;
 }
@@ -928,10 +988,10 @@ int lane_occupancy(bool gs) {
 // Class dispatch, split into parts compiled separately (PIMPC_LANE_PART of
 // PIMPC_LANE_NPARTS) so the per-class kernels build in parallel.
 // bw: waves per bin of the class's run (4 only for FP64 classes whose
-// horizons all fit four waves).
+// horizons all fit four waves); rec: the variant that records every step.
 template <int P>
-hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int bw, int grid, hipStream_t s,
-                         int* occ, bool* handled) {
+hipError_t lane_dispatch(int fp64, int cls, int gs, bool rec, const LaneArgs* a_dev, int bw, int grid,
+                         hipStream_t s, int* occ, bool* handled) {
     *handled = false;
 #define PIMPC_CASE(id, nx, nu, tv)                                                                \
     if constexpr ((id) % PIMPC_LANE_NPARTS == P) {                                               \
@@ -939,18 +999,18 @@ hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int b
             *handled = true;                                                                     \
             if (occ) {                                                                           \
                 if (!fp64)                                                                       \
-                    *occ = lane_occupancy<float, nx, nu, tv, kBinWaves>(gs != 0);                \
+                    *occ = lane_occupancy<float, nx, nu, tv, kBinWaves>(gs != 0, rec);           \
                 else if constexpr (lane_fp64_class(nx + nu))                                     \
-                    *occ = bw == 4 ? lane_occupancy<double, nx, nu, tv, 4>(gs != 0)              \
-                                   : lane_occupancy<double, nx, nu, tv, kBinWaves>(gs != 0);     \
+                    *occ = bw == 4 ? lane_occupancy<double, nx, nu, tv, 4>(gs != 0, rec)         \
+                                   : lane_occupancy<double, nx, nu, tv, kBinWaves>(gs != 0, rec); \
                 else                                                                             \
                     *occ = -1;                                                                   \
                 return *occ > 0 ? hipSuccess : hipErrorInvalidValue;                             \
             }                                                                                    \
-            if (!fp64) return launch_lane_cls<float, nx, nu, tv, kBinWaves>(a_dev, grid, s, gs != 0); \
+            if (!fp64) return launch_lane_cls<float, nx, nu, tv, kBinWaves>(a_dev, grid, s, gs != 0, rec); \
             if constexpr (lane_fp64_class(nx + nu)) {                                            \
-                if (bw == 4) return launch_lane_cls<double, nx, nu, tv, 4>(a_dev, grid, s, gs != 0); \
-                return launch_lane_cls<double, nx, nu, tv, kBinWaves>(a_dev, grid, s, gs != 0);  \
+                if (bw == 4) return launch_lane_cls<double, nx, nu, tv, 4>(a_dev, grid, s, gs != 0, rec); \
+                return launch_lane_cls<double, nx, nu, tv, kBinWaves>(a_dev, grid, s, gs != 0, rec); \
             }                                                                                    \
             return hipErrorInvalidValue;                                                         \
         }                                                                                        \
@@ -966,8 +1026,8 @@ hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int b
 }
 
 #ifdef PIMPC_LANE_PART
-template hipError_t lane_dispatch<PIMPC_LANE_PART>(int, int, int, const LaneArgs*, int, int, hipStream_t,
-                                                   int*, bool*);
+template hipError_t lane_dispatch<PIMPC_LANE_PART>(int, int, int, bool, const LaneArgs*, int, int,
+                                                   hipStream_t, int*, bool*);
 #endif
 
 }  // namespace pimpc

@@ -26,6 +26,8 @@ struct BwdArgs {
     double rho;
     int32_t K;
     int32_t ckpt_every;
+    int32_t full_tape;  // 1: the forward recorded all K steps (tape of K records, no checkpoints)
+    int32_t pad_;
 };
 
 // Backward of one lane class (time-invariant, FP32, padded nx + nu <= 16).

@@ -36,17 +36,23 @@ struct LaneArgs {
     double eta;          // restart threshold
     void* prev;          // accel: previous actual iterate (T, state layout)
     const int32_t* fbad; // per instance: non-zero when its stage factorisation failed (not SPD)
+    void* tape;          // non-null (FP32, time-invariant boxes): record every iteration's step for the
+                         // reverse sweep, per instance at InstDev::tape_off (no checkpoints then)
 };
 
 // gs != 0 selects the kernel variant that projects onto non-box sets.
+// rec != 0 selects the variant that records every step for the backward.
 template <int P>
-hipError_t lane_dispatch(int fp64, int cls, int gs, const LaneArgs* a_dev, int bw, int grid, hipStream_t s,
-                         int* occ, bool* handled);
+hipError_t lane_dispatch(int fp64, int cls, int gs, bool rec, const LaneArgs* a_dev, int bw, int grid,
+                         hipStream_t s, int* occ, bool* handled);
 
 // Whether a class of padded stage size nb fits the lane kernel in this
 // precision: the iterate, the step-1 outputs and the temporaries of one
 // stage live in the registers of one lane, which bounds FP64 classes.
 constexpr bool lane_fp64_class(int nb) { return nb <= 13; }
 inline bool lane_class_fits(int nb, size_t tsize) { return tsize == 4 || lane_fp64_class(nb); }
+// Classes with a backward kernel (padded nx + nu <= 16), and so with a
+// forward variant that records every step.
+constexpr bool lane_rec_class(int nb) { return nb <= 16; }
 
 }  // namespace pimpc

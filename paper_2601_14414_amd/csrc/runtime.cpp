@@ -63,12 +63,12 @@ inline int64_t stage_fma(int nx, int nu) {
     return nb * nb + nu * nb + 2LL * nx * nx + 3LL * nx * nu;
 }
 
-hipError_t lane_dispatch_any(int fp64, int cls, int gs, const LaneArgs* a, int bw, int grid, hipStream_t s,
-                             int* occ) {
+hipError_t lane_dispatch_any(int fp64, int cls, int gs, bool rec, const LaneArgs* a, int bw, int grid,
+                             hipStream_t s, int* occ) {
     bool handled = false;
     hipError_t e;
 #define PIMPC_TRY(P)                                                            \
-    e = lane_dispatch<P>(fp64, cls, gs, a, bw, grid, s, occ, &handled);        \
+    e = lane_dispatch<P>(fp64, cls, gs, rec, a, bw, grid, s, occ, &handled);   \
     if (handled) return e;
     PIMPC_TRY(0)
     PIMPC_TRY(1)
@@ -497,6 +497,10 @@ static void build_bins(pimpc_ctx ctx, std::vector<Bin>& bins, std::vector<ClassR
     }
 }
 
+// Whether the lane kernels record every step for the backward (a taped
+// forward with ckpt_every = 1) rather than checkpoints.
+static bool rec_steps(pimpc_ctx ctx) { return ctx->opt.ckpt_every == 1; }
+
 // Grid size of a class launch under the current schedule.
 static int class_grid(pimpc_ctx ctx, const ClassRun& r) {
     if (ctx->schedule == 3) return r.nbins;  // one workgroup per bin, hardware dispatch order
@@ -540,8 +544,9 @@ static void build_args(pimpc_ctx ctx, const void* x0, const void* up, void* u0, 
         a.warm = warm;
         a.nbmax = r.nbmax;
         a.write_iters = write_iters;
-        a.ckpt_every = ctx->opt.ckpt_every;
+        a.ckpt_every = rec_steps(ctx) ? 0 : ctx->opt.ckpt_every;
         a.ckpt = ctx->d_ckpt;
+        a.tape = rec_steps(ctx) ? ctx->d_tape : nullptr;
         a.accel = ctx->opt.accel;
         a.eta = ctx->opt.eta;
         a.prev = ctx->d_prev;
@@ -682,7 +687,7 @@ static int enqueue_launches(pimpc_ctx ctx, const LaneArgs* d_args, const RowArgs
         const ClassRun& r = ctx->runs[c];
         const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[j] += r.cost;
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, d_args + c, r.bw, class_grid(ctx, r),
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, rec_steps(ctx), d_args + c, r.bw, class_grid(ctx, r),
                                       stream_of(j), nullptr));
     }
     if (ns > 1) {
@@ -760,7 +765,8 @@ static int time_launch(pimpc_ctx ctx, LaunchSet* ls, int only_class, hipEvent_t 
     } else {
         const ClassRun& r = ctx->runs[only_class];
         if (ctx->schedule == 1) HIPCHK(ctx, launch_fill<int32_t>(ctx->d_counters + only_class, 1, 0, ctx->stream));
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, ls->d_args + only_class, r.bw, class_grid(ctx, r),
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, rec_steps(ctx), ls->d_args + only_class, r.bw,
+                                      class_grid(ctx, r),
                                       ctx->stream, nullptr));
     }
     HIPCHK(ctx, hipEventRecord(t1, ctx->stream));
@@ -975,6 +981,8 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         return ctx->fail(PIMPC_E_UNSUPPORTED, "the taped forward differentiates plain ADMM (accel = 0)");
     if (o->warm_start != 0 && o->warm_start != 1) return ctx->fail(PIMPC_E_ARG, "warm_start must be 0 or 1");
     if (o->ckpt_every < 0) return ctx->fail(PIMPC_E_ARG, "ckpt_every must be >= 0");
+    if (o->ckpt_every > 0 && o->eps > 0.0)
+        return ctx->fail(PIMPC_E_UNSUPPORTED, "the taped forward runs exactly max_iter iterations (eps <= 0)");
     if (o->schedule < 0) return ctx->fail(PIMPC_E_ARG, "schedule must be >= 0");
     if (o->family < PIMPC_FAMILY_AUTO || o->family > PIMPC_FAMILY_ROW)
         return ctx->fail(PIMPC_E_ARG, "family must be PIMPC_FAMILY_AUTO, _LANE or _ROW");
@@ -1238,7 +1246,9 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     DALLOC(ctx->d_counters, int32_t, std::max<size_t>(2 * ctx->runs.size(), 1));
     for (ClassRun& r : ctx->runs) {
         int occ = 1;
-        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, nullptr, r.bw, 0, ctx->stream, &occ));
+        // (a class without a backward is refused below, with its reason)
+        const bool rec = rec_steps(ctx) && !ctx->fp64 && !tv && r.gs == 0 && backward_class_supported(r.cls);
+        HIPCHK(ctx, lane_dispatch_any(ctx->fp64, r.cls, r.gs, rec, nullptr, r.bw, 0, ctx->stream, &occ));
         r.occ = occ;
     }
     if (!ctx->row_insts.empty()) {
@@ -1274,8 +1284,12 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         if (ctx->fp64 || tv || !ctx->row_insts.empty())
             return ctx->fail(PIMPC_E_UNSUPPORTED, "the taped forward / backward needs FP32, time-invariant "
                                                   "instances of the lane family");
+        // ckpt_every = 1: the forward records all max_iter steps, no checkpoints;
+        // otherwise checkpoints and a tape of one segment
+        const bool all = o->ckpt_every == 1;
         int64_t ck = 0, tp = 0;
-        const int nck = (o->max_iter + o->ckpt_every - 1) / o->ckpt_every;
+        const int nck = all ? 0 : (o->max_iter + o->ckpt_every - 1) / o->ckpt_every;
+        const int seg = all ? o->max_iter : o->ckpt_every;
         for (int i = 0; i < count; ++i) {
             InstDev& I = ctx->inst[i];
             if (!backward_class_supported(I.cls) || I.N > 256)
@@ -1284,7 +1298,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
             I.ck_off = ck;
             ck += (int64_t)nck * 5 * I.nbp * I.N;
             I.tape_off = tp;
-            tp += (int64_t)o->ckpt_every * tape_rec_floats(I.nbp, I.nxp) * I.N;
+            tp += (int64_t)seg * tape_rec_floats(I.nbp, I.nxp) * I.N;
             I.gr_off = (int64_t)i * kGradStride;
         }
         DALLOC(ctx->d_ckpt, float, ck);
@@ -1688,6 +1702,7 @@ int32_t pimpc_backward(pimpc_ctx ctx, uint64_t tape_id, const void* dL_du0_dev, 
         a.rho = ctx->opt.rho;
         a.K = ctx->opt.max_iter;
         a.ckpt_every = ctx->opt.ckpt_every;
+        a.full_tape = rec_steps(ctx) ? 1 : 0;
         const int grid = std::max(1, std::min(r.nbins, ctx->num_cus));
         bool handled = false;
         HIPCHK(ctx, launch_backward_class(r.cls, a, grid, s, &handled));

@@ -116,6 +116,10 @@ def test_unsupported_requests_are_reported():
     # the taped forward differentiates plain ADMM
     code, msg = _setup_code([W.plain_fp64_problem(0)], accel=1, ckpt_every=20)
     assert code == P.PIMPC_E_UNSUPPORTED and "accel" in msg
+    # ... over exactly max_iter iterations, with either kind of tape
+    for ck in (1, 20):
+        code, msg = _setup_code([W.plain_fp64_problem(0)], eps=1e-4, ckpt_every=ck)
+        assert code == P.PIMPC_E_UNSUPPORTED and "eps" in msg
 
 
 def test_shapes_without_a_kernel_are_reported():

@@ -51,10 +51,11 @@ def oracle_grad(db, i, ut, u0=None):
     return r, g
 
 
-@pytest.mark.parametrize("ckpt", [5, 7, 30])
+@pytest.mark.parametrize("ckpt", [1, 5, 7, 30])
 def test_adjoint_matches_oracle_small(ckpt):
     """8 perturbed instances, N=24, 30 iterations, several checkpoint spacings
-    (incl. one not dividing K and one larger than K)."""
+    (incl. one not dividing K and one larger than K), and the full tape the
+    forward records itself (ckpt_every = 1)."""
     db = W.diff_batch(count=8, seed=3, N=24, K=30)
     rng = np.random.default_rng(9)
     db.Qdiag *= rng.uniform(0.5, 2.0, db.Qdiag.shape)
@@ -88,12 +89,16 @@ def test_adjoint_differentiable_batch_sampled():
 
 def test_checkpoint_spacing_does_not_change_gradients():
     """Re-running segments from checkpoints reproduces the forward iterates
-    exactly, so the gradient does not depend on the spacing."""
+    exactly, and the records the forward writes itself (ckpt_every = 1) are
+    the ones a re-run writes, so the gradient depends on neither the spacing
+    nor the kind of tape."""
     db = W.diff_batch(count=16, seed=4, N=64, K=40)
     ga = run_gpu(db, 16, 40, db.u_target)
     gb = run_gpu(db, 16, 8, db.u_target)
-    for key in ("dx0", "dQd", "dRd", "dA", "dB"):
+    gc = run_gpu(db, 16, 1, db.u_target)
+    for key in ("u0", "dx0", "dQd", "dRd", "dA", "dB"):
         np.testing.assert_array_equal(ga[key], gb[key])
+        np.testing.assert_array_equal(ga[key], gc[key])
 
 
 def test_backward_without_tape_is_an_error():
@@ -105,10 +110,13 @@ def test_backward_without_tape_is_an_error():
     assert ei.value.code == P.PIMPC_E_STATE
 
 
-@pytest.mark.parametrize("nx,nu,N,K,ck", [(4, 2, 40, 20, 6), (12, 4, 70, 16, 5), (6, 1, 130, 12, 4)])
+@pytest.mark.parametrize("nx,nu,N,K,ck", [(4, 2, 40, 20, 6), (12, 4, 70, 16, 5), (6, 1, 130, 12, 4),
+                                         (4, 2, 40, 20, 1), (12, 4, 70, 16, 1), (6, 1, 130, 12, 1),
+                                         (2, 2, 200, 10, 1)])
 def test_adjoint_other_classes(nx, nu, N, K, ck):
-    """Backward kernels of other (nx, nu) classes (padded 4+2, 12+4 and 8+1)
-    and horizons over one and two waves, against the oracle's reverse mode."""
+    """Backward kernels of other (nx, nu) classes (padded 4+2, 12+4, 8+1 and
+    2+2) and horizons over one, two and four waves, against the oracle's
+    reverse mode, from checkpoints and from the full tape (ck = 1)."""
     from paper_2601_14414_amd.autograd import PiMPCLayer
     rng = np.random.default_rng(nx * 100 + nu)
     count = 5
