@@ -189,7 +189,9 @@ struct MatView {
     }
 };
 
-template <int NX, int NU>
+// FULL: the forward recorded all K steps (no checkpoints, no re-run); a
+// variant of its own, so that the re-running kernel keeps its registers.
+template <int NX, int NU, bool FULL>
 __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool have, int gw0,
                                         unsigned leader_mask) {
     constexpr int NB = NX + NU;
@@ -391,7 +393,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     // With a full tape the forward recorded all K steps: one segment, no
     // replay.  Otherwise each segment is re-run from its checkpoint first.
     const int K = a.K;
-    const bool full = a.full_tape != 0;
+    constexpr bool full = FULL;
     const int CK = full ? K : a.ckpt_every;
     const int nck = (K + CK - 1) / CK;
     float* tape = have ? a.tape + I.tape_off : a.tape;
@@ -399,7 +401,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     for (int seg = nck - 1; seg >= 0; --seg) {
         const int i0 = seg * CK;
         const int i1 = min(i0 + CK, K);
-        if (!full) load_state(have ? a.ckpt + I.ck_off + (int64_t)seg * 5 * NB * N : a.ckpt);
+        if constexpr (!full) load_state(have ? a.ckpt + I.ck_off + (int64_t)seg * 5 * NB * N : a.ckpt);
         // forward over the segment from its checkpoint, recording each step
 #pragma unroll 1
         for (int i = i0; i < (full ? i0 : i1); ++i) {
@@ -679,7 +681,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
 #undef MATS
 }
 
-template <int NX, int NU>
+template <int NX, int NU, bool FULL>
 __global__ void __launch_bounds__(kBwdThreads) lane_bwd_kernel(BwdArgs a) {
     __shared__ int s_bin;
     const int wave = threadIdx.x >> 6;
@@ -704,7 +706,7 @@ __global__ void __launch_bounds__(kBwdThreads) lane_bwd_kernel(BwdArgs a) {
         my = __builtin_amdgcn_readfirstlane(my);
         // one inlined copy: a wave without an instance shadows the barriers
         const bool have = my >= 0;
-        bwd_run<NX, NU>(a, have ? bin.e[my].inst : 0, have, have ? bin.e[my].wave0 : wave, leader_mask);
+        bwd_run<NX, NU, FULL>(a, have ? bin.e[my].inst : 0, have, have ? bin.e[my].wave0 : wave, leader_mask);
         __syncthreads();
     }
 }
@@ -874,23 +876,23 @@ inline size_t bwd_lds_bytes() {
     return (size_t)3 * 16 * kBBD * sizeof(float) + (size_t)kBwdWaves * (kStgFloats + kMatFloats) * sizeof(float);
 }
 
-template <int NX, int NU>
+template <int NX, int NU, bool FULL>
 hipError_t launch_bwd_cls(const BwdArgs& a, int grid, hipStream_t s) {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)lane_bwd_kernel<NX, NU>,
+        hipError_t e = hipFuncSetAttribute((const void*)lane_bwd_kernel<NX, NU, FULL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bwd_lds_bytes());
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((lane_bwd_kernel<NX, NU>), dim3(grid), dim3(kBwdThreads), bwd_lds_bytes(), s, a);
+    hipLaunchKernelGGL((lane_bwd_kernel<NX, NU, FULL>), dim3(grid), dim3(kBwdThreads), bwd_lds_bytes(), s, a);
     return hipGetLastError();
 }
 
 template <int NX, int NU>
 hipError_t maybe_launch_bwd(const BwdArgs& a, int grid, hipStream_t s) {
     if constexpr (NX + NU <= 16)
-        return launch_bwd_cls<NX, NU>(a, grid, s);
+        return a.full_tape ? launch_bwd_cls<NX, NU, true>(a, grid, s) : launch_bwd_cls<NX, NU, false>(a, grid, s);
     else
         return hipErrorInvalidValue;
 }
