@@ -155,19 +155,24 @@ __device__ __forceinline__ double shr1(double x) {
 
 // Run (or, with have = false, only shadow the barrier sequence of) one
 // instance on the waves [gw0, gw0 + gnw) of the workgroup.
-// Time-invariant FP32 box classes up to 18 entries wide read their stage
-// matrices from a per-wave LDS image instead of the SGPR row stream (see
-// MatImg): several rows in flight behind in-order waits.  Measured per class
-// (batches of 512-1024 instances, 300 iterations): (12,1..4) 17-20 % and
-// (16,1..2) 21-23 % faster, though the rows in flight cost the widest of them
-// a few dozen spilled VGPRs; (16,3) and (16,4) spill 180-230 and run 5-31 %
-// slower, so classes from 19 wide keep the SGPR stream, and so does (8,8)
-// (LDS rows would spill 161 VGPRs there against 24).  FP64 keeps it too
-// (measured: the single FP64 chain gains nothing from LDS rows).
+// Time-invariant FP32 box classes up to 20 entries wide (nu <= 4) read their
+// stage matrices from a per-wave LDS image instead of the SGPR row stream
+// (see MatImg).  Up to 18 wide, two rows are in flight behind in-order
+// waits; measured per class (batches of 512-1024 instances, 300 iterations):
+// (12,1..4) 17-20 % and (16,1..2) 21-23 % faster than SGPR rows, though the
+// rows in flight cost the widest of them a few dozen spilled VGPRs.  With
+// two rows in flight (16,3) and (16,4) spill 180-230 VGPRs and run 5-31 %
+// slower; with one row at a time they spill 72 and 173 (63 and 84 with SGPR
+// rows) and run 20 % and 3 % faster.  (8,8) keeps the SGPR stream (LDS rows would
+// spill 161 VGPRs there against 24), and so does FP64 (measured: the single
+// FP64 chain gains nothing from LDS rows).
 template <typename T, int NX, int NU, bool TV, bool GS, int BW>
 constexpr bool lane_lds_rows() {
-    return !TV && !GS && sizeof(T) == 4 && NX + NU <= 18 && NU <= 4;
+    return !TV && !GS && sizeof(T) == 4 && NX + NU <= 20 && NU <= 4;
 }
+// Rows the LDS row stream keeps in flight beyond the one in use.
+template <int NX, int NU>
+constexpr int lane_row_depth() { return NX + NU > 18 ? 0 : 2; }
 template <int NX, int NU>
 constexpr int lane_img_stride() { return (MatImg<NX, NU>::TOT + 3) & ~3; }
 
@@ -229,6 +234,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     using MI = MatImg<NX, NU>;
     constexpr int NBP = MI::NBP;
     constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS, BW>();
+    constexpr int kRD = lane_row_depth<NX, NU>();
     T* img = limg + (kLR ? wave * lane_img_stride<NX, NU>() : 0);  // this wave's matrix image
     if constexpr (kLR) {
         fill_mat_img<T, NX, NU>(img, (const T*)(*ap).mats + (have ? (*ip).mat_off : 0), o, have, lane);
@@ -380,13 +386,13 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     for (int c = 0; c < NU; ++c) g[NX + c] += Br[r * NU + c] * w;
                 }
             } else if constexpr (kLR) {
-                lds_rows<T, NU, NBP>(L + MI::J, [&](int r, const T (&x)[NBP]) {
+                lds_rows<T, NU, NBP, kRD>(L + MI::J, [&](int r, const T (&x)[NBP]) {
                     T s = T(0);
 #pragma unroll
                     for (int j = 0; j < NB; ++j) s += x[j] * (v[j] - be[j]);
                     du[r] = s;
                 });
-                lds_rows<T, NX, NBP>(L + MI::AB, [&](int i, const T (&x)[NBP]) {
+                lds_rows<T, NX, NBP, kRD>(L + MI::AB, [&](int i, const T (&x)[NBP]) {
                     const T w = z[i] - v[i] - L[MI::E + i] + la[i];
 #pragma unroll
                     for (int c = 0; c < NB; ++c) g[c] += x[c] * w;
@@ -443,7 +449,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                     h[i] = L[MI::Q + i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
                 }
                 // H_{N-1} for the last stage
-                lds_rows<T, NB, NBP>(L + (is_last ? MI::Hb : MI::H), [&](int r, const T (&x)[NBP]) {
+                lds_rows<T, NB, NBP, kRD>(L + (is_last ? MI::Hb : MI::H), [&](int r, const T (&x)[NBP]) {
                     T s = T(0);
 #pragma unroll
                     for (int j = 0; j < NB; ++j) s += x[j] * h[j];
@@ -624,7 +630,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                         i, [&](int j) { return Ar[(i < NX ? i : 0) * NX + j]; },
                         [&](int j) { return Br[(i < NX ? i : 0) * NU + j]; }, i < NX ? er[i] : T(0), lbq[i], ubq[i]);
             } else if constexpr (kLR) {
-                lds_rows<T, NX, NBP>(L + MI::AB, [&](int i, const T (&x)[NBP]) {
+                lds_rows<T, NX, NBP, kRD>(L + MI::AB, [&](int i, const T (&x)[NBP]) {
                     comp(
                         i, [&](int j) { return x[j]; }, [&](int j) { return x[NX + j]; }, L[MI::E + i],
                         L[MI::LB + i], L[MI::UB + i]);
@@ -706,7 +712,7 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                             for (int c = 0; c < NU; ++c) tg[NX + c] += Br[r * NU + c] * dd;
                         }
                     } else if constexpr (kLR) {
-                        lds_rows<T, NX, NBP>(L + MI::AB, [&](int r, const T (&x)[NBP]) {
+                        lds_rows<T, NX, NBP, kRD>(L + MI::AB, [&](int r, const T (&x)[NBP]) {
                             const T dd = ddl[r][tid];
 #pragma unroll
                             for (int c = 0; c < NB; ++c) tg[c] += x[c] * dd;
