@@ -351,10 +351,12 @@ uint64_t pimpc_tape_id(pimpc_ctx ctx);
  * has no tape (opts.ckpt_every = 0, no taped solve yet) or when `tape_id` is
  * not the current tape (another taped forward or a parameter update came
  * after it: its gradients can no longer be formed).
- * Given dL/du0 (count x nu, device, context precision), writes dL/dx0
- * (count x nx), dL/dQdiag (count x nx), dL/dRdiag (count x nu),
- * dL/dA (count x nx x nx) and dL/dB (count x nx x nu); any output may be
- * NULL.  The loss sees u0 = du_0 of the K-th step 1, a cold start and
+ * Given dL/du0 (device, context precision, packed like u0: sum of nu),
+ * writes per instance, in instance order, dL/dx0 and dL/dQdiag (packed like
+ * x0: sum of nx), dL/dRdiag (sum of nu), dL/dA (one nx x nx block per
+ * instance, row-major, sum of nx^2) and dL/dB (one nx x nu block, sum of
+ * nx nu): count x nx, count x nx x nx ... when all instances have the same
+ * shape.  Any output may be NULL.  The loss sees u0 = du_0 of the K-th step 1, a cold start and
  * u_prev = 0.  Asynchronous on `hip_stream`.
  */
 int32_t pimpc_backward(pimpc_ctx ctx, uint64_t tape_id, const void *dL_du0_dev, void *dx0, void *dQdiag,

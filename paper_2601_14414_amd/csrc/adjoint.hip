@@ -853,21 +853,21 @@ __global__ void __launch_bounds__(64) chain_kernel(const InstDev* __restrict__ i
         double s = (double)Atop[i * 16 + j];
         for (int r = 0; r < NB; ++r) s += rho * Ab[i * kCh + r] * (Mba[r * kCh + j] + Mba[j * kCh + r]);
         if (j < NX) {
-            if (dA && j < nx) dA[(int64_t)ii * nx * nx + i * nx + j] = (float)s;
+            if (dA && j < nx) dA[I.ga_off + i * nx + j] = (float)s;
         } else if (j - NX < nu) {
             const int c = j - NX;
             // Bbar_bar top rows: raw + (Jbar' G^-1)[i][c] + (Bbar (Gbar + Gbar'))[i][c]
             double bb = (double)Btop[i * 16 + c] + T1[c * kCh + i];
             for (int r = 0; r < NU; ++r) bb += B[i * NU + r] * (Gb[r * kCh + c] + Gb[c * kCh + r]);
-            if (dB) dB[(int64_t)ii * nx * nu + i * nu + c] = (float)(s + bb);
+            if (dB) dB[I.gb_off + i * nu + c] = (float)(s + bb);
         }
     }
     for (int i = t; i < nx; i += blockDim.x) {
-        if (dQd) dQd[(int64_t)ii * nx + i] = (float)(Mba[i * kCh + i] + Mbb[i * kCh + i]);
-        if (dx0) dx0[(int64_t)ii * nx + i] = gr[5 * 256 + i];
+        if (dQd) dQd[I.x_off + i] = (float)(Mba[i * kCh + i] + Mbb[i * kCh + i]);
+        if (dx0) dx0[I.x_off + i] = gr[5 * 256 + i];
     }
     for (int i = t; i < nu; i += blockDim.x)
-        if (dRd) dRd[(int64_t)ii * nu + i] = (float)(Mba[(NX + i) * kCh + NX + i] + Mbb[(NX + i) * kCh + NX + i]);
+        if (dRd) dRd[I.u_off + i] = (float)(Mba[(NX + i) * kCh + NX + i] + Mbb[(NX + i) * kCh + NX + i]);
 }
 
 // ---------------------------------------------------------------- host side

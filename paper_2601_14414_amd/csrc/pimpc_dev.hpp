@@ -31,8 +31,9 @@ struct InstDev {
     int64_t it_off;            // last step-1 outputs: du [nup][N], then xbar [nbp][N]
     int64_t x_off, u_off;      // offsets into packed x0 (sum nx) and u (sum nu)
     int64_t ck_off;            // checkpoints [nck][5][nbp][N] (taped forward)
-    int64_t tape_off;          // segment tape [ckpt_every][5][nbp][N] (backward)
+    int64_t tape_off;          // tape [steps][2 nbp + nxp + 1][N]: one segment, or all steps (backward)
     int64_t gr_off;            // raw parameter adjoints [kGradBlocks][16][16] + xbar0 adjoint [16]
+    int64_t ga_off, gb_off;    // offsets into the packed dL/dA (sum nx^2) and dL/dB (sum nx nu)
 };
 
 // Raw adjoint blocks written by the backward kernel (16 x 16 each, padded):

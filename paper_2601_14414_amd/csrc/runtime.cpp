@@ -1069,7 +1069,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     ctx->count = count;
     ctx->tv = tv;
     ctx->inst.resize(count);
-    int64_t mo = 0, m64 = 0, so = 0, io = 0, xo = 0, uo = 0, oq = 0, orr = 0;
+    int64_t mo = 0, m64 = 0, so = 0, io = 0, xo = 0, uo = 0, oq = 0, orr = 0, ga = 0, gb = 0;
     std::vector<FactorTask> tasks;
     for (int i = 0; i < count; ++i) {
         InstDev& I = ctx->inst[i];
@@ -1140,6 +1140,10 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         xo += I.nx;
         I.u_off = uo;
         uo += I.nu;
+        I.ga_off = ga;
+        ga += (int64_t)I.nx * I.nx;
+        I.gb_off = gb;
+        gb += (int64_t)I.nx * I.nu;
         if (!tv) {
             if (I.N > 1) tasks.push_back({i, 0, 0, 0});
             tasks.push_back({i, 1, I.N - 1, 0});

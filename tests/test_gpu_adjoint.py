@@ -147,3 +147,70 @@ def test_adjoint_other_classes(nx, nu, N, K, ck):
         g = oracle.grad(nx, nu, N, A[i], B[i], Qd[i], Rd[i], lb, ub, x0[i], 1.0, K, 2 * (r["u0"] - ut[i]))
         for key in ("dx0", "dQd", "dRd", "dA", "dB"):
             assert rel(got[key][i], g[key]) <= TOLG, (i, key, rel(got[key][i], g[key]))
+
+
+def _mixed_problems(K):
+    """Six instances of two shapes in one context, interleaved: 4 states +
+    2 inputs with N = 40, and 8 + 3 with N = 100 (two lane classes)."""
+    rng = np.random.default_rng(21)
+    ps = []
+    for i in range(6):
+        nx, nu, N = (4, 2, 40) if i % 2 == 0 else (8, 3, 100)
+        A = np.eye(nx) * 0.95 + 0.05 * rng.standard_normal((nx, nx))
+        B = rng.standard_normal((nx, nu)) / np.sqrt(nx)
+        ps.append(W.Problem(nx=nx, nu=nu, N=N, A=A, B=B, Q=np.diag(rng.uniform(0.5, 1.5, nx)),
+                            R=np.diag(rng.uniform(0.05, 0.2, nu)), xmin=-1.5 * np.ones(nx), xmax=1.5 * np.ones(nx),
+                            umin=-0.4 * np.ones(nu), umax=0.4 * np.ones(nu), x0=rng.uniform(-1, 1, nx),
+                            u_prev=np.zeros(nu), rho=1.0, K=K))
+    return ps
+
+
+def _mixed_grads(ps, K, ck, ut):
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    s = P.Solver(ps, max_iter=K, precision=P.PIMPC_FP32, ckpt_every=ck, stream=stream)
+    f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    x0 = f(np.concatenate([p.x0 for p in ps]))
+    u0 = torch.empty(s.sum_nu, dtype=torch.float32, device=dev)
+    P.pimpc_solve_batch(s.ctx, x0, None, u0, None, stream)
+    g = 2 * (u0 - f(ut))
+    sx, su = sum(p.nx for p in ps), sum(p.nu for p in ps)
+    out = dict(dx0=torch.full((sx,), np.nan, device=dev), dQd=torch.full((sx,), np.nan, device=dev),
+               dRd=torch.full((su,), np.nan, device=dev),
+               dA=torch.full((sum(p.nx * p.nx for p in ps),), np.nan, device=dev),
+               dB=torch.full((sum(p.nx * p.nu for p in ps),), np.nan, device=dev))
+    P.pimpc_backward(s.ctx, P.pimpc_tape_id(s.ctx), g, out["dx0"], out["dQd"], out["dRd"], out["dA"], out["dB"],
+                     stream)
+    torch.cuda.synchronize()
+    s.close()
+    res = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    res["u0"] = u0.cpu().numpy().astype(np.float64)
+    return res
+
+
+def test_backward_mixed_shapes_packs_per_instance():
+    """One taped context holding two classes: the gradients come packed per
+    instance in instance order (dx0 and diag Q like x0, diag R like u0, the
+    dA and dB blocks one after another), every entry written, each instance's
+    block equal to the oracle's reverse mode; the full tape (ckpt_every = 1)
+    and checkpoints give the same gradients bit for bit."""
+    K = 16
+    ps = _mixed_problems(K)
+    ut = np.random.default_rng(5).normal(0, 0.1, sum(p.nu for p in ps))
+    ga = _mixed_grads(ps, K, 1, ut)
+    gb = _mixed_grads(ps, K, 5, ut)
+    for key in ga:
+        assert np.all(np.isfinite(ga[key])), key
+        np.testing.assert_array_equal(ga[key], gb[key])
+    ox = ou = oa = ob = 0
+    for i, p in enumerate(ps):
+        nx, nu = p.nx, p.nu
+        r = oracle.solve(p)
+        assert rel(ga["u0"][ou:ou + nu], r["u0"]) <= 1e-4
+        go = oracle.grad(nx, nu, p.N, p.A, p.B, np.diag(p.Q), np.diag(p.R), p.lb(), p.ub(), p.x0, p.rho, K,
+                         2 * (r["u0"] - ut[ou:ou + nu]))
+        got = dict(dx0=ga["dx0"][ox:ox + nx], dQd=ga["dQd"][ox:ox + nx], dRd=ga["dRd"][ou:ou + nu],
+                   dA=ga["dA"][oa:oa + nx * nx].reshape(nx, nx), dB=ga["dB"][ob:ob + nx * nu].reshape(nx, nu))
+        for key, v in got.items():
+            assert rel(v, np.asarray(go[key]).reshape(v.shape)) <= TOLG, (i, key, rel(v, go[key]))
+        ox, ou, oa, ob = ox + nx, ou + nu, oa + nx * nx, ob + nx * nu
