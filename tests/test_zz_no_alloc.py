@@ -132,3 +132,32 @@ def test_noalloc_fp64_four_wave_bins():
         assert np.all(np.isfinite(outs[0][0]))
         for a, b in zip(outs[0], outs[1]):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("ck", [1, 5])
+def test_noalloc_taped_forward_feeds_the_backward(ck):
+    """A taped context (full tape, or checkpoints every 5): the no-alloc
+    forward records the same tape as pimpc_solve_batch (the tape lives in the
+    context, not in the static array), so the backward after it gives the
+    same u0 and gradients bit for bit."""
+    db = W.diff_batch(count=16, seed=4, N=64, K=40)
+    problems = [db.instance(i) for i in range(16)]
+    stream = torch.cuda.Stream()
+    dev = torch.device("cuda")
+    outs = []
+    for entry in (P.pimpc_solve_batch, P.pimpc_solve_batch_noalloc):
+        s = P.Solver(problems, max_iter=40, precision=P.PIMPC_FP32, ckpt_every=ck)
+        with torch.cuda.stream(stream):
+            x0 = torch.tensor(np.ascontiguousarray(db.x0[:16]).ravel(), dtype=torch.float32, device=dev)
+            u0 = torch.full((s.sum_nu,), float("nan"), dtype=torch.float32, device=dev)
+            entry(s.ctx, x0, None, u0, None, stream.cuda_stream)
+            g = 2 * (u0 - torch.tensor(db.u_target[:16].ravel(), dtype=torch.float32, device=dev))
+            grads = [torch.full((n,), float("nan"), dtype=torch.float32, device=dev)
+                     for n in (16 * 8, 16 * 8, 16 * 3, 16 * 64, 16 * 24)]
+            P.pimpc_backward(s.ctx, P.pimpc_tape_id(s.ctx), g, *grads, stream=stream.cuda_stream)
+        stream.synchronize()
+        outs.append([u0.cpu().numpy()] + [t.cpu().numpy() for t in grads])
+        s.close()
+    for a, b in zip(*outs):
+        assert np.all(np.isfinite(a))
+        np.testing.assert_array_equal(a, b)
