@@ -442,11 +442,21 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
         // ---- step 1b: h_k = qbar + rho (z_{k+1} - theta_k + g_{k+1}); xbar_{k+1} = H_k h_k
         if (run) {
             T h[NB];
+            // REC: h is recorded as soon as it is formed; stored after the H
+            // rows instead it spilled hundreds of VGPRs in the 12-wide classes
+            // ((12,4): 509, and a recording forward 6.9x the plain one)
             if constexpr (kLR) {
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
                     const T gn = from_next_wave ? bnd_g[wave + 1 < BW ? wave + 1 : wave][i] : g[i];
                     h[i] = L[MI::Q + i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
+                }
+                if constexpr (REC) {
+                    if (act) {
+                        const gptr<T> tr = RECP(it);
+#pragma unroll
+                        for (int i = 0; i < NB; ++i) tr[(int64_t)(NB + i) * N + k] = h[i];
+                    }
                 }
                 // H_{N-1} for the last stage
                 lds_rows<T, NB, NBP, kRD>(L + (is_last ? MI::Hb : MI::H), [&](int r, const T (&x)[NBP]) {
@@ -463,6 +473,13 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
                 for (int i = 0; i < NB; ++i) {
                     const T gn = from_next_wave ? bnd_g[wave + 1 < BW ? wave + 1 : wave][i] : g[i];
                     h[i] = q[i] + rho * (z[i] - th[i] + (hasnext ? gn : T(0)));
+                }
+                if constexpr (REC) {
+                    if (act) {
+                        const gptr<T> tr = RECP(it);
+#pragma unroll
+                        for (int i = 0; i < NB; ++i) tr[(int64_t)(NB + i) * N + k] = h[i];
+                    }
                 }
                 using Row = SRow<T, NB>;
                 stream_rows<Row, NB, kPF>(
@@ -516,13 +533,6 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
 #pragma unroll
                     for (int j = 0; j < NB; ++j) s += Hr[r * NB + j] * h[j];
                     xs[r] = s;
-                }
-            }
-            if constexpr (REC) {
-                if (act) {
-                    const gptr<T> tr = RECP(it);
-#pragma unroll
-                    for (int i = 0; i < NB; ++i) tr[(int64_t)(NB + i) * N + k] = h[i];
                 }
             }
             // xbar moves one lane up (stage k -> k + 1); lane 63 hands its
