@@ -3,7 +3,8 @@
 forward(x0, Qdiag, Rdiag, A, B) -> u0 for a batch of instances with equal
 (nx, nu): re-factors the stage caches from the device tensors
 (pimpc_set_params_dev), runs the taped batched solve (pimpc_solve_batch with
-checkpoints every `ckpt_every` iterations) and returns u0 = du_0 of the last
+checkpoints every `ckpt_every` iterations, or every step recorded when it is
+1) and returns u0 = du_0 of the last
 step 1 (cold start, u(t-1) = 0).  backward(dL/du0) runs the adjoint kernels
 (pimpc_backward) and returns dL/dx0, dL/dQdiag, dL/dRdiag, dL/dA, dL/dB.
 PyTorch only provides memory and the stream; all arithmetic is in libpimpc.
@@ -58,7 +59,11 @@ class PiMPCFunction(torch.autograd.Function):
 
 class PiMPCLayer(torch.nn.Module):
     """Batch of `count` MPC instances of one shape (nx, nu, N) with box bounds,
-    solved with `iters` plain ADMM iterations and differentiated through them."""
+    solved with `iters` plain ADMM iterations and differentiated through them.
+    ckpt_every = k >= 2 keeps the iterate every k iterations and the backward
+    re-runs each segment; ckpt_every = 1 records every step in the forward
+    (2 nb + nx + 1 floats a stage and iteration) and the backward re-runs
+    nothing."""
 
     def __init__(self, count: int, nx: int, nu: int, N: int, iters: int = 200, ckpt_every: int = 20,
                  rho: float = 1.0, xbound: float = 4.0, ubound: float = 0.5, Wdu=None):
