@@ -214,3 +214,35 @@ def test_backward_mixed_shapes_packs_per_instance():
         for key, v in got.items():
             assert rel(v, np.asarray(go[key]).reshape(v.shape)) <= TOLG, (i, key, rel(v, go[key]))
         ox, ou, oa, ob = ox + nx, ou + nu, oa + nx * nx, ob + nx * nu
+
+
+@pytest.mark.parametrize("ck", [1, 8])
+def test_host_path_taped_forward_feeds_the_backward(ck):
+    """pimpc_solve (host pointers) records the same tape as the device-pointer
+    path: u0 and the backward after it equal those of pimpc_solve_batch bit
+    for bit, with the full tape and with checkpoints."""
+    db = W.diff_batch(count=16, seed=4, N=64, K=40)
+    ps = [db.instance(i) for i in range(16)]
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    x32 = np.ascontiguousarray(db.x0[:16]).ravel().astype(np.float32)
+    ut = torch.tensor(db.u_target[:16].ravel(), dtype=torch.float32, device=dev)
+    outs = []
+    for path in ("host", "device"):
+        s = P.Solver(ps, max_iter=40, precision=P.PIMPC_FP32, ckpt_every=ck, stream=stream)
+        if path == "host":
+            u0h, info = s.solve(x0=x32.astype(np.float64))
+            assert np.all(info["status"] == 0)
+            u0 = torch.tensor(u0h, dtype=torch.float32, device=dev)
+        else:
+            x0 = torch.tensor(x32, device=dev)
+            u0 = torch.empty(s.sum_nu, dtype=torch.float32, device=dev)
+            P.pimpc_solve_batch(s.ctx, x0, None, u0, None, stream)
+        grads = [torch.full((n,), float("nan"), device=dev) for n in (16 * 8, 16 * 8, 16 * 3, 16 * 64, 16 * 24)]
+        P.pimpc_backward(s.ctx, P.pimpc_tape_id(s.ctx), 2 * (u0 - ut), *grads, stream=stream)
+        torch.cuda.synchronize()
+        outs.append([u0.cpu().numpy()] + [t.cpu().numpy() for t in grads])
+        s.close()
+    for a, b in zip(*outs):
+        assert np.all(np.isfinite(a))
+        np.testing.assert_array_equal(a, b)
