@@ -9,13 +9,13 @@
 //     workgroup (256 threads for FP64 classes whose horizons all fit four
 //     waves); several instances share a workgroup ("bin");
 //   * time-invariant stage data (J, H, A, B, e, bounds) is uniform across the
-//     wave.  FP32 classes up to 12 wide copy it once per bin into a per-wave
-//     LDS image and read each row as float4 broadcasts, two rows ahead of its
-//     use; wider classes and FP64 stream it row by row through SGPRs with
-//     scalar loads, one row ahead of its use (each row's load overlaps the
-//     previous row's FMAs), so that every mat-vec FMA takes its matrix
-//     operand from an SGPR; time-varying stage data is loaded once into VGPRs
-//     per lane;
+//     wave.  FP32 box classes up to 20 wide (nu <= 4) copy it once per bin
+//     into a per-wave LDS image and read each row as float4 broadcasts (two
+//     rows ahead of their use up to 18 wide, one at a time beyond); the other
+//     classes and FP64 stream it row by row through SGPRs with scalar loads,
+//     one row ahead of its use (each row's load overlaps the previous row's
+//     FMAs), so that every mat-vec FMA takes its matrix operand from an SGPR;
+//     time-varying stage data is loaded once into VGPRs per lane;
 //   * the two one-stage halos of an iteration (g_{k+1} for step 1 and
 //     xbar_k for step 2) move between neighbouring lanes with DPP wavefront
 //     shifts; only the value crossing a wave boundary goes through a small
@@ -30,7 +30,9 @@
 //     iterate, kept in a global buffer;
 //   * a kernel variant per class (GS) projects onto non-box factor sets
 //     (halfspace, hyperplane, second-order cone, l1 ball) once the whole
-//     projection argument of a stage is known.
+//     projection argument of a stage is known;
+//   * another (REC, FP32 time-invariant boxes) writes, at every step, the
+//     record the backward's reverse sweep reads (the full tape).
 #include <hip/hip_runtime.h>
 
 #include "pimpc_dev.hpp"
