@@ -112,10 +112,11 @@ def test_backward_without_tape_is_an_error():
 
 @pytest.mark.parametrize("nx,nu,N,K,ck", [(4, 2, 40, 20, 6), (12, 4, 70, 16, 5), (6, 1, 130, 12, 4),
                                          (4, 2, 40, 20, 1), (12, 4, 70, 16, 1), (6, 1, 130, 12, 1),
-                                         (2, 2, 200, 10, 1)])
+                                         (2, 2, 200, 10, 1), (8, 8, 90, 12, 4), (7, 5, 256, 10, 1)])
 def test_adjoint_other_classes(nx, nu, N, K, ck):
-    """Backward kernels of other (nx, nu) classes (padded 4+2, 12+4, 8+1 and
-    2+2) and horizons over one, two and four waves, against the oracle's
+    """Backward kernels of other (nx, nu) classes (padded 4+2, 12+4, 8+1, 2+2
+    and 8+8, the widest, whose matrices stream through SGPRs) and horizons
+    over one, two and four waves (N = 256 fills four), against the oracle's
     reverse mode, from checkpoints and from the full tape (ck = 1)."""
     from paper_2601_14414_amd.autograd import PiMPCLayer
     rng = np.random.default_rng(nx * 100 + nu)
