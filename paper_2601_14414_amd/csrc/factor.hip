@@ -10,8 +10,11 @@
 // with Abar = [[A, B], [0, I]], Bbar = [[B], [I]], Qbar = blkdiag(Q, R).
 // One 64-thread workgroup builds one matrix in LDS, factors it by a
 // right-looking Cholesky (pivot-column scaling and trailing update spread
-// over the workgroup) and forms the inverse one column per thread.  All of
-// it in double; results are stored in the iteration precision T.
+// over the workgroup) and forms the inverse one column per thread, each
+// column solved in LDS beside the factor.  The LDS is sized for the widest
+// matrix of the launch (n x (n + 1) doubles twice), not for the widest
+// class, so that narrow stages fit many workgroups on a compute unit.  All
+// of it in double; results are stored in the iteration precision T.
 //
 // Also here: the kernels that expand the FP64 stage data into the T layout
 // the ADMM kernels read, that load per-instance parameters from device
@@ -25,48 +28,53 @@
 
 namespace pimpc {
 
-constexpr int kMaxNb = 64;
-constexpr int kLd = kMaxNb + 1;  // LDS leading dimension (odd -> fewer bank conflicts)
+constexpr int kMaxNb = 64;  // widest matrix a launch may hold (one column per thread)
 
-// Cholesky of the n x n matrix in M (lower triangle overwritten by L);
-// returns false if a pivot is not strictly positive (or not finite).
-__device__ bool lds_cholesky(double* M, int n) {
+// LDS of one factor workgroup for matrices up to nb wide: the matrix and the
+// solution columns, each nb x (nb + 1) doubles (odd leading dimension).
+__host__ __device__ inline size_t factor_lds_bytes(int nb) { return 2 * (size_t)nb * (nb + 1) * sizeof(double); }
+
+// Cholesky of the n x n matrix in M (leading dimension ld; lower triangle
+// overwritten by L); returns false if a pivot is not strictly positive (or
+// not finite).
+__device__ bool lds_cholesky(double* M, int n, int ld) {
     __shared__ int ok;
     const int t = threadIdx.x;
     if (t == 0) ok = 1;
     __syncthreads();
     for (int j = 0; j < n; ++j) {
         if (t == 0) {
-            const double d = M[j * kLd + j];
+            const double d = M[j * ld + j];
             if (!(d > 0.0) || !(d < INFINITY)) ok = 0;
-            M[j * kLd + j] = sqrt(fmax(d, 0.0));
+            M[j * ld + j] = sqrt(fmax(d, 0.0));
         }
         __syncthreads();
-        const double piv = M[j * kLd + j];
-        for (int i = j + 1 + t; i < n; i += blockDim.x) M[i * kLd + j] = M[i * kLd + j] / piv;
+        const double piv = M[j * ld + j];
+        for (int i = j + 1 + t; i < n; i += blockDim.x) M[i * ld + j] = M[i * ld + j] / piv;
         __syncthreads();
         const int m = n - j - 1;
         for (int idx = t; idx < m * m; idx += blockDim.x) {
             const int i = j + 1 + idx / m;
             const int l = j + 1 + idx % m;
-            if (l <= i) M[i * kLd + l] -= M[i * kLd + j] * M[l * kLd + j];
+            if (l <= i) M[i * ld + l] -= M[i * ld + j] * M[l * ld + j];
         }
         __syncthreads();
     }
     return ok != 0;
 }
 
-// Solve L L' x = b in place (b in registers of one thread, length n).
-__device__ void chol_solve_col(const double* L, int n, double* x) {
+// Solve L L' x = b in place; b is one thread's column, x[i] at x[i * xs]
+// (LDS), L with leading dimension ld.
+__device__ void chol_solve_col(const double* L, int n, int ld, double* x, int xs) {
     for (int i = 0; i < n; ++i) {
-        double s = x[i];
-        for (int k = 0; k < i; ++k) s -= L[i * kLd + k] * x[k];
-        x[i] = s / L[i * kLd + i];
+        double s = x[i * xs];
+        for (int k = 0; k < i; ++k) s -= L[i * ld + k] * x[k * xs];
+        x[i * xs] = s / L[i * ld + i];
     }
     for (int i = n - 1; i >= 0; --i) {
-        double s = x[i];
-        for (int k = i + 1; k < n; ++k) s -= L[k * kLd + i] * x[k];
-        x[i] = s / L[i * kLd + i];
+        double s = x[i * xs];
+        for (int k = i + 1; k < n; ++k) s -= L[k * ld + i] * x[k * xs];
+        x[i * xs] = s / L[i * ld + i];
     }
 }
 
@@ -76,10 +84,13 @@ __global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ 
                                                     const double* __restrict__ mats64,
                                                     T* __restrict__ mats, double rho,
                                                     int32_t* __restrict__ bad, int32_t* __restrict__ ibad) {
-    __shared__ double M[kMaxNb * kLd];
+    extern __shared__ double fsm[];  // factor_lds_bytes(widest NB of the launch)
     const FactorTask tk = tasks[blockIdx.x];
     const InstDev I = inst[tk.inst];
     const int NX = I.nxp, NU = I.nup, NB = I.nbp, N = I.N;
+    const int ld = NB + 1;       // leading dimension of M and of the solution columns X
+    double* M = fsm;
+    double* X = fsm + NB * ld;   // column t of the right-hand sides / solutions at X[i * ld + t]
     const MatOffsets o = mat_offsets(NX, NU, N, I.tv);
     const double* b64 = mats64 + I.mat64_off;
     T* bt = mats + I.mat_off;
@@ -107,25 +118,25 @@ __global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ 
                 if (i >= NX && i == j) a += 1.0;
                 s += rho * a;
             }
-            M[i * kLd + j] = s;
+            M[i * ld + j] = s;
         }
         __syncthreads();
-        const bool ok = lds_cholesky(M, NB);
+        const bool ok = lds_cholesky(M, NB, ld);
         if (!ok && t == 0) {
             bad[blockIdx.x] = 1;
             ibad[tk.inst] = 1;
         }
         if (t < NB) {
-            double x[kMaxNb];
-            for (int i = 0; i < NB; ++i) x[i] = (i == t) ? 1.0 : 0.0;
-            chol_solve_col(M, NB, x);
+            double* x = X + t;
+            for (int i = 0; i < NB; ++i) x[i * ld] = (i == t) ? 1.0 : 0.0;
+            chol_solve_col(M, NB, ld, x, ld);
             // column t of H (H is symmetric)
             if (!I.tv) {
                 T* H = bt + (tk.kind == 0 ? o.H : o.Hb);
-                for (int i = 0; i < NB; ++i) H[i * NB + t] = (T)x[i];
+                for (int i = 0; i < NB; ++i) H[i * NB + t] = (T)x[i * ld];
             } else {
                 T* H = bt + o.H;
-                for (int i = 0; i < NB; ++i) H[(int64_t)(i * NB + t) * N + tk.stage] = (T)x[i];
+                for (int i = 0; i < NB; ++i) H[(int64_t)(i * NB + t) * N + tk.stage] = (T)x[i * ld];
             }
         }
     } else {
@@ -137,23 +148,23 @@ __global__ void __launch_bounds__(64) factor_kernel(const InstDev* __restrict__ 
             const int i = idx / NU, j = idx % NU;
             double s = ((i == j) ? 1.0 : 0.0) + Wd[i * NU + j] / rho;
             for (int r = 0; r < NX; ++r) s += Bk[r * NU + i] * Bk[r * NU + j];
-            M[i * kLd + j] = s;
+            M[i * ld + j] = s;
         }
         __syncthreads();
-        const bool ok = lds_cholesky(M, NU);
+        const bool ok = lds_cholesky(M, NU, ld);
         if (!ok && t == 0) {
             bad[blockIdx.x] = 1;
             ibad[tk.inst] = 1;
         }
         if (t < NB) {
-            double x[kMaxNb];
-            for (int i = 0; i < NU; ++i) x[i] = (t < NX) ? Bk[t * NU + i] : ((t - NX) == i ? 1.0 : 0.0);
-            chol_solve_col(M, NU, x);
+            double* x = X + t;
+            for (int i = 0; i < NU; ++i) x[i * ld] = (t < NX) ? Bk[t * NU + i] : ((t - NX) == i ? 1.0 : 0.0);
+            chol_solve_col(M, NU, ld, x, ld);
             T* J = bt + o.J;
             if (!I.tv) {
-                for (int i = 0; i < NU; ++i) J[i * NB + t] = (T)x[i];
+                for (int i = 0; i < NU; ++i) J[i * NB + t] = (T)x[i * ld];
             } else {
-                for (int i = 0; i < NU; ++i) J[(int64_t)(i * NB + t) * N + tk.stage] = (T)x[i];
+                for (int i = 0; i < NU; ++i) J[(int64_t)(i * NB + t) * N + tk.stage] = (T)x[i * ld];
             }
         }
     }
@@ -318,11 +329,12 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
 // ---------------------------------------------------------------- launchers
 
 template <typename T>
-hipError_t launch_factor(const InstDev* inst, const FactorTask* tasks, int ntasks, const double* mats64,
+hipError_t launch_factor(const InstDev* inst, const FactorTask* tasks, int ntasks, int nbmax, const double* mats64,
                          T* mats, double rho, int32_t* bad, int32_t* ibad, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(factor_kernel<T>, dim3(ntasks), dim3(64), 0, s, inst, tasks, mats64, mats, rho,
-                       bad, ibad);
+    if (nbmax < 1 || nbmax > kMaxNb) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(factor_kernel<T>, dim3(ntasks), dim3(64), factor_lds_bytes(nbmax), s, inst, tasks, mats64,
+                       mats, rho, bad, ibad);
     return hipGetLastError();
 }
 
@@ -350,9 +362,9 @@ hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {
     return hipGetLastError();
 }
 
-template hipError_t launch_factor<float>(const InstDev*, const FactorTask*, int, const double*, float*,
+template hipError_t launch_factor<float>(const InstDev*, const FactorTask*, int, int, const double*, float*,
                                          double, int32_t*, int32_t*, hipStream_t);
-template hipError_t launch_factor<double>(const InstDev*, const FactorTask*, int, const double*, double*,
+template hipError_t launch_factor<double>(const InstDev*, const FactorTask*, int, int, const double*, double*,
                                           double, int32_t*, int32_t*, hipStream_t);
 
 template hipError_t launch_expand<float>(const InstDev*, int, const double*, float*, hipStream_t);

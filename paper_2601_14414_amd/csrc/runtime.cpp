@@ -26,8 +26,8 @@
 
 namespace pimpc {
 template <typename T>
-hipError_t launch_factor(const InstDev*, const FactorTask*, int, const double*, T*, double, int32_t*, int32_t*,
-                         hipStream_t);
+hipError_t launch_factor(const InstDev*, const FactorTask*, int, int, const double*, T*, double, int32_t*,
+                         int32_t*, hipStream_t);
 hipError_t launch_stage_import(const InstDev*, int, const int64_t*, const double*, const double*, const double*,
                                double*, int32_t*, hipStream_t);
 hipError_t launch_bytes_store(void*, const void*, size_t, hipStream_t);
@@ -192,6 +192,7 @@ struct pimpc_ctx_s {
     InfoDev* d_info = nullptr;
     FactorTask* d_tasks = nullptr;
     int ntasks = 0;
+    int nb_max = 1;  // widest padded stage (nx + nu) of the context: the factor kernel's LDS
     int32_t* d_bad = nullptr;       // per factorisation task: not SPD
     int32_t* d_ibad = nullptr;      // per instance: some stage matrix not SPD (read by the solve kernels)
     int32_t* d_nonfinite = nullptr; // device stage import saw NaN/Inf
@@ -414,11 +415,11 @@ static int refactor(pimpc_ctx ctx, bool sync_check) {
     HIPCHK(ctx, launch_fill<int32_t>(ctx->d_ibad, ctx->count, 0, s));
     if (ctx->fp64) {
         HIPCHK(ctx, launch_expand<double>(ctx->d_inst, ctx->count, ctx->d_mats64, (double*)ctx->d_mats, s));
-        HIPCHK(ctx, launch_factor<double>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->d_mats64,
+        HIPCHK(ctx, launch_factor<double>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->nb_max, ctx->d_mats64,
                                           (double*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, ctx->d_ibad, s));
     } else {
         HIPCHK(ctx, launch_expand<float>(ctx->d_inst, ctx->count, ctx->d_mats64, (float*)ctx->d_mats, s));
-        HIPCHK(ctx, launch_factor<float>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->d_mats64,
+        HIPCHK(ctx, launch_factor<float>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->nb_max, ctx->d_mats64,
                                          (float*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, ctx->d_ibad, s));
     }
     HIPCHK(ctx, fuse_rows(ctx, s));
@@ -1162,6 +1163,7 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     ctx->sum_nx = xo;
     ctx->sum_nu = uo;
     ctx->ntasks = (int)tasks.size();
+    for (const InstDev& I : ctx->inst) ctx->nb_max = std::max(ctx->nb_max, I.nbp);
 
     // ---------------- device
     int dev = 0;
