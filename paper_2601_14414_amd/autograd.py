@@ -33,9 +33,8 @@ class PiMPCFunction(torch.autograd.Function):
         # a stage matrix that is not SPD (e.g. a negative weight) is reported
         # through the per-instance status of the info records
         status = info.view(solver.count, -1)[:, P.INFO_DTYPE.fields["status"][1] // 4]
-        bad = torch.nonzero(status).flatten()
-        if bad.numel() > 0:
-            i = int(bad[0])
+        if bool((status != 0).any()):  # one reduction and one read-back; the index only on failure
+            i = int(torch.nonzero(status).flatten()[0])
             raise P.PimpcError(int(status[i]), f"instance {i} of the differentiable batch failed "
                                                f"({'stage matrix not SPD' if int(status[i]) == P.PIMPC_E_NOT_PSD else 'non-finite iterate'})")
         ctx.solver = solver
