@@ -61,7 +61,7 @@ extern __shared__ __align__(16) unsigned char bwd_smem[];
 // then runs two products' MFMA chains interleaved.  After the areas: the
 // last stage's xsb and h (32 floats) and the x0 adjoint (16 floats).
 constexpr int kStgArea = 64 * 16;                 // floats per staged vector
-constexpr int kStgFloats = 6 * kStgArea + 48;     // six areas + 48 floats
+constexpr int kStgFloats = 6 * kStgArea + 64;     // six areas + 64 floats
 __device__ inline int stage_rot(int s) { return ((s >> 1) + (s >> 3)) & 3; }
 
 __device__ inline void stage_write(float* area, const float (&v)[16], int lane) {
@@ -253,8 +253,14 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
     float sv[NB], sz[NB], sth[NB], sbe[NB], sla[NB];  // adjoint of the iterate entering the step
 #pragma unroll
     for (int i = 0; i < NB; ++i) sv[i] = sz[i] = sth[i] = sbe[i] = sla[i] = 0.f;
-    float* lw = stg + 6 * kStgArea;  // [0, 32): the last stage's xsb and h; [32, 48): the x0 adjoint
-    if (lane < 16) lw[32 + lane] = 0.f;
+    // [0, 32): the last stage's xsb and h; [32, 48): the x0 adjoint; [48, 64):
+    // xbar_0 (read by stage 0 in every step, so kept in LDS rather than
+    // re-read through the scalar cache)
+    float* lw = stg + 6 * kStgArea;
+    if (lane < 16) {
+        lw[32 + lane] = 0.f;
+        lw[48 + lane] = lane < NB ? xb0(lane) : 0.f;
+    }
     __builtin_amdgcn_wave_barrier();
     floatx4 CHa = {0, 0, 0, 0}, CHb = {0, 0, 0, 0}, CJ = {0, 0, 0, 0}, CA = {0, 0, 0, 0}, CB = {0, 0, 0, 0};
 
@@ -354,7 +360,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const float xv = xx[i * kBBD + tid - 1];
-            xp[i] = (k == 0) ? xb0(i) : (act ? xv : 0.f);
+            xp[i] = (k == 0) ? lw[48 + i] : (act ? xv : 0.f);
         }
     };
 
@@ -611,7 +617,7 @@ __device__ __forceinline__ void bwd_run(const BwdArgs& a, int inst_idx, bool hav
             put(ar1, [&](int q) {
                 if (q >= NB) return 0.f;
                 const float xv = xq[q * kBBD + tid - 1];
-                return (k == 0) ? xb0(q) : (act ? xv : 0.f);
+                return (k == 0) ? lw[48 + q] : (act ? xv : 0.f);
             });
             // round 1: Abar += cb xbar_k' (top rows); J_bar += dub d' and
             // Bbar += bb du' (top rows) in one tile, or Bbar alone
