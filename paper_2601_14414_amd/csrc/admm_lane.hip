@@ -182,7 +182,7 @@ template <typename T, int NX, int NU, bool TV, bool GS, int BW, bool REC>
 __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bool have, int gw0,
                                          unsigned leader_mask, T (*bnd_g)[NX + NU], T (*bnd_x)[NX + NU],
                                          T (*dzl)[64 * BW], T (*ddl)[64 * BW], double* red, int* gdone,
-                                         T* limg) {
+                                         T* limg, T (*xb0l)[NX + NU]) {
     inst_idx = __builtin_amdgcn_readfirstlane(inst_idx);
     gw0 = __builtin_amdgcn_readfirstlane(gw0);
     have = __builtin_amdgcn_readfirstlane((int)have) != 0;
@@ -264,6 +264,21 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     // scalar cache where lane k = 0 needs it.
 #define XB0(i) ((i) < NX ? ((i) < nx_real ? x0p[(i)] : T(0)) \
                          : ((upp && (i) - NX < nu_real) ? upp[(i) - NX] : T(0)))
+    // xbar_0, which stage 0 reads at every step 2, goes to this wave's LDS
+    // slot once: re-reading it through the scalar cache exposed a round trip
+    // per iteration (measured: the single FP64 chain 0.90 -> 0.81 ms, the
+    // 4096-instance batch 16.2-16.5 -> 15.4-15.8 ms).  The 20- and 24-wide
+    // classes keep the scalar loads: there the change moved spills into the
+    // loop and (16,4) ran 6 % slower.
+    constexpr bool kXL = NX + NU < 20;
+    if constexpr (kXL) {
+        const cptr<T> x0p = (cptr<T>)uniform_ptr((const T*)(*ap).x0 + (have ? (*ip).x_off : 0));
+        const T* upraw = (const T*)(*ap).uprev;
+        const cptr<T> upp = (cptr<T>)uniform_ptr(upraw ? upraw + (have ? (*ip).u_off : 0) : nullptr);
+        const int nx_real = have ? (*ip).nx : 0, nu_real = have ? (*ip).nu : 0;
+        if (lane < NB) xb0l[wave][lane] = XB0(lane);
+        __builtin_amdgcn_wave_barrier();
+    }
 
     // iterate (v, z, theta, beta, lambda) of this stage
     T v[NB], z[NB], th[NB], be[NB], la[NB];
@@ -559,16 +574,24 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
             T xp[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) xp[i] = shr1(xs[i]);
-            // xbar_0 = col(x(t), u(t-1)) for stage 0 (uniform, scalar loads)
-            const cptr<T> x0p = (cptr<T>)uniform_ptr((const T*)(*AP()).x0 + (have ? (*IP()).x_off : 0));
-            const T* upraw = (const T*)(*AP()).uprev;
-            const cptr<T> upp = (cptr<T>)uniform_ptr(upraw ? upraw + (have ? (*IP()).u_off : 0) : nullptr);
-            const int nx_real = have ? (*IP()).nx : 0, nu_real = have ? (*IP()).nu : 0;
+            // xbar_0 = col(x(t), u(t-1)) for stage 0, from the wave's LDS slot
             const int wprev = wave > 0 ? wave - 1 : 0;
+            if constexpr (kXL) {
 #pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const T xv = from_prev_wave ? bnd_x[wprev][i] : xp[i];
-                xp[i] = (k == 0) ? XB0(i) : (act ? xv : T(0));
+                for (int i = 0; i < NB; ++i) {
+                    const T xv = from_prev_wave ? bnd_x[wprev][i] : xp[i];
+                    xp[i] = (k == 0) ? xb0l[wave][i] : (act ? xv : T(0));
+                }
+            } else {
+                const cptr<T> x0p = (cptr<T>)uniform_ptr((const T*)(*AP()).x0 + (have ? (*IP()).x_off : 0));
+                const T* upraw = (const T*)(*AP()).uprev;
+                const cptr<T> upp = (cptr<T>)uniform_ptr(upraw ? upraw + (have ? (*IP()).u_off : 0) : nullptr);
+                const int nx_real = have ? (*IP()).nx : 0, nu_real = have ? (*IP()).nu : 0;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const T xv = from_prev_wave ? bnd_x[wprev][i] : xp[i];
+                    xp[i] = (k == 0) ? XB0(i) : (act ? xv : T(0));
+                }
             }
 #pragma unroll
             for (int c = 0; c < NU; ++c) rdu[c] = T(0);
@@ -932,6 +955,7 @@ __global__ void __launch_bounds__(64 * BW)
     __shared__ int gdone[BW];            // per-instance stop flags (indexed by first wave)
     constexpr bool kLR = lane_lds_rows<T, NX, NU, TV, GS, BW>();
     __shared__ __align__(16) T limg[kLR ? BW * lane_img_stride<NX, NU>() : 1];  // matrix images
+    __shared__ T xb0l[BW][NX + NU];      // xbar_0 of each wave's instance
     __shared__ int s_bin;
     const int wave = threadIdx.x >> 6;
     for (int j = 0;; ++j) {
@@ -957,10 +981,10 @@ __global__ void __launch_bounds__(64 * BW)
         __syncthreads();
         if (my >= 0)
             lane_run<T, NX, NU, TV, GS, BW, REC>(ap, bin.e[my].inst, true, bin.e[my].wave0, leader_mask, bnd_g,
-                                            bnd_x, dzl, ddl, red, gdone, limg);
+                                            bnd_x, dzl, ddl, red, gdone, limg, xb0l);
         else
             lane_run<T, NX, NU, TV, GS, BW, REC>(ap, 0, false, wave, leader_mask, bnd_g, bnd_x, dzl, ddl, red, gdone,
-                                            limg);
+                                            limg, xb0l);
         __syncthreads();
     }
 }
