@@ -151,12 +151,13 @@ def test_adjoint_other_classes(nx, nu, N, K, ck):
 
 
 def _mixed_problems(K):
-    """Six instances of two shapes in one context, interleaved: 4 states +
-    2 inputs with N = 40, and 8 + 3 with N = 100 (two lane classes)."""
+    """Six instances of three shapes in one context, interleaved: 4 states +
+    2 inputs with N = 40, 8 + 3 with N = 100 and 12 + 4 with N = 70 (three
+    lane classes; the last one keeps J_bar and B_bar in separate tiles)."""
     rng = np.random.default_rng(21)
     ps = []
     for i in range(6):
-        nx, nu, N = (4, 2, 40) if i % 2 == 0 else (8, 3, 100)
+        nx, nu, N = [(4, 2, 40), (8, 3, 100), (12, 4, 70)][i % 3]
         A = np.eye(nx) * 0.95 + 0.05 * rng.standard_normal((nx, nx))
         B = rng.standard_normal((nx, nu)) / np.sqrt(nx)
         ps.append(W.Problem(nx=nx, nu=nu, N=N, A=A, B=B, Q=np.diag(rng.uniform(0.5, 1.5, nx)),
@@ -190,7 +191,7 @@ def _mixed_grads(ps, K, ck, ut):
 
 
 def test_backward_mixed_shapes_packs_per_instance():
-    """One taped context holding two classes: the gradients come packed per
+    """One taped context holding three classes: the gradients come packed per
     instance in instance order (dx0 and diag Q like x0, diag R like u0, the
     dA and dB blocks one after another), every entry written, each instance's
     block equal to the oracle's reverse mode; the full tape (ckpt_every = 1)
