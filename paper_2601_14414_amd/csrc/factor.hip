@@ -185,11 +185,10 @@ __global__ void expand_kernel(const InstDev* __restrict__ inst, int count,
     T* bt = mats + I.mat_off;
     const int S = I.tv ? N : 1;
     const int per = NX * NX + NX * NU + NX;
-    const int64_t total = (int64_t)S * per;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int k = (int)(idx / per);
-        const int q = (int)(idx % per);
+    const int total = S * per;  // < 2^31 (checked at setup)
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        const int k = idx / per;
+        const int q = idx - k * per;
         double val;
         int64_t dst;
         if (q < NX * NX) {
@@ -339,9 +338,10 @@ hipError_t launch_factor(const InstDev* inst, const FactorTask* tasks, int ntask
 }
 
 template <typename T>
-hipError_t launch_expand(const InstDev* inst, int count, const double* mats64, T* mats, hipStream_t s) {
+hipError_t launch_expand(const InstDev* inst, int count, const double* mats64, T* mats, int tv, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(expand_kernel<T>, dim3(4, count), dim3(256), 0, s, inst, count, mats64, mats);
+    // time-varying data: N stages per instance, so more workgroups per instance
+    hipLaunchKernelGGL(expand_kernel<T>, dim3(tv ? 32 : 4, count), dim3(256), 0, s, inst, count, mats64, mats);
     return hipGetLastError();
 }
 
@@ -367,8 +367,8 @@ template hipError_t launch_factor<float>(const InstDev*, const FactorTask*, int,
 template hipError_t launch_factor<double>(const InstDev*, const FactorTask*, int, int, const double*, double*,
                                           double, int32_t*, int32_t*, hipStream_t);
 
-template hipError_t launch_expand<float>(const InstDev*, int, const double*, float*, hipStream_t);
-template hipError_t launch_expand<double>(const InstDev*, int, const double*, double*, hipStream_t);
+template hipError_t launch_expand<float>(const InstDev*, int, const double*, float*, int, hipStream_t);
+template hipError_t launch_expand<double>(const InstDev*, int, const double*, double*, int, hipStream_t);
 template hipError_t launch_params<float>(const InstDev*, int, const float*, const float*, const float*,
                                          const float*, double*, hipStream_t);
 template hipError_t launch_params<double>(const InstDev*, int, const double*, const double*,

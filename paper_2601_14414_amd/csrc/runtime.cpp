@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -32,7 +33,7 @@ hipError_t launch_stage_import(const InstDev*, int, const int64_t*, const double
                                double*, int32_t*, hipStream_t);
 hipError_t launch_bytes_store(void*, const void*, size_t, hipStream_t);
 template <typename T>
-hipError_t launch_expand(const InstDev*, int, const double*, T*, hipStream_t);
+hipError_t launch_expand(const InstDev*, int, const double*, T*, int, hipStream_t);
 template <typename T>
 hipError_t launch_params(const InstDev*, int, const T*, const T*, const T*, const T*, double*, hipStream_t);
 template <typename T>
@@ -414,11 +415,11 @@ static int refactor(pimpc_ctx ctx, bool sync_check) {
     HIPCHK(ctx, launch_fill<int32_t>(ctx->d_bad, std::max(ctx->ntasks, 1), 0, s));
     HIPCHK(ctx, launch_fill<int32_t>(ctx->d_ibad, ctx->count, 0, s));
     if (ctx->fp64) {
-        HIPCHK(ctx, launch_expand<double>(ctx->d_inst, ctx->count, ctx->d_mats64, (double*)ctx->d_mats, s));
+        HIPCHK(ctx, launch_expand<double>(ctx->d_inst, ctx->count, ctx->d_mats64, (double*)ctx->d_mats, ctx->tv, s));
         HIPCHK(ctx, launch_factor<double>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->nb_max, ctx->d_mats64,
                                           (double*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, ctx->d_ibad, s));
     } else {
-        HIPCHK(ctx, launch_expand<float>(ctx->d_inst, ctx->count, ctx->d_mats64, (float*)ctx->d_mats, s));
+        HIPCHK(ctx, launch_expand<float>(ctx->d_inst, ctx->count, ctx->d_mats64, (float*)ctx->d_mats, ctx->tv, s));
         HIPCHK(ctx, launch_factor<float>(ctx->d_inst, ctx->d_tasks, ctx->ntasks, ctx->nb_max, ctx->d_mats64,
                                          (float*)ctx->d_mats, ctx->opt.rho, ctx->d_bad, ctx->d_ibad, s));
     }
@@ -1145,6 +1146,9 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
         ga += (int64_t)I.nx * I.nx;
         I.gb_off = gb;
         gb += (int64_t)I.nx * I.nu;
+        // the expansion of the stage data indexes one instance's A, B, e in 32 bits
+        if ((int64_t)(tv ? I.N : 1) * (I.nxp * I.nxp + I.nxp * I.nup + I.nxp) >= INT32_MAX)
+            return ctx->fail(PIMPC_E_DIM, "instance %d: time-varying stage data too large (N=%d)", i, I.N);
         if (!tv) {
             if (I.N > 1) tasks.push_back({i, 0, 0, 0});
             tasks.push_back({i, 1, I.N - 1, 0});
