@@ -114,7 +114,7 @@ typedef struct pimpc_ctx_s *pimpc_ctx;
  * (C = I, W_y = Q) or the output form below, the velocity-form linear term
  * qbar of Theorem 2 and the input-rate weight W_du of the experiments
  * (Section V).
- *   count          number of instances (>= 1)
+ *   count          number of instances (1 .. 65535; more: PIMPC_E_DIM)
  *   nx, nu, N      per-instance state/input sizes and horizon (count entries each)
  *   time_varying   0: one (A, B, e) per instance; 1: N stage copies per instance
  *   A, B           row-major nx*nx and nx*nu blocks (times N if time_varying)

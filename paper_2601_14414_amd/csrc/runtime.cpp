@@ -967,6 +967,8 @@ static int setup_impl(pimpc_ctx ctx, const pimpc_problem* p, const pimpc_options
     // ---------------- validation (host only, before any HIP call)
     if (!p || !o) return ctx->fail(PIMPC_E_ARG, "problem and options are required");
     if (p->count < 1) return ctx->fail(PIMPC_E_ARG, "count must be >= 1");
+    if (p->count > 65535)  // the setup kernels give each instance one row of their grid
+        return ctx->fail(PIMPC_E_DIM, "count must be <= 65535 (got %d)", p->count);
     if (!p->nx || !p->nu || !p->N || !p->A || !p->B || !p->Q || !p->R || !p->xmin || !p->xmax || !p->umin ||
         !p->umax)
         return ctx->fail(PIMPC_E_ARG, "a required problem array is NULL");

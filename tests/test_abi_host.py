@@ -62,6 +62,14 @@ def test_bad_options_rejected(field, value):
     assert code == P.PIMPC_E_ARG, (field, value, code, msg)
 
 
+def test_instance_count_beyond_the_setup_grid_is_refused():
+    """More than 65535 instances: PIMPC_E_DIM from host validation (the setup
+    kernels give each instance one row of their grid)."""
+    p = W.plain_fp64_problem(0).copy(N=1)
+    code, msg = _setup_code([p] * 65536)
+    assert code == P.PIMPC_E_DIM and "65535" in msg
+
+
 def test_bad_problem_data_rejected():
     p = W.plain_fp64_problem(0)
     q = p.copy(xmin=p.xmin.copy())
