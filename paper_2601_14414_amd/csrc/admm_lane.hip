@@ -9,7 +9,7 @@
 //     workgroup (256 threads for FP64 classes whose horizons all fit four
 //     waves); several instances share a workgroup ("bin");
 //   * time-invariant stage data (J, H, A, B, e, bounds) is uniform across the
-//     wave.  FP32 box classes up to 20 wide (nu <= 4) copy it once per bin
+//     wave.  FP32 box classes up to 19 wide (nu <= 4) copy it once per bin
 //     into a per-wave LDS image and read each row as float4 broadcasts (two
 //     rows ahead of their use up to 18 wide, one at a time beyond); the other
 //     classes and FP64 stream it row by row through SGPRs with scalar loads,
@@ -157,22 +157,24 @@ __device__ __forceinline__ double shr1(double x) {
 
 // Run (or, with have = false, only shadow the barrier sequence of) one
 // instance on the waves [gw0, gw0 + gnw) of the workgroup.
-// Time-invariant FP32 box classes up to 20 entries wide (nu <= 4) read their
+// Time-invariant FP32 box classes up to 19 entries wide (nu <= 4) read their
 // stage matrices from a per-wave LDS image instead of the SGPR row stream
 // (see MatImg).  Up to 18 wide, two rows are in flight behind in-order
 // waits; measured per class (batches of 512-1024 instances, 300 iterations):
 // (12,1..4) 17-20 % and (16,1..2) 21-23 % faster than SGPR rows, though the
 // rows in flight cost the widest of them a few dozen spilled VGPRs.  With
 // two rows in flight (16,3) and (16,4) spill 180-230 VGPRs and run 5-31 %
-// slower; with one row at a time they spill 72 and 173 (63 and 84 with SGPR
-// rows) and run 20 % and 3 % faster.  (8,8) keeps the SGPR stream (LDS rows would
-// spill 161 VGPRs there against 24), and so does FP64 (measured: the single
-// FP64 chain gains nothing from LDS rows).
+// slower; with one row at a time (16,3) runs 20 % faster.  (16,4) keeps the
+// SGPR stream: alone it ran 1-3 % faster on LDS rows, but the 4096-instance
+// batch ran 2.7 % faster with it on SGPR rows (with xbar_0 in LDS).  (8,8)
+// keeps it too (LDS rows would spill 161 VGPRs there against 24), and so
+// does FP64 (measured: the single FP64 chain gains nothing from LDS rows).
 template <typename T, int NX, int NU, bool TV, bool GS, int BW>
 constexpr bool lane_lds_rows() {
-    return !TV && !GS && sizeof(T) == 4 && NX + NU <= 20 && NU <= 4;
+    return !TV && !GS && sizeof(T) == 4 && NX + NU <= 19 && NU <= 4;
 }
-// Rows the LDS row stream keeps in flight beyond the one in use.
+// Rows the LDS row stream keeps in flight beyond the one in use ((16,3):
+// one row at a time).
 template <int NX, int NU>
 constexpr int lane_row_depth() { return NX + NU > 18 ? 0 : 2; }
 template <int NX, int NU>
@@ -267,10 +269,9 @@ __device__ __forceinline__ void lane_run(const LaneArgs* ap_in, int inst_idx, bo
     // xbar_0, which stage 0 reads at every step 2, goes to this wave's LDS
     // slot once: re-reading it through the scalar cache exposed a round trip
     // per iteration (measured: the single FP64 chain 0.90 -> 0.81 ms, the
-    // 4096-instance batch 16.2-16.5 -> 15.4-15.8 ms).  The 20- and 24-wide
-    // classes keep the scalar loads: there the change moved spills into the
-    // loop and (16,4) ran 6 % slower.
-    constexpr bool kXL = NX + NU < 20;
+    // 4096-instance batch 16.2-16.5 -> 15.2-15.4 ms).  The 24-wide class
+    // keeps the scalar loads.
+    constexpr bool kXL = NX + NU <= 20;
     if constexpr (kXL) {
         const cptr<T> x0p = (cptr<T>)uniform_ptr((const T*)(*ap).x0 + (have ? (*ip).x_off : 0));
         const T* upraw = (const T*)(*ap).uprev;
